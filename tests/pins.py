@@ -1,0 +1,451 @@
+"""Physics pins of the FP64 oracle.
+
+Each ``pin_*`` function raises ``AssertionError`` when the oracle library at
+``lib_path`` (default: the real one) violates something the paper or the
+mathematics fixes independently of the oracle's own code: the reference
+configuration, momentum balance, frame indifference, f = -grad E, closed forms
+of homogeneous deformations, the small-strain moduli, the neo-Hookean limit,
+linearity in the material parameters, a hand-derived worked example, and the
+derivative identities of the backward pass.  ``tests/test_oracle_pins.py``
+runs them on the oracle; ``tests/test_oracle_mutants.py`` runs them on copies
+of the oracle with planted mistakes and requires each copy to fail one.
+"""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+from scipy.optimize import brentq
+
+import oracle
+from synth.configs import small_sphere_case
+from synth.mesh import (boundary_faces, mean_edge_length, signed_volumes6,
+                        sphere_mesh)
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+_cache = {}
+
+
+def _mesh(n_target, seed):
+    key = ("mesh", n_target, seed)
+    if key not in _cache:
+        _cache[key] = sphere_mesh(n_target, seed)
+    return _cache[key]
+
+
+def _noisy_small(seed=1000):
+    key = ("small", seed)
+    if key not in _cache:
+        _cache[key] = small_sphere_case(seed)
+    return _cache[key]
+
+
+def _tiny_noisy(seed=7):
+    """A ~150-node sphere compressed, sheared and perturbed (for FD pins)."""
+    key = ("tiny", seed)
+    if key not in _cache:
+        x, tets = _mesh(150, seed)
+        rng = np.random.default_rng(seed)
+        A = np.array([[1.0, 0.0, 0.3], [0.0, 0.9, 0.0], [0.0, 0.0, 0.6]])
+        y = x @ A.T + rng.normal(0.0, 0.02, size=x.shape)
+        _cache[key] = (x, tets, y)
+    return _cache[key]
+
+
+def random_rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def rel_max(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max()
+                 / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def d1_5pt(g, h):
+    """Fourth-order central difference of a scalar function at 0."""
+    return (-g(2 * h) + 8 * g(h) - 8 * g(-h) + g(-2 * h)) / (12 * h)
+
+
+# ------------------------------------------------------------ closed forms
+def U_stretch(a, b, c, theta):
+    """Energy density of F = diag(a, b, c) written with principal stretches:
+    tr C = a^2 + b^2 + c^2 and (tr(C)^2 - tr(C^2))/2 = a^2 b^2 + b^2 c^2 +
+    c^2 a^2."""
+    mu, kappa, w = theta
+    J = a * b * c
+    I = (a * a + b * b + c * c) * J ** (-2.0 / 3.0)
+    K = (a * a * b * b + b * b * c * c + c * c * a * a) * J ** (-4.0 / 3.0)
+    return (w * mu / 2 * (I - 3) + (1 - w) * mu / 2 * (K - 3)
+            + kappa / 2 * (J - 1) ** 2)
+
+
+def P_stretch(a, b, c, theta, h=1e-5):
+    """dU/dF at F = diag(a, b, c): diagonal, entries dU/d(stretch)."""
+    return np.diag([
+        d1_5pt(lambda e: U_stretch(a + e, b, c, theta), h),
+        d1_5pt(lambda e: U_stretch(a, b + e, c, theta), h),
+        d1_5pt(lambda e: U_stretch(a, b, c + e, theta), h)])
+
+
+def U_uniaxial(lam, theta):
+    """F = diag(1, 1, lam)."""
+    mu, kappa, w = theta
+    return (w * mu / 2 * ((lam ** 2 + 2) * lam ** (-2.0 / 3.0) - 3)
+            + (1 - w) * mu / 2 * ((2 * lam ** 2 + 1) * lam ** (-4.0 / 3.0) - 3)
+            + kappa / 2 * (lam - 1) ** 2)
+
+
+def U_uniaxial_incompressible(lam, theta):
+    """F = diag(lam, lam^-1/2, lam^-1/2), J = 1."""
+    mu, kappa, w = theta
+    return (w * mu / 2 * (lam ** 2 + 2 / lam - 3)
+            + (1 - w) * mu / 2 * (2 * lam + 1 / lam ** 2 - 3))
+
+
+def boundary_normals(x, tets):
+    """n_a = sum over boundary faces containing a of (area * outward unit
+    normal) / 3, in the reference frame."""
+    bf = boundary_faces(tets)
+    an = 0.5 * np.cross(x[bf[:, 1]] - x[bf[:, 0]], x[bf[:, 2]] - x[bf[:, 0]])
+    n = np.zeros_like(x)
+    for k in range(3):
+        np.add.at(n, bf[:, k], an / 3.0)
+    on_boundary = np.zeros(len(x), dtype=bool)
+    on_boundary[bf.ravel()] = True
+    return n, on_boundary
+
+
+# ------------------------------------------------------------------- pins
+def pin_reference_configuration(lib_path=None):
+    """P1: y = x gives F = I, U = 0 and zero forces."""
+    x, tets = _mesh(1000, 1000)
+    m = oracle.OracleMesh(x, tets, lib_path)
+    theta = (1.3, 17.0, 0.4)
+    f, E, ninv = m.forces(x, theta)
+    h = mean_edge_length(x, tets)
+    V = signed_volumes6(x, tets).sum() / 6
+    assert np.abs(f).max() <= 1e-12 * theta[0] * h * h, np.abs(f).max()
+    assert abs(E) <= 1e-14 * theta[0] * V, E
+    assert ninv == 0
+
+
+def pin_momentum_balance(lib_path=None):
+    """P2/P3: zero net force and zero net torque for any deformed state."""
+    c = _noisy_small()
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    y = c.y.astype(np.float64)
+    f, E, _ = m.forces(y, c.theta)
+    scale = np.abs(f).sum()
+    assert np.abs(f.sum(0)).max() <= 1e-12 * scale
+    torque = np.cross(y, f).sum(0)
+    assert np.abs(torque).max() <= 1e-12 * (np.linalg.norm(y, axis=1)
+                                             * np.linalg.norm(f, axis=1)).sum()
+
+
+def pin_frame_indifference(lib_path=None):
+    """P3: E(Qy) = E(y) and f(Qy) = Q f(y) for rotations Q."""
+    c = _noisy_small(1001)
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    y = c.y.astype(np.float64)
+    f, E, _ = m.forces(y, c.theta)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        Q = random_rotation(rng)
+        t = rng.normal(size=3)
+        fq, Eq, _ = m.forces(y @ Q.T + t, c.theta)
+        assert abs(Eq - E) <= 1e-12 * abs(E)
+        assert rel_max(fq, f @ Q.T) <= 1e-11
+
+
+def pin_gradient_fd(lib_path=None):
+    """P4: f = -dE/dy, by fourth-order central differences of the energy on
+    64 random coordinates and 8 random directions."""
+    x, tets, y = _tiny_noisy()
+    theta = (1.1, 23.0, 0.35)
+    m = oracle.OracleMesh(x, tets, lib_path)
+    f, E, _ = m.forces(y, theta)
+    rng = np.random.default_rng(11)
+    fmax = np.abs(f).max()
+    h = 1e-4
+    coords = rng.choice(y.size, 64, replace=False)
+    for q in coords:
+        def g(e, q=q):
+            yy = y.copy().ravel()
+            yy[q] += e
+            return m.forces(yy, theta)[1]
+        assert abs(d1_5pt(g, h) + f.ravel()[q]) <= 1e-8 * fmax, q
+    for _ in range(8):
+        v = rng.normal(size=y.shape)
+        v /= np.linalg.norm(v)
+        g = lambda e: m.forces(y + e * v, theta)[1]
+        assert abs(d1_5pt(g, h) + (f * v).sum()) <= 1e-8 * np.abs(f).sum()
+
+
+def pin_table_vs_ad(lib_path=None):
+    """P4/P8: the derivative-table path equals dual-number AD of U."""
+    for seed in (1000, 1002):
+        c = _noisy_small(seed)
+        m = oracle.OracleMesh(c.x, c.tets, lib_path)
+        for theta in (c.theta, (0.7, 30.0, 0.0), (1.9, 6.0, 1.0)):
+            f1, E1, _ = m.forces(c.y, theta)
+            f2, E2 = m.forces_ad(c.y, theta)
+            assert rel_max(f1, f2) <= 1e-12
+            assert abs(E1 - E2) <= 1e-13 * abs(E2)
+
+
+def pin_homogeneous(lib_path=None):
+    """P5: an affine (noise-free) deformation A = Q1 diag(a, b, c) Q2 is
+    reproduced exactly by linear tetrahedra: E = V_mesh U(a, b, c), interior
+    node forces vanish and boundary node forces are -P(A) n_a with
+    P(A) = Q1 P(diag) Q2 (isotropy)."""
+    x, tets = _mesh(1000, 1000)
+    V = signed_volumes6(x, tets).sum() / 6.0
+    n, on_b = boundary_normals(x, tets)
+    m = oracle.OracleMesh(x, tets, lib_path)
+    rng = np.random.default_rng(3)
+    cases = [((1.0, 1.0, 0.3), np.eye(3), np.eye(3), (1.0, 10.0, 0.5)),
+             ((1.2, 0.9, 0.55), random_rotation(rng), random_rotation(rng),
+              (0.8, 31.0, 0.25)),
+             ((0.7, 1.4, 1.1), random_rotation(rng), np.eye(3),
+              (1.7, 9.0, 1.0)),
+             ((1.05, 1.0, 0.98), np.eye(3), random_rotation(rng),
+              (1.0, 40.0, 0.0))]
+    for (a, b, c), Q1, Q2, theta in cases:
+        A = Q1 @ np.diag([a, b, c]) @ Q2
+        f, E, _ = m.forces(x @ A.T, theta)
+        U = U_stretch(a, b, c, theta)
+        assert abs(E - V * U) <= 1e-12 * max(abs(V * U), 1e-300), (E, V * U)
+        P = Q1 @ P_stretch(a, b, c, theta) @ Q2
+        fmax = np.abs(f).max()
+        assert np.abs(f[~on_b]).max() <= 1e-11 * fmax
+        expect = -(n @ P.T)
+        assert np.abs(f[on_b] - expect[on_b]).max() <= 1e-9 * fmax
+    # the uniaxial closed forms
+    for lam in (0.2, 0.5, 0.8, 1.3):
+        theta = (1.0, 10.0, 0.5)
+        _, E, _ = m.forces(x @ np.diag([1, 1, lam]).T, theta)
+        assert abs(E / V - U_uniaxial(lam, theta)) <= 1e-12 * abs(E / V)
+        s = lam ** -0.5
+        _, E, _ = m.forces(x @ np.diag([lam, s, s]).T, theta)
+        assert abs(E / V - U_uniaxial_incompressible(lam, theta)) <= \
+            1e-11 * abs(E / V)
+
+
+def pin_small_strain(lib_path=None):
+    """P6: at F = I + sH the stress tends to linear elasticity with shear
+    modulus mu = mu1 + mu2 and bulk modulus kappa, and uniaxial stress gives
+    Young's modulus and Poisson ratio that satisfy eq. elastic-moduli:mr."""
+    rng = np.random.default_rng(21)
+    ss = (1e-3, 5e-4, 2.5e-4)
+
+    def richardson(g):
+        v = [g(s) for s in ss]
+        r1, r2 = 2 * v[1] - v[0], 2 * v[2] - v[1]
+        return (4 * r2 - r1) / 3
+
+    for theta in ((1.0, 24.67, 0.5), (0.6, 5.0, 0.0), (2.0, 80.0, 1.0)):
+        mu, kappa, w = theta
+        H = rng.normal(size=(3, 3))
+        eps = 0.5 * (H + H.T)
+        dev = eps - np.trace(eps) / 3 * np.eye(3)
+        lin = 2 * mu * dev + kappa * np.trace(eps) * np.eye(3)
+        P0 = richardson(lambda s: oracle.stress_table(np.eye(3) + s * H, theta,
+                                                      lib_path) / s)
+        assert rel_max(P0, lin) <= 1e-7
+        u0 = richardson(lambda s: oracle.energy_density(
+            np.eye(3) + s * H, theta, lib_path) / s ** 2)
+        u_lin = mu * (dev * dev).sum() + kappa / 2 * np.trace(eps) ** 2
+        assert abs(u0 - u_lin) <= 1e-7 * u_lin
+
+        def uniaxial(s):
+            def lateral(e):
+                return oracle.stress_table(np.diag([1 + e, 1 + e, 1 + s]),
+                                           theta, lib_path)[0, 0]
+            e = brentq(lateral, -s, 0.5 * s, xtol=1e-18, rtol=1e-15)
+            Pzz = oracle.stress_table(np.diag([1 + e, 1 + e, 1 + s]), theta,
+                                      lib_path)[2, 2]
+            return np.array([Pzz / s, -e / s])
+
+        E_y, nu = richardson(uniaxial)
+        assert abs(mu - E_y / (2 * (1 + nu))) <= 1e-7 * mu
+        assert abs(kappa - E_y / (3 * (1 - 2 * nu))) <= 1e-7 * kappa
+
+
+def pin_neo_hookean(lib_path=None):
+    """P7: w = 1 is the neo-Hookean energy of eq. strain-energy-density:nh,
+    whose stress is the textbook mu J^-2/3 (F - tr(C)/3 F^-T)
+    + kappa J (J - 1) F^-T."""
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        F = np.eye(3) + 0.3 * rng.normal(size=(3, 3))
+        if np.linalg.det(F) <= 0.2:
+            continue
+        mu, kappa = rng.uniform(0.5, 2.0), rng.uniform(5.0, 50.0)
+        J = np.linalg.det(F)
+        trC = np.trace(F.T @ F)
+        U_nh = mu / 2 * (trC * J ** (-2 / 3) - 3) + kappa / 2 * (J - 1) ** 2
+        assert abs(oracle.energy_density(F, (mu, kappa, 1.0), lib_path)
+                   - U_nh) <= 1e-13 * abs(U_nh)
+        FiT = np.linalg.inv(F).T
+        P_nh = mu * J ** (-2 / 3) * (F - trC / 3 * FiT) + kappa * J * (J - 1) * FiT
+        assert rel_max(oracle.stress_table(F, (mu, kappa, 1.0), lib_path),
+                       P_nh) <= 1e-12
+
+
+def pin_parameter_linearity(lib_path=None):
+    """P9: f and E are linear in (mu1, mu2, kappa)."""
+    c = _noisy_small(1003)
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    fI, EI, _ = m.forces(c.y, (1.0, 0.0, 1.0))
+    fK, EK, _ = m.forces(c.y, (1.0, 0.0, 0.0))
+    fJ, EJ, _ = m.forces(c.y, (0.0, 1.0, 0.5))
+    for mu, kappa, w in ((1.3, 20.0, 0.3), (0.5, 45.0, 0.9)):
+        f, E, _ = m.forces(c.y, (mu, kappa, w))
+        lin = mu * w * fI + mu * (1 - w) * fK + kappa * fJ
+        assert rel_max(f, lin) <= 1e-12
+        El = mu * w * EI + mu * (1 - w) * EK + kappa * EJ
+        assert abs(E - El) <= 1e-12 * abs(E)
+
+
+def load_golden(name="simple_shear_unit_tet.txt"):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *v = line.split()
+            vals[k] = [Fraction(t) for t in v]
+    return vals
+
+
+def pin_worked_example(lib_path=None):
+    """P11: the hand-derived simple-shear example of the golden fixture."""
+    g = load_golden()
+    x = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0], [0, 0, 0]])
+    tets = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    gam = float(g["gamma"][0])
+    F = np.array([[1, gam, 0], [0, 1, 0], [0, 0, 1.0]])
+    m = oracle.OracleMesh(x, tets, lib_path)
+    f, E, _ = m.forces(x @ F.T, (float(g["mu"][0]), 7.0, float(g["w"][0])))
+    assert abs(E - float(g["energy"][0])) <= 1e-15
+    for a in range(4):
+        assert np.abs(f[a] - np.array([float(t) for t in g[f"f{a+1}"]])).max() \
+            <= 1e-15
+
+
+def pin_two_tet_assembly(lib_path=None):
+    """P11: a 2-tet mesh sharing a face is the sum of its tetrahedra, each of
+    which carries zero net force and torque; f = -grad E by differences."""
+    x = np.array([[0, 0, 0], [1.0, 0, 0], [0, 1.0, 0], [0.2, 0.3, 1.0],
+                  [0.3, 0.2, -0.9]])
+    tets = np.array([[1, 2, 3, 0], [2, 1, 4, 0]], dtype=np.int32)
+    rng = np.random.default_rng(2)
+    y = x @ np.array([[0.9, 0.1, 0], [0, 1.1, 0.2], [0, 0, 0.8]]).T \
+        + 0.05 * rng.normal(size=x.shape)
+    theta = (1.2, 15.0, 0.3)
+    f, E, _ = oracle.OracleMesh(x, tets, lib_path).forces(y, theta)
+    fs, Es = np.zeros_like(f), 0.0
+    for t in range(2):
+        ft, Et, _ = oracle.OracleMesh(x, tets[t:t + 1], lib_path).forces(y, theta)
+        assert np.abs(ft.sum(0)).max() <= 1e-14 * np.abs(ft).sum()
+        assert np.abs(np.cross(y, ft).sum(0)).max() <= 1e-13 * np.abs(ft).sum()
+        fs += ft
+        Es += Et
+    assert np.abs(f - fs).max() <= 1e-15 * np.abs(f).max() * 10
+    assert abs(E - Es) <= 1e-15 * abs(E) * 10
+    m = oracle.OracleMesh(x, tets, lib_path)
+    for q in range(y.size):
+        def g(e, q=q):
+            yy = y.copy().ravel()
+            yy[q] += e
+            return m.forces(yy, theta)[1]
+        assert abs(d1_5pt(g, 1e-4) + f.ravel()[q]) <= 1e-9 * np.abs(f).max()
+
+
+def pin_inverted_tet(lib_path=None):
+    """Reading of J <= 0: with the real cube root, an inverted tetrahedron
+    has finite energy, is counted, and its forces are still -grad E."""
+    x = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0], [0, 0, 0]])
+    tets = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    y = x.copy()
+    y[2, 2] = -0.5          # vertex 3 pushed through the opposite face
+    y[0, 0] = 1.1
+    theta = (1.0, 10.0, 0.4)
+    m = oracle.OracleMesh(x, tets, lib_path)
+    f, E, ninv = m.forces(y, theta)
+    assert ninv == 1 and np.isfinite(E) and np.isfinite(f).all()
+    for q in range(12):
+        def g(e, q=q):
+            yy = y.copy().ravel()
+            yy[q] += e
+            return m.forces(yy, theta)[1]
+        assert abs(d1_5pt(g, 1e-4) + f.ravel()[q]) <= 1e-9 * np.abs(f).max()
+
+
+def pin_hvp_fd(lib_path=None):
+    """Backward: the directional derivative of the forces equals the
+    difference quotient of the forces and is symmetric (Hessian of E)."""
+    x, tets, y = _tiny_noisy()
+    theta = (0.9, 18.0, 0.6)
+    m = oracle.OracleMesh(x, tets, lib_path)
+    rng = np.random.default_rng(8)
+    u = rng.normal(size=y.shape)
+    v = rng.normal(size=y.shape)
+    Hu, _ = m.jvp(y, theta, v=u)
+    Hv, _ = m.jvp(y, theta, v=v)
+    h = 1e-5
+    fd = (-m.forces(y + 2 * h * v, theta)[0] + 8 * m.forces(y + h * v, theta)[0]
+          - 8 * m.forces(y - h * v, theta)[0]
+          + m.forces(y - 2 * h * v, theta)[0]).ravel() / (12 * h)
+    assert rel_max(Hv.ravel(), fd) <= 1e-8
+    assert abs((u * Hv).sum() - (v * Hu).sum()) <= 1e-12 * np.abs(u * Hv).sum()
+    nested = m.jvp_nested(y, theta, v)
+    assert rel_max(nested, Hv) <= 1e-12
+
+
+def pin_thetabar(lib_path=None):
+    """Backward: thetabar equals the closed form that follows from linearity
+    in (mu1, mu2, kappa), and the difference quotient of the loss."""
+    c = _noisy_small(1004)
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    mu, kappa, w = c.theta
+    rng = np.random.default_rng(9)
+    fbar = rng.normal(size=c.y.shape)
+    ebar = 0.37
+    ybar, tb = m.backward(c.y, c.theta, fbar, ebar)
+    fI, EI, _ = m.forces(c.y, (1.0, 0.0, 1.0))
+    fK, EK, _ = m.forces(c.y, (1.0, 0.0, 0.0))
+    fJ, EJ, _ = m.forces(c.y, (0.0, 1.0, 0.5))
+    closed = np.array([
+        (fbar * (w * fI + (1 - w) * fK)).sum() + ebar * (w * EI + (1 - w) * EK),
+        (fbar * fJ).sum() + ebar * EJ,
+        mu * ((fbar * (fI - fK)).sum() + ebar * (EI - EK))])
+    assert rel_max(tb, closed) <= 1e-11
+
+    def loss(th):
+        f, E, _ = m.forces(c.y, th)
+        return (fbar * f).sum() + ebar * E
+    for k, h in ((0, 1e-4), (1, 1e-3), (2, 1e-4)):
+        def g(e, k=k):
+            th = list(c.theta)
+            th[k] += e
+            return loss(tuple(th))
+        assert abs(d1_5pt(g, h) - tb[k]) <= 1e-8 * np.abs(tb).max()
+    # ybar = (df/dy) fbar - ebar f
+    Hf, _ = m.jvp(c.y, c.theta, v=fbar)
+    f, _, _ = m.forces(c.y, c.theta)
+    assert rel_max(ybar, Hf - ebar * f) <= 1e-14
+
+
+ALL_PINS = [pin_reference_configuration, pin_momentum_balance,
+            pin_frame_indifference, pin_gradient_fd, pin_table_vs_ad,
+            pin_homogeneous, pin_small_strain, pin_neo_hookean,
+            pin_parameter_linearity, pin_worked_example, pin_two_tet_assembly,
+            pin_inverted_tet, pin_hvp_fd, pin_thetabar]
