@@ -1,0 +1,250 @@
+/*
+ * cellmech: Mooney-Rivlin tetrahedral cell forces on AMD Instinct MI355X
+ * (gfx950).  C ABI of the device library libcellmech.so.
+ *
+ * Method (Mueller et al., "A hyperelastic model for simulating cells in
+ * flow", arXiv 2003.03130):
+ *   For every tetrahedron with reference vertices x^1..x^4 and deformed
+ *   vertices y^1..y^4 (vertex 4 is the local origin):
+ *     J_ik = x_i^k - x_i^4, B = J^-1, V0 = |det J| / 6   (Jacobian paragraph,
+ *                                                         computed once)
+ *     F = D_s B with (D_s)_ik = y_i^k - y_i^4             (eq. displacement-
+ *                                                         derivative: F = I + AB)
+ *     C = F^T F, J = det F, I = tr(C) J^-2/3,
+ *     K = (tr(C)^2 - tr(C^2)) / 2 J^-4/3                  (eqs. invariantJ/I/K)
+ *     U = mu1/2 (I - 3) + mu2/2 (K - 3) + kappa/2 (J - 1)^2
+ *                                                         (eq. strain-energy-
+ *                                                          density:mr)
+ *     mu1 = w mu, mu2 = (1 - w) mu                         (Sec. "Theory")
+ *     f^a = -V0 dU/dy^a                                    (eq. elastic-force-
+ *                                                          vertex-0, evaluated
+ *                                                          with the chain rule
+ *                                                          of eq. -vertex-1)
+ *   The node force is the sum over the tetrahedra sharing the node and the
+ *   cell energy is E = sum V0 U, so f = -grad_y E.
+ *   For J <= 0 (an inverted tetrahedron) J^-1/3 is the reciprocal of the
+ *   sign-preserving real cube root; such tetrahedra are counted, not rejected.
+ *
+ * Conventions shared by every call:
+ *   - A handle holds one or more cells ("batch").  Node and tetrahedron
+ *     arrays of all cells are concatenated; node_off / tet_off are CSR
+ *     offsets with n_cells + 1 entries.
+ *   - Node arrays on the device are structure-of-arrays float32:
+ *     x-components of all nodes, then y-components, then z-components
+ *     (3 * n_nodes floats), in the handle's INTERNAL node order (see
+ *     cm_permutation).  The internal order keeps each cell's nodes
+ *     contiguous and in the cell's own range of the input order.
+ *   - Every compute call is asynchronous on the given stream, allocates no
+ *     memory, and may be captured into a HIP graph.  A handle is not
+ *     thread-safe; calls that overlap on one handle race.
+ *   - Every call returns CM_OK or a negative status; cm_last_error() gives a
+ *     message (thread-local, valid until the next call on that thread).
+ *   - Device pointers may not alias each other.
+ */
+#ifndef CELLMECH_H_
+#define CELLMECH_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cm_batch_s* cm_batch;
+typedef cm_batch cm_mesh; /* a single-cell handle */
+
+enum {
+  CM_OK = 0,
+  CM_EINVAL = -1,      /* bad argument (null pointer, size, index, parameter) */
+  CM_EDEGENERATE = -2, /* a reference tetrahedron with (near) zero volume */
+  CM_EHIP = -3,        /* a HIP runtime call failed */
+  CM_ENOMEM = -4,      /* device or host allocation failed */
+  CM_ESTATE = -5       /* call out of order (e.g. forces before set_params) */
+};
+
+/* Node / tetrahedron ordering used to form tiles. */
+enum { CM_ORDER_INPUT = 0, CM_ORDER_RCM = 1, CM_ORDER_MORTON = 2 };
+
+typedef struct {
+  int32_t order;          /* CM_ORDER_*; default CM_ORDER_MORTON             */
+  int32_t tile_tets;      /* tetrahedra per tile, a multiple of 64 in        */
+                          /* [64, 4096]; 0 = default (1024)                   */
+  double degenerate_tol;  /* reject |det J| <= tol * h^3 with h the cell's   */
+                          /* mean edge length; <= 0 means the default 1e-12  */
+} cm_options;
+
+typedef struct {
+  int64_t n_cells, n_nodes, n_tets;
+  int64_t n_tiles;        /* tiles over all cells                             */
+  int64_t n_shared;       /* nodes touched by more than one tile             */
+  int64_t n_slots;        /* (tile, shared node) pairs                        */
+  int32_t tile_tets;      /* tetrahedra per tile                              */
+  int32_t max_tile_nodes; /* largest number of distinct nodes in one tile     */
+  int64_t device_bytes;   /* device memory owned by the handle                */
+  double volume;          /* sum of V0 over all cells                         */
+  double min_v0;          /* smallest reference volume                        */
+  double max_cond;        /* largest 1-norm condition number of J (ref edges) */
+} cm_info;
+
+/* Message for the last failure on this thread ("" if none). */
+const char* cm_last_error(void);
+
+/* Library ABI version (this header: 1). */
+int cm_version(void);
+
+/* Fills *opt with the defaults. */
+void cm_options_default(cm_options* opt);
+
+/*
+ * cm_batch_create: upload the reference meshes of n_cells cells.
+ *   node_off, tet_off : host int64[n_cells + 1], CSR offsets (first = 0).
+ *   ref_xyz           : host float64[n_nodes * 3], xyz per node (array of
+ *                       structures), input node order.
+ *   tets              : host int32[n_tets * 4], CELL-LOCAL vertex indices.
+ *   opt               : nullable (defaults).
+ * Precomputes in FP64 on the host, once (Jacobian paragraph of the paper):
+ * B = J^-1 and V0 per tetrahedron, stored as float32; orders and tiles the
+ * mesh; copies everything to the device on `stream` and waits for it.
+ * Errors: CM_EINVAL (sizes, offsets, an index out of range, repeated vertex
+ * in a tetrahedron, a cell without tetrahedra), CM_EDEGENERATE (the message
+ * names the cell and tetrahedron), CM_ENOMEM, CM_EHIP.
+ * The caller keeps ownership of all host arrays; *out owns its device memory.
+ */
+int cm_batch_create(int32_t n_cells, const int64_t* node_off,
+                    const int64_t* tet_off, const double* ref_xyz,
+                    const int32_t* tets, const cm_options* opt,
+                    hipStream_t stream, cm_batch* out);
+
+/* Single-cell form of cm_batch_create. */
+int cm_mesh_create(int64_t n_nodes, int64_t n_tets, const double* ref_xyz,
+                   const int32_t* tets, const cm_options* opt,
+                   hipStream_t stream, cm_mesh* out);
+
+/* Frees the handle's device memory and graphs (synchronises the device). */
+int cm_destroy(cm_batch h);
+
+int cm_get_info(cm_batch h, cm_info* out);
+
+/* new_to_old: host int64[n_nodes]; entry g is the input-order index of
+ * internal node g.  Both orders keep every cell inside its own node range. */
+int cm_permutation(cm_batch h, int64_t* new_to_old);
+
+/*
+ * cm_set_params: Mooney-Rivlin parameters per cell (mu, kappa, w), with
+ * mu1 = w mu, mu2 = (1 - w) mu (Sec. "Theory").  Arrays hold n_cells
+ * float64 values each; `on_device` = 0 for host arrays (validated, copied;
+ * the call waits for the copy), 1 for device arrays (device-to-device copy
+ * enqueued on `stream`, graph-safe; values are not validated).
+ * Host values must be finite with mu >= 0, kappa >= 0, 0 <= w <= 1, else
+ * CM_EINVAL.
+ */
+int cm_set_params(cm_batch h, const double* mu, const double* kappa,
+                  const double* w, int on_device, hipStream_t stream);
+
+/*
+ * cm_forces: forces and energies for all cells (eqs. elastic-force-vertex-0
+ * and -1, summed over tetrahedra).
+ *   y          : device float32[3 * n_nodes] SoA deformed positions.
+ *   f          : device float32[3 * n_nodes] SoA forces, overwritten.
+ *   energy     : device float64[n_cells] (E = sum V0 U per cell), nullable.
+ *   n_inverted : device int32[n_cells], tetrahedra with J <= 0, nullable.
+ * Deterministic: the same input gives bitwise the same output.
+ * CM_ESTATE before the first cm_set_params.
+ */
+int cm_forces(cm_batch h, const float* y, float* f, double* energy,
+              int32_t* n_inverted, hipStream_t stream);
+
+/*
+ * cm_forces_backward: reverse-mode cotangents of a loss L(f, E).
+ *   fbar     : device float32[3 * n_nodes] = dL/df, nullable (zero).
+ *   ebar     : device float64[n_cells] = dL/dE per cell, nullable (zero).
+ *   ybar     : device float32[3 * n_nodes] out:
+ *              ybar = (df/dy)^T fbar + ebar dE/dy = -H fbar - ebar f with
+ *              H the Hessian of E (a Hessian-vector product per cell).
+ *   thetabar : device float64[3 * n_cells] out, per cell
+ *              (dL/dmu, dL/dkappa, dL/dw); nullable.
+ * The paper gives first derivatives only; this is their exact derivative.
+ */
+int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
+                       const double* ebar, float* ybar, double* thetabar,
+                       hipStream_t stream);
+
+/*
+ * Same results as cm_forces / cm_forces_backward, but one kernel launch per
+ * cell (the plain single-cell path).  Used as the comparison baseline of the
+ * batched persistent launch.
+ */
+int cm_forces_percell(cm_batch h, const float* y, float* f, double* energy,
+                      int32_t* n_inverted, hipStream_t stream);
+int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
+                               const double* ebar, float* ybar,
+                               double* thetabar, hipStream_t stream);
+
+/*
+ * Launch configuration of the batched kernels: waves (tiles) per workgroup
+ * (1, 2, 4, 8) and persistent workgroups per compute unit (0 = one workgroup
+ * per group of tiles, not persistent).  cm_autotune times forward + backward
+ * for every candidate that fits in LDS on `stream`, with the handle's data,
+ * the caller's positions `y` (device, SoA, also used as the cotangent) and
+ * the parameters already set, and keeps the fastest.  `cache_path`
+ * (nullable) is a JSON file keyed by device name and mesh statistics; a hit
+ * skips the measurement, a miss appends the result.  Tuning allocates and
+ * frees scratch outputs and synchronises the stream: it is not graph-safe.
+ */
+int cm_set_launch(cm_batch h, int32_t waves_per_block, int32_t blocks_per_cu);
+int cm_get_launch(cm_batch h, int32_t* waves_per_block, int32_t* blocks_per_cu);
+int cm_autotune(cm_batch h, const float* y, const char* cache_path,
+                hipStream_t stream);
+
+/*
+ * HIP graph of one batched evaluation with fixed buffers.
+ *   mode 0: forward (cm_forces);
+ *   mode 1: forward then backward (cm_forces, cm_forces_backward);
+ *   mode 2: the per-cell launches of mode 0 (single-cell baseline);
+ *   mode 3: the per-cell launches of mode 1.
+ * Pointers are captured as given and must stay valid while the graph is
+ * used.  Re-capturing replaces the previous graph.  cm_graph_launch
+ * replays it on `stream` (CM_ESTATE if nothing was captured).
+ */
+int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
+                     double* energy, int32_t* n_inverted, const float* fbar,
+                     const double* ebar, float* ybar, double* thetabar,
+                     hipStream_t stream);
+int cm_graph_launch(cm_batch h, hipStream_t stream);
+
+/*
+ * Host-only view of the prepared layout (no device work), for validation and
+ * debugging of the preparation step.  cm_layout_create runs exactly the
+ * preparation of cm_batch_create (same arguments, same errors).
+ * cm_layout_sizes fills sizes[8] = {n_tiles, n_chunks, n_slots, n_shared,
+ * n_nodes, n_cells, max_tile_nodes, tile_tets}.  cm_layout_export copies the
+ * tables into caller-owned host arrays (each nullable):
+ *   tiles        int32[n_tiles * 8]   (chunk_begin, n_tets, own_begin, n_own,
+ *                                      shr_begin, n_shr, cell, 0)
+ *   chunks       uint8[n_chunks * 3072] (64 tetrahedra each: uint32 idx[64][2]
+ *                                      holding 4 x uint16 local indices,
+ *                                      float B[9][64], float V0[64])
+ *   slot_node    int32[n_slots]       shared_node   int32[n_shared]
+ *   shared_slot_ptr int32[n_shared+1] shared_slots  int32[n_slots]
+ *   cell_tile_off   int32[n_cells+1]  cell_shared_off int32[n_cells+1]
+ *   new_to_old      int64[n_nodes]
+ */
+typedef struct cm_layout_s* cm_layout;
+int cm_layout_create(int32_t n_cells, const int64_t* node_off,
+                     const int64_t* tet_off, const double* ref_xyz,
+                     const int32_t* tets, const cm_options* opt,
+                     cm_layout* out);
+int cm_layout_sizes(cm_layout l, int64_t* sizes);
+int cm_layout_export(cm_layout l, int32_t* tiles, void* chunks,
+                     int32_t* slot_node, int32_t* shared_node,
+                     int32_t* shared_slot_ptr, int32_t* shared_slots,
+                     int32_t* cell_tile_off, int32_t* cell_shared_off,
+                     int64_t* new_to_old);
+int cm_layout_destroy(cm_layout l);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CELLMECH_H_ */

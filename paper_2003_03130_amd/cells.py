@@ -1,0 +1,241 @@
+"""Python handle over the C ABI: device memory and streams come from PyTorch,
+every computation runs in libcellmech (HIP, gfx950)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native as nat
+
+
+def _ptr(a) -> ctypes.c_void_p:
+    """Raw pointer of a numpy array or a torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _options(order, tile_tets, degenerate_tol):
+    o = nat.Options()
+    nat.lib().cm_options_default(ctypes.byref(o))
+    if order is not None:
+        o.order = int(order)
+    if tile_tets is not None:
+        o.tile_tets = int(tile_tets)
+    if degenerate_tol is not None:
+        o.degenerate_tol = float(degenerate_tol)
+    return o
+
+
+def _host_inputs(node_off, tet_off, x, tets):
+    node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+    tet_off = np.ascontiguousarray(tet_off, dtype=np.int64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+    return node_off, tet_off, x, tets
+
+
+class CellBatch:
+    """Reference meshes of one or more cells resident on the current GPU.
+
+    ``node_off``/``tet_off`` are CSR offsets, ``x`` the (N, 3) float64
+    reference positions and ``tets`` the (M, 4) cell-local vertex indices.
+    Device node arrays are float32 structure-of-arrays (3 * N) in the internal
+    node order; ``to_device``/``to_host`` convert from/to (N, 3) input order.
+    """
+
+    def __init__(self, node_off, tet_off, x, tets, order=None, tile_tets=None,
+                 degenerate_tol=None, stream=None):
+        import torch
+        node_off, tet_off, x, tets = _host_inputs(node_off, tet_off, x, tets)
+        self.n_cells = len(node_off) - 1
+        opt = _options(order, tile_tets, degenerate_tol)
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().cm_batch_create(
+            self.n_cells, _ptr(node_off), _ptr(tet_off), _ptr(x), _ptr(tets),
+            ctypes.byref(opt), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        info = nat.Info()
+        nat.check(nat.lib().cm_get_info(self._h, ctypes.byref(info)))
+        self.info = info.as_dict()
+        self.n_nodes = int(info.n_nodes)
+        self.n_tets = int(info.n_tets)
+        self.node_off = node_off
+        self.tet_off = tet_off
+        self.new_to_old = np.empty(self.n_nodes, dtype=np.int64)
+        nat.check(nat.lib().cm_permutation(self._h, _ptr(self.new_to_old)))
+        self.old_to_new = np.empty_like(self.new_to_old)
+        self.old_to_new[self.new_to_old] = np.arange(self.n_nodes)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_cells(cls, cells, **kw):
+        node_off = np.concatenate([[0], np.cumsum([len(c.x) for c in cells])])
+        tet_off = np.concatenate([[0], np.cumsum([len(c.tets) for c in cells])])
+        return cls(node_off, tet_off, np.concatenate([c.x for c in cells]),
+                   np.concatenate([c.tets for c in cells]), **kw)
+
+    @classmethod
+    def single(cls, x, tets, **kw):
+        return cls([0, len(x)], [0, len(tets)], x, tets, **kw)
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            nat.lib().cm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ layout
+    def to_device(self, a_input_order):
+        """(N, 3) array in input order -> float32 SoA (3N,) device tensor."""
+        import torch
+        a = np.asarray(a_input_order, dtype=np.float32).reshape(-1, 3)
+        soa = np.ascontiguousarray(a[self.new_to_old].T).reshape(-1)
+        return torch.from_numpy(soa).to(self.device)
+
+    def to_host(self, t):
+        """float32 SoA (3N,) device tensor -> (N, 3) numpy in input order."""
+        soa = t.detach().float().cpu().numpy().reshape(3, -1)
+        out = np.empty((self.n_nodes, 3), dtype=np.float32)
+        out[self.new_to_old] = soa.T
+        return out
+
+    def empty_nodes(self):
+        import torch
+        return torch.empty(3 * self.n_nodes, dtype=torch.float32,
+                           device=self.device)
+
+    # ------------------------------------------------------------ params
+    def set_params(self, mu, kappa, w, stream=None):
+        """Host sequences (validated) or float64 device tensors (n_cells)."""
+        import torch
+        if isinstance(mu, torch.Tensor):
+            tens = [t.to(self.device, torch.float64).contiguous()
+                    for t in (mu, kappa, w)]
+            self._param_keep = tens
+            nat.check(nat.lib().cm_set_params(
+                self._h, _ptr(tens[0]), _ptr(tens[1]), _ptr(tens[2]), 1,
+                _stream(stream)))
+        else:
+            arr = [np.ascontiguousarray(np.broadcast_to(
+                np.asarray(v, dtype=np.float64), (self.n_cells,)))
+                for v in (mu, kappa, w)]
+            nat.check(nat.lib().cm_set_params(
+                self._h, _ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), 0,
+                _stream(stream)))
+
+    # ------------------------------------------------------------ compute
+    def forces(self, y, f=None, energy=None, n_inverted=None, stream=None,
+               percell=False):
+        import torch
+        if f is None:
+            f = self.empty_nodes()
+        if energy is None:
+            energy = torch.empty(self.n_cells, dtype=torch.float64,
+                                 device=self.device)
+        fn = nat.lib().cm_forces_percell if percell else nat.lib().cm_forces
+        nat.check(fn(self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(n_inverted),
+                     _stream(stream)))
+        return f, energy
+
+    def backward(self, y, fbar=None, ebar=None, ybar=None, thetabar=None,
+                 stream=None, percell=False):
+        import torch
+        if ybar is None:
+            ybar = self.empty_nodes()
+        if thetabar is None:
+            thetabar = torch.empty(3 * self.n_cells, dtype=torch.float64,
+                                   device=self.device)
+        fn = (nat.lib().cm_forces_backward_percell if percell
+              else nat.lib().cm_forces_backward)
+        nat.check(fn(self._h, _ptr(y), _ptr(fbar), _ptr(ebar), _ptr(ybar),
+                     _ptr(thetabar), _stream(stream)))
+        return ybar, thetabar
+
+    # ------------------------------------------------------------ launch
+    def set_launch(self, waves_per_block, blocks_per_cu):
+        nat.check(nat.lib().cm_set_launch(self._h, waves_per_block,
+                                          blocks_per_cu))
+
+    def get_launch(self):
+        w, b = ctypes.c_int32(), ctypes.c_int32()
+        nat.check(nat.lib().cm_get_launch(self._h, ctypes.byref(w),
+                                          ctypes.byref(b)))
+        return w.value, b.value
+
+    def autotune(self, y, cache_path=None, stream=None):
+        nat.check(nat.lib().cm_autotune(
+            self._h, _ptr(y), cache_path.encode() if cache_path else None,
+            _stream(stream)))
+        return self.get_launch()
+
+    def graph_capture(self, mode, y, f, energy=None, n_inverted=None,
+                      fbar=None, ebar=None, ybar=None, thetabar=None,
+                      stream=None):
+        nat.check(nat.lib().cm_graph_capture(
+            self._h, int(mode), _ptr(y), _ptr(f), _ptr(energy),
+            _ptr(n_inverted), _ptr(fbar), _ptr(ebar), _ptr(ybar),
+            _ptr(thetabar), _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        nat.check(nat.lib().cm_graph_launch(self._h, _stream(stream)))
+
+
+class HostLayout:
+    """The prepared tables of cm_layout_* (host only, no GPU needed)."""
+
+    def __init__(self, node_off, tet_off, x, tets, order=None, tile_tets=None,
+                 degenerate_tol=None):
+        node_off, tet_off, x, tets = _host_inputs(node_off, tet_off, x, tets)
+        opt = _options(order, tile_tets, degenerate_tol)
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().cm_layout_create(
+            len(node_off) - 1, _ptr(node_off), _ptr(tet_off), _ptr(x),
+            _ptr(tets), ctypes.byref(opt), ctypes.byref(h)))
+        try:
+            sz = np.zeros(8, dtype=np.int64)
+            nat.check(nat.lib().cm_layout_sizes(h, sz.ctypes.data_as(nat._p64)))
+            (self.n_tiles, self.n_chunks, self.n_slots, self.n_shared,
+             self.n_nodes, self.n_cells, self.max_tile_nodes,
+             self.tile_tets) = (int(v) for v in sz)
+            self.tiles = np.zeros((self.n_tiles, 8), dtype=np.int32)
+            raw = np.zeros(self.n_chunks * 3072, dtype=np.uint8)
+            self.slot_node = np.zeros(self.n_slots, dtype=np.int32)
+            self.shared_node = np.zeros(self.n_shared, dtype=np.int32)
+            self.shared_slot_ptr = np.zeros(self.n_shared + 1, dtype=np.int32)
+            self.shared_slots = np.zeros(self.n_slots, dtype=np.int32)
+            self.cell_tile_off = np.zeros(self.n_cells + 1, dtype=np.int32)
+            self.cell_shared_off = np.zeros(self.n_cells + 1, dtype=np.int32)
+            self.new_to_old = np.zeros(self.n_nodes, dtype=np.int64)
+            nat.check(nat.lib().cm_layout_export(
+                h, _ptr(self.tiles), _ptr(raw), _ptr(self.slot_node),
+                _ptr(self.shared_node), _ptr(self.shared_slot_ptr),
+                _ptr(self.shared_slots), _ptr(self.cell_tile_off),
+                _ptr(self.cell_shared_off), _ptr(self.new_to_old)))
+        finally:
+            nat.lib().cm_layout_destroy(h)
+        ch = raw.reshape(self.n_chunks, 3072)
+        idx = ch[:, :512].view(np.uint32).reshape(self.n_chunks, 64, 2)
+        self.local_idx = np.stack([idx[..., 0] & 0xFFFF, idx[..., 0] >> 16,
+                                   idx[..., 1] & 0xFFFF, idx[..., 1] >> 16],
+                                  axis=-1).astype(np.int64)
+        self.B = ch[:, 512:512 + 2304].view(np.float32).reshape(
+            self.n_chunks, 9, 64).transpose(0, 2, 1).reshape(
+            self.n_chunks, 64, 3, 3)
+        self.V0 = ch[:, 2816:].view(np.float32).reshape(self.n_chunks, 64)

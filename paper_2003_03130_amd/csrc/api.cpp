@@ -1,0 +1,600 @@
+// C ABI of libcellmech (declared in include/cellmech.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/cellmech.h"
+#include "kernels.h"
+#include "prep.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define CM_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(CM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct cm_batch_s {
+  int device = 0;
+  int n_cu = 256;
+  int64_t n_cells = 0, n_nodes = 0, n_tets = 0, n_slots = 0, n_shared = 0;
+  int64_t n_tiles = 0;
+  int32_t tile_tets = 0, max_tile_nodes = 0;
+  double volume = 0, min_v0 = 0, max_cond = 0;
+  std::vector<int32_t> cell_tile_off, cell_shared_off;
+  std::vector<int64_t> new_to_old;
+  std::vector<void*> allocs;
+  int64_t device_bytes = 0;
+  cm::DeviceTables T;
+  cm::LaunchCfg cfg;
+  bool params_set = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
+  ~cm_batch_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  template <class T>
+  int alloc(T** p, size_t count) {
+    size_t bytes = std::max<size_t>(sizeof(T) * count, 256);
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? CM_ENOMEM : CM_EHIP,
+                  std::string("hipMalloc: ") + hipGetErrorString(e));
+    allocs.push_back(*p);
+    device_bytes += (int64_t)bytes;
+    return CM_OK;
+  }
+
+  template <class T>
+  int upload(T** p, const std::vector<T>& v, hipStream_t st) {
+    int rc = alloc(p, v.size());
+    if (rc) return rc;
+    if (!v.empty())
+      CM_HIP(hipMemcpyAsync(*p, v.data(), sizeof(T) * v.size(),
+                            hipMemcpyHostToDevice, st));
+    return CM_OK;
+  }
+};
+
+namespace {
+
+int check_handle(cm_batch h) {
+  if (!h) return fail(CM_EINVAL, "null handle");
+  return CM_OK;
+}
+
+cm::Range full_range(const cm_batch_s* h) {
+  return cm::Range{0, (int32_t)h->n_tiles, 0, (int32_t)h->n_shared, 0,
+                   (int32_t)h->n_cells};
+}
+
+cm::Range cell_range(const cm_batch_s* h, int32_t c) {
+  return cm::Range{h->cell_tile_off[c], h->cell_tile_off[c + 1],
+                   h->cell_shared_off[c], h->cell_shared_off[c + 1], c, c + 1};
+}
+
+int select_device(cm_batch h) {
+  int cur = 0;
+  CM_HIP(hipGetDevice(&cur));
+  if (cur != h->device) CM_HIP(hipSetDevice(h->device));
+  return CM_OK;
+}
+
+bool lds_fits(const cm_batch_s* h, int waves, bool backward) {
+  size_t per = backward ? cm::backward_lds_per_wave(h->T.nloc)
+                        : cm::forward_lds_per_wave(h->T.nloc);
+  return per * (size_t)waves <= 65536;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cm_last_error(void) { return g_err.c_str(); }
+
+int cm_version(void) { return 1; }
+
+void cm_options_default(cm_options* opt) {
+  if (!opt) return;
+  opt->order = CM_ORDER_MORTON;
+  opt->tile_tets = 1024;
+  opt->degenerate_tol = 1e-12;
+}
+
+static cm::PrepOptions prep_options(const cm_options* opt) {
+  cm::PrepOptions po;
+  if (opt) {
+    po.order = opt->order;
+    po.tile_tets = opt->tile_tets ? opt->tile_tets : 1024;
+    po.degenerate_tol = opt->degenerate_tol > 0 ? opt->degenerate_tol : 1e-12;
+  }
+  return po;
+}
+
+int cm_batch_create(int32_t n_cells, const int64_t* node_off,
+                    const int64_t* tet_off, const double* ref_xyz,
+                    const int32_t* tets, const cm_options* opt,
+                    hipStream_t stream, cm_batch* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  const cm::PrepOptions po = prep_options(opt);
+  cm::Prepared P;
+  std::string err;
+  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &P, &err);
+  if (rc != CM_OK) return fail(rc, err);
+
+  cm_batch_s* h = new (std::nothrow) cm_batch_s();
+  if (!h) return fail(CM_ENOMEM, "host allocation failed");
+  auto bail = [&](int st) { delete h; return st; };
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) return bail(fail(CM_EHIP, hipGetErrorString(e)));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, h->device);
+  if (e != hipSuccess) return bail(fail(CM_EHIP, hipGetErrorString(e)));
+  h->n_cu = prop.multiProcessorCount;
+
+  h->n_cells = P.n_cells;
+  h->n_nodes = P.n_nodes;
+  h->n_tets = P.n_tets;
+  h->n_slots = (int64_t)P.slot_node.size();
+  h->n_shared = (int64_t)P.shared_node.size();
+  h->n_tiles = (int64_t)P.tiles.size();
+  h->tile_tets = po.tile_tets;
+  h->max_tile_nodes = P.max_tile_nodes;
+  h->volume = P.volume;
+  h->min_v0 = P.min_v0;
+  h->max_cond = P.max_cond;
+  h->cell_tile_off = P.cell_tile_off;
+  h->cell_shared_off = P.cell_shared_off;
+  h->new_to_old = std::move(P.new_to_old);
+
+  cm::DeviceTables& T = h->T;
+  {
+    cm::TileDesc* tiles;
+    cm::TetChunk* chunks;
+    int32_t *slot_node, *shared_node, *ssp, *ss, *cto;
+    if ((rc = h->upload(&tiles, P.tiles, stream)) ||
+        (rc = h->upload(&chunks, P.chunks, stream)) ||
+        (rc = h->upload(&slot_node, P.slot_node, stream)) ||
+        (rc = h->upload(&shared_node, P.shared_node, stream)) ||
+        (rc = h->upload(&ssp, P.shared_slot_ptr, stream)) ||
+        (rc = h->upload(&ss, P.shared_slots, stream)) ||
+        (rc = h->upload(&cto, P.cell_tile_off, stream)))
+      return bail(rc);
+    T.tiles = tiles;
+    T.chunks = chunks;
+    T.slot_node = slot_node;
+    T.shared_node = shared_node;
+    T.shared_slot_ptr = ssp;
+    T.shared_slots = ss;
+    T.cell_tile_off = cto;
+    double* params;
+    float* part;
+    double* tile_acc;
+    int32_t* tile_ninv;
+    if ((rc = h->alloc(&params, 3 * (size_t)h->n_cells)) ||
+        (rc = h->alloc(&part, 3 * (size_t)h->n_slots)) ||
+        (rc = h->alloc(&tile_acc, 3 * (size_t)h->n_tiles)) ||
+        (rc = h->alloc(&tile_ninv, (size_t)h->n_tiles)))
+      return bail(rc);
+    T.params = params;
+    T.part = part;
+    T.tile_acc = tile_acc;
+    T.tile_ninv = tile_ninv;
+  }
+  T.n_nodes = h->n_nodes;
+  T.n_slots = h->n_slots;
+  T.n_tiles = h->n_tiles;
+  T.n_cells = (int32_t)h->n_cells;
+  T.nloc = (h->max_tile_nodes + 3) & ~3;
+  if (T.nloc == 0) T.nloc = 4;
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return bail(fail(CM_EHIP, hipGetErrorString(e)));
+  h->cfg.waves = 1;
+  h->cfg.blocks = 0;
+  *out = h;
+  return CM_OK;
+}
+
+int cm_mesh_create(int64_t n_nodes, int64_t n_tets, const double* ref_xyz,
+                   const int32_t* tets, const cm_options* opt,
+                   hipStream_t stream, cm_mesh* out) {
+  int64_t no[2] = {0, n_nodes}, to[2] = {0, n_tets};
+  if (n_nodes < 0 || n_tets < 0) return fail(CM_EINVAL, "negative size");
+  return cm_batch_create(1, no, to, ref_xyz, tets, opt, stream, out);
+}
+
+int cm_destroy(cm_batch h) {
+  if (!h) return CM_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  delete h;
+  return CM_OK;
+}
+
+int cm_get_info(cm_batch h, cm_info* o) {
+  if (int rc = check_handle(h)) return rc;
+  if (!o) return fail(CM_EINVAL, "out is null");
+  o->n_cells = h->n_cells;
+  o->n_nodes = h->n_nodes;
+  o->n_tets = h->n_tets;
+  o->n_tiles = h->n_tiles;
+  o->n_shared = h->n_shared;
+  o->n_slots = h->n_slots;
+  o->tile_tets = h->tile_tets;
+  o->max_tile_nodes = h->max_tile_nodes;
+  o->device_bytes = h->device_bytes;
+  o->volume = h->volume;
+  o->min_v0 = h->min_v0;
+  o->max_cond = h->max_cond;
+  return CM_OK;
+}
+
+int cm_permutation(cm_batch h, int64_t* new_to_old) {
+  if (int rc = check_handle(h)) return rc;
+  if (!new_to_old) return fail(CM_EINVAL, "out is null");
+  std::memcpy(new_to_old, h->new_to_old.data(), sizeof(int64_t) * h->n_nodes);
+  return CM_OK;
+}
+
+int cm_set_params(cm_batch h, const double* mu, const double* kappa,
+                  const double* w, int on_device, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!mu || !kappa || !w) return fail(CM_EINVAL, "null parameter array");
+  if (int rc = select_device(h)) return rc;
+  const size_t n = (size_t)h->n_cells;
+  double* dst = const_cast<double*>(h->T.params);
+  if (on_device) {
+    CM_HIP(hipMemcpyAsync(dst, mu, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    CM_HIP(hipMemcpyAsync(dst + n, kappa, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    CM_HIP(hipMemcpyAsync(dst + 2 * n, w, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  } else {
+    std::vector<double> buf(3 * n);
+    for (size_t c = 0; c < n; ++c) {
+      if (!std::isfinite(mu[c]) || !std::isfinite(kappa[c]) || !std::isfinite(w[c]) ||
+          mu[c] < 0 || kappa[c] < 0 || w[c] < 0 || w[c] > 1)
+        return fail(CM_EINVAL, "cell " + std::to_string(c) +
+                                   ": parameters must be finite with mu >= 0, "
+                                   "kappa >= 0, 0 <= w <= 1");
+      buf[c] = mu[c];
+      buf[n + c] = kappa[c];
+      buf[2 * n + c] = w[c];
+    }
+    CM_HIP(hipMemcpyAsync(dst, buf.data(), 3 * n * sizeof(double),
+                          hipMemcpyHostToDevice, stream));
+    // the staging buffer is pageable and local: wait for the copy
+    CM_HIP(hipStreamSynchronize(stream));
+  }
+  h->params_set = true;
+  return CM_OK;
+}
+
+static int forces_impl(cm_batch h, const float* y, float* f, double* energy,
+                       int32_t* ninv, hipStream_t st, bool percell) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !f) return fail(CM_EINVAL, "y and f must be device pointers");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (!lds_fits(h, h->cfg.waves, false))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  if (!percell) {
+    CM_HIP(cm::launch_forward(h->T, full_range(h), h->cfg, y, f, energy, ninv, st));
+  } else {
+    cm::LaunchCfg one{h->cfg.waves, 0};
+    for (int32_t c = 0; c < (int32_t)h->n_cells; ++c)
+      CM_HIP(cm::launch_forward(h->T, cell_range(h, c), one, y, f, energy, ninv, st));
+  }
+  return CM_OK;
+}
+
+static int backward_impl(cm_batch h, const float* y, const float* fbar,
+                         const double* ebar, float* ybar, double* thetabar,
+                         hipStream_t st, bool percell) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !ybar) return fail(CM_EINVAL, "y and ybar must be device pointers");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (!lds_fits(h, h->cfg.waves, true))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  if (!percell) {
+    CM_HIP(cm::launch_backward(h->T, full_range(h), h->cfg, y, fbar, ebar, ybar,
+                               thetabar, st));
+  } else {
+    cm::LaunchCfg one{h->cfg.waves, 0};
+    for (int32_t c = 0; c < (int32_t)h->n_cells; ++c)
+      CM_HIP(cm::launch_backward(h->T, cell_range(h, c), one, y, fbar, ebar,
+                                 ybar, thetabar, st));
+  }
+  return CM_OK;
+}
+
+int cm_forces(cm_batch h, const float* y, float* f, double* energy,
+              int32_t* n_inverted, hipStream_t stream) {
+  return forces_impl(h, y, f, energy, n_inverted, stream, false);
+}
+
+int cm_forces_percell(cm_batch h, const float* y, float* f, double* energy,
+                      int32_t* n_inverted, hipStream_t stream) {
+  return forces_impl(h, y, f, energy, n_inverted, stream, true);
+}
+
+int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
+                       const double* ebar, float* ybar, double* thetabar,
+                       hipStream_t stream) {
+  return backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, false);
+}
+
+int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
+                               const double* ebar, float* ybar,
+                               double* thetabar, hipStream_t stream) {
+  return backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, true);
+}
+
+int cm_set_launch(cm_batch h, int32_t waves, int32_t blocks_per_cu) {
+  if (int rc = check_handle(h)) return rc;
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(CM_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64)
+    return fail(CM_EINVAL, "blocks_per_cu must be in [0, 64]");
+  if (!lds_fits(h, waves, true) || !lds_fits(h, waves, false))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  h->cfg.waves = waves;
+  h->cfg.blocks = blocks_per_cu * h->n_cu;
+  return CM_OK;
+}
+
+int cm_get_launch(cm_batch h, int32_t* waves, int32_t* blocks_per_cu) {
+  if (int rc = check_handle(h)) return rc;
+  if (waves) *waves = h->cfg.waves;
+  if (blocks_per_cu) *blocks_per_cu = h->n_cu ? h->cfg.blocks / h->n_cu : 0;
+  return CM_OK;
+}
+
+// Autotuner cache: one JSON object, one entry per line,
+//   "<key>": {"waves": W, "blocks_per_cu": B, "ms": T},
+static bool cache_lookup(const char* path, const std::string& key, int* w, int* b) {
+  std::ifstream in(path);
+  if (!in) return false;
+  std::string line, pre = "\"" + key + "\":";
+  while (std::getline(in, line)) {
+    size_t p = line.find(pre);
+    if (p == std::string::npos) continue;
+    return std::sscanf(line.c_str() + p + pre.size(),
+                       " {\"waves\": %d, \"blocks_per_cu\": %d", w, b) == 2;
+  }
+  return false;
+}
+
+static void cache_store(const char* path, const std::string& key, int w, int b,
+                        double ms) {
+  std::vector<std::string> entries;
+  {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+      size_t p = line.find("\": {\"waves\"");
+      if (p == std::string::npos) continue;
+      if (line.find("\"" + key + "\":") != std::string::npos) continue;
+      while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+      entries.push_back(line);
+    }
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "  \"%s\": {\"waves\": %d, \"blocks_per_cu\": %d, \"ms\": %.6f}",
+                key.c_str(), w, b, ms);
+  entries.push_back(buf);
+  std::ofstream out(path, std::ios::trunc);
+  out << "{\n";
+  for (size_t i = 0; i < entries.size(); ++i)
+    out << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+  out << "}\n";
+}
+
+int cm_autotune(cm_batch h, const float* y, const char* cache_path,
+                hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y) return fail(CM_EINVAL, "y must be a device pointer");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (int rc = select_device(h)) return rc;
+  hipDeviceProp_t prop;
+  CM_HIP(hipGetDeviceProperties(&prop, h->device));
+  std::string key = std::string(prop.gcnArchName) + "|cu" + std::to_string(h->n_cu) +
+                    "|tets" + std::to_string(h->n_tets) + "|tiles" +
+                    std::to_string(h->n_tiles) + "|tile" + std::to_string(h->tile_tets) +
+                    "|nloc" + std::to_string(h->T.nloc);
+  for (char& ch : key)
+    if (ch == '"' || ch == '\\') ch = '_';
+  int w = 0, b = 0;
+  if (cache_path && cache_lookup(cache_path, key, &w, &b))
+    return cm_set_launch(h, w, b);
+
+  const size_t n3 = 3 * (size_t)h->n_nodes;
+  float *f = nullptr, *ybar = nullptr;
+  double *energy = nullptr, *tb = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = CM_OK;
+  double best_ms = INFINITY;
+  int best_w = h->cfg.waves, best_b = h->n_cu ? h->cfg.blocks / h->n_cu : 0;
+  const cm::LaunchCfg saved = h->cfg;
+  auto cleanup = [&]() {
+    if (f) (void)hipFree(f);
+    if (ybar) (void)hipFree(ybar);
+    if (energy) (void)hipFree(energy);
+    if (tb) (void)hipFree(tb);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc((void**)&f, n3 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&ybar, n3 * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&energy, h->n_cells * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&tb, 3 * h->n_cells * sizeof(double)) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(CM_ENOMEM, "autotune scratch allocation failed");
+  }
+  const int waves[4] = {1, 2, 4, 8};
+  const int bpcu[6] = {0, 1, 2, 4, 8, 16};
+  for (int wi = 0; wi < 4 && rc == CM_OK; ++wi) {
+    if (!lds_fits(h, waves[wi], true) || !lds_fits(h, waves[wi], false)) continue;
+    for (int bi = 0; bi < 6 && rc == CM_OK; ++bi) {
+      h->cfg.waves = waves[wi];
+      h->cfg.blocks = bpcu[bi] * h->n_cu;
+      auto run = [&]() {
+        int r = forces_impl(h, y, f, energy, nullptr, stream, false);
+        if (r == CM_OK) r = backward_impl(h, y, y, energy, ybar, tb, stream, false);
+        return r;
+      };
+      for (int k = 0; k < 2 && rc == CM_OK; ++k) rc = run();
+      if (rc != CM_OK) break;
+      const int reps = 5;
+      if (hipEventRecord(e0, stream) != hipSuccess) { rc = fail(CM_EHIP, "event"); break; }
+      for (int k = 0; k < reps && rc == CM_OK; ++k) rc = run();
+      if (rc != CM_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, stream) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(CM_EHIP, "autotune timing failed");
+        break;
+      }
+      if (ms / reps < best_ms) {
+        best_ms = ms / reps;
+        best_w = waves[wi];
+        best_b = bpcu[bi];
+      }
+    }
+  }
+  cleanup();
+  h->cfg = saved;
+  if (rc != CM_OK) return rc;
+  if (cache_path) cache_store(cache_path, key, best_w, best_b, best_ms);
+  return cm_set_launch(h, best_w, best_b);
+}
+
+int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
+                     double* energy, int32_t* n_inverted, const float* fbar,
+                     const double* ebar, float* ybar, double* thetabar,
+                     hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (mode < 0 || mode > 3) return fail(CM_EINVAL, "mode must be 0..3");
+  if (!stream) return fail(CM_EINVAL, "capture needs a non-null stream");
+  if (int rc = select_device(h)) return rc;
+  if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+  CM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  const bool percell = mode >= 2;
+  const bool bwd = mode == 1 || mode == 3;
+  int rc = forces_impl(h, y, f, energy, n_inverted, stream, percell);
+  if (rc == CM_OK && bwd)
+    rc = backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, percell);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(stream, &g);
+  if (rc != CM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(CM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  h->graph = g;
+  CM_HIP(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+  return CM_OK;
+}
+
+int cm_graph_launch(cm_batch h, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->graph_exec) return fail(CM_ESTATE, "no graph captured");
+  CM_HIP(hipGraphLaunch(h->graph_exec, stream));
+  return CM_OK;
+}
+
+struct cm_layout_s {
+  cm::Prepared P;
+  int32_t tile_tets;
+};
+
+int cm_layout_create(int32_t n_cells, const int64_t* node_off,
+                     const int64_t* tet_off, const double* ref_xyz,
+                     const int32_t* tets, const cm_options* opt,
+                     cm_layout* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  cm_layout_s* l = new (std::nothrow) cm_layout_s();
+  if (!l) return fail(CM_ENOMEM, "host allocation failed");
+  const cm::PrepOptions po = prep_options(opt);
+  std::string err;
+  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &l->P, &err);
+  if (rc != CM_OK) {
+    delete l;
+    return fail(rc, err);
+  }
+  l->tile_tets = po.tile_tets;
+  *out = l;
+  return CM_OK;
+}
+
+int cm_layout_sizes(cm_layout l, int64_t* s) {
+  if (!l || !s) return fail(CM_EINVAL, "null argument");
+  s[0] = (int64_t)l->P.tiles.size();
+  s[1] = (int64_t)l->P.chunks.size();
+  s[2] = (int64_t)l->P.slot_node.size();
+  s[3] = (int64_t)l->P.shared_node.size();
+  s[4] = l->P.n_nodes;
+  s[5] = l->P.n_cells;
+  s[6] = l->P.max_tile_nodes;
+  s[7] = l->tile_tets;
+  return CM_OK;
+}
+
+int cm_layout_export(cm_layout l, int32_t* tiles, void* chunks,
+                     int32_t* slot_node, int32_t* shared_node,
+                     int32_t* shared_slot_ptr, int32_t* shared_slots,
+                     int32_t* cell_tile_off, int32_t* cell_shared_off,
+                     int64_t* new_to_old) {
+  if (!l) return fail(CM_EINVAL, "null layout");
+  const cm::Prepared& P = l->P;
+  auto cp = [](void* dst, const void* src, size_t bytes) {
+    if (dst && bytes) std::memcpy(dst, src, bytes);
+  };
+  cp(tiles, P.tiles.data(), P.tiles.size() * sizeof(cm::TileDesc));
+  cp(chunks, P.chunks.data(), P.chunks.size() * sizeof(cm::TetChunk));
+  cp(slot_node, P.slot_node.data(), P.slot_node.size() * 4);
+  cp(shared_node, P.shared_node.data(), P.shared_node.size() * 4);
+  cp(shared_slot_ptr, P.shared_slot_ptr.data(), P.shared_slot_ptr.size() * 4);
+  cp(shared_slots, P.shared_slots.data(), P.shared_slots.size() * 4);
+  cp(cell_tile_off, P.cell_tile_off.data(), P.cell_tile_off.size() * 4);
+  cp(cell_shared_off, P.cell_shared_off.data(), P.cell_shared_off.size() * 4);
+  cp(new_to_old, P.new_to_old.data(), P.new_to_old.size() * 8);
+  return CM_OK;
+}
+
+int cm_layout_destroy(cm_layout l) {
+  delete l;
+  return CM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Launch interface of the device kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.h"
+
+namespace cm {
+
+// Device-resident tables of a prepared batch (see layout.h).
+struct DeviceTables {
+  const TileDesc* tiles = nullptr;
+  const TetChunk* chunks = nullptr;
+  const int32_t* slot_node = nullptr;
+  const int32_t* shared_node = nullptr;
+  const int32_t* shared_slot_ptr = nullptr;
+  const int32_t* shared_slots = nullptr;
+  const int32_t* cell_tile_off = nullptr;
+  const double* params = nullptr;  // SoA: mu[n_cells], kappa[n_cells], w[n_cells]
+  float* part = nullptr;           // SoA slot partials, 3 * n_slots
+  double* tile_acc = nullptr;      // per tile: energy (fwd) or 3 sums (bwd)
+  int32_t* tile_ninv = nullptr;    // per tile
+  int64_t n_nodes = 0, n_slots = 0, n_tiles = 0;
+  int32_t n_cells = 0;
+  int32_t nloc = 0;                // LDS node capacity per wave (multiple of 4)
+};
+
+// Work range of one launch: tiles, shared nodes and cells.
+struct Range {
+  int32_t tile_begin, tile_end;
+  int32_t shared_begin, shared_end;
+  int32_t cell_begin, cell_end;
+};
+
+struct LaunchCfg {
+  int waves = 1;   // tiles (wavefronts) per workgroup: 1, 2, 4 or 8
+  int blocks = 0;  // persistent workgroups; 0 = one workgroup per W tiles
+};
+
+// LDS bytes per wave of the forward / backward kernel for nloc tile nodes.
+size_t forward_lds_per_wave(int nloc);
+size_t backward_lds_per_wave(int nloc);
+
+hipError_t launch_forward(const DeviceTables& T, const Range& r,
+                          const LaunchCfg& cfg, const float* y, float* f,
+                          double* energy, int32_t* ninv, hipStream_t st);
+
+hipError_t launch_backward(const DeviceTables& T, const Range& r,
+                           const LaunchCfg& cfg, const float* y,
+                           const float* fbar, const double* ebar, float* ybar,
+                           double* thetabar, hipStream_t st);
+
+}  // namespace cm

@@ -1,0 +1,149 @@
+// Per-tetrahedron Mooney-Rivlin evaluation for gfx950.
+//
+// The paper evaluates f_i^a = -V0 dU/du_i^a with the chain rule of
+// eq. elastic-force-vertex-1 and the derivative table that follows the
+// Jacobian paragraph.  Collecting that chain rule gives the first
+// Piola-Kirchhoff stress P = dU/dF in closed form:
+//   P = mu1 J^-2/3 (F - T_C/3 F^-T)
+//     + mu2 J^-4/3 (T_C F - F C - 2/3 I2 F^-T)
+//     + kappa J (J - 1) F^-T,                 I2 = (T_C^2 - T_C2)/2,
+// and, with dF_kl/du_i^a = delta_ki B_ml (delta_ma - delta_4a), the forces
+//   [f^1 f^2 f^3] = -V0 P B^T,   f^4 = -(f^1 + f^2 + f^3).
+// With cof F = J F^-T (division free) this is
+//   P = c1 F + c2 (F C) + c3 cof F,
+//   c1 = mu1 J^-2/3 + mu2 J^-4/3 T_C,  c2 = -mu2 J^-4/3,
+//   c3 = -(mu1 J^-2/3 T_C + 2 mu2 J^-4/3 I2) / (3 J) + kappa (J - 1).
+//
+// Precision: the 3x3 tensor algebra is float32; the invariants, the powers of
+// J, the energy density and the coefficients c1..c3 are float64 (their inputs
+// are the float32 entries of F, so T_C, tr(C^2) and det F are exact to double
+// rounding, and I - 3, K - 3, J - 1 carry no float32 cancellation).
+// J^-1/3 is the reciprocal of the real (sign-preserving) cube root: a float32
+// hardware log2/exp2 seed refined by one Newton step in float64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cm {
+
+struct Material {
+  double mu1, mu2, kappa;
+};
+
+// Real J^-1/3 (negative for J < 0, infinite/NaN for J = 0).
+__device__ __forceinline__ double inv_cbrt(double J) {
+  const float jf = (float)J;
+  float s = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(fabsf(jf)) * (1.0f / 3.0f));
+  s = copysignf(s, jf);
+  const double r = (double)s;
+  // Newton step for g(r) = r^-3 - J: r <- r (4 - J r^3) / 3.
+  return r * (4.0 - J * (r * r * r)) * (1.0 / 3.0);
+}
+
+// Scalar part shared by the forward and backward passes.
+struct Scalars {
+  double TC, TC2, J, r, r2, r4, I2;
+};
+
+// Float64 invariants of a float32 deformation gradient.
+__device__ __forceinline__ void invariants(const float F[3][3], float Cf[6],
+                                           Scalars& s) {
+  double f[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) f[i][j] = (double)F[i][j];
+  // C = F^T F: C00 C11 C22 C01 C02 C12
+  const double C00 = f[0][0] * f[0][0] + f[1][0] * f[1][0] + f[2][0] * f[2][0];
+  const double C11 = f[0][1] * f[0][1] + f[1][1] * f[1][1] + f[2][1] * f[2][1];
+  const double C22 = f[0][2] * f[0][2] + f[1][2] * f[1][2] + f[2][2] * f[2][2];
+  const double C01 = f[0][0] * f[0][1] + f[1][0] * f[1][1] + f[2][0] * f[2][1];
+  const double C02 = f[0][0] * f[0][2] + f[1][0] * f[1][2] + f[2][0] * f[2][2];
+  const double C12 = f[0][1] * f[0][2] + f[1][1] * f[1][2] + f[2][1] * f[2][2];
+  Cf[0] = (float)C00; Cf[1] = (float)C11; Cf[2] = (float)C22;
+  Cf[3] = (float)C01; Cf[4] = (float)C02; Cf[5] = (float)C12;
+  s.TC = C00 + C11 + C22;
+  s.TC2 = C00 * C00 + C11 * C11 + C22 * C22 +
+          2.0 * (C01 * C01 + C02 * C02 + C12 * C12);
+  s.J = f[0][0] * (f[1][1] * f[2][2] - f[1][2] * f[2][1]) -
+        f[0][1] * (f[1][0] * f[2][2] - f[1][2] * f[2][0]) +
+        f[0][2] * (f[1][0] * f[2][1] - f[1][1] * f[2][0]);
+  s.r = inv_cbrt(s.J);
+  s.r2 = s.r * s.r;
+  s.r4 = s.r2 * s.r2;
+  s.I2 = 0.5 * (s.TC * s.TC - s.TC2);
+}
+
+// Cofactor matrix cof F = det(F) F^-T (columns are cross products of the
+// other two columns of F).
+__device__ __forceinline__ void cofactor(const float F[3][3], float K[3][3]) {
+  K[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  K[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  K[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  K[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  K[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  K[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  K[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  K[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  K[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+}
+
+// F C with C symmetric stored as C00 C11 C22 C01 C02 C12.
+__device__ __forceinline__ void times_sym(const float F[3][3], const float C[6],
+                                          float R[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    R[i][0] = F[i][0] * C[0] + F[i][1] * C[3] + F[i][2] * C[4];
+    R[i][1] = F[i][0] * C[3] + F[i][1] * C[1] + F[i][2] * C[5];
+    R[i][2] = F[i][0] * C[4] + F[i][1] * C[5] + F[i][2] * C[2];
+  }
+}
+
+// F = D_s B, D_s columns = edges e[k] = y^k - y^4.
+__device__ __forceinline__ void deformation_gradient(const float e[3][3],
+                                                     const float B[9],
+                                                     float F[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      F[i][j] = e[0][i] * B[j] + e[1][i] * B[3 + j] + e[2][i] * B[6 + j];
+}
+
+// Forward: forces h[k][i] on vertices k = 0..2 (vertex 3 takes the negative
+// sum) and the tetrahedron's energy V0 U (float64).
+__device__ __forceinline__ void tet_forward(const float e[3][3],
+                                            const float B[9], float V0,
+                                            const Material& m, float h[3][3],
+                                            double& vU, bool& inverted) {
+  float F[3][3], Cf[6];
+  deformation_gradient(e, B, F);
+  Scalars s;
+  invariants(F, Cf, s);
+  inverted = !(s.J > 0.0);
+  const double Jm1 = s.J - 1.0;
+  const double U = 0.5 * m.mu1 * (s.TC * s.r2 - 3.0) +
+                   0.5 * m.mu2 * (s.I2 * s.r4 - 3.0) + 0.5 * m.kappa * Jm1 * Jm1;
+  vU = (double)V0 * U;
+  const double a = m.mu1 * s.r2, b = m.mu2 * s.r4;
+  const double c1 = a + b * s.TC;
+  const double c2 = -b;
+  const double c3 = -(a * s.TC + 2.0 * b * s.I2) * (1.0 / 3.0) * (s.r2 * s.r) +
+                    m.kappa * Jm1;
+  const double nv = -(double)V0;
+  const float s1 = (float)(nv * c1), s2 = (float)(nv * c2), s3 = (float)(nv * c3);
+  float FC[3][3], K[3][3], P[3][3];
+  times_sym(F, Cf, FC);
+  cofactor(F, K);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[i][j] = s1 * F[i][j] + s2 * FC[i][j] + s3 * K[i][j];
+  // h[k][i] = (P B^T)_ik, already scaled by -V0
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      h[k][i] = P[i][0] * B[3 * k] + P[i][1] * B[3 * k + 1] + P[i][2] * B[3 * k + 2];
+}
+
+}  // namespace cm

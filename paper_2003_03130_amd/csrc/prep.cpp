@@ -1,0 +1,458 @@
+// Host preparation of tetrahedral cells: validation, the FP64 reference
+// precompute (B = J^-1 and V0, computed once as the paper prescribes in the
+// paragraph defining the Jacobian J_ik = x_i^k - x_i^4), locality ordering,
+// tiling and the owned/shared node tables described in layout.h.
+#include "prep.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "../../include/cellmech.h"
+
+namespace cm {
+namespace {
+
+struct CellOut {
+  int status = CM_OK;
+  std::string err;
+  std::vector<TileDesc> tiles;       // chunk_begin, own_begin, shr_begin local
+  std::vector<TetChunk> chunks;
+  std::vector<int32_t> slot_node;    // local internal ids
+  std::vector<int32_t> shared_node;  // local internal ids
+  std::vector<int32_t> shared_slot_ptr;
+  std::vector<int32_t> shared_slots;  // local slot ids
+  std::vector<int64_t> new_to_old;    // local
+  int32_t max_tile_nodes = 0;
+  double volume = 0.0, min_v0 = INFINITY, max_cond = 0.0;
+};
+
+// Spread the low 10 bits of v so that bit b lands on bit 3b.
+inline uint32_t spread3(uint32_t v) {
+  v &= 0x3ff;
+  v = (v | (v << 16)) & 0x030000ff;
+  v = (v | (v << 8)) & 0x0300f00f;
+  v = (v | (v << 4)) & 0x030c30c3;
+  v = (v | (v << 2)) & 0x09249249;
+  return v;
+}
+
+// Tet order by the Morton (Z-order) code of the reference centroid.
+void morton_order(int64_t m, const int32_t* T, const double* X,
+                  std::vector<int64_t>& perm) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  std::vector<double> cen(3 * m);
+  for (int64_t t = 0; t < m; ++t)
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+      for (int a = 0; a < 4; ++a) s += X[3 * (int64_t)T[4 * t + a] + i];
+      cen[3 * t + i] = 0.25 * s;
+      lo[i] = std::min(lo[i], cen[3 * t + i]);
+      hi[i] = std::max(hi[i], cen[3 * t + i]);
+    }
+  std::vector<uint32_t> code(m);
+  for (int64_t t = 0; t < m; ++t) {
+    uint32_t c = 0;
+    for (int i = 0; i < 3; ++i) {
+      double span = hi[i] - lo[i];
+      double q = span > 0 ? (cen[3 * t + i] - lo[i]) / span : 0.0;
+      uint32_t qi = (uint32_t)std::min(1023.0, std::max(0.0, std::floor(q * 1024.0)));
+      c |= spread3(qi) << i;
+    }
+    code[t] = c;
+  }
+  perm.resize(m);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int64_t a, int64_t b) { return code[a] < code[b]; });
+}
+
+// Tet order by the smallest reverse Cuthill-McKee label of its vertices.
+void rcm_order(int64_t n, int64_t m, const int32_t* T,
+               std::vector<int64_t>& perm) {
+  static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  std::vector<std::pair<int32_t, int32_t>> edges;
+  edges.reserve(12 * m);
+  for (int64_t t = 0; t < m; ++t)
+    for (auto& e : E) {
+      int32_t a = T[4 * t + e[0]], b = T[4 * t + e[1]];
+      edges.emplace_back(a, b);
+      edges.emplace_back(b, a);
+    }
+  std::sort(edges.begin(), edges.end());
+  edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+  std::vector<int64_t> ptr(n + 1, 0);
+  for (auto& e : edges) ptr[e.first + 1]++;
+  for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int32_t> adj(edges.size());
+  for (size_t q = 0; q < edges.size(); ++q) adj[q] = edges[q].second;
+  auto deg = [&](int32_t v) { return ptr[v + 1] - ptr[v]; };
+
+  std::vector<int32_t> label(n, -1), order;
+  order.reserve(n);
+  std::vector<int32_t> level(n, -1);
+  auto bfs_last = [&](int32_t s, std::vector<int32_t>& seen) {
+    // returns a minimum-degree vertex of the last BFS level from s
+    std::vector<int32_t> cur{s}, nxt, last{s};
+    seen[s] = s;
+    while (!cur.empty()) {
+      last = cur;
+      nxt.clear();
+      for (int32_t v : cur)
+        for (int64_t q = ptr[v]; q < ptr[v + 1]; ++q)
+          if (seen[adj[q]] != s) { seen[adj[q]] = s; nxt.push_back(adj[q]); }
+      cur.swap(nxt);
+    }
+    return *std::min_element(last.begin(), last.end(), [&](int32_t a, int32_t b) {
+      return deg(a) < deg(b) || (deg(a) == deg(b) && a < b);
+    });
+  };
+  std::vector<int32_t> seen(n, -1);
+  for (int32_t start = 0; start < n; ++start) {
+    if (label[start] >= 0) continue;
+    // pseudo-peripheral start vertex of this component
+    int32_t s = start;
+    for (int it = 0; it < 2; ++it) s = bfs_last(s, seen);
+    size_t head = order.size();
+    order.push_back(s);
+    label[s] = 0;
+    std::vector<int32_t> nb;
+    while (head < order.size()) {
+      int32_t v = order[head++];
+      nb.clear();
+      for (int64_t q = ptr[v]; q < ptr[v + 1]; ++q)
+        if (label[adj[q]] < 0) { label[adj[q]] = 0; nb.push_back(adj[q]); }
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+        return deg(a) < deg(b) || (deg(a) == deg(b) && a < b);
+      });
+      for (int32_t u : nb) order.push_back(u);
+    }
+  }
+  for (int64_t k = 0; k < n; ++k) label[order[k]] = (int32_t)(n - 1 - k);
+  std::vector<int32_t> key(m);
+  for (int64_t t = 0; t < m; ++t) {
+    int32_t k = label[T[4 * t]];
+    for (int a = 1; a < 4; ++a) k = std::min(k, label[T[4 * t + a]]);
+    key[t] = k;
+  }
+  perm.resize(m);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+}
+
+void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
+                  const int32_t* T, const PrepOptions& opt, CellOut& out) {
+  auto fail = [&](int st, const std::string& msg) {
+    out.status = st;
+    out.err = "cell " + std::to_string(c) + ": " + msg;
+  };
+  if (m <= 0) return fail(CM_EINVAL, "has no tetrahedra");
+  if (n < 4) return fail(CM_EINVAL, "has fewer than 4 nodes");
+  if (n > 0x7fffffffLL || m > 0x7fffffffLL) return fail(CM_EINVAL, "too large");
+  for (int64_t t = 0; t < m; ++t) {
+    const int32_t* v = T + 4 * t;
+    for (int a = 0; a < 4; ++a) {
+      if (v[a] < 0 || v[a] >= n)
+        return fail(CM_EINVAL, "tetrahedron " + std::to_string(t) +
+                                   " has a vertex index out of range");
+      for (int b = 0; b < a; ++b)
+        if (v[a] == v[b])
+          return fail(CM_EINVAL, "tetrahedron " + std::to_string(t) +
+                                     " repeats a vertex");
+    }
+  }
+  for (int64_t q = 0; q < 3 * n; ++q)
+    if (!std::isfinite(X[q])) return fail(CM_EINVAL, "non-finite reference position");
+
+  // FP64 precompute: J_ik = x_i^k - x_i^4, B = J^-1, V0 = |det J| / 6.
+  std::vector<double> B(9 * m), V0(m), absdet(m);
+  double hsum = 0.0;
+  static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  for (int64_t t = 0; t < m; ++t) {
+    const int32_t* v = T + 4 * t;
+    double Jm[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) Jm[i][k] = X[3 * (int64_t)v[k] + i] - X[3 * (int64_t)v[3] + i];
+    double adj[3][3];
+    adj[0][0] = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+    adj[0][1] = Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2];
+    adj[0][2] = Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1];
+    adj[1][0] = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+    adj[1][1] = Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0];
+    adj[1][2] = Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2];
+    adj[2][0] = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+    adj[2][1] = Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1];
+    adj[2][2] = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+    double det = Jm[0][0] * adj[0][0] + Jm[0][1] * adj[1][0] + Jm[0][2] * adj[2][0];
+    absdet[t] = std::fabs(det);
+    double n1J = 0.0, n1B = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double sJ = 0.0, sB = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        B[9 * t + 3 * k + i] = adj[k][i] / det;
+        sJ += std::fabs(Jm[i][k]);
+        sB += std::fabs(adj[i][k] / det);
+      }
+      n1J = std::max(n1J, sJ);
+      n1B = std::max(n1B, sB);
+    }
+    V0[t] = absdet[t] / 6.0;
+    out.max_cond = std::max(out.max_cond, n1J * n1B);
+    for (auto& e : E) {
+      double d2 = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        double d = X[3 * (int64_t)v[e[0]] + i] - X[3 * (int64_t)v[e[1]] + i];
+        d2 += d * d;
+      }
+      hsum += std::sqrt(d2);
+    }
+  }
+  double h = hsum / (6.0 * (double)m);
+  double thr = opt.degenerate_tol * h * h * h;
+  for (int64_t t = 0; t < m; ++t) {
+    if (!(absdet[t] > thr))
+      return fail(CM_EDEGENERATE, "tetrahedron " + std::to_string(t) +
+                                      " is degenerate (|det J| = " +
+                                      std::to_string(absdet[t]) + ")");
+    out.volume += V0[t];
+    out.min_v0 = std::min(out.min_v0, V0[t]);
+  }
+
+  // Locality order of the tetrahedra.
+  std::vector<int64_t> perm;
+  if (opt.order == CM_ORDER_MORTON) {
+    morton_order(m, T, X, perm);
+  } else if (opt.order == CM_ORDER_RCM) {
+    rcm_order(n, m, T, perm);
+  } else {
+    perm.resize(m);
+    std::iota(perm.begin(), perm.end(), 0);
+  }
+
+  const int64_t TT = opt.tile_tets;
+  const int64_t n_tiles = (m + TT - 1) / TT;
+  // Number of distinct tiles touching each node.
+  std::vector<int32_t> last(n, -1), ntile(n, 0);
+  for (int64_t p = 0; p < m; ++p) {
+    int32_t k = (int32_t)(p / TT);
+    const int32_t* v = T + 4 * perm[p];
+    for (int a = 0; a < 4; ++a)
+      if (last[v[a]] != k) { last[v[a]] = k; ntile[v[a]]++; }
+  }
+  // Internal numbering: owned nodes tile by tile, then shared nodes in order
+  // of first appearance, then nodes no tetrahedron uses.
+  std::vector<int32_t> newid(n, -1);
+  std::vector<int32_t> own_begin(n_tiles), n_own(n_tiles);
+  int32_t next = 0;
+  for (int64_t k = 0; k < n_tiles; ++k) {
+    own_begin[k] = next;
+    for (int64_t p = k * TT; p < std::min(m, (k + 1) * TT); ++p) {
+      const int32_t* v = T + 4 * perm[p];
+      for (int a = 0; a < 4; ++a)
+        if (ntile[v[a]] == 1 && newid[v[a]] < 0) newid[v[a]] = next++;
+    }
+    n_own[k] = next - own_begin[k];
+  }
+  const int32_t n_owned = next;
+  for (int64_t p = 0; p < m; ++p) {
+    const int32_t* v = T + 4 * perm[p];
+    for (int a = 0; a < 4; ++a)
+      if (newid[v[a]] < 0) newid[v[a]] = next++;
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (newid[v] < 0) newid[v] = next++;
+  const int32_t n_shared = (int32_t)n - n_owned;
+
+  out.new_to_old.resize(n);
+  for (int64_t v = 0; v < n; ++v) out.new_to_old[newid[v]] = v;
+
+  // Tiles, slots and chunks.
+  out.tiles.resize(n_tiles);
+  std::vector<int32_t> stamp(n, -1), loc(n, 0);
+  int64_t n_chunks = 0;
+  for (int64_t k = 0; k < n_tiles; ++k)
+    n_chunks += (std::min(m, (k + 1) * TT) - k * TT + kChunk - 1) / kChunk;
+  out.chunks.assign(n_chunks, TetChunk());
+  std::memset(out.chunks.data(), 0, sizeof(TetChunk) * n_chunks);
+  int64_t chunk = 0;
+  for (int64_t k = 0; k < n_tiles; ++k) {
+    const int64_t p0 = k * TT, p1 = std::min(m, (k + 1) * TT);
+    TileDesc& d = out.tiles[k];
+    d.chunk_begin = (int32_t)chunk;
+    d.n_tets = (int32_t)(p1 - p0);
+    d.own_begin = own_begin[k];
+    d.n_own = n_own[k];
+    d.shr_begin = (int32_t)out.slot_node.size();
+    d.cell = c;
+    d.pad = 0;
+    int32_t nsh = 0;
+    for (int64_t p = p0; p < p1; ++p) {
+      const int32_t* v = T + 4 * perm[p];
+      for (int a = 0; a < 4; ++a) {
+        int32_t u = v[a];
+        if (ntile[u] == 1) {
+          loc[u] = newid[u] - own_begin[k];
+        } else if (stamp[u] != (int32_t)k) {
+          stamp[u] = (int32_t)k;
+          loc[u] = n_own[k] + nsh++;
+          out.slot_node.push_back(newid[u]);
+        }
+      }
+    }
+    d.n_shr = nsh;
+    out.max_tile_nodes = std::max(out.max_tile_nodes, d.n_own + d.n_shr);
+    for (int64_t p = p0; p < p1; ++p) {
+      int64_t t = perm[p];
+      const int32_t* v = T + 4 * t;
+      TetChunk& ch = out.chunks[chunk + (p - p0) / kChunk];
+      int lane = (int)((p - p0) % kChunk);
+      ch.idx[lane][0] = (uint32_t)loc[v[0]] | ((uint32_t)loc[v[1]] << 16);
+      ch.idx[lane][1] = (uint32_t)loc[v[2]] | ((uint32_t)loc[v[3]] << 16);
+      for (int q = 0; q < 9; ++q) ch.B[q][lane] = (float)B[9 * t + q];
+      ch.V0[lane] = (float)V0[t];
+    }
+    chunk += (p1 - p0 + kChunk - 1) / kChunk;
+  }
+  // Shared node -> its slots, in tile order.
+  out.shared_node.resize(n_shared);
+  for (int32_t s = 0; s < n_shared; ++s) out.shared_node[s] = n_owned + s;
+  out.shared_slot_ptr.assign(n_shared + 1, 0);
+  for (int32_t node : out.slot_node) out.shared_slot_ptr[node - n_owned + 1]++;
+  for (int32_t s = 0; s < n_shared; ++s)
+    out.shared_slot_ptr[s + 1] += out.shared_slot_ptr[s];
+  out.shared_slots.resize(out.slot_node.size());
+  std::vector<int32_t> fill(out.shared_slot_ptr.begin(), out.shared_slot_ptr.end() - 1);
+  for (size_t q = 0; q < out.slot_node.size(); ++q)
+    out.shared_slots[fill[out.slot_node[q] - n_owned]++] = (int32_t)q;
+}
+
+}  // namespace
+
+int prepare_batch(int32_t n_cells, const int64_t* node_off,
+                  const int64_t* tet_off, const double* ref_xyz,
+                  const int32_t* tets, const PrepOptions& opt, Prepared* P,
+                  std::string* err) {
+  if (n_cells <= 0 || !node_off || !tet_off || !ref_xyz || !tets) {
+    *err = "null pointer or n_cells <= 0";
+    return CM_EINVAL;
+  }
+  if (opt.tile_tets < kChunk || opt.tile_tets > kMaxTileTets || opt.tile_tets % kChunk) {
+    *err = "tile_tets must be a multiple of 64 in [64, 4096]";
+    return CM_EINVAL;
+  }
+  if (opt.order < 0 || opt.order > 2) {
+    *err = "unknown order";
+    return CM_EINVAL;
+  }
+  if (node_off[0] != 0 || tet_off[0] != 0) {
+    *err = "offsets must start at 0";
+    return CM_EINVAL;
+  }
+  for (int32_t c = 0; c < n_cells; ++c)
+    if (node_off[c + 1] < node_off[c] || tet_off[c + 1] < tet_off[c]) {
+      *err = "offsets must be non-decreasing";
+      return CM_EINVAL;
+    }
+  if (node_off[n_cells] >= 0x7fffffffLL) {
+    *err = "more than 2^31 - 1 nodes";
+    return CM_EINVAL;
+  }
+
+  std::vector<CellOut> cells(n_cells);
+  std::atomic<int32_t> next_cell(0);
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nt = std::min<unsigned>(nt, (unsigned)n_cells);
+  auto work = [&]() {
+    for (;;) {
+      int32_t c = next_cell.fetch_add(1);
+      if (c >= n_cells) break;
+      prepare_cell(c, node_off[c + 1] - node_off[c], tet_off[c + 1] - tet_off[c],
+                   ref_xyz + 3 * node_off[c], tets + 4 * tet_off[c], opt, cells[c]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (unsigned i = 1; i < nt; ++i) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  for (auto& cell : cells)
+    if (cell.status != CM_OK) {
+      *err = cell.err;
+      return cell.status;
+    }
+
+  // Concatenate with global offsets.
+  int64_t n_tiles = 0, n_chunks = 0, n_slots = 0, n_shared = 0;
+  for (auto& cell : cells) {
+    n_tiles += cell.tiles.size();
+    n_chunks += cell.chunks.size();
+    n_slots += cell.slot_node.size();
+    n_shared += cell.shared_node.size();
+  }
+  if (n_chunks >= 0x7fffffffLL || n_slots >= 0x7fffffffLL) {
+    *err = "batch too large for 32-bit tile tables";
+    return CM_EINVAL;
+  }
+  P->n_cells = n_cells;
+  P->n_nodes = node_off[n_cells];
+  P->n_tets = tet_off[n_cells];
+  P->tiles.resize(n_tiles);
+  P->chunks.resize(n_chunks);
+  P->slot_node.resize(n_slots);
+  P->shared_node.resize(n_shared);
+  P->shared_slot_ptr.resize(n_shared + 1);
+  P->shared_slots.resize(n_slots);
+  P->cell_tile_off.resize(n_cells + 1);
+  P->cell_shared_off.resize(n_cells + 1);
+  P->node_off.assign(node_off, node_off + n_cells + 1);
+  P->new_to_old.resize(P->n_nodes);
+  P->volume = 0.0;
+  P->min_v0 = INFINITY;
+  P->max_cond = 0.0;
+  P->max_tile_nodes = 0;
+  int64_t tb = 0, cb = 0, sb = 0, hb = 0;
+  P->shared_slot_ptr[0] = 0;
+  for (int32_t c = 0; c < n_cells; ++c) {
+    CellOut& cell = cells[c];
+    const int32_t nb = (int32_t)node_off[c];
+    P->cell_tile_off[c] = (int32_t)tb;
+    P->cell_shared_off[c] = (int32_t)hb;
+    for (size_t k = 0; k < cell.tiles.size(); ++k) {
+      TileDesc d = cell.tiles[k];
+      d.chunk_begin += (int32_t)cb;
+      d.own_begin += nb;
+      d.shr_begin += (int32_t)sb;
+      P->tiles[tb + k] = d;
+    }
+    std::memcpy(P->chunks.data() + cb, cell.chunks.data(),
+                sizeof(TetChunk) * cell.chunks.size());
+    for (size_t q = 0; q < cell.slot_node.size(); ++q) {
+      P->slot_node[sb + q] = cell.slot_node[q] + nb;
+      P->shared_slots[sb + q] = cell.shared_slots[q] + (int32_t)sb;
+    }
+    for (size_t s = 0; s < cell.shared_node.size(); ++s) {
+      P->shared_node[hb + s] = cell.shared_node[s] + nb;
+      P->shared_slot_ptr[hb + s + 1] = cell.shared_slot_ptr[s + 1] + (int32_t)sb;
+    }
+    for (size_t v = 0; v < cell.new_to_old.size(); ++v)
+      P->new_to_old[nb + v] = cell.new_to_old[v] + nb;
+    P->volume += cell.volume;
+    P->min_v0 = std::min(P->min_v0, cell.min_v0);
+    P->max_cond = std::max(P->max_cond, cell.max_cond);
+    P->max_tile_nodes = std::max(P->max_tile_nodes, cell.max_tile_nodes);
+    tb += cell.tiles.size();
+    cb += cell.chunks.size();
+    sb += cell.slot_node.size();
+    hb += cell.shared_node.size();
+    std::vector<TetChunk>().swap(cell.chunks);
+  }
+  P->cell_tile_off[n_cells] = (int32_t)tb;
+  P->cell_shared_off[n_cells] = (int32_t)hb;
+  return CM_OK;
+}
+
+}  // namespace cm

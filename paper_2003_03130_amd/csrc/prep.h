@@ -1,0 +1,40 @@
+// Host-side preparation of tetrahedral cells for the device kernels.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "layout.h"
+
+namespace cm {
+
+struct PrepOptions {
+  int order = 2;                // 0 input, 1 RCM, 2 Morton
+  int tile_tets = 1024;         // multiple of 64, <= kMaxTileTets
+  double degenerate_tol = 1e-12;
+};
+
+// Everything the device needs, in host memory, for all cells.
+struct Prepared {
+  int64_t n_cells = 0, n_nodes = 0, n_tets = 0;
+  std::vector<TileDesc> tiles;
+  std::vector<TetChunk> chunks;
+  std::vector<int32_t> slot_node;        // internal node id of every slot
+  std::vector<int32_t> shared_node;      // internal node id of every shared node
+  std::vector<int32_t> shared_slot_ptr;  // CSR (n_shared + 1) into shared_slots
+  std::vector<int32_t> shared_slots;     // slot ids, grouped by shared node, in tile order
+  std::vector<int32_t> cell_tile_off;    // n_cells + 1
+  std::vector<int32_t> cell_shared_off;  // n_cells + 1
+  std::vector<int64_t> node_off;         // n_cells + 1 (same as input)
+  std::vector<int64_t> new_to_old;       // n_nodes
+  int32_t max_tile_nodes = 0;
+  double volume = 0.0, min_v0 = 0.0, max_cond = 0.0;
+};
+
+// Returns 0 on success, or a CM_* status with `err` set.
+int prepare_batch(int32_t n_cells, const int64_t* node_off,
+                  const int64_t* tet_off, const double* ref_xyz,
+                  const int32_t* tets, const PrepOptions& opt, Prepared* out,
+                  std::string* err);
+
+}  // namespace cm
