@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Throughput of the batched Mooney-Rivlin tetrahedral force path on one GPU.
+
+Workload: 4,096 cells of uneven size (ellipsoids with semi-axes
+U[0.7, 1.3] R, 500-20,000 tetrahedra each, ~42 M tetrahedra in total), each
+with its own compression + shear, node noise and (mu, kappa, w); synthetic,
+seeded (synth.configs.uneven_batch).
+
+One step = one hot-path pass over the whole batch: the forward kernels
+(forces + energies) followed by the backward kernels (Hessian-vector product
+and parameter gradient), replayed as one captured HIP graph.  The reported
+value is tetrahedra per second of that step.  Also reported: forward-only
+throughput, the same passes as one launch per cell (single-cell baseline),
+per-kernel device times from HIP events, a roofline entry for the dominant
+kernel, sampled parity against the FP64 oracle, and the oracle timed on the
+host (CPU baseline).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("tets/sec (fwd; fwd+bwd) and % of HBM roofline, batched vs "
+          "single-cell, at 1e-5 rel err")
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per tetrahedron and per node (int32 indices, float32
+# inverse edge matrix and volume, float32 SoA node arrays), per pass.
+FWD_BYTES = (56, 24)    # 16 idx + 36 B + 4 V0 per tet; y in + f out per node
+BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
+F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr,
+          flush=True)
+
+
+def time_graph(cb, stream, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        cb.graph_launch(stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        cb.graph_launch(stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def parity(cb, b, f, E, ybar, tb, vbar, ebar, cells):
+    """Max errors of sampled cells against the oracle (forward + backward)."""
+    import oracle
+    fh, yh = cb.to_host(f), cb.to_host(ybar)
+    Eh, th = E.cpu().numpy(), tb.cpu().numpy().reshape(-1, 3)
+    worst = {"force": 0.0, "energy": 0.0, "ybar": 0.0, "thetabar": 0.0}
+    for c in cells:
+        cell = b.cell(c)
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        y64 = cell.y.astype(np.float64)
+        fo, Eo, _ = m.forces(y64, cell.theta)
+        yo, to = m.backward(y64, cell.theta, vbar[n0:n1].astype(np.float64),
+                            float(ebar[c]))
+        worst["force"] = max(worst["force"], float(
+            np.abs(fh[n0:n1] - fo).max() / np.abs(fo).max()))
+        worst["energy"] = max(worst["energy"], abs(Eh[c] - Eo) / abs(Eo))
+        worst["ybar"] = max(worst["ybar"], float(
+            np.abs(yh[n0:n1] - yo).max() / np.abs(yo).max()))
+        worst["thetabar"] = max(worst["thetabar"], float(
+            np.abs(th[c] - to).max() / np.abs(to).max()))
+    worst["ok"] = bool(worst["force"] <= F_TOL and worst["energy"] <= E_TOL
+                       and worst["ybar"] <= G_TOL and worst["thetabar"] <= G_TOL)
+    worst["cells_checked"] = len(cells)
+    return worst
+
+
+def cpu_baseline(b, vbar, ebar, seconds):
+    """The FP64 oracle (forward + backward) on the first cells of the same
+    workload until about `seconds` of single-thread CPU time."""
+    import oracle
+    tets, spent, ncell = 0, 0.0, 0
+    for c in range(b.n_cells):
+        cell = b.cell(c)
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        y64 = cell.y.astype(np.float64)
+        v64 = vbar[n0:n1].astype(np.float64)
+        t0 = time.perf_counter()
+        m.forces(y64, cell.theta)
+        m.backward(y64, cell.theta, v64, float(ebar[c]))
+        spent += time.perf_counter() - t0
+        tets += cell.n_tets
+        ncell += 1
+        if spent >= seconds:
+            break
+    return {"value": tets / spent, "unit": "tets/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {ncell} cells of the workload ({tets} tets), "
+                      f"FP64 oracle forward (derivative-table path) + backward "
+                      f"(dual-number JVPs), single thread, {spent:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cells", type=int, default=4096)
+    ap.add_argument("--seed", type=int, default=3000)
+    ap.add_argument("--tile-tets", type=int, default=1024)
+    ap.add_argument("--parity-cells", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-percell", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the batched cell-force path "
+              "has no multi-GPU mode (cells shard independently; see the "
+              "design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import cotangent, uneven_batch
+
+    t = time.time()
+    b = uneven_batch(n_cells=args.cells, seed=args.seed)
+    log(f"workload: {b.n_cells} cells, {b.n_tets} tets, {b.n_nodes} nodes "
+        f"({time.time() - t:.1f} s)")
+    t = time.time()
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets,
+                   tile_tets=args.tile_tets)
+    log(f"prepared + uploaded in {time.time() - t:.1f} s: {cb.info}")
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    dev = cb.device
+    y = cb.to_device(b.y)
+    vbar = cotangent(b.n_nodes, args.seed + 1)
+    fbar = cb.to_device(vbar)
+    ebar_h = np.random.default_rng(args.seed + 2).uniform(0.0, 1.0, b.n_cells)
+    ebar = torch.tensor(ebar_h, dtype=torch.float64, device=dev)
+    f, ybar = cb.empty_nodes(), cb.empty_nodes()
+    E = torch.empty(b.n_cells, dtype=torch.float64, device=dev)
+    tb = torch.empty(3 * b.n_cells, dtype=torch.float64, device=dev)
+    ninv = torch.empty(b.n_cells, dtype=torch.int32, device=dev)
+
+    if not args.no_autotune:
+        t = time.time()
+        launch = cb.autotune(y)
+        log(f"autotuned launch (waves/block, blocks/CU) = {launch} in "
+            f"{time.time() - t:.1f} s")
+    launch = cb.get_launch()
+
+    # eager pass for the parity gate
+    cb.forces(y, f, E, ninv)
+    cb.backward(y, fbar, ebar, ybar, tb)
+    torch.cuda.synchronize()
+    sample = sorted(set(np.linspace(0, b.n_cells - 1,
+                                    args.parity_cells).astype(int).tolist()))
+    t = time.time()
+    par = parity(cb, b, f, E, ybar, tb, vbar, ebar_h, sample)
+    log(f"parity on {len(sample)} cells ({time.time() - t:.1f} s): {par}")
+    n_inverted = int(ninv.sum().item())
+
+    s = torch.cuda.Stream()
+    M, N = b.n_tets, b.n_nodes
+    res = {}
+    for name, mode in (("fwd_bwd", 1), ("fwd", 0)):
+        with torch.cuda.stream(s):
+            cb.graph_capture(mode, y, f, E, ninv, fbar, ebar, ybar, tb,
+                             stream=s)
+        res[name] = time_graph(cb, s, args.steps, args.warmup)
+        log(f"batched {name}: {res[name]:.4f} ms/step")
+    step_ms = res["fwd_bwd"]
+    if not args.no_percell:
+        psteps = max(2, args.steps // 4)
+        for name, mode in (("percell_fwd_bwd", 3), ("percell_fwd", 2)):
+            t = time.time()
+            with torch.cuda.stream(s):
+                cb.graph_capture(mode, y, f, E, ninv, fbar, ebar, ybar, tb,
+                                 stream=s)
+            res[name] = time_graph(cb, s, psteps, 1)
+            log(f"single-cell launches {name}: {res[name]:.3f} ms/step "
+                f"(capture {time.time() - t:.1f} s)")
+
+    ms = cb.profile_kernels(y, f, E, fbar, ebar, ybar, tb, reps=10,
+                            stream=s)
+    log(f"kernel ms (fwd tile, fwd finalize, bwd tile, bwd finalize): "
+        f"{np.round(ms, 4).tolist()}")
+    fwd_b = FWD_BYTES[0] * M + FWD_BYTES[1] * N
+    bwd_b = BWD_BYTES[0] * M + BWD_BYTES[1] * N
+    kern = {
+        "forward_tile": {"ms": ms[0], "bytes": fwd_b,
+                         "GBps": fwd_b / ms[0] / 1e6},
+        "backward_tile": {"ms": ms[2], "bytes": bwd_b,
+                          "GBps": bwd_b / ms[2] / 1e6},
+        "forward_finalize_ms": ms[1], "backward_finalize_ms": ms[3],
+    }
+    dom = "backward_tile" if ms[2] >= ms[0] else "forward_tile"
+    ach = kern[dom]["GBps"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.time()
+        cpu = cpu_baseline(b, vbar, ebar_h, args.cpu_seconds)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": M / (step_ms * 1e-3),
+        "unit": "tets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{b.n_cells} uneven ellipsoid cells, {M} tets, "
+                        f"{N} nodes; one step = batched forward + backward",
+            "n_cells": b.n_cells, "n_tets": M, "n_nodes": N,
+            "tile_tets": cb.info["tile_tets"], "launch": list(launch),
+            "parallelism": "single GPU",
+        },
+        "fwd_tets_per_s": M / (res["fwd"] * 1e-3),
+        "fwd_bwd_tets_per_s": M / (step_ms * 1e-3),
+        "hbm_frac_fwd": fwd_b / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "hbm_frac_fwd_bwd": (fwd_b + bwd_b) / (step_ms * 1e-3)
+        / (HBM_PEAK_GBS * 1e9),
+        "ms": {k: round(v, 5) for k, v in res.items()},
+        "kernels": kern,
+        "roofline": roofline,
+        "parity": par,
+        "n_inverted": n_inverted,
+        "cpu_baseline": cpu,
+    }
+    if not args.no_percell:
+        out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)
+        out["percell_fwd_bwd_tets_per_s"] = M / (res["percell_fwd_bwd"] * 1e-3)
+        out["batched_speedup_fwd_bwd"] = res["percell_fwd_bwd"] / step_ms
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -79,6 +79,7 @@ typedef struct {
   int64_t n_tiles;        /* tiles over all cells                             */
   int64_t n_shared;       /* nodes touched by more than one tile             */
   int64_t n_slots;        /* (tile, shared node) pairs                        */
+  int64_t n_chunks;       /* 64-lane chunks over all tiles                    */
   int32_t tile_tets;      /* tetrahedra per tile                              */
   int32_t max_tile_nodes; /* largest number of distinct nodes in one tile     */
   int64_t device_bytes;   /* device memory owned by the handle                */
@@ -214,6 +215,20 @@ int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
 int cm_graph_launch(cm_batch h, hipStream_t stream);
 
 /*
+ * cm_profile_kernels: average device time of each kernel of one batched
+ * forward + backward evaluation, measured with HIP events recorded on
+ * `stream` around `reps` back-to-back launches of each kernel:
+ *   ms[0] forward tile kernel,  ms[1] forward finalize kernel,
+ *   ms[2] backward tile kernel, ms[3] backward finalize kernel.
+ * Buffers as in cm_forces / cm_forces_backward (fbar, ebar nullable).
+ * Synchronises the stream; not graph-safe.
+ */
+int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
+                       const float* fbar, const double* ebar, float* ybar,
+                       double* thetabar, int32_t reps, double* ms,
+                       hipStream_t stream);
+
+/*
  * Host-only view of the prepared layout (no device work), for validation and
  * debugging of the preparation step.  cm_layout_create runs exactly the
  * preparation of cm_batch_create (same arguments, same errors).
@@ -221,9 +236,11 @@ int cm_graph_launch(cm_batch h, hipStream_t stream);
  * n_nodes, n_cells, max_tile_nodes, tile_tets}.  cm_layout_export copies the
  * tables into caller-owned host arrays (each nullable):
  *   tiles        int32[n_tiles * 8]   (chunk_begin, n_tets, own_begin, n_own,
- *                                      shr_begin, n_shr, cell, 0)
+ *                                      shr_begin, n_shr, cell, n_chunks)
  *   chunks       uint8[n_chunks * 3072] (64 tetrahedra each: uint32 idx[64][2]
- *                                      holding 4 x uint16 local indices,
+ *                                      holding 4 x uint16 local indices in
+ *                                      vertex-slot order, 0xffffffff in
+ *                                      idx[lane][0] for an empty lane,
  *                                      float B[9][64], float V0[64])
  *   slot_node    int32[n_slots]       shared_node   int32[n_shared]
  *   shared_slot_ptr int32[n_shared+1] shared_slots  int32[n_slots]

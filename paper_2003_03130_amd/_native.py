@@ -32,6 +32,7 @@ class Info(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
                 ("n_tets", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("n_shared", ctypes.c_int64), ("n_slots", ctypes.c_int64),
+                ("n_chunks", ctypes.c_int64),
                 ("tile_tets", ctypes.c_int32),
                 ("max_tile_nodes", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("volume", ctypes.c_double),
@@ -71,6 +72,8 @@ SIGNATURES = {
     "cm_graph_capture": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp]),
     "cm_graph_launch": (_int, [_vp, _vp]),
+    "cm_profile_kernels": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _i32, _vp, _vp]),
     "cm_layout_create": (_int, [_i32, _vp, _vp, _vp, _vp,
                                 ctypes.POINTER(Options), ctypes.POINTER(_vp)]),
     "cm_layout_sizes": (_int, [_vp, _p64]),

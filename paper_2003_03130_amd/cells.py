@@ -185,6 +185,16 @@ class CellBatch:
             _stream(stream)))
         return self.get_launch()
 
+    def profile_kernels(self, y, f, energy, fbar, ebar, ybar, thetabar,
+                        reps=10, stream=None):
+        """Average ms per launch of the forward tile, forward finalize,
+        backward tile and backward finalize kernels (HIP events)."""
+        ms = np.zeros(4, dtype=np.float64)
+        nat.check(nat.lib().cm_profile_kernels(
+            self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(fbar), _ptr(ebar),
+            _ptr(ybar), _ptr(thetabar), int(reps), _ptr(ms), _stream(stream)))
+        return ms
+
     def graph_capture(self, mode, y, f, energy=None, n_inverted=None,
                       fbar=None, ebar=None, ybar=None, thetabar=None,
                       stream=None):
@@ -235,6 +245,7 @@ class HostLayout:
         self.local_idx = np.stack([idx[..., 0] & 0xFFFF, idx[..., 0] >> 16,
                                    idx[..., 1] & 0xFFFF, idx[..., 1] >> 16],
                                   axis=-1).astype(np.int64)
+        self.empty = idx[..., 0] == 0xFFFFFFFF
         self.B = ch[:, 512:512 + 2304].view(np.float32).reshape(
             self.n_chunks, 9, 64).transpose(0, 2, 1).reshape(
             self.n_chunks, 64, 3, 3)

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cellmech.h"
+#include "cellmech.h"
 #include "kernels.h"
 #include "prep.h"
 
@@ -37,7 +37,7 @@ struct cm_batch_s {
   int device = 0;
   int n_cu = 256;
   int64_t n_cells = 0, n_nodes = 0, n_tets = 0, n_slots = 0, n_shared = 0;
-  int64_t n_tiles = 0;
+  int64_t n_tiles = 0, n_chunks = 0;
   int32_t tile_tets = 0, max_tile_nodes = 0;
   double volume = 0, min_v0 = 0, max_cond = 0;
   std::vector<int32_t> cell_tile_off, cell_shared_off;
@@ -163,6 +163,7 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
   h->n_slots = (int64_t)P.slot_node.size();
   h->n_shared = (int64_t)P.shared_node.size();
   h->n_tiles = (int64_t)P.tiles.size();
+  h->n_chunks = (int64_t)P.chunks.size();
   h->tile_tets = po.tile_tets;
   h->max_tile_nodes = P.max_tile_nodes;
   h->volume = P.volume;
@@ -245,6 +246,7 @@ int cm_get_info(cm_batch h, cm_info* o) {
   o->n_tiles = h->n_tiles;
   o->n_shared = h->n_shared;
   o->n_slots = h->n_slots;
+  o->n_chunks = h->n_chunks;
   o->tile_tets = h->tile_tets;
   o->max_tile_nodes = h->max_tile_nodes;
   o->device_bytes = h->device_bytes;
@@ -494,6 +496,44 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   if (rc != CM_OK) return rc;
   if (cache_path) cache_store(cache_path, key, best_w, best_b, best_ms);
   return cm_set_launch(h, best_w, best_b);
+}
+
+int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
+                       const float* fbar, const double* ebar, float* ybar,
+                       double* thetabar, int32_t reps, double* ms,
+                       hipStream_t st) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !f || !ybar || !ms || reps <= 0)
+    return fail(CM_EINVAL, "y, f, ybar, ms must be non-null and reps > 0");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (!lds_fits(h, h->cfg.waves, true) || !lds_fits(h, h->cfg.waves, false))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  const cm::Range r = full_range(h);
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i) CM_HIP(hipEventCreate(&ev[i]));
+  int rc = CM_OK;
+  for (int k = 0; k < 4 && rc == CM_OK; ++k) {
+    auto once = [&]() -> hipError_t {
+      switch (k) {
+        case 0: return cm::launch_forward_main(h->T, r, h->cfg, y, f, st);
+        case 1: return cm::launch_forward_finalize(h->T, r, f, energy, nullptr, st);
+        case 2: return cm::launch_backward_main(h->T, r, h->cfg, y, fbar, ebar, ybar, st);
+        default: return cm::launch_backward_finalize(h->T, r, ybar, thetabar, st);
+      }
+    };
+    hipError_t e = once();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ev[k], st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = once();
+    if (e == hipSuccess) e = hipEventRecord(ev[k + 1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[k + 1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+    if (e != hipSuccess) rc = fail(CM_EHIP, std::string("profile: ") + hipGetErrorString(e));
+    ms[k] = (double)t / reps;
+  }
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  return rc;
 }
 
 int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,

@@ -1,9 +1,203 @@
+// Backward (adjoint) kernels for gfx950: for a loss L(f, E) with cotangents
+// fbar = dL/df (per node) and ebar = dL/dE (per cell),
+//   ybar     = (df/dy)^T fbar - ebar f  (a Hessian-vector product of E),
+//   thetabar = dL/d(mu, kappa, w) per cell.
+// Same tiling as the forward kernel: one wavefront per tile; positions and
+// fbar of the tile's nodes are staged in LDS, ybar is accumulated in LDS slot
+// by slot without atomics (see layout.h), owned nodes are stored directly and
+// shared nodes go through the slot partials and the finalize kernel, in a
+// fixed order (deterministic).
 #include <hip/hip_runtime.h>
+
+#include "device_util.h"
 #include "kernels.h"
+#include "mr_tet.h"
+
 namespace cm {
-size_t backward_lds_per_wave(int nloc) { return (size_t)44 * nloc; }
-hipError_t launch_backward(const DeviceTables&, const Range&, const LaunchCfg&, const float*,
-                           const float*, const double*, float*, double*, hipStream_t) {
-  return hipErrorNotSupported;
+namespace {
+
+struct BwdArgs {
+  DeviceTables T;
+  Range r;
+  const float* y;
+  const float* fbar;    // nullable
+  const double* ebar;   // nullable
+  float* ybar;
+};
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
+  extern __shared__ float4 lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nloc = a.T.nloc;
+  // per wave: positions, fbar and ybar accumulators, one float4 each
+  float4* ys = lds + (size_t)wave * 3 * nloc;
+  float4* vs = ys + nloc;
+  float4* gs = vs + nloc;
+  const int64_t N = a.T.n_nodes, S = a.T.n_slots;
+  const bool has_fbar = a.fbar != nullptr;
+
+  int t0, t1;
+  block_tiles(a.r, t0, t1);
+  for (int t = t0 + wave; t < t1; t += W) {
+    const TileDesc d = a.T.tiles[t];
+    const int nc = a.T.n_cells;
+    const double mu = a.T.params[d.cell];
+    const double kappa = a.T.params[nc + d.cell];
+    const double w = a.T.params[2 * nc + d.cell];
+    const Material mat{w * mu, (1.0 - w) * mu, kappa};
+    const double eb = a.ebar ? a.ebar[d.cell] : 0.0;
+
+    for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
+      const int64_t g = l < d.n_own ? (int64_t)d.own_begin + l
+                                    : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
+      ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], 0.f);
+      vs[l] = has_fbar ? make_float4(a.fbar[g], a.fbar[N + g], a.fbar[2 * N + g], 0.f)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+      gs[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    wave_sync();
+
+    double acc[3] = {0.0, 0.0, 0.0};
+    const TetChunk* ch = a.T.chunks + d.chunk_begin;
+    for (int k = 0; k < d.n_chunks; ++k, ++ch) {
+      const uint2 q = *reinterpret_cast<const uint2*>(ch->idx[lane]);
+      float B[9];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) B[m] = ch->B[m][lane];
+      const float V0 = ch->V0[lane];
+      if (q.x != kEmptyLane) {
+        const int i0 = q.x & 0xffff, i1 = q.x >> 16;
+        const int i2 = q.y & 0xffff, i3 = q.y >> 16;
+        const float4 p0 = ys[i0], p1 = ys[i1], p2 = ys[i2], p3 = ys[i3];
+        const float4 v0 = vs[i0], v1 = vs[i1], v2 = vs[i2], v3 = vs[i3];
+        const float e[3][3] = {{p0.x - p3.x, p0.y - p3.y, p0.z - p3.z},
+                               {p1.x - p3.x, p1.y - p3.y, p1.z - p3.z},
+                               {p2.x - p3.x, p2.y - p3.y, p2.z - p3.z}};
+        const float dv[3][3] = {{v0.x - v3.x, v0.y - v3.y, v0.z - v3.z},
+                                {v1.x - v3.x, v1.y - v3.y, v1.z - v3.z},
+                                {v2.x - v3.x, v2.y - v3.y, v2.z - v3.z}};
+        float h[3][3];
+        double gt[3];
+        tet_backward(e, dv, B, V0, mat, eb, h, gt);
+        lds_accumulate(gs, i0, i1, i2, i3, h);
+        acc[0] += gt[0];
+        acc[1] += gt[1];
+        acc[2] += gt[2];
+      }
+    }
+    wave_sync();
+
+    for (int i = lane; i < d.n_own; i += 64) {
+      const int64_t g = d.own_begin + i;
+      const float4 v = gs[i];
+      a.ybar[g] = v.x; a.ybar[N + g] = v.y; a.ybar[2 * N + g] = v.z;
+    }
+    for (int j = lane; j < d.n_shr; j += 64) {
+      const int64_t s = d.shr_begin + j;
+      const float4 v = gs[d.n_own + j];
+      a.T.part[s] = v.x; a.T.part[S + s] = v.y; a.T.part[2 * S + s] = v.z;
+    }
+    acc[0] = wave_sum(acc[0]);
+    acc[1] = wave_sum(acc[1]);
+    acc[2] = wave_sum(acc[2]);
+    if (lane == 0) {
+      a.T.tile_acc[3 * (int64_t)t] = acc[0];
+      a.T.tile_acc[3 * (int64_t)t + 1] = acc[1];
+      a.T.tile_acc[3 * (int64_t)t + 2] = acc[2];
+    }
+    wave_sync();
+  }
 }
+
+struct BwdFinArgs {
+  DeviceTables T;
+  Range r;
+  float* ybar;
+  double* thetabar;  // nullable
+};
+
+// Shared-node slot sums in tile order, and per cell
+//   dL/dmu = w g_I + (1 - w) g_K, dL/dkappa = g_J, dL/dw = mu (g_I - g_K)
+// from the per-tile sums of dL/d(mu1, mu2, kappa) (mu1 = w mu, mu2 = (1-w) mu).
+__global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = a.T.n_nodes, S = a.T.n_slots;
+  if (gid < a.r.shared_end - a.r.shared_begin) {
+    const int s = a.r.shared_begin + (int)gid;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
+      const int64_t sl = a.T.shared_slots[q];
+      sx += a.T.part[sl];
+      sy += a.T.part[S + sl];
+      sz += a.T.part[2 * S + sl];
+    }
+    const int64_t g = a.T.shared_node[s];
+    a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
+  }
+  if (a.thetabar && gid < a.r.cell_end - a.r.cell_begin) {
+    const int c = a.r.cell_begin + (int)gid;
+    double gI = 0.0, gK = 0.0, gJ = 0.0;
+    for (int t = a.T.cell_tile_off[c]; t < a.T.cell_tile_off[c + 1]; ++t) {
+      gI += a.T.tile_acc[3 * (int64_t)t];
+      gK += a.T.tile_acc[3 * (int64_t)t + 1];
+      gJ += a.T.tile_acc[3 * (int64_t)t + 2];
+    }
+    const int nc = a.T.n_cells;
+    const double mu = a.T.params[c], w = a.T.params[2 * nc + c];
+    a.thetabar[3 * (int64_t)c] = w * gI + (1.0 - w) * gK;
+    a.thetabar[3 * (int64_t)c + 1] = gJ;
+    a.thetabar[3 * (int64_t)c + 2] = mu * (gI - gK);
+  }
 }
+
+template <int W>
+hipError_t bwd_w(const BwdArgs& a, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(backward_kernel<W>, dim3(grid), dim3(64 * W), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t backward_lds_per_wave(int nloc) { return (size_t)48 * nloc; }
+
+hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
+                                const LaunchCfg& cfg, const float* y,
+                                const float* fbar, const double* ebar,
+                                float* ybar, hipStream_t st) {
+  if (r.tile_end <= r.tile_begin) return hipSuccess;
+  BwdArgs a{T, r, y, fbar, ebar, ybar};
+  const int grid = grid_for(r, cfg);
+  const size_t lds = backward_lds_per_wave(T.nloc) * cfg.waves;
+  switch (cfg.waves) {
+    case 1: return bwd_w<1>(a, grid, lds, st);
+    case 2: return bwd_w<2>(a, grid, lds, st);
+    case 4: return bwd_w<4>(a, grid, lds, st);
+    case 8: return bwd_w<8>(a, grid, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
+                                    float* ybar, double* thetabar,
+                                    hipStream_t st) {
+  const int64_t work = std::max<int64_t>(r.shared_end - r.shared_begin,
+                                         r.cell_end - r.cell_begin);
+  if (work <= 0) return hipSuccess;
+  BwdFinArgs b{T, r, ybar, thetabar};
+  hipLaunchKernelGGL(backward_finalize_kernel,
+                     dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const DeviceTables& T, const Range& r,
+                           const LaunchCfg& cfg, const float* y,
+                           const float* fbar, const double* ebar, float* ybar,
+                           double* thetabar, hipStream_t st) {
+  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st);
+  if (e != hipSuccess) return e;
+  return launch_backward_finalize(T, r, ybar, thetabar, st);
+}
+
+}  // namespace cm

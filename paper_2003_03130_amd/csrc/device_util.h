@@ -1,0 +1,79 @@
+// Device helpers shared by the forward and backward kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace cm {
+
+// LDS written by one lane is read by other lanes of the same wavefront only
+// after this point: LDS instructions of a wavefront execute in order, so a
+// compiler-level fence plus a wave barrier is enough.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Adds the contributions h[0..2] of vertex slots 0..2 and -(h0 + h1 + h2) of
+// slot 3 to the float4 accumulators acc[i_s].  The layout guarantees that
+// the active lanes of the wave name distinct nodes within each slot, so each
+// slot is one LDS read and one LDS write per lane with no races; slots are
+// processed in order (LDS instructions of a wavefront execute in order).
+__device__ __forceinline__ void lds_accumulate(float4* acc, int i0, int i1,
+                                               int i2, int i3,
+                                               const float h[3][3]) {
+  float4 v = acc[i0];
+  v.x += h[0][0]; v.y += h[0][1]; v.z += h[0][2];
+  acc[i0] = v;
+  v = acc[i1];
+  v.x += h[1][0]; v.y += h[1][1]; v.z += h[1][2];
+  acc[i1] = v;
+  v = acc[i2];
+  v.x += h[2][0]; v.y += h[2][1]; v.z += h[2][2];
+  acc[i2] = v;
+  v = acc[i3];
+  v.x -= h[0][0] + h[1][0] + h[2][0];
+  v.y -= h[0][1] + h[1][1] + h[2][1];
+  v.z -= h[0][2] + h[1][2] + h[2][2];
+  acc[i3] = v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of logical block ids so neighbouring tiles (which share
+// nodes) run under the same L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int x = b & 7, j = b >> 3, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// Tiles [t0, t1) of logical block lb out of G.
+__device__ __forceinline__ void block_tiles(const Range& r, int& t0, int& t1) {
+  const int G = gridDim.x;
+  const int lb = xcd_block(blockIdx.x, G);
+  const int64_t ntl = r.tile_end - r.tile_begin;
+  t0 = r.tile_begin + (int)((int64_t)lb * ntl / G);
+  t1 = r.tile_begin + (int)((int64_t)(lb + 1) * ntl / G);
+}
+
+inline int grid_for(const Range& r, const LaunchCfg& cfg) {
+  const int64_t ntl = r.tile_end - r.tile_begin;
+  const int64_t groups = (ntl + cfg.waves - 1) / cfg.waves;
+  int64_t g = cfg.blocks > 0 ? std::min<int64_t>(cfg.blocks, groups) : groups;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+}  // namespace cm

@@ -42,6 +42,21 @@ struct LaunchCfg {
 size_t forward_lds_per_wave(int nloc);
 size_t backward_lds_per_wave(int nloc);
 
+// The two kernels of each pass, separately (for per-kernel timing).
+hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
+                               const LaunchCfg& cfg, const float* y, float* f,
+                               hipStream_t st);
+hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
+                                   float* f, double* energy, int32_t* ninv,
+                                   hipStream_t st);
+hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
+                                const LaunchCfg& cfg, const float* y,
+                                const float* fbar, const double* ebar,
+                                float* ybar, hipStream_t st);
+hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
+                                    float* ybar, double* thetabar,
+                                    hipStream_t st);
+
 hipError_t launch_forward(const DeviceTables& T, const Range& r,
                           const LaunchCfg& cfg, const float* y, float* f,
                           double* energy, int32_t* ninv, hipStream_t st);

@@ -1,15 +1,15 @@
 // Device data layout of a prepared batch of tetrahedral cells.
 //
 // Tetrahedra are grouped into tiles of at most `tile_tets` tetrahedra, one
-// wavefront (64 lanes) per tile.  A tile's distinct vertices ("tile nodes")
+// wavefront (64 lanes) per tile, processed 64 at a time ("chunks").  A tile's distinct vertices ("tile nodes")
 // are staged in LDS; the tile's tetrahedra refer to them by 16-bit local
 // index.  Nodes touched by exactly one tile are "owned" and numbered so that
 // each tile's owned nodes form one contiguous internal range: the tile loads
 // their positions and stores their forces with plain coalesced accesses.
 // Nodes touched by several tiles are "shared": every (tile, shared node) pair
 // is a "slot"; the tile writes its partial force to the slot, and a second
-// pass sums the slots of each shared node in tile order.  No floating-point
-// global atomics are used and the result is deterministic.
+// pass sums the slots of each shared node in tile order.  No atomics are used
+// anywhere and the result is deterministic.
 #pragma once
 #include <cstdint>
 
@@ -27,11 +27,20 @@ struct TileDesc {
   int32_t shr_begin;    // first slot of the tile
   int32_t n_shr;        // shared nodes: local indices [n_own, n_own + n_shr)
   int32_t cell;         // cell the tile belongs to
-  int32_t pad;
+  int32_t n_chunks;     // chunks of the tile (lanes without a tetrahedron
+                        // carry kEmptyLane in idx[lane][0])
 };
+
+// Marks a chunk lane that holds no tetrahedron.
+constexpr uint32_t kEmptyLane = 0xffffffffu;
 
 // 64 tetrahedra, structure of arrays inside the chunk (3072 bytes): every
 // lane of a wave reads its tetrahedron with fully coalesced loads.
+// Within a chunk the tetrahedra and the order of their vertices are chosen
+// so that, for each vertex slot 0..3, the 64 lanes name 64 different tile
+// nodes: the lanes of one wave can then add their contributions to the
+// tile's LDS accumulators slot by slot with plain read-modify-writes and no
+// two lanes of an instruction touch the same node.
 struct TetChunk {
   uint32_t idx[kChunk][2];  // 4 x uint16 local vertex indices (v0|v1<<16, v2|v3<<16)
   float B[9][kChunk];       // B = J^-1, row-major B[k][j], k = edge, j = axis

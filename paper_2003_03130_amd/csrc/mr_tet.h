@@ -146,4 +146,111 @@ __device__ __forceinline__ void tet_forward(const float e[3][3],
       h[k][i] = P[i][0] * B[3 * k] + P[i][1] * B[3 * k + 1] + P[i][2] * B[3 * k + 2];
 }
 
+// d(cof F) along dF: the columns of cof F are cross products of the other
+// two columns of F (cyclic), so each derivative column is a sum of two
+// cross products.
+__device__ __forceinline__ void cofactor_dir(const float F[3][3],
+                                             const float D[3][3],
+                                             float R[3][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    // cross(D[:,a], F[:,b]) + cross(F[:,a], D[:,b])
+    R[0][c] = D[1][a] * F[2][b] - D[2][a] * F[1][b] + F[1][a] * D[2][b] - F[2][a] * D[1][b];
+    R[1][c] = D[2][a] * F[0][b] - D[0][a] * F[2][b] + F[2][a] * D[0][b] - F[0][a] * D[2][b];
+    R[2][c] = D[0][a] * F[1][b] - D[1][a] * F[0][b] + F[0][a] * D[1][b] - F[1][a] * D[0][b];
+  }
+}
+
+// Backward of one tetrahedron for a loss L(f, E):
+//   dF = D_fbar B is the direction of the Hessian-vector product (the forces
+//   are -grad E, so (df/dy)^T fbar = d/de f(y + e fbar));
+//   h[k][i] = (-V0 (dP[dF] - ebar P) B^T)_ik, the contribution to ybar of
+//   vertices k = 0..2 (vertex 3 takes the negative sum);
+//   g = dL/d(mu1, mu2, kappa) of this tetrahedron.  P is linear in
+//   (mu1, mu2, kappa): P = mu1 P_I + mu2 P_K + kappa P_J, so
+//   g_I = V0 (-<P_I, dF> + ebar (I - 3)/2), g_K likewise with K, and
+//   g_J = V0 (-(J - 1) <cof F, dF> + ebar (J - 1)^2 / 2).
+__device__ __forceinline__ void tet_backward(const float e[3][3],
+                                             const float dv[3][3],
+                                             const float B[9], float V0,
+                                             const Material& m, double ebar,
+                                             float h[3][3], double g[3]) {
+  float F[3][3], dF[3][3], Cf[6];
+  deformation_gradient(e, B, F);
+  deformation_gradient(dv, B, dF);
+  Scalars s;
+  invariants(F, Cf, s);
+  float K[3][3], FC[3][3];
+  cofactor(F, K);
+  times_sym(F, Cf, FC);
+  float fF = 0.f, fFC = 0.f, fK = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      fF += F[i][j] * dF[i][j];
+      fFC += FC[i][j] * dF[i][j];
+      fK += K[i][j] * dF[i][j];
+    }
+  // directional derivatives of tr C, tr C^2, J and I2 = (trC^2 - trC2)/2
+  const double dTC = 2.0 * (double)fF;
+  const double dTC2 = 4.0 * (double)fFC;
+  const double dJ = (double)fK;
+  const double dI2 = s.TC * dTC - 0.5 * dTC2;
+  const double r3 = s.r2 * s.r;          // 1/J
+  const double r5 = s.r4 * s.r, r7 = r5 * s.r2;
+  const double dr2 = -(2.0 / 3.0) * r5 * dJ;   // d J^-2/3
+  const double dr4 = -(4.0 / 3.0) * r7 * dJ;   // d J^-4/3
+  const double a = m.mu1 * s.r2, b = m.mu2 * s.r4;
+  const double da = m.mu1 * dr2, db = m.mu2 * dr4;
+  const double c1 = a + b * s.TC, dc1 = da + db * s.TC + b * dTC;
+  const double c2 = -b, dc2 = -db;
+  const double q = -(a * s.TC + 2.0 * b * s.I2) * (1.0 / 3.0);
+  const double dq = -(da * s.TC + a * dTC + 2.0 * (db * s.I2 + b * dI2)) * (1.0 / 3.0);
+  const double Jm1 = s.J - 1.0;
+  const double c3 = q * r3 + m.kappa * Jm1;
+  const double dc3 = dq * r3 - q * (r3 * r3) * dJ + m.kappa * dJ;
+  const double nv = -(double)V0;
+  const float s1 = (float)(nv * (dc1 - ebar * c1)), t1 = (float)(nv * c1);
+  const float s2 = (float)(nv * (dc2 - ebar * c2)), t2 = (float)(nv * c2);
+  const float s3 = (float)(nv * (dc3 - ebar * c3)), t3 = (float)(nv * c3);
+
+  // dC = dF^T F + F^T dF (symmetric), d(FC) = dF C + F dC
+  float dC[6];
+  dC[0] = 2.f * (dF[0][0] * F[0][0] + dF[1][0] * F[1][0] + dF[2][0] * F[2][0]);
+  dC[1] = 2.f * (dF[0][1] * F[0][1] + dF[1][1] * F[1][1] + dF[2][1] * F[2][1]);
+  dC[2] = 2.f * (dF[0][2] * F[0][2] + dF[1][2] * F[1][2] + dF[2][2] * F[2][2]);
+  dC[3] = dF[0][0] * F[0][1] + dF[1][0] * F[1][1] + dF[2][0] * F[2][1] +
+          F[0][0] * dF[0][1] + F[1][0] * dF[1][1] + F[2][0] * dF[2][1];
+  dC[4] = dF[0][0] * F[0][2] + dF[1][0] * F[1][2] + dF[2][0] * F[2][2] +
+          F[0][0] * dF[0][2] + F[1][0] * dF[1][2] + F[2][0] * dF[2][2];
+  dC[5] = dF[0][1] * F[0][2] + dF[1][1] * F[1][2] + dF[2][1] * F[2][2] +
+          F[0][1] * dF[0][2] + F[1][1] * dF[1][2] + F[2][1] * dF[2][2];
+  float dFC[3][3], FdC[3][3], dK[3][3];
+  times_sym(dF, Cf, dFC);
+  times_sym(F, dC, FdC);
+  cofactor_dir(F, dF, dK);
+  float Q[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Q[i][j] = s1 * F[i][j] + t1 * dF[i][j] + s2 * FC[i][j] +
+                t2 * (dFC[i][j] + FdC[i][j]) + s3 * K[i][j] + t3 * dK[i][j];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      h[k][i] = Q[i][0] * B[3 * k] + Q[i][1] * B[3 * k + 1] + Q[i][2] * B[3 * k + 2];
+
+  const double vol = (double)V0;
+  const double pI = s.r2 * (0.5 * dTC - r3 * s.TC * dJ * (1.0 / 3.0));
+  const double pK = s.r4 * (0.5 * s.TC * dTC - 0.25 * dTC2 - (2.0 / 3.0) * s.I2 * r3 * dJ);
+  const double pJ = Jm1 * dJ;
+  g[0] = vol * (-pI + 0.5 * ebar * (s.TC * s.r2 - 3.0));
+  g[1] = vol * (-pK + 0.5 * ebar * (s.I2 * s.r4 - 3.0));
+  g[2] = vol * (-pJ + 0.5 * ebar * Jm1 * Jm1);
+}
+
 }  // namespace cm

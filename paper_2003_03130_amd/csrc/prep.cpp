@@ -11,7 +11,7 @@
 #include <numeric>
 #include <thread>
 
-#include "../../include/cellmech.h"
+#include "cellmech.h"
 
 namespace cm {
 namespace {
@@ -145,6 +145,53 @@ void rcm_order(int64_t n, int64_t m, const int32_t* T,
                    [&](int64_t a, int64_t b) { return key[a] < key[b]; });
 }
 
+// FP64 reference data of one tetrahedron with vertices v[0..3] (v[3] is the
+// local origin): J_ik = x_i^(v_k) - x_i^(v_3), B = J^-1 (row-major, B[k][j]),
+// returns det J.  Also the 1-norm condition number of J.
+double reference_inverse(const double* X, const int32_t v[4], double B[9],
+                         double* cond1) {
+  double Jm[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) Jm[i][k] = X[3 * (int64_t)v[k] + i] - X[3 * (int64_t)v[3] + i];
+  double adj[3][3];
+  adj[0][0] = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+  adj[0][1] = Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2];
+  adj[0][2] = Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1];
+  adj[1][0] = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+  adj[1][1] = Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0];
+  adj[1][2] = Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2];
+  adj[2][0] = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+  adj[2][1] = Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1];
+  adj[2][2] = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+  const double det = Jm[0][0] * adj[0][0] + Jm[0][1] * adj[1][0] + Jm[0][2] * adj[2][0];
+  double n1J = 0.0, n1B = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double sJ = 0.0, sB = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      B[3 * k + i] = adj[k][i] / det;
+      sJ += std::fabs(Jm[i][k]);
+      sB += std::fabs(adj[i][k] / det);
+    }
+    n1J = std::max(n1J, sJ);
+    n1B = std::max(n1B, sB);
+  }
+  if (cond1) *cond1 = n1J * n1B;
+  return det;
+}
+
+// The 24 assignments of the 4 vertices of a tetrahedron to the 4 slots.
+struct Perms {
+  int p[24][4];
+  Perms() {
+    int k = 0, a[4] = {0, 1, 2, 3};
+    do {
+      for (int i = 0; i < 4; ++i) p[k][i] = a[i];
+      ++k;
+    } while (std::next_permutation(a, a + 4));
+  }
+};
+const Perms kPerms;
+
 void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
                   const int32_t* T, const PrepOptions& opt, CellOut& out) {
   auto fail = [&](int st, const std::string& msg) {
@@ -169,40 +216,17 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
   for (int64_t q = 0; q < 3 * n; ++q)
     if (!std::isfinite(X[q])) return fail(CM_EINVAL, "non-finite reference position");
 
-  // FP64 precompute: J_ik = x_i^k - x_i^4, B = J^-1, V0 = |det J| / 6.
-  std::vector<double> B(9 * m), V0(m), absdet(m);
+  // FP64 precompute: J_ik = x_i^k - x_i^4, B = J^-1, V0 = |det J| / 6
+  // (checked and summarised here in the input vertex order; recomputed for
+  // the slot order when the chunks are packed).
+  std::vector<double> absdet(m);
   double hsum = 0.0;
   static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
   for (int64_t t = 0; t < m; ++t) {
     const int32_t* v = T + 4 * t;
-    double Jm[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 3; ++k) Jm[i][k] = X[3 * (int64_t)v[k] + i] - X[3 * (int64_t)v[3] + i];
-    double adj[3][3];
-    adj[0][0] = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
-    adj[0][1] = Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2];
-    adj[0][2] = Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1];
-    adj[1][0] = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
-    adj[1][1] = Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0];
-    adj[1][2] = Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2];
-    adj[2][0] = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
-    adj[2][1] = Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1];
-    adj[2][2] = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
-    double det = Jm[0][0] * adj[0][0] + Jm[0][1] * adj[1][0] + Jm[0][2] * adj[2][0];
-    absdet[t] = std::fabs(det);
-    double n1J = 0.0, n1B = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      double sJ = 0.0, sB = 0.0;
-      for (int i = 0; i < 3; ++i) {
-        B[9 * t + 3 * k + i] = adj[k][i] / det;
-        sJ += std::fabs(Jm[i][k]);
-        sB += std::fabs(adj[i][k] / det);
-      }
-      n1J = std::max(n1J, sJ);
-      n1B = std::max(n1B, sB);
-    }
-    V0[t] = absdet[t] / 6.0;
-    out.max_cond = std::max(out.max_cond, n1J * n1B);
+    double Bt[9], cond1;
+    absdet[t] = std::fabs(reference_inverse(X, v, Bt, &cond1));
+    out.max_cond = std::max(out.max_cond, cond1);
     for (auto& e : E) {
       double d2 = 0.0;
       for (int i = 0; i < 3; ++i) {
@@ -219,8 +243,8 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
       return fail(CM_EDEGENERATE, "tetrahedron " + std::to_string(t) +
                                       " is degenerate (|det J| = " +
                                       std::to_string(absdet[t]) + ")");
-    out.volume += V0[t];
-    out.min_v0 = std::min(out.min_v0, V0[t]);
+    out.volume += absdet[t] / 6.0;
+    out.min_v0 = std::min(out.min_v0, absdet[t] / 6.0);
   }
 
   // Locality order of the tetrahedra.
@@ -274,22 +298,19 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
   // Tiles, slots and chunks.
   out.tiles.resize(n_tiles);
   std::vector<int32_t> stamp(n, -1), loc(n, 0);
-  int64_t n_chunks = 0;
-  for (int64_t k = 0; k < n_tiles; ++k)
-    n_chunks += (std::min(m, (k + 1) * TT) - k * TT + kChunk - 1) / kChunk;
-  out.chunks.assign(n_chunks, TetChunk());
-  std::memset(out.chunks.data(), 0, sizeof(TetChunk) * n_chunks);
-  int64_t chunk = 0;
+  std::vector<std::vector<uint8_t>> used;  // per chunk: slot mask per tile node
+  std::vector<int32_t> cnt;
+  struct Placed { int32_t chunk, lane; int32_t v[4]; };
+  std::vector<Placed> placed;
   for (int64_t k = 0; k < n_tiles; ++k) {
     const int64_t p0 = k * TT, p1 = std::min(m, (k + 1) * TT);
     TileDesc& d = out.tiles[k];
-    d.chunk_begin = (int32_t)chunk;
+    d.chunk_begin = (int32_t)out.chunks.size();
     d.n_tets = (int32_t)(p1 - p0);
     d.own_begin = own_begin[k];
     d.n_own = n_own[k];
     d.shr_begin = (int32_t)out.slot_node.size();
     d.cell = c;
-    d.pad = 0;
     int32_t nsh = 0;
     for (int64_t p = p0; p < p1; ++p) {
       const int32_t* v = T + 4 * perm[p];
@@ -305,18 +326,73 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
       }
     }
     d.n_shr = nsh;
-    out.max_tile_nodes = std::max(out.max_tile_nodes, d.n_own + d.n_shr);
+    const int32_t nloc = d.n_own + d.n_shr;
+    out.max_tile_nodes = std::max(out.max_tile_nodes, nloc);
+
+    // Chunk assignment: tetrahedron p prefers chunk p mod nmin (neighbours
+    // in the locality order land in different chunks) and takes the first
+    // chunk with a free lane in which some assignment of its vertices to
+    // the 4 slots uses nodes not yet used in those slots; if none exists a
+    // chunk is added.
+    const int nmin = (int)((p1 - p0 + kChunk - 1) / kChunk);
+    used.assign(nmin, std::vector<uint8_t>(nloc, 0));
+    cnt.assign(nmin, 0);
+    placed.clear();
     for (int64_t p = p0; p < p1; ++p) {
-      int64_t t = perm[p];
-      const int32_t* v = T + 4 * t;
-      TetChunk& ch = out.chunks[chunk + (p - p0) / kChunk];
-      int lane = (int)((p - p0) % kChunk);
-      ch.idx[lane][0] = (uint32_t)loc[v[0]] | ((uint32_t)loc[v[1]] << 16);
-      ch.idx[lane][1] = (uint32_t)loc[v[2]] | ((uint32_t)loc[v[3]] << 16);
-      for (int q = 0; q < 9; ++q) ch.B[q][lane] = (float)B[9 * t + q];
-      ch.V0[lane] = (float)V0[t];
+      const int32_t* v = T + 4 * perm[p];
+      int32_t lv[4];
+      for (int a = 0; a < 4; ++a) lv[a] = loc[v[a]];
+      const int nc = (int)used.size();
+      const int c0 = (int)((p - p0) % nmin);
+      int chosen = -1, pi = -1;
+      for (int dc = 0; dc < nc && chosen < 0; ++dc) {
+        const int ch = (c0 + dc) % nc;
+        if (cnt[ch] >= kChunk) continue;
+        uint8_t mk[4];
+        for (int a = 0; a < 4; ++a) mk[a] = used[ch][lv[a]];
+        for (int q = 0; q < 24; ++q) {
+          const int* pm = kPerms.p[q];
+          if (!((mk[0] >> pm[0]) & 1) && !((mk[1] >> pm[1]) & 1) &&
+              !((mk[2] >> pm[2]) & 1) && !((mk[3] >> pm[3]) & 1)) {
+            chosen = ch;
+            pi = q;
+            break;
+          }
+        }
+      }
+      if (chosen < 0) {
+        used.emplace_back(nloc, 0);
+        cnt.push_back(0);
+        chosen = (int)used.size() - 1;
+        pi = 0;
+      }
+      const int* pm = kPerms.p[pi];
+      Placed pl;
+      pl.chunk = chosen;
+      pl.lane = cnt[chosen]++;
+      for (int a = 0; a < 4; ++a) {
+        used[chosen][lv[a]] |= (uint8_t)(1u << pm[a]);
+        pl.v[pm[a]] = v[a];  // vertex a goes to slot pm[a]
+      }
+      placed.push_back(pl);
     }
-    chunk += (p1 - p0 + kChunk - 1) / kChunk;
+    d.n_chunks = (int32_t)used.size();
+    const size_t base = out.chunks.size();
+    out.chunks.resize(base + used.size());
+    for (size_t q = base; q < out.chunks.size(); ++q) {
+      TetChunk& ch = out.chunks[q];
+      std::memset(&ch, 0, sizeof(TetChunk));
+      for (int l = 0; l < kChunk; ++l) ch.idx[l][0] = ch.idx[l][1] = kEmptyLane;
+    }
+    for (const Placed& pl : placed) {
+      TetChunk& ch = out.chunks[base + pl.chunk];
+      ch.idx[pl.lane][0] = (uint32_t)loc[pl.v[0]] | ((uint32_t)loc[pl.v[1]] << 16);
+      ch.idx[pl.lane][1] = (uint32_t)loc[pl.v[2]] | ((uint32_t)loc[pl.v[3]] << 16);
+      double Bt[9];
+      const double det = reference_inverse(X, pl.v, Bt, nullptr);
+      for (int q = 0; q < 9; ++q) ch.B[q][pl.lane] = (float)Bt[q];
+      ch.V0[pl.lane] = (float)(std::fabs(det) / 6.0);
+    }
   }
   // Shared node -> its slots, in tile order.
   out.shared_node.resize(n_shared);

@@ -46,17 +46,22 @@ def _batch(n_cells=5):
 
 
 def _decode_tets(L, b):
-    """Rebuild every tetrahedron (input numbering, cell-local) from the tiles."""
+    """Rebuild every tetrahedron (input numbering, cell-local, in the slot
+    order the layout chose) from the tiles: rows (cell, v0..v3, chunk, lane)."""
     out = []
     for t in range(L.n_tiles):
-        cb, nt, ob, no, sb, ns, cell, _ = L.tiles[t]
-        for k in range(nt):
-            loc = L.local_idx[cb + k // 64, k % 64]
-            internal = np.where(loc < no, ob + loc,
-                                L.slot_node[sb + np.minimum(loc - no, ns - 1)])
-            assert (loc < no + ns).all()
-            out.append((cell, *(L.new_to_old[internal] - b.node_off[cell]),
-                        cb + k // 64, k % 64))
+        cb, nt, ob, no, sb, ns, cell, nch = L.tiles[t]
+        count = 0
+        for c in range(cb, cb + nch):
+            for lane in np.flatnonzero(~L.empty[c]):
+                loc = L.local_idx[c, lane]
+                assert (loc < no + ns).all()
+                internal = np.where(loc < no, ob + loc,
+                                    L.slot_node[sb + np.minimum(loc - no, ns - 1)])
+                out.append((cell, *(L.new_to_old[internal] - b.node_off[cell]),
+                            c, lane))
+                count += 1
+        assert count == nt
     return np.array(out, dtype=np.int64)
 
 
@@ -72,20 +77,28 @@ def test_layout_is_a_relabelling_of_the_input(order, tile):
     for c in range(b.n_cells):
         seg = L.new_to_old[b.node_off[c]:b.node_off[c + 1]]
         assert seg.min() >= b.node_off[c] and seg.max() < b.node_off[c + 1]
-    # every input tetrahedron (with its vertex order) exactly once
+    # every input tetrahedron exactly once (its vertices may be reordered)
     rec = _decode_tets(L, b)
-    got = rec[:, :5]
+    got = np.concatenate([rec[:, :1], np.sort(rec[:, 1:5], axis=1)], axis=1)
     cell_of_tet = np.repeat(np.arange(b.n_cells), np.diff(b.tet_off))
-    want = np.concatenate([cell_of_tet[:, None], b.tets], axis=1)
+    want = np.concatenate([cell_of_tet[:, None], np.sort(b.tets, axis=1)],
+                          axis=1)
     got_s = got[np.lexsort(got.T[::-1])]
     want_s = want[np.lexsort(want.T[::-1])]
     assert np.array_equal(got_s, want_s)
     # tiles stay within a cell and hold at most tile_tets tetrahedra
     assert (L.tiles[:, 1] <= tile).all() and (L.tiles[:, 1] > 0).all()
+    # within a chunk, each vertex slot names distinct nodes (the kernels add
+    # slot by slot without atomics)
+    for c in range(L.n_chunks):
+        live = ~L.empty[c]
+        for slot in range(4):
+            ids = L.local_idx[c, live, slot]
+            assert len(np.unique(ids)) == len(ids), (c, slot)
     for c in range(b.n_cells):
         assert (L.tiles[L.cell_tile_off[c]:L.cell_tile_off[c + 1], 6] == c).all()
     # FP64-derived B and V0, stored in float32: B (x^k - x^4) = I
-    xg = b.x[b.node_off[got[:, 0]][:, None] + got[:, 1:5]]
+    xg = b.x[b.node_off[rec[:, 0]][:, None] + rec[:, 1:5]]
     Dm = np.stack([xg[:, k] - xg[:, 3] for k in range(3)], axis=2)
     Bst = L.B[rec[:, 5], rec[:, 6]].astype(np.float64)
     err = np.abs(Bst @ Dm - np.eye(3)).max(axis=(1, 2))
@@ -110,8 +123,7 @@ def test_owned_and_shared_tables_partition_the_nodes():
     # tiles touching each node, from the decoded tetrahedra
     rec = _decode_tets(L, b)
     touch = {}
-    tile_of_chunk = np.repeat(np.arange(L.n_tiles),
-                              (L.tiles[:, 1] + 63) // 64)
+    tile_of_chunk = np.repeat(np.arange(L.n_tiles), L.tiles[:, 7])
     internal = L.new_to_old.argsort()
     for row in rec:
         cell = row[0]
@@ -144,7 +156,7 @@ def test_layout_scatter_matches_direct_assembly():
     # through the layout
     out = np.full(b.n_nodes, np.nan)
     part = np.zeros(L.n_slots)
-    tile_of_chunk = np.repeat(np.arange(L.n_tiles), (L.tiles[:, 1] + 63) // 64)
+    tile_of_chunk = np.repeat(np.arange(L.n_tiles), L.tiles[:, 7])
     by_tile = {}
     for r, v in zip(rec, vals):
         by_tile.setdefault(tile_of_chunk[r[5]], []).append((r, v))
