@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--cells", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--tile-tets", type=int, default=1024)
-    ap.add_argument("--parity-cells", type=int, default=16)
+    ap.add_argument("--parity-cells", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-percell", action="store_true")

@@ -61,26 +61,22 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
 
     double acc[3] = {0.0, 0.0, 0.0};
     const TetChunk* ch = a.T.chunks + d.chunk_begin;
-    for (int k = 0; k < d.n_chunks; ++k, ++ch) {
-      const uint2 q = *reinterpret_cast<const uint2*>(ch->idx[lane]);
-      float B[9];
-#pragma unroll
-      for (int m = 0; m < 9; ++m) B[m] = ch->B[m][lane];
-      const float V0 = ch->V0[lane];
+    TetRegs nxt;
+    load_tet(ch, lane, nxt);
+    for (int k = 0; k < d.n_chunks; ++k) {
+      const TetRegs cur = nxt;
+      if (k + 1 < d.n_chunks) load_tet(ch + k + 1, lane, nxt);
+      const uint2 q = cur.q;
+      const float* B = cur.B;
+      const float V0 = cur.V0;
       if (q.x != kEmptyLane) {
         const int i0 = q.x & 0xffff, i1 = q.x >> 16;
         const int i2 = q.y & 0xffff, i3 = q.y >> 16;
         const float4 p0 = ys[i0], p1 = ys[i1], p2 = ys[i2], p3 = ys[i3];
         const float4 v0 = vs[i0], v1 = vs[i1], v2 = vs[i2], v3 = vs[i3];
-        const float e[3][3] = {{p0.x - p3.x, p0.y - p3.y, p0.z - p3.z},
-                               {p1.x - p3.x, p1.y - p3.y, p1.z - p3.z},
-                               {p2.x - p3.x, p2.y - p3.y, p2.z - p3.z}};
-        const float dv[3][3] = {{v0.x - v3.x, v0.y - v3.y, v0.z - v3.z},
-                                {v1.x - v3.x, v1.y - v3.y, v1.z - v3.z},
-                                {v2.x - v3.x, v2.y - v3.y, v2.z - v3.z}};
         float h[3][3];
         double gt[3];
-        tet_backward(e, dv, B, V0, mat, eb, h, gt);
+        tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, B, V0, mat, eb, h, gt);
         lds_accumulate(gs, i0, i1, i2, i3, h);
         acc[0] += gt[0];
         acc[1] += gt[1];

@@ -16,6 +16,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// One lane's tetrahedron of a chunk: packed local indices, B and V0.
+struct TetRegs {
+  uint2 q;
+  float B[9];
+  float V0;
+};
+
+__device__ __forceinline__ void load_tet(const TetChunk* ch, int lane,
+                                         TetRegs& r) {
+  r.q = *reinterpret_cast<const uint2*>(ch->idx[lane]);
+#pragma unroll
+  for (int m = 0; m < 9; ++m) r.B[m] = ch->B[m][lane];
+  r.V0 = ch->V0[lane];
+}
+
 // Adds the contributions h[0..2] of vertex slots 0..2 and -(h0 + h1 + h2) of
 // slot 3 to the float4 accumulators acc[i_s].  The layout guarantees that
 // the active lanes of the wave name distinct nodes within each slot, so each

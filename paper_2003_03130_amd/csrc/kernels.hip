@@ -55,23 +55,24 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     double eacc = 0.0;
     int ninv = 0;
     const TetChunk* ch = a.T.chunks + d.chunk_begin;
-    for (int k = 0; k < d.n_chunks; ++k, ++ch) {
-      const uint2 q = *reinterpret_cast<const uint2*>(ch->idx[lane]);
-      float B[9];
-#pragma unroll
-      for (int m = 0; m < 9; ++m) B[m] = ch->B[m][lane];
-      const float V0 = ch->V0[lane];
+    // software pipeline: the next chunk's loads are in flight while the
+    // current chunk is evaluated
+    TetRegs nxt;
+    load_tet(ch, lane, nxt);
+    for (int k = 0; k < d.n_chunks; ++k) {
+      const TetRegs cur = nxt;
+      if (k + 1 < d.n_chunks) load_tet(ch + k + 1, lane, nxt);
+      const uint2 q = cur.q;
+      const float* B = cur.B;
+      const float V0 = cur.V0;
       if (q.x != kEmptyLane) {
         const int i0 = q.x & 0xffff, i1 = q.x >> 16;
         const int i2 = q.y & 0xffff, i3 = q.y >> 16;
         const float4 p0 = ys[i0], p1 = ys[i1], p2 = ys[i2], p3 = ys[i3];
-        const float e[3][3] = {{p0.x - p3.x, p0.y - p3.y, p0.z - p3.z},
-                               {p1.x - p3.x, p1.y - p3.y, p1.z - p3.z},
-                               {p2.x - p3.x, p2.y - p3.y, p2.z - p3.z}};
         float h[3][3];
         double vU;
         bool inv;
-        tet_forward(e, B, V0, mat, h, vU, inv);
+        tet_forward(p0, p1, p2, p3, B, V0, mat, h, vU, inv);
         lds_accumulate(fs, i0, i1, i2, i3, h);
         eacc += vU;
         ninv += inv ? 1 : 0;

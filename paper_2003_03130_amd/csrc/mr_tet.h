@@ -14,12 +14,15 @@
 //   c1 = mu1 J^-2/3 + mu2 J^-4/3 T_C,  c2 = -mu2 J^-4/3,
 //   c3 = -(mu1 J^-2/3 T_C + 2 mu2 J^-4/3 I2) / (3 J) + kappa (J - 1).
 //
-// Precision: the 3x3 tensor algebra is float32; the invariants, the powers of
-// J, the energy density and the coefficients c1..c3 are float64 (their inputs
-// are the float32 entries of F, so T_C, tr(C^2) and det F are exact to double
-// rounding, and I - 3, K - 3, J - 1 carry no float32 cancellation).
-// J^-1/3 is the reciprocal of the real (sign-preserving) cube root: a float32
-// hardware log2/exp2 seed refined by one Newton step in float64.
+// Precision: the edge vectors y^k - y^4 and F = D_s B are formed in float64
+// (the difference of two float32 positions is exact in float64, so F is the
+// exact product of the float32 inputs up to one float64 rounding; a float32
+// edge or product would amplify rounding by the condition number of the
+// reference tetrahedron).  The invariants, the powers of J, the energy
+// density and the coefficients c1..c3 are float64; the remaining 3x3 tensor
+// algebra (F C, cof F, P B^T) is float32.  J^-1/3 is the reciprocal of the
+// real (sign-preserving) cube root: a float32 hardware log2/exp2 seed
+// refined by one Newton step in float64.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -44,15 +47,10 @@ struct Scalars {
   double TC, TC2, J, r, r2, r4, I2;
 };
 
-// Float64 invariants of a float32 deformation gradient.
-__device__ __forceinline__ void invariants(const float F[3][3], float Cf[6],
+// Float64 invariants of the float64 deformation gradient f; Cf receives
+// C = F^T F rounded to float32 (C00 C11 C22 C01 C02 C12).
+__device__ __forceinline__ void invariants(const double f[3][3], float Cf[6],
                                            Scalars& s) {
-  double f[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) f[i][j] = (double)F[i][j];
-  // C = F^T F: C00 C11 C22 C01 C02 C12
   const double C00 = f[0][0] * f[0][0] + f[1][0] * f[1][0] + f[2][0] * f[2][0];
   const double C11 = f[0][1] * f[0][1] + f[1][1] * f[1][1] + f[2][1] * f[2][1];
   const double C22 = f[0][2] * f[0][2] + f[1][2] * f[1][2] + f[2][2] * f[2][2];
@@ -98,27 +96,53 @@ __device__ __forceinline__ void times_sym(const float F[3][3], const float C[6],
   }
 }
 
-// F = D_s B, D_s columns = edges e[k] = y^k - y^4.
-__device__ __forceinline__ void deformation_gradient(const float e[3][3],
-                                                     const float B[9],
-                                                     float F[3][3]) {
+// F = D_s B in float64 from the float32 vertex positions p0..p3 (columns of
+// D_s are the edges y^k - y^4, exact in float64); f32 receives F rounded.
+__device__ __forceinline__ void deformation_gradient(
+    const float4& p0, const float4& p1, const float4& p2, const float4& p3,
+    const float B[9], double F[3][3], float f32[3][3]) {
+  const double e[3][3] = {
+      {(double)p0.x - (double)p3.x, (double)p0.y - (double)p3.y, (double)p0.z - (double)p3.z},
+      {(double)p1.x - (double)p3.x, (double)p1.y - (double)p3.y, (double)p1.z - (double)p3.z},
+      {(double)p2.x - (double)p3.x, (double)p2.y - (double)p3.y, (double)p2.z - (double)p3.z}};
+  double b[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) b[m] = (double)B[m];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      F[i][j] = e[0][i] * b[j] + e[1][i] * b[3 + j] + e[2][i] * b[6 + j];
+      f32[i][j] = (float)F[i][j];
+    }
+}
+
+// Direction dF = D_v B (float32) from the float32 cotangents v0..v3.
+__device__ __forceinline__ void direction_gradient(
+    const float4& v0, const float4& v1, const float4& v2, const float4& v3,
+    const float B[9], float D[3][3]) {
+  const float e[3][3] = {{v0.x - v3.x, v0.y - v3.y, v0.z - v3.z},
+                         {v1.x - v3.x, v1.y - v3.y, v1.z - v3.z},
+                         {v2.x - v3.x, v2.y - v3.y, v2.z - v3.z}};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      F[i][j] = e[0][i] * B[j] + e[1][i] * B[3 + j] + e[2][i] * B[6 + j];
+      D[i][j] = e[0][i] * B[j] + e[1][i] * B[3 + j] + e[2][i] * B[6 + j];
 }
 
 // Forward: forces h[k][i] on vertices k = 0..2 (vertex 3 takes the negative
 // sum) and the tetrahedron's energy V0 U (float64).
-__device__ __forceinline__ void tet_forward(const float e[3][3],
+__device__ __forceinline__ void tet_forward(const float4& p0, const float4& p1,
+                                            const float4& p2, const float4& p3,
                                             const float B[9], float V0,
                                             const Material& m, float h[3][3],
                                             double& vU, bool& inverted) {
+  double Fd[3][3];
   float F[3][3], Cf[6];
-  deformation_gradient(e, B, F);
+  deformation_gradient(p0, p1, p2, p3, B, Fd, F);
   Scalars s;
-  invariants(F, Cf, s);
+  invariants(Fd, Cf, s);
   inverted = !(s.J > 0.0);
   const double Jm1 = s.J - 1.0;
   const double U = 0.5 * m.mu1 * (s.TC * s.r2 - 3.0) +
@@ -171,16 +195,17 @@ __device__ __forceinline__ void cofactor_dir(const float F[3][3],
 //   (mu1, mu2, kappa): P = mu1 P_I + mu2 P_K + kappa P_J, so
 //   g_I = V0 (-<P_I, dF> + ebar (I - 3)/2), g_K likewise with K, and
 //   g_J = V0 (-(J - 1) <cof F, dF> + ebar (J - 1)^2 / 2).
-__device__ __forceinline__ void tet_backward(const float e[3][3],
-                                             const float dv[3][3],
-                                             const float B[9], float V0,
-                                             const Material& m, double ebar,
-                                             float h[3][3], double g[3]) {
+__device__ __forceinline__ void tet_backward(
+    const float4& p0, const float4& p1, const float4& p2, const float4& p3,
+    const float4& v0, const float4& v1, const float4& v2, const float4& v3,
+    const float B[9], float V0, const Material& m, double ebar, float h[3][3],
+    double g[3]) {
+  double Fd[3][3];
   float F[3][3], dF[3][3], Cf[6];
-  deformation_gradient(e, B, F);
-  deformation_gradient(dv, B, dF);
+  deformation_gradient(p0, p1, p2, p3, B, Fd, F);
+  direction_gradient(v0, v1, v2, v3, B, dF);
   Scalars s;
-  invariants(F, Cf, s);
+  invariants(Fd, Cf, s);
   float K[3][3], FC[3][3];
   cofactor(F, K);
   times_sym(F, Cf, FC);
