@@ -43,8 +43,16 @@ def log(msg):
           flush=True)
 
 
-def time_graph(cb, stream, steps, warmup):
+def time_graph(cb, stream, steps, warmup, ramp_s=0.0):
+    """ms per replay of the captured graph over `steps` timed replays, after
+    `warmup` untimed ones (and, if ramp_s > 0, untimed replays for about
+    ramp_s seconds first, so that clocks reach their loaded state)."""
     import torch
+    t_end = time.time() + ramp_s
+    while time.time() < t_end:
+        for _ in range(10):
+            cb.graph_launch(stream=stream)
+        torch.cuda.synchronize()
     for _ in range(warmup):
         cb.graph_launch(stream=stream)
     torch.cuda.synchronize()
@@ -61,6 +69,8 @@ def time_graph(cb, stream, steps, warmup):
 def parity(cb, b, f, E, ybar, tb, vbar, ebar, cells):
     """Max errors of sampled cells against the oracle (forward + backward)."""
     import oracle
+    if not cells:
+        return {"cells_checked": 0, "ok": None}
     fh, yh = cb.to_host(f), cb.to_host(ybar)
     Eh, th = E.cpu().numpy(), tb.cpu().numpy().reshape(-1, 3)
     worst = {"force": 0.0, "energy": 0.0, "ybar": 0.0, "thetabar": 0.0}
@@ -114,16 +124,21 @@ def cpu_baseline(b, vbar, ebar, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cells", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=3000)
-    ap.add_argument("--tile-tets", type=int, default=1024)
+    ap.add_argument("--tile-tets", type=int, default=768)
     ap.add_argument("--parity-cells", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-percell", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", type=str, default=None,
+                    help="fixed launch 'waves,blocks_per_cu' (skips autotune)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB "
+                         "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -160,7 +175,18 @@ def main():
     tb = torch.empty(3 * b.n_cells, dtype=torch.float64, device=dev)
     ninv = torch.empty(b.n_cells, dtype=torch.int32, device=dev)
 
-    if not args.no_autotune:
+    if args.calibrate_copy:
+        nf = args.calibrate_copy * 2 ** 20 // 4
+        src = torch.ones(nf, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + written")
+        del src, dst
+    if args.launch:
+        w_, b_ = (int(v) for v in args.launch.split(","))
+        cb.set_launch(w_, b_)
+    elif not args.no_autotune:
         t = time.time()
         launch = cb.autotune(y)
         log(f"autotuned launch (waves/block, blocks/CU) = {launch} in "
@@ -172,7 +198,8 @@ def main():
     cb.backward(y, fbar, ebar, ybar, tb)
     torch.cuda.synchronize()
     sample = sorted(set(np.linspace(0, b.n_cells - 1,
-                                    args.parity_cells).astype(int).tolist()))
+                                    args.parity_cells).astype(int).tolist())
+                    ) if args.parity_cells > 0 else []
     t = time.time()
     par = parity(cb, b, f, E, ybar, tb, vbar, ebar_h, sample)
     log(f"parity on {len(sample)} cells ({time.time() - t:.1f} s): {par}")
@@ -185,7 +212,7 @@ def main():
         with torch.cuda.stream(s):
             cb.graph_capture(mode, y, f, E, ninv, fbar, ebar, ybar, tb,
                              stream=s)
-        res[name] = time_graph(cb, s, args.steps, args.warmup)
+        res[name] = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
         log(f"batched {name}: {res[name]:.4f} ms/step")
     step_ms = res["fwd_bwd"]
     if not args.no_percell:

@@ -36,7 +36,10 @@
  *     contiguous and in the cell's own range of the input order.
  *   - Every compute call is asynchronous on the given stream, allocates no
  *     memory, and may be captured into a HIP graph.  A handle is not
- *     thread-safe; calls that overlap on one handle race.
+ *     thread-safe.  Forward calls (cm_forces*) and backward calls
+ *     (cm_forces_backward*) use separate scratch memory of the handle, so
+ *     one forward and one backward may run concurrently on two streams; two
+ *     forward calls (or two backward calls) that overlap race.
  *   - Every call returns CM_OK or a negative status; cm_last_error() gives a
  *     message (thread-local, valid until the next call on that thread).
  *   - Device pointers may not alias each other.
@@ -69,7 +72,7 @@ enum { CM_ORDER_INPUT = 0, CM_ORDER_RCM = 1, CM_ORDER_MORTON = 2 };
 typedef struct {
   int32_t order;          /* CM_ORDER_*; default CM_ORDER_MORTON             */
   int32_t tile_tets;      /* tetrahedra per tile, a multiple of 64 in        */
-                          /* [64, 4096]; 0 = default (1024)                   */
+                          /* [64, 4096]; 0 = default (768)                    */
   double degenerate_tol;  /* reject |det J| <= tol * h^3 with h the cell's   */
                           /* mean edge length; <= 0 means the default 1e-12  */
 } cm_options;
@@ -205,8 +208,10 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
  *   mode 2: the per-cell launches of mode 0 (single-cell baseline);
  *   mode 3: the per-cell launches of mode 1.
  * Pointers are captured as given and must stay valid while the graph is
- * used.  Re-capturing replaces the previous graph.  cm_graph_launch
- * replays it on `stream` (CM_ESTATE if nothing was captured).
+ * used.  In modes 1 and 3 the backward pass is a parallel branch of the
+ * graph (it reads y, fbar and ebar only).  Re-capturing replaces the
+ * previous graph.  cm_graph_launch replays it on `stream` (CM_ESTATE if
+ * nothing was captured).
  */
 int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
                      double* energy, int32_t* n_inverted, const float* fbar,

@@ -31,10 +31,11 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nloc = a.T.nloc;
-  // per wave: positions, fbar and ybar accumulators, one float4 each
-  float4* ys = lds + (size_t)wave * 3 * nloc;
-  float4* vs = ys + nloc;
-  float4* gs = vs + nloc;
+  // per wave (40 bytes per tile node): (y.x, y.y, y.z, fbar.x) as float4,
+  // ybar accumulators as float4, (fbar.y, fbar.z) as float2
+  float4* ys = lds + (size_t)wave * (10 * nloc / 4);
+  float4* gs = ys + nloc;
+  float2* vs = reinterpret_cast<float2*>(gs + nloc);
   const int64_t N = a.T.n_nodes, S = a.T.n_slots;
   const bool has_fbar = a.fbar != nullptr;
 
@@ -52,9 +53,10 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
       const int64_t g = l < d.n_own ? (int64_t)d.own_begin + l
                                     : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
-      ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], 0.f);
-      vs[l] = has_fbar ? make_float4(a.fbar[g], a.fbar[N + g], a.fbar[2 * N + g], 0.f)
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float vx = has_fbar ? a.fbar[g] : 0.f;
+      ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], vx);
+      vs[l] = has_fbar ? make_float2(a.fbar[N + g], a.fbar[2 * N + g])
+                       : make_float2(0.f, 0.f);
       gs[l] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
@@ -73,7 +75,11 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
         const int i0 = q.x & 0xffff, i1 = q.x >> 16;
         const int i2 = q.y & 0xffff, i3 = q.y >> 16;
         const float4 p0 = ys[i0], p1 = ys[i1], p2 = ys[i2], p3 = ys[i3];
-        const float4 v0 = vs[i0], v1 = vs[i1], v2 = vs[i2], v3 = vs[i3];
+        const float2 w0 = vs[i0], w1 = vs[i1], w2 = vs[i2], w3 = vs[i3];
+        const float4 v0 = make_float4(p0.w, w0.x, w0.y, 0.f);
+        const float4 v1 = make_float4(p1.w, w1.x, w1.y, 0.f);
+        const float4 v2 = make_float4(p2.w, w2.x, w2.y, 0.f);
+        const float4 v3 = make_float4(p3.w, w3.x, w3.y, 0.f);
         float h[3][3];
         double gt[3];
         tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, B, V0, mat, eb, h, gt);
@@ -156,7 +162,7 @@ hipError_t bwd_w(const BwdArgs& a, int grid, size_t lds, hipStream_t st) {
 
 }  // namespace
 
-size_t backward_lds_per_wave(int nloc) { return (size_t)48 * nloc; }
+size_t backward_lds_per_wave(int nloc) { return (size_t)40 * nloc; }
 
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,

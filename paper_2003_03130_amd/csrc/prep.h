@@ -10,7 +10,7 @@ namespace cm {
 
 struct PrepOptions {
   int order = 2;                // 0 input, 1 RCM, 2 Morton
-  int tile_tets = 1024;         // multiple of 64, <= kMaxTileTets
+  int tile_tets = 768;         // multiple of 64, <= kMaxTileTets
   double degenerate_tol = 1e-12;
 };
 
