@@ -121,6 +121,67 @@ def cpu_baseline(b, vbar, ebar, seconds):
                       f"(dual-number JVPs), single thread, {spent:.1f} s"}
 
 
+def hertz_targets(theta, top, radius=1.0):
+    """Synthetic force-indentation curves of the hidden parameters (Hertz
+    contact of a sphere between two plates, the paper's small-deformation
+    comparison): F = (4/3) E/(1 - nu^2) sqrt(R/2) (d/2)^(3/2), d = R - top,
+    with E and nu from the small-strain relations of Sec. "Theory"."""
+    mu, kappa = theta[:, 0], theta[:, 1]
+    E = 9 * kappa * mu / (3 * kappa + mu)
+    nu = (3 * kappa - 2 * mu) / (2 * (3 * kappa + mu))
+    d = np.clip(radius - np.asarray(top), 0, None)[:, None]
+    return 4.0 / 3.0 * (E / (1 - nu ** 2))[None, :] * np.sqrt(radius / 2) \
+        * (d / 2) ** 1.5
+
+
+def run_relax(args):
+    """Plate compression of 256 cells x ~51k tets over 200 steps: forward
+    sweep and checkpointed reverse-mode gradient (dL/d(mu, kappa, w))."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.relax import PlateCompression
+    from synth.configs import (DRAG, K_PLATE, STOKES_DT, compression_batch,
+                               plate_schedule)
+    t = time.time()
+    b = compression_batch(args.relax_cells, 9000, 5000, n_meshes=8)
+    log(f"relax workload: {b.n_cells} cells, {b.n_tets} tets "
+        f"({time.time() - t:.1f} s)")
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets,
+                   tile_tets=args.tile_tets)
+    top, bot = plate_schedule(args.relax_steps, compression=0.2)
+    pc = PlateCompression(cb, top, bot, K_PLATE, STOKES_DT / DRAG,
+                          checkpoint=20)
+    pc.set_theta(b.info["theta0"])
+    Ft = torch.from_numpy(hertz_targets(b.info["theta_star"], top)).to(cb.device)
+    y0 = cb.to_device(b.y)
+    scale = 1.0 / (args.relax_steps * b.n_cells)
+    pc.forward(y0)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    F, yN, _ = pc.forward(y0)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    loss, g, _ = pc.gradient(y0, Ft, scale)
+    torch.cuda.synchronize()
+    t_bptt = time.perf_counter() - t
+    M, N, S = b.n_tets, b.n_nodes, args.relax_steps
+    step_bytes = FWD_BYTES[0] * M + FWD_BYTES[1] * N + 36 * N
+    out = {
+        "workload": f"{b.n_cells} spheres, {M} tets, {N} nodes, {S} steps, "
+                    f"plates to 20% compression, checkpoint every 20",
+        "fwd_s": t_fwd, "bptt_s": t_bptt,
+        "fwd_tet_steps_per_s": M * S / t_fwd,
+        "bptt_tet_steps_per_s": M * S / t_bptt,
+        "fwd_step_hbm_frac": step_bytes * S / t_fwd / (HBM_PEAK_GBS * 1e9),
+        "loss": loss, "grad_finite": bool(torch.isfinite(g).all()),
+        "max_plate_force": float(F.max()),
+        "targets": "Hertz curves of hidden (mu, kappa, w)",
+    }
+    log(f"relax: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +197,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", type=str, default=None,
                     help="fixed launch 'waves,blocks_per_cu' (skips autotune)")
+    ap.add_argument("--relax-cells", type=int, default=256)
+    ap.add_argument("--relax-steps", type=int, default=200)
+    ap.add_argument("--no-relax", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
@@ -245,6 +309,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
+    relax = None
+    if not args.no_relax:
+        relax = run_relax(args)
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()
@@ -282,6 +350,7 @@ def main():
         "parity": par,
         "n_inverted": n_inverted,
         "cpu_baseline": cpu,
+        "relax": relax,
     }
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)

@@ -220,6 +220,42 @@ int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
 int cm_graph_launch(cm_batch h, hipStream_t stream);
 
 /*
+ * Plate compression (time-stepped relaxation).  The paper compresses cells
+ * between a resting and a moving plate with a repulsive force that keeps
+ * vertices out of the plates (Sec. "Simulation setup"); the force law and
+ * the time integration are in its unavailable supporting information.
+ * This library implements the reading (overdamped explicit steps, quadratic
+ * penalty):
+ *   p_z = -k max(0, y_z - top_c)^2 + k max(0, bottom_c - y_z)^2,
+ *   y_next = y + m (f + p),   force[c] = k sum_{nodes of c} max(0, y_z - top_c)^2,
+ * with f the elastic forces of cm_forces for the same y, k = k_plate and
+ * m = mobility (time step over drag).
+ *   plate   : device float64[2 * n_cells], (top_c, bottom_c) per cell.
+ *   y, f    : device float32[3 * n_nodes] SoA; y_next likewise (no aliasing).
+ *   force   : device float64[n_cells] out, nullable.
+ * cm_plate_step_adjoint gives the reverse-mode step for a loss that adds
+ * scale * (F_meas[c] - F_target[c])^2 per cell at this step (F_target
+ * nullable = no loss term, F_meas = the force of cm_plate_step at y):
+ *   lam = lam_next + m ((df/dy)^T lam_next + dp/dy lam_next)
+ *         + 2 scale (F_meas - F_target) dF/dy,
+ * where ybar_el = (df/dy)^T lam_next is cm_forces_backward(y, fbar =
+ * lam_next); and, if given, thetabar_acc[3c + j] += m thetabar_el[3c + j]
+ * (thetabar_el from the same cm_forces_backward call).  lam must not alias
+ * any input.  Errors: CM_EINVAL for null/aliased pointers or negative or
+ * non-finite k_plate / mobility.
+ */
+int cm_plate_step(cm_batch h, const float* y, const float* f,
+                  const double* plate, double k_plate, double mobility,
+                  float* y_next, double* force, hipStream_t stream);
+int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
+                          const float* ybar_el, const double* plate,
+                          double k_plate, double mobility,
+                          const double* F_meas, const double* F_target,
+                          double scale, const double* thetabar_el,
+                          double* thetabar_acc, float* lam,
+                          hipStream_t stream);
+
+/*
  * cm_profile_kernels: average device time of each kernel of one batched
  * forward + backward evaluation, measured with HIP events recorded on
  * `stream` around `reps` back-to-back launches of each kernel:

@@ -13,6 +13,10 @@ Routes (see the header of ``cm_oracle.cpp``):
                      parameter sensitivities)
   * ``backward``     reverse-mode cotangents of L(f, E)
   * ``jvp_nested``   second-order duals through O2 (cross-check of ``jvp``)
+  * ``relax_forward`` / ``relax_grad``  plate compression with explicit
+                     overdamped steps (a reading of the paper's unavailable
+                     supporting information; parity unpinned by the paper)
+                     and its parameter gradient by forward-mode duals
 """
 from __future__ import annotations
 
@@ -65,6 +69,13 @@ def lib(path: str = None):
         L.or_backward.restype = None
         L.or_forces_jvp_nested.argtypes = common + [_dp, _d, _d, _d, _dp]
         L.or_forces_jvp_nested.restype = None
+        L.or_relax_forward.argtypes = common + [_d, _d, _d, ctypes.c_int,
+                                                _dp, _d, _d, _d, _dp, _dp]
+        L.or_relax_forward.restype = None
+        L.or_relax_grad.argtypes = common + [_d, _d, _d, ctypes.c_int,
+                                             _dp, _d, _d, _d, _dp, _d, _dp,
+                                             _dp, _dp]
+        L.or_relax_grad.restype = None
         L.or_energy_density.argtypes = [_dp, _d, _d, _d]
         L.or_energy_density.restype = ctypes.c_double
         L.or_stress_table.argtypes = [_dp, _d, _d, _d, _dp]
@@ -169,6 +180,38 @@ class OracleMesh:
         self.L.or_forces_jvp_nested(*self._args(), _ptr(y), _ptr(vv), mu,
                                    kappa, w, _ptr(df))
         return df
+
+
+    def relax_forward(self, y0, theta, top, bottom, k_plate, mobility):
+        """Plate compression (reading of the missing supporting information):
+        per-step top-plate forces (N,) and final positions (N_nodes, 3)."""
+        y0 = self._y(y0)
+        top = _f64(top)
+        F = np.empty(len(top))
+        yf = np.empty_like(y0)
+        mu, kappa, w = theta
+        self.L.or_relax_forward(*self._args(), _ptr(y0), mu, kappa, w,
+                                len(top), _ptr(top), float(bottom),
+                                float(k_plate), float(mobility), _ptr(F),
+                                _ptr(yf))
+        return F, yf
+
+    def relax_grad(self, y0, theta, top, bottom, k_plate, mobility, F_target,
+                   scale):
+        """(loss, dL/d(mu, kappa, w), F) by forward-mode duals through all
+        steps, L = scale * sum_n (F_n - F_target[n])^2."""
+        y0 = self._y(y0)
+        top = _f64(top)
+        Ft = _f64(F_target)
+        F = np.empty(len(top))
+        g = np.empty(3)
+        loss = ctypes.c_double()
+        mu, kappa, w = theta
+        self.L.or_relax_grad(*self._args(), _ptr(y0), mu, kappa, w, len(top),
+                             _ptr(top), float(bottom), float(k_plate),
+                             float(mobility), _ptr(Ft), float(scale),
+                             ctypes.byref(loss), _ptr(g), _ptr(F))
+        return loss.value, g, F
 
 
 def energy_density(F, theta, lib_path: str = None) -> float:

@@ -38,6 +38,18 @@
 //      derivative of the forces (a Hessian-vector product of E, up to sign)
 //      and of forces/energy with respect to (mu, kappa, w).
 //  A second-order check of the Hessian-vector product runs O2 on nested duals.
+//
+// Plate compression (time-stepped relaxation): the paper compresses cells
+// between two plates with a repulsive force that keeps vertices out of the
+// plates (Sec. "Simulation setup") and defers the force law and the time
+// integration to its supporting information, which is not available.  The
+// reading implemented here (parity unpinned by the paper):
+//   y_{n+1} = y_n + m (f(y_n) + p(y_n; h_n)),       n = 0 .. N-1,
+//   p_z = -k max(0, y_z - h_n)^2 + k max(0, b - y_z)^2 (x, y components 0),
+//   F_n = k sum_vertices max(0, y_z - h_n)^2        (force on the top plate),
+// with top-plate heights h_n, bottom plate b, penalty k and mobility m.
+// Its gradient with respect to (mu, kappa, w) is taken by forward-mode dual
+// numbers through all steps (independent of any reverse-mode scheme).
 
 #include <cmath>
 #include <cstdint>
@@ -104,6 +116,9 @@ Dual<T, N> real_cbrt(const Dual<T, N>& a) {
   for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / den;
   return r;
 }
+
+inline double value_of(double a) { return a; }
+template <class T, int N> double value_of(const Dual<T, N>& a) { return value_of(a.v); }
 
 // ------------------------------------------------------------- 3x3 helpers
 template <class S>
@@ -321,6 +336,57 @@ bool check_indices(int64_t n_nodes, int64_t n_tets, const int32_t* tets) {
   return true;
 }
 
+// O1 over a whole mesh for any scalar type S (positions and parameters may
+// carry tangents); forces accumulated in tetrahedron order.
+template <class S>
+void o1_mesh(const View& m, const S* y, const S& mu1, const S& mu2,
+             const S& kappa, S* f) {
+  for (int64_t q = 0; q < 3 * m.n_nodes; ++q) f[q] = S(0.0);
+  for (int64_t t = 0; t < m.n_tets; ++t) {
+    double xt[4][3], Bt[3][3];
+    gather_ref(m, t, xt, Bt);
+    S yt[4][3], ft[4][3], U, J;
+    for (int a = 0; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) yt[a][i] = y[3 * (int64_t)m.tets[4 * t + a] + i];
+    o1_tet<S>(yt, xt, Bt, m.V0[t], mu1, mu2, kappa, ft, &U, &J);
+    for (int a = 0; a < 4; ++a)
+      for (int i = 0; i < 3; ++i) {
+        S& dst = f[3 * (int64_t)m.tets[4 * t + a] + i];
+        dst = dst + ft[a][i];
+      }
+  }
+}
+
+// The plate-compression run for scalar type S; returns F_n in F (n_steps).
+template <class S>
+void relax_run(const View& m, std::vector<S>& y, const S& mu1, const S& mu2,
+               const S& kappa, int n_steps, const double* top, double bottom,
+               double k, double mob, S* F) {
+  std::vector<S> f(3 * m.n_nodes);
+  for (int n = 0; n < n_steps; ++n) {
+    o1_mesh<S>(m, y.data(), mu1, mu2, kappa, f.data());
+    S Fn(0.0);
+    for (int64_t a = 0; a < m.n_nodes; ++a) {
+      S& z = y[3 * a + 2];
+      S pz(0.0);
+      if (value_of(z) > top[n]) {
+        S d = z - top[n];
+        pz = pz - k * d * d;
+        Fn = Fn + k * d * d;
+      }
+      if (value_of(z) < bottom) {
+        S d = bottom - z;
+        pz = pz + k * d * d;
+      }
+      // y_{n+1} = y_n + m (f + p), computed from the old state
+      y[3 * a] = y[3 * a] + mob * f[3 * a];
+      y[3 * a + 1] = y[3 * a + 1] + mob * f[3 * a + 1];
+      y[3 * a + 2] = z + mob * (f[3 * a + 2] + pz);
+    }
+    F[n] = Fn;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -509,6 +575,52 @@ void or_stress_table(const double* F9, double mu, double kappa, double w,
   // f_i^a = -V0 P_il B_al for a = 1..3 and B = I: P_ia = -f_i^a / V0.
   for (int i = 0; i < 3; ++i)
     for (int a = 0; a < 3; ++a) P9[3 * i + a] = -f[a][i] / V0;
+}
+
+// Plate compression of one cell (see the header): F_out[n] for n < n_steps
+// and the final positions (y_final, nullable).
+void or_relax_forward(int64_t n_nodes, int64_t n_tets, const double* x,
+                      const int32_t* tets, const double* B, const double* V0,
+                      const double* y0, double mu, double kappa, double w,
+                      int n_steps, const double* top, double bottom,
+                      double k_plate, double mobility, double* F_out,
+                      double* y_final) {
+  View m{n_nodes, n_tets, x, tets, B, V0};
+  std::vector<double> y(y0, y0 + 3 * n_nodes);
+  relax_run<double>(m, y, w * mu, (1.0 - w) * mu, kappa, n_steps, top, bottom,
+                    k_plate, mobility, F_out);
+  if (y_final) std::memcpy(y_final, y.data(), sizeof(double) * 3 * n_nodes);
+}
+
+// Loss L = scale * sum_n (F_n - F_target[n])^2 of the plate compression and
+// dL/d(mu, kappa, w) by forward-mode duals (three tangents) through all
+// steps.  F_out (nullable) receives F_n.
+void or_relax_grad(int64_t n_nodes, int64_t n_tets, const double* x,
+                   const int32_t* tets, const double* B, const double* V0,
+                   const double* y0, double mu, double kappa, double w,
+                   int n_steps, const double* top, double bottom,
+                   double k_plate, double mobility, const double* F_target,
+                   double scale, double* loss, double* dtheta, double* F_out) {
+  typedef Dual<double, 3> D;
+  View m{n_nodes, n_tets, x, tets, B, V0};
+  std::vector<D> y(3 * n_nodes);
+  for (int64_t q = 0; q < 3 * n_nodes; ++q) y[q] = D(y0[q]);
+  D dmu(mu), dka(kappa), dw(w);
+  dmu.d[0] = 1.0;
+  dka.d[1] = 1.0;
+  dw.d[2] = 1.0;
+  std::vector<D> F(n_steps);
+  relax_run<D>(m, y, dw * dmu, (1.0 - dw) * dmu, dka, n_steps, top, bottom,
+               k_plate, mobility, F.data());
+  double L = 0.0, g[3] = {0.0, 0.0, 0.0};
+  for (int n = 0; n < n_steps; ++n) {
+    const double r = F[n].v - F_target[n];
+    L += scale * r * r;
+    for (int k = 0; k < 3; ++k) g[k] += 2.0 * scale * r * F[n].d[k];
+    if (F_out) F_out[n] = F[n].v;
+  }
+  *loss = L;
+  for (int k = 0; k < 3; ++k) dtheta[k] = g[k];
 }
 
 }  // extern "C"

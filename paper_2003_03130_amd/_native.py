@@ -74,6 +74,12 @@ SIGNATURES = {
     "cm_graph_launch": (_int, [_vp, _vp]),
     "cm_profile_kernels": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _vp, _vp]),
+    "cm_plate_step": (_int, [_vp, _vp, _vp, _vp, ctypes.c_double,
+                             ctypes.c_double, _vp, _vp, _vp]),
+    "cm_plate_step_adjoint": (_int, [_vp, _vp, _vp, _vp, _vp,
+                                     ctypes.c_double, ctypes.c_double, _vp,
+                                     _vp, ctypes.c_double, _vp, _vp, _vp,
+                                     _vp]),
     "cm_layout_create": (_int, [_i32, _vp, _vp, _vp, _vp,
                                 ctypes.POINTER(Options), ctypes.POINTER(_vp)]),
     "cm_layout_sizes": (_int, [_vp, _p64]),

@@ -185,6 +185,23 @@ class CellBatch:
             _stream(stream)))
         return self.get_launch()
 
+    def plate_step(self, y, f, plate, k_plate, mobility, y_next, force=None,
+                   stream=None):
+        """y_next = y + m (f + plate penalty); force = per-cell top force."""
+        nat.check(nat.lib().cm_plate_step(
+            self._h, _ptr(y), _ptr(f), _ptr(plate), float(k_plate),
+            float(mobility), _ptr(y_next), _ptr(force), _stream(stream)))
+
+    def plate_step_adjoint(self, y, lam_next, ybar_el, plate, k_plate,
+                           mobility, lam, F_meas=None, F_target=None,
+                           scale=0.0, thetabar_el=None, thetabar_acc=None,
+                           stream=None):
+        nat.check(nat.lib().cm_plate_step_adjoint(
+            self._h, _ptr(y), _ptr(lam_next), _ptr(ybar_el), _ptr(plate),
+            float(k_plate), float(mobility), _ptr(F_meas), _ptr(F_target),
+            float(scale), _ptr(thetabar_el), _ptr(thetabar_acc), _ptr(lam),
+            _stream(stream)))
+
     def profile_kernels(self, y, f, energy, fbar, ebar, ybar, thetabar,
                         reps=10, stream=None):
         """Average ms per launch of the forward tile, forward finalize,

@@ -41,6 +41,7 @@ struct cm_batch_s {
   int32_t tile_tets = 0, max_tile_nodes = 0;
   double volume = 0, min_v0 = 0, max_cond = 0;
   std::vector<int32_t> cell_tile_off, cell_shared_off;
+  const int64_t* d_node_off = nullptr;  // device copy of the cell node offsets
   std::vector<int64_t> new_to_old;
   std::vector<void*> allocs;
   int64_t device_bytes = 0;
@@ -185,14 +186,17 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
     cm::TileDesc* tiles;
     cm::TetChunk* chunks;
     int32_t *slot_node, *shared_node, *ssp, *ss, *cto;
+    int64_t* noff;
     if ((rc = h->upload(&tiles, P.tiles, stream)) ||
         (rc = h->upload(&chunks, P.chunks, stream)) ||
         (rc = h->upload(&slot_node, P.slot_node, stream)) ||
         (rc = h->upload(&shared_node, P.shared_node, stream)) ||
         (rc = h->upload(&ssp, P.shared_slot_ptr, stream)) ||
         (rc = h->upload(&ss, P.shared_slots, stream)) ||
-        (rc = h->upload(&cto, P.cell_tile_off, stream)))
+        (rc = h->upload(&cto, P.cell_tile_off, stream)) ||
+        (rc = h->upload(&noff, P.node_off, stream)))
       return bail(rc);
+    h->d_node_off = noff;
     T.tiles = tiles;
     T.chunks = chunks;
     T.slot_node = slot_node;
@@ -526,6 +530,47 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   if (rc != CM_OK) return rc;
   if (cache_path) cache_store(cache_path, key, best_w, best_b, best_ms);
   return cm_set_launch(h, best_w, best_b);
+}
+
+int cm_plate_step(cm_batch h, const float* y, const float* f,
+                  const double* plate, double k_plate, double mobility,
+                  float* y_next, double* force, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !f || !plate || !y_next)
+    return fail(CM_EINVAL, "y, f, plate and y_next must be device pointers");
+  if (y_next == y || y_next == f)
+    return fail(CM_EINVAL, "y_next may not alias y or f");
+  if (!std::isfinite(k_plate) || !std::isfinite(mobility) || k_plate < 0 || mobility < 0)
+    return fail(CM_EINVAL, "k_plate and mobility must be finite and >= 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_plate_step(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y,
+                               f, plate, k_plate, mobility, y_next, force, stream));
+  return CM_OK;
+}
+
+int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
+                          const float* ybar_el, const double* plate,
+                          double k_plate, double mobility,
+                          const double* F_meas, const double* F_target,
+                          double scale, const double* thetabar_el,
+                          double* thetabar_acc, float* lam,
+                          hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !lam_next || !ybar_el || !plate || !lam)
+    return fail(CM_EINVAL, "y, lam_next, ybar_el, plate and lam must be device pointers");
+  if (lam == lam_next || lam == ybar_el || lam == y)
+    return fail(CM_EINVAL, "lam may not alias the inputs");
+  if (F_target && !F_meas) return fail(CM_EINVAL, "F_target needs F_meas");
+  if ((thetabar_el == nullptr) != (thetabar_acc == nullptr))
+    return fail(CM_EINVAL, "thetabar_el and thetabar_acc go together");
+  if (!std::isfinite(k_plate) || !std::isfinite(mobility) || k_plate < 0 || mobility < 0)
+    return fail(CM_EINVAL, "k_plate and mobility must be finite and >= 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_plate_adjoint(h->d_node_off, h->n_nodes, (int32_t)h->n_cells,
+                                  y, lam_next, ybar_el, plate, k_plate, mobility,
+                                  F_meas, F_target, scale, thetabar_el,
+                                  thetabar_acc, lam, stream));
+  return CM_OK;
 }
 
 int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,

@@ -66,4 +66,18 @@ hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const float* fbar, const double* ebar, float* ybar,
                            double* thetabar, hipStream_t st);
 
+// Plate compression step and its adjoint (one workgroup per cell).
+hipError_t launch_plate_step(const int64_t* node_off, int64_t N, int32_t n_cells,
+                             const float* y, const float* f, const double* plate,
+                             double k, double m, float* y_next, double* force,
+                             hipStream_t st);
+hipError_t launch_plate_adjoint(const int64_t* node_off, int64_t N,
+                                int32_t n_cells, const float* y,
+                                const float* lam_next, const float* ybar_el,
+                                const double* plate, double k, double m,
+                                const double* F_meas, const double* F_target,
+                                double scale, const double* thetabar_el,
+                                double* thetabar_acc, float* lam,
+                                hipStream_t st);
+
 }  // namespace cm

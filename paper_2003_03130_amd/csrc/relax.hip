@@ -1,0 +1,129 @@
+// Plate compression steps for gfx950 (forward and adjoint).
+//
+// The paper compresses cells between two plates with a repulsive force that
+// keeps vertices out of the plates; the force law and the time integration
+// are in its missing supporting information.  The reading implemented here:
+//   p_z = -k max(0, y_z - top)^2 + k max(0, bottom - y_z)^2,
+//   y_next = y + m (f + p),      F = k sum max(0, y_z - top)^2,
+// with f the elastic forces (cm_forces), k the plate penalty and m the
+// mobility (time step over drag).  One workgroup per cell: the cell's nodes
+// are contiguous in the internal order; each thread walks a fixed strided
+// subset and the per-cell force is reduced in a fixed tree order, so the
+// result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace cm {
+namespace {
+
+constexpr int kRelaxThreads = 1024;
+
+struct StepArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* y;
+  const float* f;
+  const double* plate;  // per cell: top, bottom
+  double k, m;
+  float* y_next;
+  double* force;
+};
+
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kRelaxThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(kRelaxThreads) void plate_step_kernel(StepArgs a) {
+  __shared__ double red[kRelaxThreads];
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1];
+  const float top = (float)a.plate[2 * c], bot = (float)a.plate[2 * c + 1];
+  const float k = (float)a.k, m = (float)a.m;
+  const int64_t N = a.N;
+  double acc = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads) {
+    const float z = a.y[2 * N + i];
+    const float dt = fmaxf(z - top, 0.f), db = fmaxf(bot - z, 0.f);
+    const float pz = k * (db * db - dt * dt);
+    a.y_next[i] = a.y[i] + m * a.f[i];
+    a.y_next[N + i] = a.y[N + i] + m * a.f[N + i];
+    a.y_next[2 * N + i] = z + m * (a.f[2 * N + i] + pz);
+    acc += (double)(k * dt * dt);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0 && a.force) a.force[c] = s;
+}
+
+struct AdjArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* y;
+  const float* lam_next;
+  const float* ybar_el;
+  const double* plate;
+  double k, m;
+  const double* F_meas;    // nullable (with F_target)
+  const double* F_target;  // nullable: no loss term at this step
+  double scale;
+  const double* thetabar_el;  // nullable (with thetabar_acc)
+  double* thetabar_acc;
+  float* lam;
+};
+
+// lam = lam_next + m ((df/dy)^T lam_next + dp/dy lam_next) + g dF/dy with
+// g = 2 scale (F_meas - F_target); dp_z/dy_z = -2k (max(0, z - top) +
+// max(0, bottom - z)), dF/dy_z = 2k max(0, z - top).
+__global__ __launch_bounds__(kRelaxThreads) void plate_adjoint_kernel(AdjArgs a) {
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1];
+  const float top = (float)a.plate[2 * c], bot = (float)a.plate[2 * c + 1];
+  const float k = (float)a.k, m = (float)a.m;
+  const float g = a.F_target ? (float)(2.0 * a.scale * (a.F_meas[c] - a.F_target[c])) : 0.f;
+  const int64_t N = a.N;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads) {
+    const float z = a.y[2 * N + i];
+    const float dt = fmaxf(z - top, 0.f), db = fmaxf(bot - z, 0.f);
+    const float lz = a.lam_next[2 * N + i];
+    a.lam[i] = a.lam_next[i] + m * a.ybar_el[i];
+    a.lam[N + i] = a.lam_next[N + i] + m * a.ybar_el[N + i];
+    a.lam[2 * N + i] = lz + m * (a.ybar_el[2 * N + i] - 2.f * k * (dt + db) * lz) +
+                       g * 2.f * k * dt;
+  }
+  if (threadIdx.x < 3 && a.thetabar_acc)
+    a.thetabar_acc[3 * c + threadIdx.x] += a.m * a.thetabar_el[3 * c + threadIdx.x];
+}
+
+}  // namespace
+
+hipError_t launch_plate_step(const int64_t* node_off, int64_t N, int32_t n_cells,
+                             const float* y, const float* f, const double* plate,
+                             double k, double m, float* y_next, double* force,
+                             hipStream_t st) {
+  StepArgs a{node_off, N, y, f, plate, k, m, y_next, force};
+  hipLaunchKernelGGL(plate_step_kernel, dim3(n_cells), dim3(kRelaxThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_plate_adjoint(const int64_t* node_off, int64_t N,
+                                int32_t n_cells, const float* y,
+                                const float* lam_next, const float* ybar_el,
+                                const double* plate, double k, double m,
+                                const double* F_meas, const double* F_target,
+                                double scale, const double* thetabar_el,
+                                double* thetabar_acc, float* lam,
+                                hipStream_t st) {
+  AdjArgs a{node_off, N, y, lam_next, ybar_el, plate, k, m, F_meas, F_target,
+            scale, thetabar_el, thetabar_acc, lam};
+  hipLaunchKernelGGL(plate_adjoint_kernel, dim3(n_cells), dim3(kRelaxThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace cm

@@ -231,3 +231,38 @@ def uneven_batch(n_cells=4096, seed=3000, tet_lo=500, tet_hi=20000,
     b = batch_from_cells(cells)
     b.info = {"ladder_tets": lad_m.tolist()}
     return b
+
+
+# ---------------------------------------------------------------- plates
+STOKES_DT = 1e-3      # time step of the compression runs
+DRAG = 0.25           # uniform nodal drag; mobility = STOKES_DT / DRAG
+K_PLATE = 100.0       # plate penalty in units of mu_ref / R^2 (mu_ref = 1)
+
+
+def plate_schedule(n_steps, radius=1.0, compression=0.8):
+    """Top-plate heights: linear from +R to R - 2 R compression over the
+    steps (80 % of the diameter by default); the bottom plate rests at -R."""
+    top = radius - 2.0 * radius * compression * np.arange(n_steps) / max(
+        n_steps - 1, 1)
+    return top, -radius
+
+
+def compression_batch(n_cells, n_target, seed, n_meshes=None):
+    """Spheres (R = 1) for the plate-compression runs, each with a hidden
+    parameter set theta* (seed) and a start theta0 (seed + 1), both drawn
+    like random_theta.  Meshes come from ``n_meshes`` distinct seeds (all
+    cells by default); every cell keeps its own arrays."""
+    n_meshes = n_meshes or n_cells
+    meshes = [sphere_mesh(n_target, seed + 17 * k) for k in range(n_meshes)]
+    r_star = np.random.default_rng(seed)
+    r_zero = np.random.default_rng(seed + 1)
+    cells, th0 = [], []
+    for c in range(n_cells):
+        x, tets = meshes[c % n_meshes]
+        cells.append(Cell(x.copy(), tets.copy(), x.astype(np.float32),
+                          random_theta(r_star)))
+        th0.append(random_theta(r_zero))
+    b = batch_from_cells(cells)
+    b.info = {"theta_star": b.theta.copy(),
+              "theta0": np.array(th0, dtype=np.float64)}
+    return b

@@ -444,8 +444,92 @@ def pin_thetabar(lib_path=None):
     assert rel_max(ybar, Hf - ebar * f) <= 1e-14
 
 
+# --------------------------------------------------- plate compression
+# The force law and the time integration of the compression runs come from a
+# reading of the paper's unavailable supporting information (see oracle/); the
+# pins below check the oracle's implementation of that reading for
+# consistency (gradient, rest state, descent, contact, momentum), not the
+# reading itself: parity of this part is unpinned by the paper.
+
+def _relax_cell():
+    key = ("relax",)
+    if key not in _cache:
+        from synth.configs import compression_batch
+        _cache[key] = compression_batch(1, 300, 5000).cell(0)
+    return _cache[key]
+
+
+RELAX = dict(bottom=-1.0, k_plate=100.0, mobility=0.004)
+
+
+def pin_relax_gradient_fd(lib_path=None):
+    """dL/d(mu, kappa, w) by forward-mode duals equals fourth-order central
+    differences of the FP64 loss."""
+    from synth.configs import plate_schedule
+    c = _relax_cell()
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    top, _ = plate_schedule(40, compression=0.1)
+    F, _ = m.relax_forward(c.x, c.theta, top, **RELAX)
+    Ft = 0.9 * F + 0.01
+    L, g, _ = m.relax_grad(c.x, c.theta, top, RELAX["bottom"],
+                           RELAX["k_plate"], RELAX["mobility"], Ft, 1 / 40)
+    assert np.isfinite(L) and L > 0
+    for k in range(3):
+        hk = 1e-5 * max(1.0, abs(c.theta[k]))
+
+        def loss(e, k=k):
+            th = list(c.theta)
+            th[k] += e
+            return ((m.relax_forward(c.x, th, top, **RELAX)[0] - Ft) ** 2).sum() / 40
+        assert abs(d1_5pt(loss, hk) - g[k]) <= 1e-6 * np.abs(g).max(), k
+
+
+def pin_relax_rest_state(lib_path=None):
+    """Plates away from the cell and y0 = x: no force, no motion."""
+    c = _relax_cell()
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    F, yf = m.relax_forward(c.x, c.theta, np.full(20, 2.0), -2.0, 100.0, 0.004)
+    assert np.abs(F).max() == 0.0
+    assert np.abs(yf - c.x).max() <= 1e-13
+
+
+def pin_relax_descent(lib_path=None):
+    """Without contact the steps are gradient descent on E: the energy drops
+    at every step, and the lateral center of mass stays put (elastic forces
+    sum to zero)."""
+    c = _relax_cell()
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    rng = np.random.default_rng(3)
+    y0 = c.x @ np.diag([1.1, 0.95, 0.9]).T + 0.01 * rng.normal(size=c.x.shape)
+    energies = []
+    for n in range(6):
+        _, yn = m.relax_forward(y0, c.theta, np.full(n, 5.0), -5.0, 100.0,
+                                0.004) if n else (None, y0)
+        energies.append(m.forces(yn, c.theta)[1])
+        if n:
+            assert np.abs(yn[:, :2].mean(0) - y0[:, :2].mean(0)).max() <= 1e-13
+    assert all(b < a for a, b in zip(energies, energies[1:])), energies
+
+
+def pin_relax_contact(lib_path=None):
+    """No force before the top plate reaches the cell, then a positive force
+    that grows while the plate descends."""
+    from synth.configs import plate_schedule
+    c = _relax_cell()
+    m = oracle.OracleMesh(c.x, c.tets, lib_path)
+    top, bot = plate_schedule(30, compression=0.1)
+    top = np.concatenate([[1.2, 1.1], top])
+    F, yf = m.relax_forward(c.x, c.theta, top, bot, 100.0, 0.004)
+    assert F[0] == 0.0 and F[1] == 0.0 and F[2] == 0.0   # plate at z >= R
+    assert (F[3:] > 0).all() and (np.diff(F[3:]) > 0).all()
+    # the force is repulsive: vertices stay (nearly) out of both plates
+    assert yf[:, 2].max() - top[-1] < 0.25
+    assert bot - yf[:, 2].min() < 0.25
+
+
 ALL_PINS = [pin_reference_configuration, pin_momentum_balance,
             pin_frame_indifference, pin_gradient_fd, pin_table_vs_ad,
             pin_homogeneous, pin_small_strain, pin_neo_hookean,
             pin_parameter_linearity, pin_worked_example, pin_two_tet_assembly,
-            pin_inverted_tet, pin_hvp_fd, pin_thetabar]
+            pin_inverted_tet, pin_hvp_fd, pin_thetabar, pin_relax_gradient_fd,
+            pin_relax_rest_state, pin_relax_descent, pin_relax_contact]

@@ -39,6 +39,12 @@ MUTANTS = [
     ("ybar_energy_sign", "ybar[q] -= ebar * f[q];", "ybar[q] += ebar * f[q];"),
     ("thetabar_w_not_tracked", "D mu1 = dw * dmu, mu2 = (1.0 - dw) * dmu;",
      "D mu1 = dw * dmu, mu2 = (1.0 - w) * dmu;"),
+    ("plate_penalty_sign", "pz = pz - k * d * d;", "pz = pz + k * d * d;"),
+    ("plate_step_uses_old_force_sign",
+     "y[3 * a + 2] = z + mob * (f[3 * a + 2] + pz);",
+     "y[3 * a + 2] = z - mob * (f[3 * a + 2] + pz);"),
+    ("relax_gradient_factor", "g[k] += 2.0 * scale * r * F[n].d[k];",
+     "g[k] += scale * r * F[n].d[k];"),
     ("left_instead_of_right_cauchy_green",
      "for (int m = 0; m < 3; ++m) s = s + F[m][k] * F[m][l];",
      "for (int m = 0; m < 3; ++m) s = s + F[k][m] * F[l][m];"),
