@@ -2,10 +2,11 @@
 discrete scheme (a reading of the paper's unavailable supporting
 information: the paper itself pins nothing here).
 
-Tolerances (max-normalised over a run): plate forces 1e-4, parameter
-gradient 1e-4.  They are looser than the single-evaluation 1e-5 because the
-float32 state carries a rounding of about 6e-8 relative per step, integrated
-over the run, against the float64 replay.
+Tolerances (max-normalised over a run): plate forces, final positions and
+the parameter gradient 1e-5, the bar of the single evaluation.  The float32
+state carries a rounding of about 6e-8 relative per step against the float64
+replay; over the 40 contracting steps of these runs the measured errors stay
+near 1e-6.
 """
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ from synth.configs import (DRAG, K_PLATE, STOKES_DT, compression_batch,
                            plate_schedule)
 
 pytestmark = pytest.mark.gpu
-TRAJ_TOL, GRAD_TOL = 1e-4, 1e-4
+TRAJ_TOL, GRAD_TOL = 1e-5, 1e-5
 MOB = STOKES_DT / DRAG
 
 
