@@ -206,12 +206,13 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
  *   mode 0: forward (cm_forces);
  *   mode 1: forward then backward (cm_forces, cm_forces_backward);
  *   mode 2: the per-cell launches of mode 0 (single-cell baseline);
- *   mode 3: the per-cell launches of mode 1.
+ *   mode 3: the per-cell launches of mode 1;
+ *   mode 4, 5: as 1, 3 but with the backward pass as a parallel branch of
+ *   the graph (it reads y, fbar and ebar only and has its own scratch), so
+ *   the two passes may overlap on the device.
  * Pointers are captured as given and must stay valid while the graph is
- * used.  In modes 1 and 3 the backward pass is a parallel branch of the
- * graph (it reads y, fbar and ebar only).  Re-capturing replaces the
- * previous graph.  cm_graph_launch replays it on `stream` (CM_ESTATE if
- * nothing was captured).
+ * used.  Re-capturing replaces the previous graph.  cm_graph_launch replays
+ * it on `stream` (CM_ESTATE if nothing was captured).
  */
 int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
                      double* energy, int32_t* n_inverted, const float* fbar,

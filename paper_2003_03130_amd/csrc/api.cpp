@@ -616,19 +616,20 @@ int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
                      const double* ebar, float* ybar, double* thetabar,
                      hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
-  if (mode < 0 || mode > 3) return fail(CM_EINVAL, "mode must be 0..3");
+  if (mode < 0 || mode > 5) return fail(CM_EINVAL, "mode must be 0..5");
   if (!stream) return fail(CM_EINVAL, "capture needs a non-null stream");
   if (int rc = select_device(h)) return rc;
   if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
   if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
   CM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  const bool percell = mode >= 2;
-  const bool bwd = mode == 1 || mode == 3;
+  const bool percell = mode == 2 || mode == 3 || mode == 5;
+  const bool bwd = mode == 1 || mode == 3 || mode >= 4;
+  const bool fork = mode >= 4;
   int rc = CM_OK;
   hipError_t e = hipSuccess;
-  if (bwd) {
+  if (fork) {
     // The backward pass reads y, fbar, ebar only (never the forward's
-    // outputs) and uses its own scratch, so it is a parallel branch.
+    // outputs) and uses its own scratch, so it can be a parallel branch.
     e = hipEventRecord(h->ev_fork, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
     if (e == hipSuccess)
@@ -636,7 +637,9 @@ int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
   }
   if (e == hipSuccess && rc == CM_OK)
     rc = forces_impl(h, y, f, energy, n_inverted, stream, percell);
-  if (bwd && e == hipSuccess) {
+  if (bwd && !fork && rc == CM_OK)
+    rc = backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, percell);
+  if (fork && e == hipSuccess) {
     e = hipEventRecord(h->ev_join, h->side);
     if (e == hipSuccess) e = hipStreamWaitEvent(stream, h->ev_join, 0);
   }
