@@ -43,16 +43,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 FWD_BYTES = (56, 24)    # 16 idx + 36 B + 4 V0 per tet; y in + f out per node
 BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
 F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
+DEVICE_HEADERS = ("device_util.h", "kernels.h", "layout.h", "mr_tet.h")
 
 
 def kernel_source_hash():
-    """sha256 of the device sources; a stored counter record applies only to
-    the kernels it was measured on."""
+    """sha256 of the device-code sources (kernels and the headers they
+    include); a stored counter record applies only to the kernels it was
+    measured on.  Host-only sources (api.cpp, prep.*) are not part of it."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_03130_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".h", ".cpp")):
+        if fn.endswith(".hip") or fn in DEVICE_HEADERS:
             with open(os.path.join(csrc, fn), "rb") as fh:
                 h.update(fn.encode() + fh.read())
     return h.hexdigest()
@@ -99,6 +101,21 @@ def time_graph(cb, stream, steps, warmup, ramp_s=0.0):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def kernel_times(cb, stream, y, f, E, fbar, ebar, ybar, tb, reps=20):
+    """Average device time of each kernel (cm_profile_kernels: HIP events on
+    the launch stream around `reps` back-to-back launches), taken after
+    about 0.3 s of replays of the captured step so that clocks are in their
+    loaded state."""
+    import torch
+    t_end = time.time() + 0.3
+    while time.time() < t_end:
+        for _ in range(10):
+            cb.graph_launch(stream=stream)
+        torch.cuda.synchronize()
+    return cb.profile_kernels(y, f, E, fbar, ebar, ybar, tb, reps=reps,
+                              stream=stream)
 
 
 def parity(cb, b, f, E, ybar, tb, vbar, ebar, cells):
@@ -217,6 +234,70 @@ def run_relax(args):
     return out
 
 
+def run_template(args):
+    """Shared-mesh batch: args.template_cells copies of one ~10k-tet sphere,
+    each with its own deformation and parameters (cm_template_create).  The
+    tet stream is stored once, so a step moves the per-node arrays and one
+    copy of the tet data."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import cotangent, template_batch
+    t = time.time()
+    b = template_batch(args.template_cells, args.template_nodes, args.seed + 7)
+    n1, m1 = b.info["template_nodes"], b.info["template_tets"]
+    log(f"template workload: {b.n_cells} x ({n1} nodes, {m1} tets) "
+        f"({time.time() - t:.1f} s)")
+    cb = CellBatch.template(b.n_cells, b.x[:n1], b.tets[:m1],
+                            tile_tets=args.tile_tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    dev = cb.device
+    y = cb.to_device(b.y)
+    vbar = cotangent(b.n_nodes, args.seed + 8)
+    fbar = cb.to_device(vbar)
+    ebar_h = np.full(b.n_cells, 0.5)
+    ebar = torch.tensor(ebar_h, dtype=torch.float64, device=dev)
+    f, ybar = cb.empty_nodes(), cb.empty_nodes()
+    E = torch.empty(b.n_cells, dtype=torch.float64, device=dev)
+    tb = torch.empty(3 * b.n_cells, dtype=torch.float64, device=dev)
+    if args.launch:
+        cb.set_launch(*(int(v) for v in args.launch.split(",")))
+    elif not args.no_autotune:
+        cb.autotune(y)
+    cb.forces(y, f, E)
+    cb.backward(y, fbar, ebar, ybar, tb)
+    torch.cuda.synchronize()
+    sample = [0, b.n_cells // 2, b.n_cells - 1] if args.parity_cells else []
+    par = parity(cb, b, f, E, ybar, tb, vbar, ebar_h, sample)
+    s = torch.cuda.Stream()
+    res = {}
+    for name, mode in (("fwd", 0), ("fwd_bwd", 1)):
+        with torch.cuda.stream(s):
+            cb.graph_capture(mode, y, f, E, None, fbar, ebar, ybar, tb,
+                             stream=s)
+        res[name] = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
+    ms = kernel_times(cb, s, y, f, E, fbar, ebar, ybar, tb)
+    M, N = b.n_tets, b.n_nodes
+    fwd_b = FWD_BYTES[0] * m1 + FWD_BYTES[1] * N
+    bwd_b = BWD_BYTES[0] * m1 + BWD_BYTES[1] * N
+    out = {
+        "workload": f"{b.n_cells} copies of one sphere mesh ({n1} nodes, "
+                    f"{m1} tets), {M} tets, {N} nodes, per-cell deformation "
+                    f"and parameters",
+        "launch": list(cb.get_launch()),
+        "fwd_bwd_tets_per_s": M / (res["fwd_bwd"] * 1e-3),
+        "fwd_tets_per_s": M / (res["fwd"] * 1e-3),
+        "ms": {k: round(v, 5) for k, v in res.items()},
+        "kernel_ms": [round(v, 5) for v in ms],
+        "hbm_frac_fwd_bwd": (fwd_b + bwd_b) / (res["fwd_bwd"] * 1e-3)
+        / (HBM_PEAK_GBS * 1e9),
+        "alu_frac_fwd_bwd": (FWD_FLOPS + BWD_FLOPS) * M
+        / (res["fwd_bwd"] * 1e-3) / (ALU_PEAK_TFLOPS * 1e12),
+        "parity": par,
+    }
+    log(f"template: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +316,10 @@ def main():
     ap.add_argument("--relax-cells", type=int, default=256)
     ap.add_argument("--relax-steps", type=int, default=200)
     ap.add_argument("--no-relax", action="store_true")
+    ap.add_argument("--template-cells", type=int, default=4096)
+    ap.add_argument("--template-nodes", type=int, default=1930,
+                    help="node target of the shared sphere mesh (~10k tets)")
+    ap.add_argument("--no-template", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
@@ -307,13 +392,17 @@ def main():
     s = torch.cuda.Stream()
     M, N = b.n_tets, b.n_nodes
     res = {}
-    for name, mode in (("fwd_bwd", 1), ("fwd", 0)):
+    for name, mode in (("fwd", 0), ("fwd_bwd", 1)):
         with torch.cuda.stream(s):
             cb.graph_capture(mode, y, f, E, ninv, fbar, ebar, ybar, tb,
                              stream=s)
         res[name] = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
         log(f"batched {name}: {res[name]:.4f} ms/step")
     step_ms = res["fwd_bwd"]
+    # per-kernel event times right after the step timing, clocks loaded
+    ms = kernel_times(cb, s, y, f, E, fbar, ebar, ybar, tb)
+    log(f"kernel ms (fwd tile, fwd finalize, bwd tile, bwd finalize): "
+        f"{np.round(ms, 4).tolist()}")
     if not args.no_percell:
         psteps = max(2, args.steps // 4)
         for name, mode in (("percell_fwd_bwd", 3), ("percell_fwd", 2)):
@@ -325,10 +414,6 @@ def main():
             log(f"single-cell launches {name}: {res[name]:.3f} ms/step "
                 f"(capture {time.time() - t:.1f} s)")
 
-    ms = cb.profile_kernels(y, f, E, fbar, ebar, ybar, tb, reps=10,
-                            stream=s)
-    log(f"kernel ms (fwd tile, fwd finalize, bwd tile, bwd finalize): "
-        f"{np.round(ms, 4).tolist()}")
     fwd_b = FWD_BYTES[0] * M + FWD_BYTES[1] * N
     bwd_b = BWD_BYTES[0] * M + BWD_BYTES[1] * N
     def views(ms_k, nbytes, flops):
@@ -359,6 +444,9 @@ def main():
     relax = None
     if not args.no_relax:
         relax = run_relax(args)
+    template = None
+    if not args.no_template:
+        template = run_template(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -398,6 +486,7 @@ def main():
         "n_inverted": n_inverted,
         "cpu_baseline": cpu,
         "relax": relax,
+        "template": template,
     }
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)

@@ -125,6 +125,24 @@ int cm_mesh_create(int64_t n_nodes, int64_t n_tets, const double* ref_xyz,
                    const int32_t* tets, const cm_options* opt,
                    hipStream_t stream, cm_mesh* out);
 
+/*
+ * cm_template_create: n_cells cells that share ONE reference mesh
+ * (ref_xyz: host float64[n_nodes * 3], tets: host int32[n_tets * 4]) but have
+ * their own deformed positions and parameters.  The precomputed tet data
+ * (indices, B, V0) is stored once; the tiles of all cells are interleaved
+ * (tile k of every cell, then tile k + 1), so cells running together read the
+ * same tet data and HBM sees it about once.  Node arrays hold n_cells blocks
+ * of n_nodes nodes (cell c at [c n_nodes, (c + 1) n_nodes) in each SoA
+ * component), every block in the same internal order.  Results equal those
+ * of cm_batch_create with n_cells copies of the mesh.  The per-cell launch
+ * calls return CM_EINVAL on such a handle.  Errors as cm_batch_create.
+ * (Several copies of one cell model, as in the paper's suspension runs.)
+ */
+int cm_template_create(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                       const double* ref_xyz, const int32_t* tets,
+                       const cm_options* opt, hipStream_t stream,
+                       cm_batch* out);
+
 /* Frees the handle's device memory and graphs (synchronises the device). */
 int cm_destroy(cm_batch h);
 
@@ -288,12 +306,18 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
  *   shared_slot_ptr int32[n_shared+1] shared_slots  int32[n_slots]
  *   cell_tile_off   int32[n_cells+1]  cell_shared_off int32[n_cells+1]
  *   new_to_old      int64[n_nodes]
+ * cm_layout_create_template runs the preparation of cm_template_create (same
+ * arguments minus the stream, same errors); its layout leaves cell_tile_off
+ * untouched (the tiles of cell c are c + k n_cells, k = 0, 1, ...).
  */
 typedef struct cm_layout_s* cm_layout;
 int cm_layout_create(int32_t n_cells, const int64_t* node_off,
                      const int64_t* tet_off, const double* ref_xyz,
                      const int32_t* tets, const cm_options* opt,
                      cm_layout* out);
+int cm_layout_create_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                              const double* ref_xyz, const int32_t* tets,
+                              const cm_options* opt, cm_layout* out);
 int cm_layout_sizes(cm_layout l, int64_t* sizes);
 int cm_layout_export(cm_layout l, int32_t* tiles, void* chunks,
                      int32_t* slot_node, int32_t* shared_node,

@@ -58,6 +58,9 @@ SIGNATURES = {
                                ctypes.POINTER(_vp)]),
     "cm_mesh_create": (_int, [_i64, _i64, _vp, _vp, ctypes.POINTER(Options),
                               _vp, ctypes.POINTER(_vp)]),
+    "cm_template_create": (_int, [_i32, _i64, _i64, _vp, _vp,
+                                  ctypes.POINTER(Options), _vp,
+                                  ctypes.POINTER(_vp)]),
     "cm_destroy": (_int, [_vp]),
     "cm_get_info": (_int, [_vp, ctypes.POINTER(Info)]),
     "cm_permutation": (_int, [_vp, _vp]),
@@ -82,6 +85,9 @@ SIGNATURES = {
                                      _vp]),
     "cm_layout_create": (_int, [_i32, _vp, _vp, _vp, _vp,
                                 ctypes.POINTER(Options), ctypes.POINTER(_vp)]),
+    "cm_layout_create_template": (_int, [_i32, _i64, _i64, _vp, _vp,
+                                         ctypes.POINTER(Options),
+                                         ctypes.POINTER(_vp)]),
     "cm_layout_sizes": (_int, [_vp, _p64]),
     "cm_layout_export": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),

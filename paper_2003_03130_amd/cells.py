@@ -56,7 +56,6 @@ class CellBatch:
 
     def __init__(self, node_off, tet_off, x, tets, order=None, tile_tets=None,
                  degenerate_tol=None, stream=None):
-        import torch
         node_off, tet_off, x, tets = _host_inputs(node_off, tet_off, x, tets)
         self.n_cells = len(node_off) - 1
         opt = _options(order, tile_tets, degenerate_tol)
@@ -64,6 +63,11 @@ class CellBatch:
         nat.check(nat.lib().cm_batch_create(
             self.n_cells, _ptr(node_off), _ptr(tet_off), _ptr(x), _ptr(tets),
             ctypes.byref(opt), _stream(stream), ctypes.byref(h)))
+        self._finish(h, node_off, tet_off)
+        self.is_template = False
+
+    def _finish(self, h, node_off, tet_off):
+        import torch
         self._h = h
         info = nat.Info()
         nat.check(nat.lib().cm_get_info(self._h, ctypes.byref(info)))
@@ -88,6 +92,30 @@ class CellBatch:
     @classmethod
     def single(cls, x, tets, **kw):
         return cls([0, len(x)], [0, len(tets)], x, tets, **kw)
+
+    @classmethod
+    def template(cls, n_cells, x, tets, order=None, tile_tets=None,
+                 degenerate_tol=None, stream=None):
+        """``n_cells`` copies of one reference mesh (cm_template_create).
+
+        The tet data is stored once and shared; node arrays and parameters
+        are per cell, cell c owning input rows [c n, (c + 1) n) of the
+        (n_cells n, 3) arrays that ``to_device``/``to_host`` take.  Per-cell
+        launches are not available on such a batch.
+        """
+        _, _, x, tets = _host_inputs([0], [0], x, tets)
+        n, m = len(x), len(tets)
+        opt = _options(order, tile_tets, degenerate_tol)
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().cm_template_create(
+            int(n_cells), n, m, _ptr(x), _ptr(tets), ctypes.byref(opt),
+            _stream(stream), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.n_cells = int(n_cells)
+        self._finish(h, np.arange(n_cells + 1, dtype=np.int64) * n,
+                     np.arange(n_cells + 1, dtype=np.int64) * m)
+        self.is_template = True
+        return self
 
     # ------------------------------------------------------------ lifetime
     def close(self):
@@ -235,6 +263,26 @@ class HostLayout:
         nat.check(nat.lib().cm_layout_create(
             len(node_off) - 1, _ptr(node_off), _ptr(tet_off), _ptr(x),
             _ptr(tets), ctypes.byref(opt), ctypes.byref(h)))
+        self._load(h)
+        self.is_template = False
+
+    @classmethod
+    def template(cls, n_cells, x, tets, order=None, tile_tets=None,
+                 degenerate_tol=None):
+        """Layout of ``n_cells`` copies of one mesh (cm_layout_create_template);
+        ``cell_tile_off`` stays zero, the tiles of cell c being c + k n_cells."""
+        _, _, x, tets = _host_inputs([0], [0], x, tets)
+        opt = _options(order, tile_tets, degenerate_tol)
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().cm_layout_create_template(
+            int(n_cells), len(x), len(tets), _ptr(x), _ptr(tets),
+            ctypes.byref(opt), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._load(h)
+        self.is_template = True
+        return self
+
+    def _load(self, h):
         try:
             sz = np.zeros(8, dtype=np.int64)
             nat.check(nat.lib().cm_layout_sizes(h, sz.ctypes.data_as(nat._p64)))

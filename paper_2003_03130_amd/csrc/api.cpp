@@ -49,6 +49,7 @@ struct cm_batch_s {
   cm::DeviceTables Tb;  // same tables + backward scratch
   cm::LaunchCfg cfg;
   bool params_set = false;
+  bool is_template = false;  // cells share one chunk array (tiles interleaved)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   // fork/join of the forward and backward branches of a captured graph
@@ -142,19 +143,10 @@ static cm::PrepOptions prep_options(const cm_options* opt) {
   return po;
 }
 
-int cm_batch_create(int32_t n_cells, const int64_t* node_off,
-                    const int64_t* tet_off, const double* ref_xyz,
-                    const int32_t* tets, const cm_options* opt,
-                    hipStream_t stream, cm_batch* out) {
-  g_err.clear();
-  if (!out) return fail(CM_EINVAL, "out is null");
-  *out = nullptr;
-  const cm::PrepOptions po = prep_options(opt);
-  cm::Prepared P;
-  std::string err;
-  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &P, &err);
-  if (rc != CM_OK) return fail(rc, err);
-
+// Uploads a prepared layout and builds the handle.
+static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
+                       hipStream_t stream, cm_batch* out) {
+  int rc = CM_OK;
   cm_batch_s* h = new (std::nothrow) cm_batch_s();
   if (!h) return fail(CM_ENOMEM, "host allocation failed");
   auto bail = [&](int st) { delete h; return st; };
@@ -179,13 +171,14 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
   h->max_cond = P.max_cond;
   h->cell_tile_off = P.cell_tile_off;
   h->cell_shared_off = P.cell_shared_off;
+  h->is_template = P.tile_stride != 1;
   h->new_to_old = std::move(P.new_to_old);
 
   cm::DeviceTables& T = h->T;
   {
     cm::TileDesc* tiles;
     cm::TetChunk* chunks;
-    int32_t *slot_node, *shared_node, *ssp, *ss, *cto;
+    int32_t *slot_node, *shared_node, *ssp, *ss, *ctf, *ctc;
     int64_t* noff;
     if ((rc = h->upload(&tiles, P.tiles, stream)) ||
         (rc = h->upload(&chunks, P.chunks, stream)) ||
@@ -193,7 +186,8 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
         (rc = h->upload(&shared_node, P.shared_node, stream)) ||
         (rc = h->upload(&ssp, P.shared_slot_ptr, stream)) ||
         (rc = h->upload(&ss, P.shared_slots, stream)) ||
-        (rc = h->upload(&cto, P.cell_tile_off, stream)) ||
+        (rc = h->upload(&ctf, P.cell_tile_first, stream)) ||
+        (rc = h->upload(&ctc, P.cell_tile_count, stream)) ||
         (rc = h->upload(&noff, P.node_off, stream)))
       return bail(rc);
     h->d_node_off = noff;
@@ -203,7 +197,9 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
     T.shared_node = shared_node;
     T.shared_slot_ptr = ssp;
     T.shared_slots = ss;
-    T.cell_tile_off = cto;
+    T.cell_tile_first = ctf;
+    T.cell_tile_count = ctc;
+    T.tile_stride = P.tile_stride;
     double* params;
     float *part, *part_b;
     double *tile_acc, *tile_acc_b;
@@ -242,6 +238,38 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
   h->cfg.blocks = 0;
   *out = h;
   return CM_OK;
+}
+
+int cm_batch_create(int32_t n_cells, const int64_t* node_off,
+                    const int64_t* tet_off, const double* ref_xyz,
+                    const int32_t* tets, const cm_options* opt,
+                    hipStream_t stream, cm_batch* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  const cm::PrepOptions po = prep_options(opt);
+  cm::Prepared P;
+  std::string err;
+  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &P, &err);
+  if (rc != CM_OK) return fail(rc, err);
+  return create_from(P, po, stream, out);
+}
+
+int cm_template_create(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                       const double* ref_xyz, const int32_t* tets,
+                       const cm_options* opt, hipStream_t stream,
+                       cm_batch* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  if (!ref_xyz || !tets || n_nodes < 0 || n_tets < 0)
+    return fail(CM_EINVAL, "null pointer or negative size");
+  const cm::PrepOptions po = prep_options(opt);
+  cm::Prepared P;
+  std::string err;
+  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, po, &P, &err);
+  if (rc != CM_OK) return fail(rc, err);
+  return create_from(P, po, stream, out);
 }
 
 int cm_mesh_create(int64_t n_nodes, int64_t n_tets, const double* ref_xyz,
@@ -326,6 +354,8 @@ static int forces_impl(cm_batch h, const float* y, float* f, double* energy,
   if (!lds_fits(h, h->cfg.waves, false))
     return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
   if (int rc = select_device(h)) return rc;
+  if (percell && h->is_template)
+    return fail(CM_EINVAL, "per-cell launches need contiguous tiles (not a template batch)");
   if (!percell) {
     CM_HIP(cm::launch_forward(h->T, full_range(h), h->cfg, y, f, energy, ninv, st));
   } else {
@@ -345,6 +375,8 @@ static int backward_impl(cm_batch h, const float* y, const float* fbar,
   if (!lds_fits(h, h->cfg.waves, true))
     return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
   if (int rc = select_device(h)) return rc;
+  if (percell && h->is_template)
+    return fail(CM_EINVAL, "per-cell launches need contiguous tiles (not a template batch)");
   if (!percell) {
     CM_HIP(cm::launch_backward(h->Tb, full_range(h), h->cfg, y, fbar, ebar, ybar,
                                thetabar, st));
@@ -451,7 +483,8 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   std::string key = std::string(prop.gcnArchName) + "|cu" + std::to_string(h->n_cu) +
                     "|tets" + std::to_string(h->n_tets) + "|tiles" +
                     std::to_string(h->n_tiles) + "|tile" + std::to_string(h->tile_tets) +
-                    "|nloc" + std::to_string(h->T.nloc);
+                    "|nloc" + std::to_string(h->T.nloc) +
+                    (h->is_template ? "|template" : "");
   for (char& ch : key)
     if (ch == '"' || ch == '\\') ch = '_';
   int w = 0, b = 0;
@@ -681,6 +714,28 @@ int cm_layout_create(int32_t n_cells, const int64_t* node_off,
   const cm::PrepOptions po = prep_options(opt);
   std::string err;
   int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &l->P, &err);
+  if (rc != CM_OK) {
+    delete l;
+    return fail(rc, err);
+  }
+  l->tile_tets = po.tile_tets;
+  *out = l;
+  return CM_OK;
+}
+
+int cm_layout_create_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                              const double* ref_xyz, const int32_t* tets,
+                              const cm_options* opt, cm_layout* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  if (!ref_xyz || !tets || n_nodes < 0 || n_tets < 0)
+    return fail(CM_EINVAL, "null pointer or negative size");
+  cm_layout_s* l = new (std::nothrow) cm_layout_s();
+  if (!l) return fail(CM_ENOMEM, "host allocation failed");
+  const cm::PrepOptions po = prep_options(opt);
+  std::string err;
+  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, po, &l->P, &err);
   if (rc != CM_OK) {
     delete l;
     return fail(rc, err);

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   float4* ys = lds + (size_t)wave * (10 * nloc / 4);
   float4* gs = ys + nloc;
   float2* vs = reinterpret_cast<float2*>(gs + nloc);
-  const int64_t N = a.T.n_nodes, S = a.T.n_slots;
+  const int64_t N = a.T.n_nodes;
   const bool has_fbar = a.fbar != nullptr;
 
   int t0, t1;
@@ -99,7 +99,8 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     for (int j = lane; j < d.n_shr; j += 64) {
       const int64_t s = d.shr_begin + j;
       const float4 v = gs[d.n_own + j];
-      a.T.part[s] = v.x; a.T.part[S + s] = v.y; a.T.part[2 * S + s] = v.z;
+      float* pp = a.T.part + 3 * s;
+      pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
     }
     acc[0] = wave_sum(acc[0]);
     acc[1] = wave_sum(acc[1]);
@@ -125,15 +126,16 @@ struct BwdFinArgs {
 // from the per-tile sums of dL/d(mu1, mu2, kappa) (mu1 = w mu, mu2 = (1-w) mu).
 __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = a.T.n_nodes, S = a.T.n_slots;
+  const int64_t N = a.T.n_nodes;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
       const int64_t sl = a.T.shared_slots[q];
-      sx += a.T.part[sl];
-      sy += a.T.part[S + sl];
-      sz += a.T.part[2 * S + sl];
+      const float* pp = a.T.part + 3 * sl;
+      sx += pp[0];
+      sy += pp[1];
+      sz += pp[2];
     }
     const int64_t g = a.T.shared_node[s];
     a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
@@ -141,10 +143,12 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
   if (a.thetabar && gid < a.r.cell_end - a.r.cell_begin) {
     const int c = a.r.cell_begin + (int)gid;
     double gI = 0.0, gK = 0.0, gJ = 0.0;
-    for (int t = a.T.cell_tile_off[c]; t < a.T.cell_tile_off[c + 1]; ++t) {
-      gI += a.T.tile_acc[3 * (int64_t)t];
-      gK += a.T.tile_acc[3 * (int64_t)t + 1];
-      gJ += a.T.tile_acc[3 * (int64_t)t + 2];
+    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
+    for (int k = 0; k < nt; ++k) {
+      const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
+      gI += a.T.tile_acc[3 * t];
+      gK += a.T.tile_acc[3 * t + 1];
+      gJ += a.T.tile_acc[3 * t + 2];
     }
     const int nc = a.T.n_cells;
     const double mu = a.T.params[c], w = a.T.params[2 * nc + c];

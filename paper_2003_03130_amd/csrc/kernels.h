@@ -16,9 +16,12 @@ struct DeviceTables {
   const int32_t* shared_node = nullptr;
   const int32_t* shared_slot_ptr = nullptr;
   const int32_t* shared_slots = nullptr;
-  const int32_t* cell_tile_off = nullptr;
+  // tiles of cell c: cell_tile_first[c] + k * tile_stride, k < cell_tile_count[c]
+  const int32_t* cell_tile_first = nullptr;
+  const int32_t* cell_tile_count = nullptr;
+  int32_t tile_stride = 1;
   const double* params = nullptr;  // SoA: mu[n_cells], kappa[n_cells], w[n_cells]
-  float* part = nullptr;           // SoA slot partials, 3 * n_slots
+  float* part = nullptr;           // slot partials, (x, y, z) per slot
   double* tile_acc = nullptr;      // per tile: energy (fwd) or 3 sums (bwd)
   int32_t* tile_ninv = nullptr;    // per tile
   int64_t n_nodes = 0, n_slots = 0, n_tiles = 0;

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
   const int nloc = a.T.nloc;
   float4* ys = lds + (size_t)wave * 2 * nloc;  // positions
   float4* fs = ys + nloc;                      // force accumulators
-  const int64_t N = a.T.n_nodes, S = a.T.n_slots;
+  const int64_t N = a.T.n_nodes;
 
   int t0, t1;
   block_tiles(a.r, t0, t1);
@@ -88,7 +88,8 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     for (int j = lane; j < d.n_shr; j += 64) {
       const int64_t s = d.shr_begin + j;
       const float4 v = fs[d.n_own + j];
-      a.T.part[s] = v.x; a.T.part[S + s] = v.y; a.T.part[2 * S + s] = v.z;
+      float* pp = a.T.part + 3 * s;
+      pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
     }
     eacc = wave_sum(eacc);
     ninv = wave_sum(ninv);
@@ -112,15 +113,16 @@ struct FinArgs {
 // energies / inverted counts of every cell.
 __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = a.T.n_nodes, S = a.T.n_slots;
+  const int64_t N = a.T.n_nodes;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
       const int64_t sl = a.T.shared_slots[q];
-      sx += a.T.part[sl];
-      sy += a.T.part[S + sl];
-      sz += a.T.part[2 * S + sl];
+      const float* pp = a.T.part + 3 * sl;
+      sx += pp[0];
+      sy += pp[1];
+      sz += pp[2];
     }
     const int64_t g = a.T.shared_node[s];
     a.f[g] = sx; a.f[N + g] = sy; a.f[2 * N + g] = sz;
@@ -129,7 +131,9 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a) {
     const int c = a.r.cell_begin + (int)gid;
     double e = 0.0;
     int ni = 0;
-    for (int t = a.T.cell_tile_off[c]; t < a.T.cell_tile_off[c + 1]; ++t) {
+    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
+    for (int k = 0; k < nt; ++k) {
+      const int t = t0 + k * a.T.tile_stride;
       e += a.T.tile_acc[t];
       ni += a.T.tile_ninv[t];
     }

@@ -155,13 +155,16 @@ __device__ __forceinline__ void tet_forward(const float4& p0, const float4& p1,
                     m.kappa * Jm1;
   const double nv = -(double)V0;
   const float s1 = (float)(nv * c1), s2 = (float)(nv * c2), s3 = (float)(nv * c3);
-  float FC[3][3], K[3][3], P[3][3];
-  times_sym(F, Cf, FC);
+  // P = F (s1 I + s2 C) + s3 cof F
+  const float M[6] = {fmaf(s2, Cf[0], s1), fmaf(s2, Cf[1], s1), fmaf(s2, Cf[2], s1),
+                      s2 * Cf[3], s2 * Cf[4], s2 * Cf[5]};
+  float K[3][3], P[3][3];
+  times_sym(F, M, P);
   cofactor(F, K);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P[i][j] = s1 * F[i][j] + s2 * FC[i][j] + s3 * K[i][j];
+    for (int j = 0; j < 3; ++j) P[i][j] = fmaf(s3, K[i][j], P[i][j]);
   // h[k][i] = (P B^T)_ik, already scaled by -V0
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -206,18 +209,28 @@ __device__ __forceinline__ void tet_backward(
   direction_gradient(v0, v1, v2, v3, B, dF);
   Scalars s;
   invariants(Fd, Cf, s);
-  float K[3][3], FC[3][3];
+  float K[3][3];
   cofactor(F, K);
-  times_sym(F, Cf, FC);
-  float fF = 0.f, fFC = 0.f, fK = 0.f;
+  // dC = dF^T F + F^T dF (symmetric: 00 11 22 01 02 12)
+  float dC[6];
+  dC[0] = 2.f * (dF[0][0] * F[0][0] + dF[1][0] * F[1][0] + dF[2][0] * F[2][0]);
+  dC[1] = 2.f * (dF[0][1] * F[0][1] + dF[1][1] * F[1][1] + dF[2][1] * F[2][1]);
+  dC[2] = 2.f * (dF[0][2] * F[0][2] + dF[1][2] * F[1][2] + dF[2][2] * F[2][2]);
+  dC[3] = dF[0][0] * F[0][1] + dF[1][0] * F[1][1] + dF[2][0] * F[2][1] +
+          F[0][0] * dF[0][1] + F[1][0] * dF[1][1] + F[2][0] * dF[2][1];
+  dC[4] = dF[0][0] * F[0][2] + dF[1][0] * F[1][2] + dF[2][0] * F[2][2] +
+          F[0][0] * dF[0][2] + F[1][0] * dF[1][2] + F[2][0] * dF[2][2];
+  dC[5] = dF[0][1] * F[0][2] + dF[1][1] * F[1][2] + dF[2][1] * F[2][2] +
+          F[0][1] * dF[0][2] + F[1][1] * dF[1][2] + F[2][1] * dF[2][2];
+  // <F, dF> = tr(dC)/2, <F C, dF> = <C, F^T dF> = <C, dC>/2, <cof F, dF> = dJ
+  const float fF = 0.5f * (dC[0] + dC[1] + dC[2]);
+  const float fFC = 0.5f * (Cf[0] * dC[0] + Cf[1] * dC[1] + Cf[2] * dC[2]) +
+                    (Cf[3] * dC[3] + Cf[4] * dC[4] + Cf[5] * dC[5]);
+  float fK = 0.f;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      fF += F[i][j] * dF[i][j];
-      fFC += FC[i][j] * dF[i][j];
-      fK += K[i][j] * dF[i][j];
-    }
+    for (int j = 0; j < 3; ++j) fK = fmaf(K[i][j], dF[i][j], fK);
   // directional derivatives of tr C, tr C^2, J and I2 = (trC^2 - trC2)/2
   const double dTC = 2.0 * (double)fF;
   const double dTC2 = 4.0 * (double)fFC;
@@ -241,28 +254,27 @@ __device__ __forceinline__ void tet_backward(
   const float s2 = (float)(nv * (dc2 - ebar * c2)), t2 = (float)(nv * c2);
   const float s3 = (float)(nv * (dc3 - ebar * c3)), t3 = (float)(nv * c3);
 
-  // dC = dF^T F + F^T dF (symmetric), d(FC) = dF C + F dC
-  float dC[6];
-  dC[0] = 2.f * (dF[0][0] * F[0][0] + dF[1][0] * F[1][0] + dF[2][0] * F[2][0]);
-  dC[1] = 2.f * (dF[0][1] * F[0][1] + dF[1][1] * F[1][1] + dF[2][1] * F[2][1]);
-  dC[2] = 2.f * (dF[0][2] * F[0][2] + dF[1][2] * F[1][2] + dF[2][2] * F[2][2]);
-  dC[3] = dF[0][0] * F[0][1] + dF[1][0] * F[1][1] + dF[2][0] * F[2][1] +
-          F[0][0] * dF[0][1] + F[1][0] * dF[1][1] + F[2][0] * dF[2][1];
-  dC[4] = dF[0][0] * F[0][2] + dF[1][0] * F[1][2] + dF[2][0] * F[2][2] +
-          F[0][0] * dF[0][2] + F[1][0] * dF[1][2] + F[2][0] * dF[2][2];
-  dC[5] = dF[0][1] * F[0][2] + dF[1][1] * F[1][2] + dF[2][1] * F[2][2] +
-          F[0][1] * dF[0][2] + F[1][1] * dF[1][2] + F[2][1] * dF[2][2];
-  float dFC[3][3], FdC[3][3], dK[3][3];
-  times_sym(dF, Cf, dFC);
-  times_sym(F, dC, FdC);
+  // -V0 (dP - ebar P) with P = c1 F + c2 F C + c3 cof F:
+  //   s1 F + t1 dF + s2 F C + t2 (dF C + F dC) + s3 cof F + t3 d(cof F)
+  //   = F (s1 I + s2 C + t2 dC) + dF (t1 I + t2 C) + s3 cof F + t3 d(cof F)
+  const float M[6] = {fmaf(t2, dC[0], fmaf(s2, Cf[0], s1)),
+                      fmaf(t2, dC[1], fmaf(s2, Cf[1], s1)),
+                      fmaf(t2, dC[2], fmaf(s2, Cf[2], s1)),
+                      fmaf(t2, dC[3], s2 * Cf[3]), fmaf(t2, dC[4], s2 * Cf[4]),
+                      fmaf(t2, dC[5], s2 * Cf[5])};
+  const float Nm[6] = {fmaf(t2, Cf[0], t1), fmaf(t2, Cf[1], t1), fmaf(t2, Cf[2], t1),
+                       t2 * Cf[3], t2 * Cf[4], t2 * Cf[5]};
+  float dK[3][3];
   cofactor_dir(F, dF, dK);
+  const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
   float Q[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      Q[i][j] = s1 * F[i][j] + t1 * dF[i][j] + s2 * FC[i][j] +
-                t2 * (dFC[i][j] + FdC[i][j]) + s3 * K[i][j] + t3 * dK[i][j];
+      Q[i][j] = F[i][0] * M[sym[0][j]] + F[i][1] * M[sym[1][j]] + F[i][2] * M[sym[2][j]] +
+                dF[i][0] * Nm[sym[0][j]] + dF[i][1] * Nm[sym[1][j]] +
+                dF[i][2] * Nm[sym[2][j]] + s3 * K[i][j] + t3 * dK[i][j];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll

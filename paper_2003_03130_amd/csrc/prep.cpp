@@ -528,6 +528,79 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
   }
   P->cell_tile_off[n_cells] = (int32_t)tb;
   P->cell_shared_off[n_cells] = (int32_t)hb;
+  P->cell_tile_first.resize(n_cells);
+  P->cell_tile_count.resize(n_cells);
+  for (int32_t c = 0; c < n_cells; ++c) {
+    P->cell_tile_first[c] = P->cell_tile_off[c];
+    P->cell_tile_count[c] = P->cell_tile_off[c + 1] - P->cell_tile_off[c];
+  }
+  P->tile_stride = 1;
+  return CM_OK;
+}
+
+int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                     const double* ref_xyz, const int32_t* tets,
+                     const PrepOptions& opt, Prepared* P, std::string* err) {
+  if (n_cells <= 0) {
+    *err = "n_cells must be positive";
+    return CM_EINVAL;
+  }
+  const int64_t no[2] = {0, n_nodes}, to[2] = {0, n_tets};
+  Prepared one;
+  int rc = prepare_batch(1, no, to, ref_xyz, tets, opt, &one, err);
+  if (rc != CM_OK) return rc;
+  const int64_t C = n_cells, N = n_nodes;
+  const int64_t T1 = (int64_t)one.tiles.size(), S1 = (int64_t)one.slot_node.size();
+  const int64_t H1 = (int64_t)one.shared_node.size();
+  if (C * N >= 0x7fffffffLL || C * T1 >= 0x7fffffffLL || C * S1 >= 0x7fffffffLL) {
+    *err = "template batch too large for 32-bit tables";
+    return CM_EINVAL;
+  }
+  P->n_cells = C;
+  P->n_nodes = C * N;
+  P->n_tets = C * n_tets;
+  P->chunks = std::move(one.chunks);
+  P->tiles.resize(C * T1);
+  for (int64_t k = 0; k < T1; ++k)
+    for (int64_t c = 0; c < C; ++c) {
+      TileDesc d = one.tiles[k];
+      d.own_begin += (int32_t)(c * N);
+      d.shr_begin += (int32_t)(c * S1);
+      d.cell = (int32_t)c;
+      P->tiles[k * C + c] = d;
+    }
+  P->slot_node.resize(C * S1);
+  P->shared_slots.resize(C * S1);
+  P->shared_node.resize(C * H1);
+  P->shared_slot_ptr.resize(C * H1 + 1);
+  P->new_to_old.resize(C * N);
+  P->node_off.resize(C + 1);
+  P->cell_shared_off.resize(C + 1);
+  P->cell_tile_first.resize(C);
+  P->cell_tile_count.assign(C, (int32_t)T1);
+  P->shared_slot_ptr[0] = 0;
+  for (int64_t c = 0; c < C; ++c) {
+    for (int64_t q = 0; q < S1; ++q) {
+      P->slot_node[c * S1 + q] = one.slot_node[q] + (int32_t)(c * N);
+      P->shared_slots[c * S1 + q] = one.shared_slots[q] + (int32_t)(c * S1);
+    }
+    for (int64_t h = 0; h < H1; ++h) {
+      P->shared_node[c * H1 + h] = one.shared_node[h] + (int32_t)(c * N);
+      P->shared_slot_ptr[c * H1 + h + 1] = one.shared_slot_ptr[h + 1] + (int32_t)(c * S1);
+    }
+    for (int64_t v = 0; v < N; ++v) P->new_to_old[c * N + v] = one.new_to_old[v] + c * N;
+    P->node_off[c] = c * N;
+    P->cell_shared_off[c] = (int32_t)(c * H1);
+    P->cell_tile_first[c] = (int32_t)c;
+  }
+  P->node_off[C] = C * N;
+  P->cell_shared_off[C] = (int32_t)(C * H1);
+  P->cell_tile_off.clear();
+  P->tile_stride = (int32_t)C;
+  P->max_tile_nodes = one.max_tile_nodes;
+  P->volume = one.volume * (double)C;
+  P->min_v0 = one.min_v0;
+  P->max_cond = one.max_cond;
   return CM_OK;
 }
 

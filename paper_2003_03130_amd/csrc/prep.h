@@ -23,7 +23,10 @@ struct Prepared {
   std::vector<int32_t> shared_node;      // internal node id of every shared node
   std::vector<int32_t> shared_slot_ptr;  // CSR (n_shared + 1) into shared_slots
   std::vector<int32_t> shared_slots;     // slot ids, grouped by shared node, in tile order
-  std::vector<int32_t> cell_tile_off;    // n_cells + 1
+  std::vector<int32_t> cell_tile_off;    // n_cells + 1 (contiguous tiles per cell)
+  std::vector<int32_t> cell_tile_first;  // n_cells: first tile of the cell
+  std::vector<int32_t> cell_tile_count;  // n_cells: tiles of the cell
+  int32_t tile_stride = 1;               // distance between a cell's tiles
   std::vector<int32_t> cell_shared_off;  // n_cells + 1
   std::vector<int64_t> node_off;         // n_cells + 1 (same as input)
   std::vector<int64_t> new_to_old;       // n_nodes
@@ -32,6 +35,15 @@ struct Prepared {
 };
 
 // Returns 0 on success, or a CM_* status with `err` set.
+// prepare_template: n_cells cells that share one reference mesh (n_nodes,
+// n_tets, ref_xyz, tets).  The tet chunks are stored once; tile descriptors,
+// slot and shared-node tables are replicated per cell with offsets, ordered
+// template tile major and cell minor (tile k of every cell, then tile k + 1),
+// so cell_tile_off is empty and the tiles of cell c are c + k * n_cells.
+int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                     const double* ref_xyz, const int32_t* tets,
+                     const PrepOptions& opt, Prepared* out, std::string* err);
+
 int prepare_batch(int32_t n_cells, const int64_t* node_off,
                   const int64_t* tet_off, const double* ref_xyz,
                   const int32_t* tets, const PrepOptions& opt, Prepared* out,

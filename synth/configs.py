@@ -233,6 +233,27 @@ def uneven_batch(n_cells=4096, seed=3000, tet_lo=500, tet_hi=20000,
     return b
 
 
+def template_batch(n_cells, n_target, seed) -> Batch:
+    """``n_cells`` copies of one sphere mesh (about ``n_target`` nodes), each
+    with its own compression + shear, node noise and (mu, kappa, w), drawn as
+    in uneven_batch.  The arrays hold every copy, so the same Batch feeds a
+    shared-mesh handle (first copy) and a distinct-array handle (all)."""
+    x, tets = sphere_mesh(n_target, seed)
+    h = mean_edge_length(x, tets)
+    ss = np.random.SeedSequence(seed + 1)
+    cells = []
+    for child in ss.spawn(n_cells):
+        rng = np.random.default_rng(child)
+        A = compression_shear_map(1.0 - rng.uniform(0.0, 0.8),
+                                  rng.uniform(0.0, 0.5))
+        theta = random_theta(rng)
+        y, info = deform(x, tets, A, rng, h_mean=h)
+        cells.append(Cell(x, tets, y.astype(np.float32), theta, A, info))
+    b = batch_from_cells(cells)
+    b.info = {"template_nodes": len(x), "template_tets": len(tets)}
+    return b
+
+
 # ---------------------------------------------------------------- plates
 STOKES_DT = 1e-3      # time step of the compression runs
 DRAG = 0.25           # uniform nodal drag; mobility = STOKES_DT / DRAG

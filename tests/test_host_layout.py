@@ -47,7 +47,8 @@ def _batch(n_cells=5):
 
 def _decode_tets(L, b):
     """Rebuild every tetrahedron (input numbering, cell-local, in the slot
-    order the layout chose) from the tiles: rows (cell, v0..v3, chunk, lane)."""
+    order the layout chose) from the tiles: rows (cell, v0..v3, chunk, lane,
+    tile)."""
     out = []
     for t in range(L.n_tiles):
         cb, nt, ob, no, sb, ns, cell, nch = L.tiles[t]
@@ -59,7 +60,7 @@ def _decode_tets(L, b):
                 internal = np.where(loc < no, ob + loc,
                                     L.slot_node[sb + np.minimum(loc - no, ns - 1)])
                 out.append((cell, *(L.new_to_old[internal] - b.node_off[cell]),
-                            c, lane))
+                            c, lane, t))
                 count += 1
         assert count == nt
     return np.array(out, dtype=np.int64)
@@ -173,6 +174,93 @@ def test_layout_scatter_matches_direct_assembly():
     got = np.empty_like(out)
     got[L.new_to_old] = out
     assert np.allclose(got, direct, rtol=0, atol=1e-12)
+
+
+def test_template_layout_replicates_one_cell():
+    """cm_layout_create_template: one chunk array, and per cell the tables of
+    the single-cell layout shifted by that cell's node and slot offsets, tile
+    k of cell c at k n_cells + c; decoding it gives every cell's tetrahedra
+    and the reduction plumbing still equals a direct scatter-add."""
+    from paper_2003_03130_amd import HostLayout
+    cell = small_sphere_case(1001)
+    x, tets = cell.x, cell.tets
+    n, C = len(x), 3
+    L1 = HostLayout([0, n], [0, len(tets)], x, tets, tile_tets=256)
+    LT = HostLayout.template(C, x, tets, tile_tets=256)
+    assert LT.n_chunks == L1.n_chunks and LT.n_cells == C
+    assert LT.n_tiles == C * L1.n_tiles and LT.n_nodes == C * n
+    assert LT.n_slots == C * L1.n_slots and LT.n_shared == C * L1.n_shared
+    assert np.array_equal(LT.local_idx, L1.local_idx)
+    assert np.array_equal(LT.B, L1.B) and np.array_equal(LT.V0, L1.V0)
+    S1, H1 = L1.n_slots, L1.n_shared
+    for c in range(C):
+        t = LT.tiles[c::C]
+        want = L1.tiles.copy()
+        want[:, 2] += c * n
+        want[:, 4] += c * S1
+        want[:, 6] = c
+        assert np.array_equal(t, want)
+        sl = slice(c * S1, (c + 1) * S1)
+        assert np.array_equal(LT.slot_node[sl], L1.slot_node + c * n)
+        assert np.array_equal(LT.shared_slots[sl], L1.shared_slots + c * S1)
+        sh = slice(c * H1, (c + 1) * H1)
+        assert np.array_equal(LT.shared_node[sh], L1.shared_node + c * n)
+        assert np.array_equal(LT.shared_slot_ptr[c * H1:(c + 1) * H1 + 1],
+                              L1.shared_slot_ptr + c * S1)
+        assert np.array_equal(LT.new_to_old[c * n:(c + 1) * n],
+                              L1.new_to_old + c * n)
+        assert np.array_equal(LT.cell_shared_off[c:c + 2],
+                              [c * H1, (c + 1) * H1])
+
+    class _B:
+        node_off = np.arange(C + 1) * n
+    rec = _decode_tets(LT, _B)
+    for c in range(C):
+        got = np.sort(rec[rec[:, 0] == c, 1:5], axis=1)
+        want = np.sort(tets, axis=1)
+        assert np.array_equal(got[np.lexsort(got.T[::-1])],
+                              want[np.lexsort(want.T[::-1])])
+    # plumbing with shared chunks: per (tile, lane) values through the tables
+    rng = np.random.default_rng(5)
+    vals = rng.normal(size=(len(rec), 4))
+    direct = np.zeros(C * n)
+    for r, v in zip(rec, vals):
+        np.add.at(direct, r[0] * n + r[1:5], v)
+    out = np.full(C * n, np.nan)
+    part = np.zeros(LT.n_slots)
+    acc = {}
+    for r, v in zip(rec, vals):
+        cb, nt, ob, no, sb, ns, _, _ = LT.tiles[r[7]]
+        a = acc.setdefault(int(r[7]), np.zeros(no + ns))
+        np.add.at(a, LT.local_idx[r[5], r[6]], v)
+    for t, a in acc.items():
+        cb, nt, ob, no, sb, ns, _, _ = LT.tiles[t]
+        out[ob:ob + no] = a[:no]
+        part[sb:sb + ns] = a[no:]
+    for s_, g in enumerate(LT.shared_node):
+        out[g] = part[LT.shared_slots[LT.shared_slot_ptr[s_]:
+                                      LT.shared_slot_ptr[s_ + 1]]].sum()
+    got = np.empty_like(out)
+    got[LT.new_to_old] = out
+    assert np.allclose(got, direct, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["cells", "sizes", "index_range"])
+def test_template_preparation_errors(case):
+    from paper_2003_03130_amd import HostLayout, CellmechError
+    from paper_2003_03130_amd import _native as nat
+    x, tets = sphere_mesh(150, 3)
+    tets = tets.copy()
+    n_cells = 2
+    if case == "cells":
+        n_cells = 0
+    elif case == "sizes":
+        x = np.zeros((0, 3))
+    elif case == "index_range":
+        tets[5, 2] = len(x)
+    with pytest.raises(CellmechError) as ei:
+        HostLayout.template(n_cells, x, tets)
+    assert ei.value.status == nat.CM_EINVAL
 
 
 def test_unreferenced_node_is_shared_with_no_slots():
