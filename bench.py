@@ -298,6 +298,80 @@ def run_template(args):
     return out
 
 
+def run_regions(args, b):
+    """The main workload with three material regions per cell (nucleus,
+    cytoplasm, cortex shell by reference radius), each (cell, region) with
+    its own parameters: one step = forward + backward, as the main value."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import cotangent, radial_regions, random_theta
+    R = 3
+    t = time.time()
+    reg = np.concatenate([
+        radial_regions(b.x[b.node_off[c]:b.node_off[c + 1]],
+                       b.tets[b.tet_off[c]:b.tet_off[c + 1]])
+        for c in range(b.n_cells)])
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets,
+                   tile_tets=args.tile_tets, regions=reg, n_regions=R)
+    rng = np.random.default_rng(args.seed + 9)
+    th = np.array([random_theta(rng) for _ in range(cb.n_mat)])
+    cb.set_params(th[:, 0], th[:, 1], th[:, 2])
+    log(f"regions workload prepared in {time.time() - t:.1f} s: "
+        f"{cb.info['n_tiles']} tiles")
+    dev = cb.device
+    y = cb.to_device(b.y)
+    vbar = cotangent(b.n_nodes, args.seed + 1)
+    fbar = cb.to_device(vbar)
+    ebar_h = np.full(b.n_cells, 0.5)
+    ebar = torch.tensor(ebar_h, dtype=torch.float64, device=dev)
+    f, ybar = cb.empty_nodes(), cb.empty_nodes()
+    E = torch.empty(b.n_cells, dtype=torch.float64, device=dev)
+    tb = torch.empty(3 * cb.n_mat, dtype=torch.float64, device=dev)
+    if args.launch:
+        cb.set_launch(*(int(v) for v in args.launch.split(",")))
+    elif not args.no_autotune:
+        cb.autotune(y)
+    cb.forces(y, f, E)
+    cb.backward(y, fbar, ebar, ybar, tb)
+    torch.cuda.synchronize()
+    # parity: three cells against the oracle's region composition
+    import oracle
+    fh, yh = cb.to_host(f), cb.to_host(ybar)
+    th_h = tb.cpu().numpy().reshape(-1, 3)
+    worst = {"force": 0.0, "ybar": 0.0, "thetabar": 0.0}
+    for c in (0, b.n_cells // 2, b.n_cells - 1) if args.parity_cells else ():
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        t0, t1 = b.tet_off[c], b.tet_off[c + 1]
+        rm = oracle.RegionMesh(b.x[n0:n1], b.tets[t0:t1], reg[t0:t1], R)
+        y64 = b.y[n0:n1].astype(np.float64)
+        fo, _, _ = rm.forces(y64, th[c * R:(c + 1) * R])
+        yo, to = rm.backward(y64, th[c * R:(c + 1) * R],
+                             vbar[n0:n1].astype(np.float64), ebar_h[c])
+        worst["force"] = max(worst["force"], float(
+            np.abs(fh[n0:n1] - fo).max() / np.abs(fo).max()))
+        worst["ybar"] = max(worst["ybar"], float(
+            np.abs(yh[n0:n1] - yo).max() / np.abs(yo).max()))
+        worst["thetabar"] = max(worst["thetabar"], float(
+            np.abs(th_h[c * R:(c + 1) * R] - to).max() / np.abs(to).max()))
+    worst["ok"] = bool(max(worst["force"], worst["ybar"], worst["thetabar"])
+                       <= F_TOL)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        cb.graph_capture(1, y, f, E, None, fbar, ebar, ybar, tb, stream=s)
+    step = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
+    out = {
+        "workload": f"main workload, {R} material regions per cell "
+                    f"(nucleus, cytoplasm, cortex by reference radius), "
+                    f"{cb.n_mat} parameter sets",
+        "n_tiles": cb.info["n_tiles"], "launch": list(cb.get_launch()),
+        "ms_per_step": step, "fwd_bwd_tets_per_s": b.n_tets / (step * 1e-3),
+        "parity": worst,
+    }
+    log(f"regions: {out}")
+    cb.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +394,7 @@ def main():
     ap.add_argument("--template-nodes", type=int, default=1930,
                     help="node target of the shared sphere mesh (~10k tets)")
     ap.add_argument("--no-template", action="store_true")
+    ap.add_argument("--no-regions", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
@@ -447,6 +522,9 @@ def main():
     template = None
     if not args.no_template:
         template = run_template(args)
+    regions = None
+    if not args.no_regions:
+        regions = run_regions(args, b)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -487,6 +565,7 @@ def main():
         "cpu_baseline": cpu,
         "relax": relax,
         "template": template,
+        "regions": regions,
     }
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)

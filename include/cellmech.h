@@ -89,6 +89,7 @@ typedef struct {
   double volume;          /* sum of V0 over all cells                         */
   double min_v0;          /* smallest reference volume                        */
   double max_cond;        /* largest 1-norm condition number of J (ref edges) */
+  int32_t n_regions;      /* material regions per cell (1 without regions)    */
 } cm_info;
 
 /* Message for the last failure on this thread ("" if none). */
@@ -143,6 +144,31 @@ int cm_template_create(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
                        const cm_options* opt, hipStream_t stream,
                        cm_batch* out);
 
+/*
+ * Material regions (the paper notes that the force evaluation is local to a
+ * tetrahedron, so parts of a cell such as the nucleus or an actin cortex can
+ * carry their own elastic parameters: Sec. "Theory", after eq.
+ * elastic-force-vertex-1).  tet_region: host uint8[n_tets], the region of
+ * every tetrahedron in input order, each < n_regions; n_regions in [1, 64].
+ * Every cell then has n_regions material slots: slot c * n_regions + r holds
+ * the (mu, kappa, w) of region r of cell c (cm_set_params) and receives its
+ * gradient (cm_forces_backward thetabar, 3 values per slot).  Energies and
+ * inverted counts stay per cell.  No tile spans two regions (each region is
+ * tiled on its own).  With n_regions = 1 (tet_region may then be NULL) the
+ * handle equals the one of cm_batch_create / cm_template_create.  Errors as
+ * those, plus CM_EINVAL for a region id >= n_regions.
+ */
+int cm_batch_create_regions(int32_t n_cells, const int64_t* node_off,
+                            const int64_t* tet_off, const double* ref_xyz,
+                            const int32_t* tets, const uint8_t* tet_region,
+                            int32_t n_regions, const cm_options* opt,
+                            hipStream_t stream, cm_batch* out);
+int cm_template_create_regions(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                               const double* ref_xyz, const int32_t* tets,
+                               const uint8_t* tet_region, int32_t n_regions,
+                               const cm_options* opt, hipStream_t stream,
+                               cm_batch* out);
+
 /* Frees the handle's device memory and graphs (synchronises the device). */
 int cm_destroy(cm_batch h);
 
@@ -153,9 +179,9 @@ int cm_get_info(cm_batch h, cm_info* out);
 int cm_permutation(cm_batch h, int64_t* new_to_old);
 
 /*
- * cm_set_params: Mooney-Rivlin parameters per cell (mu, kappa, w), with
- * mu1 = w mu, mu2 = (1 - w) mu (Sec. "Theory").  Arrays hold n_cells
- * float64 values each; `on_device` = 0 for host arrays (validated, copied;
+ * cm_set_params: Mooney-Rivlin parameters per material slot (mu, kappa, w),
+ * with mu1 = w mu, mu2 = (1 - w) mu (Sec. "Theory").  Arrays hold
+ * n_cells * n_regions float64 values each (one per cell without regions); `on_device` = 0 for host arrays (validated, copied;
  * the call waits for the copy), 1 for device arrays (device-to-device copy
  * enqueued on `stream`, graph-safe; values are not validated).
  * Host values must be finite with mu >= 0, kappa >= 0, 0 <= w <= 1, else
@@ -184,8 +210,8 @@ int cm_forces(cm_batch h, const float* y, float* f, double* energy,
  *   ybar     : device float32[3 * n_nodes] out:
  *              ybar = (df/dy)^T fbar + ebar dE/dy = -H fbar - ebar f with
  *              H the Hessian of E (a Hessian-vector product per cell).
- *   thetabar : device float64[3 * n_cells] out, per cell
- *              (dL/dmu, dL/dkappa, dL/dw); nullable.
+ *   thetabar : device float64[3 * n_cells * n_regions] out, per material
+ *              slot (dL/dmu, dL/dkappa, dL/dw); nullable.
  * The paper gives first derivatives only; this is their exact derivative.
  */
 int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
@@ -258,7 +284,8 @@ int cm_graph_launch(cm_batch h, hipStream_t stream);
  *   lam = lam_next + m ((df/dy)^T lam_next + dp/dy lam_next)
  *         + 2 scale (F_meas - F_target) dF/dy,
  * where ybar_el = (df/dy)^T lam_next is cm_forces_backward(y, fbar =
- * lam_next); and, if given, thetabar_acc[3c + j] += m thetabar_el[3c + j]
+ * lam_next); and, if given, thetabar_acc[q] += m thetabar_el[q] for the
+ * 3 n_regions entries q of every cell
  * (thetabar_el from the same cm_forces_backward call).  lam must not alias
  * any input.  Errors: CM_EINVAL for null/aliased pointers or negative or
  * non-finite k_plate / mobility.
@@ -318,6 +345,17 @@ int cm_layout_create(int32_t n_cells, const int64_t* node_off,
 int cm_layout_create_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
                               const double* ref_xyz, const int32_t* tets,
                               const cm_options* opt, cm_layout* out);
+/* The preparation of cm_batch_create_regions; cm_layout_export_regions
+ * copies tile_mat int32[n_tiles] (material slot of every tile) and the tiles
+ * of every slot, mat_tile_first / mat_tile_count int32[n_cells * n_regions]
+ * (tiles first + k, k < count). */
+int cm_layout_create_regions(int32_t n_cells, const int64_t* node_off,
+                             const int64_t* tet_off, const double* ref_xyz,
+                             const int32_t* tets, const uint8_t* tet_region,
+                             int32_t n_regions, const cm_options* opt,
+                             cm_layout* out);
+int cm_layout_export_regions(cm_layout l, int32_t* tile_mat,
+                             int32_t* mat_tile_first, int32_t* mat_tile_count);
 int cm_layout_sizes(cm_layout l, int64_t* sizes);
 int cm_layout_export(cm_layout l, int32_t* tiles, void* chunks,
                      int32_t* slot_node, int32_t* shared_node,

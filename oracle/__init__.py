@@ -17,6 +17,11 @@ Routes (see the header of ``cm_oracle.cpp``):
                      overdamped steps (a reading of the paper's unavailable
                      supporting information; parity unpinned by the paper)
                      and its parameter gradient by forward-mode duals
+  * ``RegionMesh``   a cell whose tetrahedra belong to material regions with
+                     their own parameters: the forces and the energy are sums
+                     over tetrahedra (eq. elastic-force-vertex-0), so they are
+                     the sums of the single-material results of each region's
+                     tetrahedra
 """
 from __future__ import annotations
 
@@ -228,3 +233,36 @@ def stress_table(F, theta, lib_path: str = None) -> np.ndarray:
     mu, kappa, w = theta
     lib(lib_path).or_stress_table(_ptr(F), mu, kappa, w, _ptr(P))
     return P.reshape(3, 3)
+
+
+class RegionMesh:
+    """One cell with per-tetrahedron material regions.  The paper's force
+    evaluation is local to each tetrahedron, so parts of a cell can carry
+    their own parameters (Sec. "Theory", after eq. elastic-force-vertex-1).
+    Region r uses thetas[r] = (mu, kappa, w); results are the sums over the
+    regions of OracleMesh results on that region's tetrahedra."""
+
+    def __init__(self, x, tets, regions, n_regions, lib_path: str = None):
+        regions = np.asarray(regions)
+        self.n_regions = int(n_regions)
+        self.parts = [OracleMesh(x, np.asarray(tets)[regions == r], lib_path)
+                      if (regions == r).any() else None
+                      for r in range(self.n_regions)]
+
+    def forces(self, y, thetas):
+        f, E, ninv = 0.0, 0.0, 0
+        for part, th in zip(self.parts, thetas):
+            if part is not None:
+                fr, Er, nr = part.forces(y, tuple(th))
+                f, E, ninv = f + fr, E + Er, ninv + nr
+        return f, E, ninv
+
+    def backward(self, y, thetas, fbar=None, ebar=0.0):
+        """ybar summed over regions and thetabar (n_regions, 3); a region
+        without tetrahedra has a zero gradient."""
+        ybar, tb = 0.0, np.zeros((self.n_regions, 3))
+        for r, (part, th) in enumerate(zip(self.parts, thetas)):
+            if part is not None:
+                yr, tr = part.backward(y, tuple(th), fbar, ebar)
+                ybar, tb[r] = ybar + yr, tr
+        return ybar, tb

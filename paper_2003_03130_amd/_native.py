@@ -36,7 +36,8 @@ class Info(ctypes.Structure):
                 ("tile_tets", ctypes.c_int32),
                 ("max_tile_nodes", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("volume", ctypes.c_double),
-                ("min_v0", ctypes.c_double), ("max_cond", ctypes.c_double)]
+                ("min_v0", ctypes.c_double), ("max_cond", ctypes.c_double),
+                ("n_regions", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -61,6 +62,12 @@ SIGNATURES = {
     "cm_template_create": (_int, [_i32, _i64, _i64, _vp, _vp,
                                   ctypes.POINTER(Options), _vp,
                                   ctypes.POINTER(_vp)]),
+    "cm_batch_create_regions": (_int, [_i32, _vp, _vp, _vp, _vp, _vp, _i32,
+                                       ctypes.POINTER(Options), _vp,
+                                       ctypes.POINTER(_vp)]),
+    "cm_template_create_regions": (_int, [_i32, _i64, _i64, _vp, _vp, _vp,
+                                          _i32, ctypes.POINTER(Options), _vp,
+                                          ctypes.POINTER(_vp)]),
     "cm_destroy": (_int, [_vp]),
     "cm_get_info": (_int, [_vp, ctypes.POINTER(Info)]),
     "cm_permutation": (_int, [_vp, _vp]),
@@ -88,6 +95,10 @@ SIGNATURES = {
     "cm_layout_create_template": (_int, [_i32, _i64, _i64, _vp, _vp,
                                          ctypes.POINTER(Options),
                                          ctypes.POINTER(_vp)]),
+    "cm_layout_create_regions": (_int, [_i32, _vp, _vp, _vp, _vp, _vp, _i32,
+                                        ctypes.POINTER(Options),
+                                        ctypes.POINTER(_vp)]),
+    "cm_layout_export_regions": (_int, [_vp, _vp, _vp, _vp]),
     "cm_layout_sizes": (_int, [_vp, _p64]),
     "cm_layout_export": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),

@@ -1,8 +1,9 @@
 """torch.autograd.Function over the HIP forward/backward kernels.
 
 forward:  (y, theta) -> (f, E) with y the float32 SoA positions (3N,) in the
-          handle's internal node order and theta a float64 (n_cells, 3)
-          device tensor of (mu, kappa, w) per cell.
+          handle's internal node order and theta a float64 (n_mat, 3)
+          device tensor of (mu, kappa, w) per material slot (per cell, or
+          per cell and region for a batch with material regions).
 backward: (dL/df, dL/dE) -> (dL/dy, dL/dtheta) from cm_forces_backward:
           dL/dy is a Hessian-vector product of the energy minus dL/dE times
           the forces; dL/dtheta is exact (f is linear in mu1, mu2, kappa).

@@ -37,6 +37,17 @@ def _options(order, tile_tets, degenerate_tol):
     return o
 
 
+def _regions(regions, n_regions, n_tets):
+    """uint8 region id per tetrahedron and the region count (default:
+    largest id + 1)."""
+    reg = np.asarray(regions)
+    if reg.shape != (n_tets,) or (reg.size and (reg.min() < 0 or reg.max() > 255)):
+        raise ValueError("regions must be one id in [0, 255] per tetrahedron")
+    reg = np.ascontiguousarray(reg, dtype=np.uint8)
+    nr = int(n_regions) if n_regions is not None else int(reg.max()) + 1
+    return reg, nr
+
+
 def _host_inputs(node_off, tet_off, x, tets):
     node_off = np.ascontiguousarray(node_off, dtype=np.int64)
     tet_off = np.ascontiguousarray(tet_off, dtype=np.int64)
@@ -55,14 +66,23 @@ class CellBatch:
     """
 
     def __init__(self, node_off, tet_off, x, tets, order=None, tile_tets=None,
-                 degenerate_tol=None, stream=None):
+                 degenerate_tol=None, stream=None, regions=None,
+                 n_regions=None):
         node_off, tet_off, x, tets = _host_inputs(node_off, tet_off, x, tets)
         self.n_cells = len(node_off) - 1
         opt = _options(order, tile_tets, degenerate_tol)
         h = ctypes.c_void_p()
-        nat.check(nat.lib().cm_batch_create(
-            self.n_cells, _ptr(node_off), _ptr(tet_off), _ptr(x), _ptr(tets),
-            ctypes.byref(opt), _stream(stream), ctypes.byref(h)))
+        if regions is None:
+            nat.check(nat.lib().cm_batch_create(
+                self.n_cells, _ptr(node_off), _ptr(tet_off), _ptr(x),
+                _ptr(tets), ctypes.byref(opt), _stream(stream),
+                ctypes.byref(h)))
+        else:
+            reg, nr = _regions(regions, n_regions, len(tets))
+            nat.check(nat.lib().cm_batch_create_regions(
+                self.n_cells, _ptr(node_off), _ptr(tet_off), _ptr(x),
+                _ptr(tets), _ptr(reg), nr, ctypes.byref(opt), _stream(stream),
+                ctypes.byref(h)))
         self._finish(h, node_off, tet_off)
         self.is_template = False
 
@@ -72,6 +92,8 @@ class CellBatch:
         info = nat.Info()
         nat.check(nat.lib().cm_get_info(self._h, ctypes.byref(info)))
         self.info = info.as_dict()
+        self.n_regions = int(info.n_regions)
+        self.n_mat = self.n_cells * self.n_regions
         self.n_nodes = int(info.n_nodes)
         self.n_tets = int(info.n_tets)
         self.node_off = node_off
@@ -95,7 +117,8 @@ class CellBatch:
 
     @classmethod
     def template(cls, n_cells, x, tets, order=None, tile_tets=None,
-                 degenerate_tol=None, stream=None):
+                 degenerate_tol=None, stream=None, regions=None,
+                 n_regions=None):
         """``n_cells`` copies of one reference mesh (cm_template_create).
 
         The tet data is stored once and shared; node arrays and parameters
@@ -107,9 +130,15 @@ class CellBatch:
         n, m = len(x), len(tets)
         opt = _options(order, tile_tets, degenerate_tol)
         h = ctypes.c_void_p()
-        nat.check(nat.lib().cm_template_create(
-            int(n_cells), n, m, _ptr(x), _ptr(tets), ctypes.byref(opt),
-            _stream(stream), ctypes.byref(h)))
+        if regions is None:
+            nat.check(nat.lib().cm_template_create(
+                int(n_cells), n, m, _ptr(x), _ptr(tets), ctypes.byref(opt),
+                _stream(stream), ctypes.byref(h)))
+        else:
+            reg, nr = _regions(regions, n_regions, m)
+            nat.check(nat.lib().cm_template_create_regions(
+                int(n_cells), n, m, _ptr(x), _ptr(tets), _ptr(reg), nr,
+                ctypes.byref(opt), _stream(stream), ctypes.byref(h)))
         self = cls.__new__(cls)
         self.n_cells = int(n_cells)
         self._finish(h, np.arange(n_cells + 1, dtype=np.int64) * n,
@@ -151,19 +180,27 @@ class CellBatch:
 
     # ------------------------------------------------------------ params
     def set_params(self, mu, kappa, w, stream=None):
-        """Host sequences (validated) or float64 device tensors (n_cells)."""
+        """Host sequences (validated) or float64 device tensors with one
+        value per material slot (cell c, region r at c * n_regions + r; an
+        (n_cells, n_regions) array is taken in that order); host scalars
+        broadcast."""
         import torch
         if isinstance(mu, torch.Tensor):
-            tens = [t.to(self.device, torch.float64).contiguous()
+            tens = [t.to(self.device, torch.float64).contiguous().reshape(-1)
                     for t in (mu, kappa, w)]
+            if any(t.numel() != self.n_mat for t in tens):
+                raise ValueError(f"need {self.n_mat} values per parameter")
             self._param_keep = tens
             nat.check(nat.lib().cm_set_params(
                 self._h, _ptr(tens[0]), _ptr(tens[1]), _ptr(tens[2]), 1,
                 _stream(stream)))
         else:
-            arr = [np.ascontiguousarray(np.broadcast_to(
-                np.asarray(v, dtype=np.float64), (self.n_cells,)))
-                for v in (mu, kappa, w)]
+            arr = []
+            for v in (mu, kappa, w):
+                v = np.asarray(v, dtype=np.float64)
+                v = v.reshape(-1) if v.size == self.n_mat else v
+                arr.append(np.ascontiguousarray(
+                    np.broadcast_to(v, (self.n_mat,))))
             nat.check(nat.lib().cm_set_params(
                 self._h, _ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), 0,
                 _stream(stream)))
@@ -188,7 +225,7 @@ class CellBatch:
         if ybar is None:
             ybar = self.empty_nodes()
         if thetabar is None:
-            thetabar = torch.empty(3 * self.n_cells, dtype=torch.float64,
+            thetabar = torch.empty(3 * self.n_mat, dtype=torch.float64,
                                    device=self.device)
         fn = (nat.lib().cm_forces_backward_percell if percell
               else nat.lib().cm_forces_backward)
@@ -256,13 +293,16 @@ class HostLayout:
     """The prepared tables of cm_layout_* (host only, no GPU needed)."""
 
     def __init__(self, node_off, tet_off, x, tets, order=None, tile_tets=None,
-                 degenerate_tol=None):
+                 degenerate_tol=None, regions=None, n_regions=None):
         node_off, tet_off, x, tets = _host_inputs(node_off, tet_off, x, tets)
         opt = _options(order, tile_tets, degenerate_tol)
         h = ctypes.c_void_p()
-        nat.check(nat.lib().cm_layout_create(
+        reg, nr = (None, 1) if regions is None else _regions(
+            regions, n_regions, len(tets))
+        nat.check(nat.lib().cm_layout_create_regions(
             len(node_off) - 1, _ptr(node_off), _ptr(tet_off), _ptr(x),
-            _ptr(tets), ctypes.byref(opt), ctypes.byref(h)))
+            _ptr(tets), _ptr(reg), nr, ctypes.byref(opt), ctypes.byref(h)))
+        self.n_regions = nr
         self._load(h)
         self.is_template = False
 
@@ -278,6 +318,7 @@ class HostLayout:
             int(n_cells), len(x), len(tets), _ptr(x), _ptr(tets),
             ctypes.byref(opt), ctypes.byref(h)))
         self = cls.__new__(cls)
+        self.n_regions = 1
         self._load(h)
         self.is_template = True
         return self
@@ -303,6 +344,13 @@ class HostLayout:
                 _ptr(self.shared_node), _ptr(self.shared_slot_ptr),
                 _ptr(self.shared_slots), _ptr(self.cell_tile_off),
                 _ptr(self.cell_shared_off), _ptr(self.new_to_old)))
+            nmat = self.n_cells * self.n_regions
+            self.tile_mat = np.zeros(self.n_tiles, dtype=np.int32)
+            self.mat_tile_first = np.zeros(nmat, dtype=np.int32)
+            self.mat_tile_count = np.zeros(nmat, dtype=np.int32)
+            nat.check(nat.lib().cm_layout_export_regions(
+                h, _ptr(self.tile_mat), _ptr(self.mat_tile_first),
+                _ptr(self.mat_tile_count)))
         finally:
             nat.lib().cm_layout_destroy(h)
         ch = raw.reshape(self.n_chunks, 3072)

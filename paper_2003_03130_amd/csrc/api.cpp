@@ -38,6 +38,8 @@ struct cm_batch_s {
   int n_cu = 256;
   int64_t n_cells = 0, n_nodes = 0, n_tets = 0, n_slots = 0, n_shared = 0;
   int64_t n_tiles = 0, n_chunks = 0;
+  int32_t n_regions = 1;
+  int64_t n_mat = 0;  // material slots: n_cells * n_regions
   int32_t tile_tets = 0, max_tile_nodes = 0;
   double volume = 0, min_v0 = 0, max_cond = 0;
   std::vector<int32_t> cell_tile_off, cell_shared_off;
@@ -158,6 +160,8 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
   h->n_cu = prop.multiProcessorCount;
 
   h->n_cells = P.n_cells;
+  h->n_regions = P.n_regions;
+  h->n_mat = P.n_cells * (int64_t)P.n_regions;
   h->n_nodes = P.n_nodes;
   h->n_tets = P.n_tets;
   h->n_slots = (int64_t)P.slot_node.size();
@@ -178,7 +182,7 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
   {
     cm::TileDesc* tiles;
     cm::TetChunk* chunks;
-    int32_t *slot_node, *shared_node, *ssp, *ss, *ctf, *ctc;
+    int32_t *slot_node, *shared_node, *ssp, *ss, *ctf, *ctc, *tmat, *mtf, *mtc;
     int64_t* noff;
     if ((rc = h->upload(&tiles, P.tiles, stream)) ||
         (rc = h->upload(&chunks, P.chunks, stream)) ||
@@ -188,6 +192,9 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
         (rc = h->upload(&ss, P.shared_slots, stream)) ||
         (rc = h->upload(&ctf, P.cell_tile_first, stream)) ||
         (rc = h->upload(&ctc, P.cell_tile_count, stream)) ||
+        (rc = h->upload(&tmat, P.tile_mat, stream)) ||
+        (rc = h->upload(&mtf, P.mat_tile_first, stream)) ||
+        (rc = h->upload(&mtc, P.mat_tile_count, stream)) ||
         (rc = h->upload(&noff, P.node_off, stream)))
       return bail(rc);
     h->d_node_off = noff;
@@ -200,11 +207,14 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     T.cell_tile_first = ctf;
     T.cell_tile_count = ctc;
     T.tile_stride = P.tile_stride;
+    T.tile_mat = tmat;
+    T.mat_tile_first = mtf;
+    T.mat_tile_count = mtc;
     double* params;
     float *part, *part_b;
     double *tile_acc, *tile_acc_b;
     int32_t* tile_ninv;
-    if ((rc = h->alloc(&params, 3 * (size_t)h->n_cells)) ||
+    if ((rc = h->alloc(&params, 3 * (size_t)h->n_mat)) ||
         (rc = h->alloc(&part, 3 * (size_t)h->n_slots)) ||
         (rc = h->alloc(&part_b, 3 * (size_t)h->n_slots)) ||
         (rc = h->alloc(&tile_acc, (size_t)h->n_tiles)) ||
@@ -225,6 +235,8 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     t->n_slots = h->n_slots;
     t->n_tiles = h->n_tiles;
     t->n_cells = (int32_t)h->n_cells;
+    t->n_regions = h->n_regions;
+    t->n_mat = (int32_t)h->n_mat;
     t->nloc = (h->max_tile_nodes + 3) & ~3;
     if (t->nloc == 0) t->nloc = 4;
   }
@@ -250,7 +262,25 @@ int cm_batch_create(int32_t n_cells, const int64_t* node_off,
   const cm::PrepOptions po = prep_options(opt);
   cm::Prepared P;
   std::string err;
-  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &P, &err);
+  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, nullptr, 1,
+                             po, &P, &err);
+  if (rc != CM_OK) return fail(rc, err);
+  return create_from(P, po, stream, out);
+}
+
+int cm_batch_create_regions(int32_t n_cells, const int64_t* node_off,
+                            const int64_t* tet_off, const double* ref_xyz,
+                            const int32_t* tets, const uint8_t* tet_region,
+                            int32_t n_regions, const cm_options* opt,
+                            hipStream_t stream, cm_batch* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  const cm::PrepOptions po = prep_options(opt);
+  cm::Prepared P;
+  std::string err;
+  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, tet_region,
+                             n_regions, po, &P, &err);
   if (rc != CM_OK) return fail(rc, err);
   return create_from(P, po, stream, out);
 }
@@ -267,7 +297,27 @@ int cm_template_create(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   const cm::PrepOptions po = prep_options(opt);
   cm::Prepared P;
   std::string err;
-  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, po, &P, &err);
+  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, nullptr, 1,
+                                po, &P, &err);
+  if (rc != CM_OK) return fail(rc, err);
+  return create_from(P, po, stream, out);
+}
+
+int cm_template_create_regions(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
+                               const double* ref_xyz, const int32_t* tets,
+                               const uint8_t* tet_region, int32_t n_regions,
+                               const cm_options* opt, hipStream_t stream,
+                               cm_batch* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  if (!ref_xyz || !tets || n_nodes < 0 || n_tets < 0)
+    return fail(CM_EINVAL, "null pointer or negative size");
+  const cm::PrepOptions po = prep_options(opt);
+  cm::Prepared P;
+  std::string err;
+  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, tet_region,
+                                n_regions, po, &P, &err);
   if (rc != CM_OK) return fail(rc, err);
   return create_from(P, po, stream, out);
 }
@@ -304,6 +354,7 @@ int cm_get_info(cm_batch h, cm_info* o) {
   o->volume = h->volume;
   o->min_v0 = h->min_v0;
   o->max_cond = h->max_cond;
+  o->n_regions = h->n_regions;
   return CM_OK;
 }
 
@@ -319,7 +370,7 @@ int cm_set_params(cm_batch h, const double* mu, const double* kappa,
   if (int rc = check_handle(h)) return rc;
   if (!mu || !kappa || !w) return fail(CM_EINVAL, "null parameter array");
   if (int rc = select_device(h)) return rc;
-  const size_t n = (size_t)h->n_cells;
+  const size_t n = (size_t)h->n_mat;
   double* dst = const_cast<double*>(h->T.params);
   if (on_device) {
     CM_HIP(hipMemcpyAsync(dst, mu, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
@@ -330,7 +381,7 @@ int cm_set_params(cm_batch h, const double* mu, const double* kappa,
     for (size_t c = 0; c < n; ++c) {
       if (!std::isfinite(mu[c]) || !std::isfinite(kappa[c]) || !std::isfinite(w[c]) ||
           mu[c] < 0 || kappa[c] < 0 || w[c] < 0 || w[c] > 1)
-        return fail(CM_EINVAL, "cell " + std::to_string(c) +
+        return fail(CM_EINVAL, "material slot " + std::to_string(c) +
                                    ": parameters must be finite with mu >= 0, "
                                    "kappa >= 0, 0 <= w <= 1");
       buf[c] = mu[c];
@@ -510,7 +561,7 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   if (hipMalloc((void**)&f, n3 * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&ybar, n3 * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&energy, h->n_cells * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&tb, 3 * h->n_cells * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&tb, 3 * h->n_mat * sizeof(double)) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     return fail(CM_ENOMEM, "autotune scratch allocation failed");
@@ -602,7 +653,7 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
   CM_HIP(cm::launch_plate_adjoint(h->d_node_off, h->n_nodes, (int32_t)h->n_cells,
                                   y, lam_next, ybar_el, plate, k_plate, mobility,
                                   F_meas, F_target, scale, thetabar_el,
-                                  thetabar_acc, lam, stream));
+                                  thetabar_acc, h->n_regions, lam, stream));
   return CM_OK;
 }
 
@@ -706,6 +757,15 @@ int cm_layout_create(int32_t n_cells, const int64_t* node_off,
                      const int64_t* tet_off, const double* ref_xyz,
                      const int32_t* tets, const cm_options* opt,
                      cm_layout* out) {
+  return cm_layout_create_regions(n_cells, node_off, tet_off, ref_xyz, tets,
+                                  nullptr, 1, opt, out);
+}
+
+int cm_layout_create_regions(int32_t n_cells, const int64_t* node_off,
+                             const int64_t* tet_off, const double* ref_xyz,
+                             const int32_t* tets, const uint8_t* tet_region,
+                             int32_t n_regions, const cm_options* opt,
+                             cm_layout* out) {
   g_err.clear();
   if (!out) return fail(CM_EINVAL, "out is null");
   *out = nullptr;
@@ -713,7 +773,8 @@ int cm_layout_create(int32_t n_cells, const int64_t* node_off,
   if (!l) return fail(CM_ENOMEM, "host allocation failed");
   const cm::PrepOptions po = prep_options(opt);
   std::string err;
-  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, po, &l->P, &err);
+  int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, tet_region,
+                             n_regions, po, &l->P, &err);
   if (rc != CM_OK) {
     delete l;
     return fail(rc, err);
@@ -735,7 +796,8 @@ int cm_layout_create_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   if (!l) return fail(CM_ENOMEM, "host allocation failed");
   const cm::PrepOptions po = prep_options(opt);
   std::string err;
-  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, po, &l->P, &err);
+  int rc = cm::prepare_template(n_cells, n_nodes, n_tets, ref_xyz, tets, nullptr, 1,
+                                po, &l->P, &err);
   if (rc != CM_OK) {
     delete l;
     return fail(rc, err);
@@ -777,6 +839,19 @@ int cm_layout_export(cm_layout l, int32_t* tiles, void* chunks,
   cp(cell_tile_off, P.cell_tile_off.data(), P.cell_tile_off.size() * 4);
   cp(cell_shared_off, P.cell_shared_off.data(), P.cell_shared_off.size() * 4);
   cp(new_to_old, P.new_to_old.data(), P.new_to_old.size() * 8);
+  return CM_OK;
+}
+
+int cm_layout_export_regions(cm_layout l, int32_t* tile_mat,
+                             int32_t* mat_tile_first, int32_t* mat_tile_count) {
+  if (!l) return fail(CM_EINVAL, "null layout");
+  const cm::Prepared& P = l->P;
+  auto cp = [](void* dst, const void* src, size_t bytes) {
+    if (dst && bytes) std::memcpy(dst, src, bytes);
+  };
+  cp(tile_mat, P.tile_mat.data(), P.tile_mat.size() * 4);
+  cp(mat_tile_first, P.mat_tile_first.data(), P.mat_tile_first.size() * 4);
+  cp(mat_tile_count, P.mat_tile_count.data(), P.mat_tile_count.size() * 4);
   return CM_OK;
 }
 

@@ -1,7 +1,7 @@
 // Backward (adjoint) kernels for gfx950: for a loss L(f, E) with cotangents
 // fbar = dL/df (per node) and ebar = dL/dE (per cell),
 //   ybar     = (df/dy)^T fbar - ebar f  (a Hessian-vector product of E),
-//   thetabar = dL/d(mu, kappa, w) per cell.
+//   thetabar = dL/d(mu, kappa, w) per material slot (cell and region).
 // Same tiling as the forward kernel: one wavefront per tile; positions and
 // fbar of the tile's nodes are staged in LDS, ybar is accumulated in LDS slot
 // by slot without atomics (see layout.h), owned nodes are stored directly and
@@ -43,10 +43,10 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   block_tiles(a.r, t0, t1);
   for (int t = t0 + wave; t < t1; t += W) {
     const TileDesc d = a.T.tiles[t];
-    const int nc = a.T.n_cells;
-    const double mu = a.T.params[d.cell];
-    const double kappa = a.T.params[nc + d.cell];
-    const double w = a.T.params[2 * nc + d.cell];
+    const int mt = a.T.tile_mat[t], nm = a.T.n_mat;
+    const double mu = a.T.params[mt];
+    const double kappa = a.T.params[nm + mt];
+    const double w = a.T.params[2 * nm + mt];
     const Material mat{w * mu, (1.0 - w) * mu, kappa};
     const double eb = a.ebar ? a.ebar[d.cell] : 0.0;
 
@@ -121,7 +121,7 @@ struct BwdFinArgs {
   double* thetabar;  // nullable
 };
 
-// Shared-node slot sums in tile order, and per cell
+// Shared-node slot sums in tile order, and per material slot
 //   dL/dmu = w g_I + (1 - w) g_K, dL/dkappa = g_J, dL/dw = mu (g_I - g_K)
 // from the per-tile sums of dL/d(mu1, mu2, kappa) (mu1 = w mu, mu2 = (1-w) mu).
 __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
@@ -140,21 +140,22 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
     const int64_t g = a.T.shared_node[s];
     a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
   }
-  if (a.thetabar && gid < a.r.cell_end - a.r.cell_begin) {
-    const int c = a.r.cell_begin + (int)gid;
+  const int R = a.T.n_regions;
+  if (a.thetabar && gid < (int64_t)(a.r.cell_end - a.r.cell_begin) * R) {
+    const int mt = a.r.cell_begin * R + (int)gid;  // material slot
     double gI = 0.0, gK = 0.0, gJ = 0.0;
-    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
+    const int t0 = a.T.mat_tile_first[mt], nt = a.T.mat_tile_count[mt];
     for (int k = 0; k < nt; ++k) {
       const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
       gI += a.T.tile_acc[3 * t];
       gK += a.T.tile_acc[3 * t + 1];
       gJ += a.T.tile_acc[3 * t + 2];
     }
-    const int nc = a.T.n_cells;
-    const double mu = a.T.params[c], w = a.T.params[2 * nc + c];
-    a.thetabar[3 * (int64_t)c] = w * gI + (1.0 - w) * gK;
-    a.thetabar[3 * (int64_t)c + 1] = gJ;
-    a.thetabar[3 * (int64_t)c + 2] = mu * (gI - gK);
+    const int nm = a.T.n_mat;
+    const double mu = a.T.params[mt], w = a.T.params[2 * nm + mt];
+    a.thetabar[3 * (int64_t)mt] = w * gI + (1.0 - w) * gK;
+    a.thetabar[3 * (int64_t)mt + 1] = gJ;
+    a.thetabar[3 * (int64_t)mt + 2] = mu * (gI - gK);
   }
 }
 
@@ -188,8 +189,8 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
 hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
                                     float* ybar, double* thetabar,
                                     hipStream_t st) {
-  const int64_t work = std::max<int64_t>(r.shared_end - r.shared_begin,
-                                         r.cell_end - r.cell_begin);
+  const int64_t work = std::max<int64_t>(
+      r.shared_end - r.shared_begin, (int64_t)(r.cell_end - r.cell_begin) * T.n_regions);
   if (work <= 0) return hipSuccess;
   BwdFinArgs b{T, r, ybar, thetabar};
   hipLaunchKernelGGL(backward_finalize_kernel,

@@ -20,7 +20,14 @@ struct DeviceTables {
   const int32_t* cell_tile_first = nullptr;
   const int32_t* cell_tile_count = nullptr;
   int32_t tile_stride = 1;
-  const double* params = nullptr;  // SoA: mu[n_cells], kappa[n_cells], w[n_cells]
+  // material slot of every tile (cell * n_regions + region); tiles of slot
+  // m: mat_tile_first[m] + k * tile_stride, k < mat_tile_count[m]
+  const int32_t* tile_mat = nullptr;
+  const int32_t* mat_tile_first = nullptr;
+  const int32_t* mat_tile_count = nullptr;
+  int32_t n_regions = 1;
+  int32_t n_mat = 0;               // n_cells * n_regions
+  const double* params = nullptr;  // SoA: mu[n_mat], kappa[n_mat], w[n_mat]
   float* part = nullptr;           // slot partials, (x, y, z) per slot
   double* tile_acc = nullptr;      // per tile: energy (fwd) or 3 sums (bwd)
   int32_t* tile_ninv = nullptr;    // per tile
@@ -80,7 +87,7 @@ hipError_t launch_plate_adjoint(const int64_t* node_off, int64_t N,
                                 const double* plate, double k, double m,
                                 const double* F_meas, const double* F_target,
                                 double scale, const double* thetabar_el,
-                                double* thetabar_acc, float* lam,
+                                double* thetabar_acc, int n_regions, float* lam,
                                 hipStream_t st);
 
 }  // namespace cm

@@ -38,10 +38,10 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
   block_tiles(a.r, t0, t1);
   for (int t = t0 + wave; t < t1; t += W) {
     const TileDesc d = a.T.tiles[t];
-    const int nc = a.T.n_cells;
-    const double mu = a.T.params[d.cell];
-    const double kappa = a.T.params[nc + d.cell];
-    const double w = a.T.params[2 * nc + d.cell];
+    const int mt = a.T.tile_mat[t], nm = a.T.n_mat;
+    const double mu = a.T.params[mt];
+    const double kappa = a.T.params[nm + mt];
+    const double w = a.T.params[2 * nm + mt];
     const Material mat{w * mu, (1.0 - w) * mu, kappa};
 
     for (int l = lane; l < d.n_own + d.n_shr; l += 64) {

@@ -17,6 +17,7 @@ namespace cm {
 
 constexpr int kChunk = 64;          // tetrahedra per chunk = lanes per wave
 constexpr int kMaxTileTets = 4096;  // keeps local indices below 2^16
+constexpr int kMaxRegions = 64;     // material regions per cell
 
 // 32 bytes, read with scalar loads.
 struct TileDesc {

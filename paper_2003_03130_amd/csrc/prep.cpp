@@ -26,6 +26,8 @@ struct CellOut {
   std::vector<int32_t> shared_slot_ptr;
   std::vector<int32_t> shared_slots;  // local slot ids
   std::vector<int64_t> new_to_old;    // local
+  std::vector<int32_t> tile_region;   // region of every tile
+  std::vector<int32_t> region_tile_first, region_tile_count;  // local tiles
   int32_t max_tile_nodes = 0;
   double volume = 0.0, min_v0 = INFINITY, max_cond = 0.0;
 };
@@ -193,7 +195,8 @@ struct Perms {
 const Perms kPerms;
 
 void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
-                  const int32_t* T, const PrepOptions& opt, CellOut& out) {
+                  const int32_t* T, const uint8_t* region, int32_t n_regions,
+                  const PrepOptions& opt, CellOut& out) {
   auto fail = [&](int st, const std::string& msg) {
     out.status = st;
     out.err = "cell " + std::to_string(c) + ": " + msg;
@@ -215,6 +218,11 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
   }
   for (int64_t q = 0; q < 3 * n; ++q)
     if (!std::isfinite(X[q])) return fail(CM_EINVAL, "non-finite reference position");
+  if (region)
+    for (int64_t t = 0; t < m; ++t)
+      if ((int32_t)region[t] >= n_regions)
+        return fail(CM_EINVAL, "tetrahedron " + std::to_string(t) +
+                                   " has a region id >= n_regions");
 
   // FP64 precompute: J_ik = x_i^k - x_i^4, B = J^-1, V0 = |det J| / 6
   // (checked and summarised here in the input vertex order; recomputed for
@@ -258,16 +266,39 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
     std::iota(perm.begin(), perm.end(), 0);
   }
 
+  // Material regions: the tetrahedra of each region are contiguous in the
+  // order (stable, so the locality order holds inside a region) and no tile
+  // spans two regions, so every tile has one material.
+  if (region && n_regions > 1)
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+      return region[a] < region[b];
+    });
   const int64_t TT = opt.tile_tets;
-  const int64_t n_tiles = (m + TT - 1) / TT;
+  std::vector<int64_t> tlo, thi;  // tet range [tlo, thi) of every tile in the order
+  out.region_tile_first.assign(n_regions, 0);
+  out.region_tile_count.assign(n_regions, 0);
+  for (int64_t p = 0; p < m;) {
+    const int32_t r = region ? (int32_t)region[perm[p]] : 0;
+    int64_t e = p;
+    while (e < m && (region ? (int32_t)region[perm[e]] : 0) == r) ++e;
+    out.region_tile_first[r] = (int32_t)tlo.size();
+    for (int64_t a = p; a < e; a += TT) {
+      tlo.push_back(a);
+      thi.push_back(std::min(e, a + TT));
+      out.tile_region.push_back(r);
+    }
+    out.region_tile_count[r] = (int32_t)tlo.size() - out.region_tile_first[r];
+    p = e;
+  }
+  const int64_t n_tiles = (int64_t)tlo.size();
   // Number of distinct tiles touching each node.
   std::vector<int32_t> last(n, -1), ntile(n, 0);
-  for (int64_t p = 0; p < m; ++p) {
-    int32_t k = (int32_t)(p / TT);
-    const int32_t* v = T + 4 * perm[p];
-    for (int a = 0; a < 4; ++a)
-      if (last[v[a]] != k) { last[v[a]] = k; ntile[v[a]]++; }
-  }
+  for (int64_t k = 0; k < n_tiles; ++k)
+    for (int64_t p = tlo[k]; p < thi[k]; ++p) {
+      const int32_t* v = T + 4 * perm[p];
+      for (int a = 0; a < 4; ++a)
+        if (last[v[a]] != (int32_t)k) { last[v[a]] = (int32_t)k; ntile[v[a]]++; }
+    }
   // Internal numbering: owned nodes tile by tile, then shared nodes in order
   // of first appearance, then nodes no tetrahedron uses.
   std::vector<int32_t> newid(n, -1);
@@ -275,7 +306,7 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
   int32_t next = 0;
   for (int64_t k = 0; k < n_tiles; ++k) {
     own_begin[k] = next;
-    for (int64_t p = k * TT; p < std::min(m, (k + 1) * TT); ++p) {
+    for (int64_t p = tlo[k]; p < thi[k]; ++p) {
       const int32_t* v = T + 4 * perm[p];
       for (int a = 0; a < 4; ++a)
         if (ntile[v[a]] == 1 && newid[v[a]] < 0) newid[v[a]] = next++;
@@ -303,7 +334,7 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
   struct Placed { int32_t chunk, lane; int32_t v[4]; };
   std::vector<Placed> placed;
   for (int64_t k = 0; k < n_tiles; ++k) {
-    const int64_t p0 = k * TT, p1 = std::min(m, (k + 1) * TT);
+    const int64_t p0 = tlo[k], p1 = thi[k];
     TileDesc& d = out.tiles[k];
     d.chunk_begin = (int32_t)out.chunks.size();
     d.n_tets = (int32_t)(p1 - p0);
@@ -411,10 +442,20 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
 
 int prepare_batch(int32_t n_cells, const int64_t* node_off,
                   const int64_t* tet_off, const double* ref_xyz,
-                  const int32_t* tets, const PrepOptions& opt, Prepared* P,
+                  const int32_t* tets, const uint8_t* tet_region,
+                  int32_t n_regions, const PrepOptions& opt, Prepared* P,
                   std::string* err) {
   if (n_cells <= 0 || !node_off || !tet_off || !ref_xyz || !tets) {
     *err = "null pointer or n_cells <= 0";
+    return CM_EINVAL;
+  }
+  if (n_regions < 1 || n_regions > kMaxRegions || (n_regions > 1 && !tet_region)) {
+    *err = "n_regions must be in [1, " + std::to_string(kMaxRegions) +
+           "] (with a region array when > 1)";
+    return CM_EINVAL;
+  }
+  if ((int64_t)n_cells * n_regions >= 0x7fffffffLL) {
+    *err = "too many material slots";
     return CM_EINVAL;
   }
   if (opt.tile_tets < kChunk || opt.tile_tets > kMaxTileTets || opt.tile_tets % kChunk) {
@@ -448,7 +489,9 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
       int32_t c = next_cell.fetch_add(1);
       if (c >= n_cells) break;
       prepare_cell(c, node_off[c + 1] - node_off[c], tet_off[c + 1] - tet_off[c],
-                   ref_xyz + 3 * node_off[c], tets + 4 * tet_off[c], opt, cells[c]);
+                   ref_xyz + 3 * node_off[c], tets + 4 * tet_off[c],
+                   tet_region ? tet_region + tet_off[c] : nullptr, n_regions, opt,
+                   cells[c]);
     }
   };
   std::vector<std::thread> pool;
@@ -486,6 +529,10 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
   P->cell_shared_off.resize(n_cells + 1);
   P->node_off.assign(node_off, node_off + n_cells + 1);
   P->new_to_old.resize(P->n_nodes);
+  P->n_regions = n_regions;
+  P->tile_mat.resize(n_tiles);
+  P->mat_tile_first.resize((size_t)n_cells * n_regions);
+  P->mat_tile_count.resize((size_t)n_cells * n_regions);
   P->volume = 0.0;
   P->min_v0 = INFINITY;
   P->max_cond = 0.0;
@@ -503,6 +550,11 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
       d.own_begin += nb;
       d.shr_begin += (int32_t)sb;
       P->tiles[tb + k] = d;
+      P->tile_mat[tb + k] = c * n_regions + cell.tile_region[k];
+    }
+    for (int32_t r = 0; r < n_regions; ++r) {
+      P->mat_tile_first[(size_t)c * n_regions + r] = (int32_t)tb + cell.region_tile_first[r];
+      P->mat_tile_count[(size_t)c * n_regions + r] = cell.region_tile_count[r];
     }
     std::memcpy(P->chunks.data() + cb, cell.chunks.data(),
                 sizeof(TetChunk) * cell.chunks.size());
@@ -540,6 +592,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
 
 int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
                      const double* ref_xyz, const int32_t* tets,
+                     const uint8_t* tet_region, int32_t n_regions,
                      const PrepOptions& opt, Prepared* P, std::string* err) {
   if (n_cells <= 0) {
     *err = "n_cells must be positive";
@@ -547,12 +600,15 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   }
   const int64_t no[2] = {0, n_nodes}, to[2] = {0, n_tets};
   Prepared one;
-  int rc = prepare_batch(1, no, to, ref_xyz, tets, opt, &one, err);
+  int rc = prepare_batch(1, no, to, ref_xyz, tets, tet_region, n_regions, opt,
+                         &one, err);
   if (rc != CM_OK) return rc;
   const int64_t C = n_cells, N = n_nodes;
   const int64_t T1 = (int64_t)one.tiles.size(), S1 = (int64_t)one.slot_node.size();
   const int64_t H1 = (int64_t)one.shared_node.size();
-  if (C * N >= 0x7fffffffLL || C * T1 >= 0x7fffffffLL || C * S1 >= 0x7fffffffLL) {
+  const int64_t R = n_regions;
+  if (C * N >= 0x7fffffffLL || C * T1 >= 0x7fffffffLL || C * S1 >= 0x7fffffffLL ||
+      C * R >= 0x7fffffffLL) {
     *err = "template batch too large for 32-bit tables";
     return CM_EINVAL;
   }
@@ -561,6 +617,7 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   P->n_tets = C * n_tets;
   P->chunks = std::move(one.chunks);
   P->tiles.resize(C * T1);
+  P->tile_mat.resize(C * T1);
   for (int64_t k = 0; k < T1; ++k)
     for (int64_t c = 0; c < C; ++c) {
       TileDesc d = one.tiles[k];
@@ -568,6 +625,15 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
       d.shr_begin += (int32_t)(c * S1);
       d.cell = (int32_t)c;
       P->tiles[k * C + c] = d;
+      P->tile_mat[k * C + c] = (int32_t)(c * R) + one.tile_mat[k];
+    }
+  P->n_regions = n_regions;
+  P->mat_tile_first.resize(C * R);
+  P->mat_tile_count.resize(C * R);
+  for (int64_t c = 0; c < C; ++c)
+    for (int64_t r = 0; r < R; ++r) {
+      P->mat_tile_first[c * R + r] = (int32_t)(c + one.mat_tile_first[r] * C);
+      P->mat_tile_count[c * R + r] = one.mat_tile_count[r];
     }
   P->slot_node.resize(C * S1);
   P->shared_slots.resize(C * S1);

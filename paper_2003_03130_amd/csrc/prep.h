@@ -27,6 +27,13 @@ struct Prepared {
   std::vector<int32_t> cell_tile_first;  // n_cells: first tile of the cell
   std::vector<int32_t> cell_tile_count;  // n_cells: tiles of the cell
   int32_t tile_stride = 1;               // distance between a cell's tiles
+  // Materials: slot c * n_regions + r holds the parameters of region r of
+  // cell c; every tile lies in one region.  Tiles of a slot:
+  // mat_tile_first[slot] + k * tile_stride, k < mat_tile_count[slot].
+  int32_t n_regions = 1;
+  std::vector<int32_t> tile_mat;          // n_tiles
+  std::vector<int32_t> mat_tile_first;    // n_cells * n_regions
+  std::vector<int32_t> mat_tile_count;
   std::vector<int32_t> cell_shared_off;  // n_cells + 1
   std::vector<int64_t> node_off;         // n_cells + 1 (same as input)
   std::vector<int64_t> new_to_old;       // n_nodes
@@ -40,13 +47,17 @@ struct Prepared {
 // slot and shared-node tables are replicated per cell with offsets, ordered
 // template tile major and cell minor (tile k of every cell, then tile k + 1),
 // so cell_tile_off is empty and the tiles of cell c are c + k * n_cells.
+// tet_region (nullable, per tetrahedron in input order, each < n_regions)
+// splits every cell into material regions.
 int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
                      const double* ref_xyz, const int32_t* tets,
+                     const uint8_t* tet_region, int32_t n_regions,
                      const PrepOptions& opt, Prepared* out, std::string* err);
 
 int prepare_batch(int32_t n_cells, const int64_t* node_off,
                   const int64_t* tet_off, const double* ref_xyz,
-                  const int32_t* tets, const PrepOptions& opt, Prepared* out,
+                  const int32_t* tets, const uint8_t* tet_region,
+                  int32_t n_regions, const PrepOptions& opt, Prepared* out,
                   std::string* err);
 
 }  // namespace cm

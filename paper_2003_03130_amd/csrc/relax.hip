@@ -75,6 +75,7 @@ struct AdjArgs {
   double scale;
   const double* thetabar_el;  // nullable (with thetabar_acc)
   double* thetabar_acc;
+  int n_regions;              // material slots per cell (3 gradient entries each)
   float* lam;
 };
 
@@ -97,8 +98,11 @@ __global__ __launch_bounds__(kRelaxThreads) void plate_adjoint_kernel(AdjArgs a)
     a.lam[2 * N + i] = lz + m * (a.ybar_el[2 * N + i] - 2.f * k * (dt + db) * lz) +
                        g * 2.f * k * dt;
   }
-  if (threadIdx.x < 3 && a.thetabar_acc)
-    a.thetabar_acc[3 * c + threadIdx.x] += a.m * a.thetabar_el[3 * c + threadIdx.x];
+  const int nq = 3 * a.n_regions;
+  if ((int)threadIdx.x < nq && a.thetabar_acc) {
+    const int64_t q = (int64_t)nq * c + threadIdx.x;
+    a.thetabar_acc[q] += a.m * a.thetabar_el[q];
+  }
 }
 
 }  // namespace
@@ -118,10 +122,10 @@ hipError_t launch_plate_adjoint(const int64_t* node_off, int64_t N,
                                 const double* plate, double k, double m,
                                 const double* F_meas, const double* F_target,
                                 double scale, const double* thetabar_el,
-                                double* thetabar_acc, float* lam,
+                                double* thetabar_acc, int n_regions, float* lam,
                                 hipStream_t st) {
   AdjArgs a{node_off, N, y, lam_next, ybar_el, plate, k, m, F_meas, F_target,
-            scale, thetabar_el, thetabar_acc, lam};
+            scale, thetabar_el, thetabar_acc, n_regions, lam};
   hipLaunchKernelGGL(plate_adjoint_kernel, dim3(n_cells), dim3(kRelaxThreads), 0, st, a);
   return hipGetLastError();
 }

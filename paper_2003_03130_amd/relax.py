@@ -58,12 +58,13 @@ class PlateCompression:
         nn = 3 * batch.n_nodes
         self._f = torch.empty(nn, dtype=torch.float32, device=dev)
         self._ybar = torch.empty(nn, dtype=torch.float32, device=dev)
-        self._tb = torch.empty(3 * batch.n_cells, dtype=torch.float64,
+        self._tb = torch.empty(3 * batch.n_mat, dtype=torch.float64,
                                device=dev)
         self._E = torch.empty(batch.n_cells, dtype=torch.float64, device=dev)
 
     def set_theta(self, theta):
-        """theta: (n_cells, 3) host array or float64 device tensor."""
+        """theta: (n_mat, 3) host array or float64 device tensor, one row
+        per material slot (one per cell without regions)."""
         import torch
         if isinstance(theta, torch.Tensor):
             t = theta.to(self.cb.device, torch.float64)
@@ -95,7 +96,7 @@ class PlateCompression:
         return F, y, kept
 
     def gradient(self, y0, F_target, scale):
-        """Loss and dL/dtheta (n_cells, 3) by checkpointed reverse mode.
+        """Loss and dL/dtheta (n_mat, 3) by checkpointed reverse mode.
         F_target: (N, n_cells) float64 device tensor."""
         import torch
         N, C = self.n_steps, self.checkpoint
@@ -104,7 +105,7 @@ class PlateCompression:
         cb = self.cb
         lam = torch.zeros(3 * cb.n_nodes, dtype=torch.float32, device=cb.device)
         lam_new = torch.empty_like(lam)
-        tacc = torch.zeros(3 * cb.n_cells, dtype=torch.float64,
+        tacc = torch.zeros(3 * cb.n_mat, dtype=torch.float64,
                            device=cb.device)
         seg_states = [torch.empty_like(lam) for _ in range(C)]
         spare = torch.empty_like(lam)

@@ -254,6 +254,19 @@ def template_batch(n_cells, n_target, seed) -> Batch:
     return b
 
 
+def radial_regions(x, tets, r_nucleus=0.45, r_cortex=0.85):
+    """Material region of every tetrahedron from the distance of its
+    reference centroid to the cell's centre of mass (radius-normalised):
+    1 = nucleus (< r_nucleus), 2 = cortex shell (> r_cortex), 0 = cytoplasm."""
+    c = x[tets].mean(axis=1)
+    c = c - x.mean(axis=0)
+    r = np.linalg.norm(c, axis=1) / np.linalg.norm(x - x.mean(axis=0), axis=1).max()
+    reg = np.zeros(len(tets), dtype=np.uint8)
+    reg[r < r_nucleus] = 1
+    reg[r > r_cortex] = 2
+    return reg
+
+
 # ---------------------------------------------------------------- plates
 STOKES_DT = 1e-3      # time step of the compression runs
 DRAG = 0.25           # uniform nodal drag; mobility = STOKES_DT / DRAG

@@ -527,9 +527,48 @@ def pin_relax_contact(lib_path=None):
     assert bot - yf[:, 2].min() < 0.25
 
 
+def pin_region_composition(lib_path=None):
+    """Material regions: the composed cell is one energy, E = sum over
+    tetrahedra of V0 U with each tetrahedron's own parameters.  With equal
+    parameters it is the single-material cell; its forces are -grad E and
+    each region's thetabar is the difference quotient of the loss in that
+    region's parameters."""
+    x, tets, y = _tiny_noisy()
+    from synth.configs import radial_regions
+    reg = radial_regions(x, tets, 0.5, 0.8)
+    assert len(np.unique(reg)) == 3
+    rm = oracle.RegionMesh(x, tets, reg, 3, lib_path)
+    one = oracle.OracleMesh(x, tets, lib_path)
+    theta = (1.3, 25.0, 0.4)
+    f1, E1, _ = one.forces(y, theta)
+    fr, Er, _ = rm.forces(y, [theta] * 3)
+    assert rel_max(fr, f1) <= 1e-13 and abs(Er - E1) <= 1e-13 * abs(E1)
+    thetas = [(1.0, 20.0, 0.3), (4.0, 60.0, 0.8), (2.0, 10.0, 0.0)]
+    f, E, _ = rm.forces(y, thetas)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        v = rng.normal(size=y.shape)
+
+        def g(e, v=v):
+            return rm.forces(y + e * v, thetas)[1]
+        assert abs(d1_5pt(g, 1e-4) + (f * v).sum()) <= 1e-8 * np.abs(f * v).sum()
+    fbar = rng.normal(size=y.shape)
+    ebar = 0.6
+    _, tb = rm.backward(y, thetas, fbar, ebar)
+    for r in range(3):
+        for k, h in ((0, 1e-4), (1, 1e-3), (2, 1e-4)):
+            def L(e, r=r, k=k):
+                th = [list(t) for t in thetas]
+                th[r][k] += e
+                ff, EE, _ = rm.forces(y, th)
+                return (fbar * ff).sum() + ebar * EE
+            assert abs(d1_5pt(L, h) - tb[r, k]) <= 1e-8 * np.abs(tb).max()
+
+
 ALL_PINS = [pin_reference_configuration, pin_momentum_balance,
             pin_frame_indifference, pin_gradient_fd, pin_table_vs_ad,
             pin_homogeneous, pin_small_strain, pin_neo_hookean,
             pin_parameter_linearity, pin_worked_example, pin_two_tet_assembly,
             pin_inverted_tet, pin_hvp_fd, pin_thetabar, pin_relax_gradient_fd,
-            pin_relax_rest_state, pin_relax_descent, pin_relax_contact]
+            pin_relax_rest_state, pin_relax_descent, pin_relax_contact,
+            pin_region_composition]

@@ -8,7 +8,7 @@ import re
 import numpy as np
 import pytest
 
-from synth.configs import small_sphere_case, uneven_batch
+from synth.configs import radial_regions, small_sphere_case, uneven_batch
 from synth.mesh import sphere_mesh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -243,6 +243,74 @@ def test_template_layout_replicates_one_cell():
     got = np.empty_like(out)
     got[LT.new_to_old] = out
     assert np.allclose(got, direct, rtol=0, atol=1e-12)
+
+
+def test_region_layout_tiles_one_region_each():
+    """cm_layout_create_regions: still a relabelling of every cell's
+    tetrahedra; every tile holds tetrahedra of one region only, the one its
+    material slot names; the tiles of each slot are its first/count range; a
+    region without tetrahedra in a cell gets no tiles."""
+    from paper_2003_03130_amd import HostLayout
+    b = _batch(4)
+    R = 4  # region 3 is never used
+    reg = np.concatenate([radial_regions(b.x[b.node_off[c]:b.node_off[c + 1]],
+                                         b.tets[b.tet_off[c]:b.tet_off[c + 1]])
+                          for c in range(b.n_cells)])
+    L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256,
+                   regions=reg, n_regions=R)
+    rec = _decode_tets(L, b)
+    # region of every decoded tetrahedron, by matching its sorted vertices
+    key = {}
+    for c in range(b.n_cells):
+        for t in range(b.tet_off[c], b.tet_off[c + 1]):
+            key[(c, *np.sort(b.tets[t]))] = int(reg[t])
+    seen = set()
+    for row in rec:
+        k = (int(row[0]), *np.sort(row[1:5]))
+        assert k not in seen
+        seen.add(k)
+        mt = L.tile_mat[row[7]]
+        assert mt // R == row[0] and mt % R == key[k]
+    assert len(seen) == b.n_tets
+    for c in range(b.n_cells):
+        tiles_c = []
+        for r in range(R):
+            m = c * R + r
+            first, cnt = L.mat_tile_first[m], L.mat_tile_count[m]
+            t = np.arange(first, first + cnt)
+            assert (L.tile_mat[t] == m).all()
+            tiles_c.extend(t.tolist())
+            n_r = int((reg[b.tet_off[c]:b.tet_off[c + 1]] == r).sum())
+            assert L.tiles[t, 1].sum() == n_r
+            assert (cnt == 0) == (n_r == 0)
+        assert sorted(tiles_c) == list(range(L.cell_tile_off[c],
+                                             L.cell_tile_off[c + 1]))
+    # one region: same tiles as the plain layout
+    L1 = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256,
+                    regions=np.zeros(b.n_tets, np.uint8), n_regions=1)
+    L0 = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256)
+    assert np.array_equal(L1.tiles, L0.tiles)
+    assert np.array_equal(L1.local_idx, L0.local_idx)
+    assert np.array_equal(L1.tile_mat, L0.tiles[:, 6])
+
+
+@pytest.mark.parametrize("case", ["id_range", "zero", "too_many"])
+def test_region_preparation_errors(case):
+    from paper_2003_03130_amd import HostLayout, CellmechError
+    from paper_2003_03130_amd import _native as nat
+    x, tets = sphere_mesh(150, 3)
+    reg = np.zeros(len(tets), np.uint8)
+    nr = 2
+    if case == "id_range":
+        reg[4] = 2
+    elif case == "zero":
+        nr = 0
+    else:
+        nr = 65
+    with pytest.raises(CellmechError) as ei:
+        HostLayout([0, len(x)], [0, len(tets)], x, tets, regions=reg,
+                   n_regions=nr)
+    assert ei.value.status == nat.CM_EINVAL
 
 
 @pytest.mark.parametrize("case", ["cells", "sizes", "index_range"])
