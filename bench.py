@@ -298,6 +298,52 @@ def run_template(args):
     return out
 
 
+def run_shape(args, cb, b, y):
+    """Shape diagnostics (Taylor deformation D, semi-axes, cell strain) of
+    every cell of the main workload: ms per cm_shape call (moments over all
+    tetrahedra, all node pairs of every cell, per-cell eigen-solve)."""
+    import torch
+    from oracle import shape as oshape
+    d_ref = torch.full((b.n_cells,), 2.0, dtype=torch.float64, device=cb.device)
+    out = cb.shape(y, d_ref)
+    torch.cuda.synchronize()
+    worst = {"volume": 0.0, "axes": 0.0, "D": 0.0, "d_max": 0.0}
+    oh = out.cpu().numpy()
+    for c in (0, b.n_cells // 2, b.n_cells - 1) if args.parity_cells else ():
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        t0, t1 = b.tet_off[c], b.tet_off[c + 1]
+        ref = oshape.cell_shape(b.x[n0:n1], b.y[n0:n1].astype(np.float64),
+                                b.tets[t0:t1], 2.0)
+        worst["volume"] = max(worst["volume"],
+                              abs(oh[c, 0] - ref["volume"]) / ref["volume"])
+        worst["axes"] = max(worst["axes"], float(
+            np.abs(oh[c, 4:7] - ref["axes"]).max() / ref["axes"].max()))
+        worst["D"] = max(worst["D"], abs(oh[c, 7] - ref["D"]))
+        worst["d_max"] = max(worst["d_max"],
+                             abs(oh[c, 8] - ref["d_max"]) / ref["d_max"])
+    worst["ok"] = bool(worst["volume"] <= 1e-12 and worst["axes"] <= 1e-10
+                       and worst["D"] <= 1e-10 and worst["d_max"] <= 1e-12)
+    for _ in range(3):
+        cb.shape(y, d_ref, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(5, args.steps // 5)
+    e0.record()
+    for _ in range(reps):
+        cb.shape(y, d_ref, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    npairs = float(sum(int(n) * (int(n) - 1) // 2 for n in np.diff(b.node_off)))
+    res = {"workload": "main workload, every cell", "ms": ms,
+           "tets_per_s": b.n_tets / (ms * 1e-3),
+           "node_pairs_per_s": npairs / (ms * 1e-3),
+           "mean_D": float(oh[:, 7].mean()), "parity": worst}
+    log(f"shape: {res}")
+    return res
+
+
 def run_regions(args, b):
     """The main workload with three material regions per cell (nucleus,
     cytoplasm, cortex shell by reference radius), each (cell, region) with
@@ -395,6 +441,7 @@ def main():
                     help="node target of the shared sphere mesh (~10k tets)")
     ap.add_argument("--no-template", action="store_true")
     ap.add_argument("--no-regions", action="store_true")
+    ap.add_argument("--no-shape", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
@@ -516,6 +563,9 @@ def main():
                     "unit": "GB/s", "frac": round(kd["hbm_frac"], 4),
                     "traffic": traffic, "alu_frac": round(kd["alu_frac"], 4)}
 
+    shape = None
+    if not args.no_shape:
+        shape = run_shape(args, cb, b, y)
     relax = None
     if not args.no_relax:
         relax = run_relax(args)
@@ -566,6 +616,7 @@ def main():
         "relax": relax,
         "template": template,
         "regions": regions,
+        "shape": shape,
     }
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)

@@ -302,6 +302,29 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
                           hipStream_t stream);
 
 /*
+ * cm_shape: deformation diagnostics of every cell at positions y.
+ *   Taylor deformation parameter D = (a3 - a1) / (a3 + a1) (Sec. "Taylor
+ *   deformation parameter", eq. taylor-deformation-parameter-definition)
+ *   from the discretised inertia tensor I = sum_l V_l (|r_l|^2 1 - r_l r_l^T)
+ *   (eq. inertia-tensor-discretized; V_l the current volume of tetrahedron
+ *   l with its reference orientation, r_l its centroid, taken about the
+ *   cell's centre of mass) and the semi-axes of eq.
+ *   inertia-tensor-ellipsoid-semiaxes read as squared semi-axes
+ *   (a_i = sqrt(5 / (2 M) (...)), M the current volume, 0 if negative);
+ *   cell strain (d_max - d_ref) / d_ref (eq. cell-strain) with d_max the
+ *   largest distance between two nodes of the cell.
+ *   y     : device float32[3 * n_nodes] SoA positions.
+ *   d_ref : device float64[n_cells] reference diameters (2 R for the paper's
+ *           spherical cell), nullable: strain = NaN.
+ *   out   : device float64[n_cells * 10], per cell: volume, centre of mass
+ *           (x, y, z), a1 <= a2 <= a3, D, d_max, strain.
+ * All sums in float64 in a fixed order (deterministic).  Errors: CM_EINVAL
+ * for null y / out or tiles whose nodes exceed 64 KiB of LDS (16 B each).
+ */
+int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
+             hipStream_t stream);
+
+/*
  * cm_profile_kernels: average device time of each kernel of one batched
  * forward + backward evaluation, measured with HIP events recorded on
  * `stream` around `reps` back-to-back launches of each kernel:

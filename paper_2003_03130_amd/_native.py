@@ -99,6 +99,7 @@ SIGNATURES = {
                                         ctypes.POINTER(Options),
                                         ctypes.POINTER(_vp)]),
     "cm_layout_export_regions": (_int, [_vp, _vp, _vp, _vp]),
+    "cm_shape": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "cm_layout_sizes": (_int, [_vp, _p64]),
     "cm_layout_export": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),

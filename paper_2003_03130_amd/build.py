@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcellmech.so")
-SOURCES = ["api.cpp", "prep.cpp", "kernels.hip", "backward.hip", "relax.hip"]
+SOURCES = ["api.cpp", "prep.cpp", "kernels.hip", "backward.hip", "relax.hip",
+           "shape.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -267,6 +267,25 @@ class CellBatch:
             float(scale), _ptr(thetabar_el), _ptr(thetabar_acc), _ptr(lam),
             _stream(stream)))
 
+    SHAPE_FIELDS = ("volume", "com_x", "com_y", "com_z", "a1", "a2", "a3",
+                    "D", "d_max", "strain")
+
+    def shape(self, y, d_ref=None, out=None, stream=None):
+        """Taylor deformation and cell strain per cell (cm_shape): a float64
+        (n_cells, 10) device tensor with the columns of SHAPE_FIELDS."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_cells, 10, dtype=torch.float64,
+                              device=self.device)
+        if d_ref is not None and not isinstance(d_ref, torch.Tensor):
+            d_ref = torch.as_tensor(np.broadcast_to(
+                np.asarray(d_ref, dtype=np.float64), (self.n_cells,)).copy(),
+                device=self.device)
+            self._dref_keep = d_ref
+        nat.check(nat.lib().cm_shape(self._h, _ptr(y), _ptr(d_ref), _ptr(out),
+                                     _stream(stream)))
+        return out
+
     def profile_kernels(self, y, f, energy, fbar, ebar, ybar, thetabar,
                         reps=10, stream=None):
         """Average ms per launch of the forward tile, forward finalize,

@@ -40,6 +40,11 @@ struct cm_batch_s {
   int64_t n_tiles = 0, n_chunks = 0;
   int32_t n_regions = 1;
   int64_t n_mat = 0;  // material slots: n_cells * n_regions
+  // shape diagnostics scratch
+  const int4* pair_blocks = nullptr;
+  int64_t n_pair_blocks = 0;
+  double* shape_mom = nullptr;
+  unsigned long long* d2max = nullptr;
   int32_t tile_tets = 0, max_tile_nodes = 0;
   double volume = 0, min_v0 = 0, max_cond = 0;
   std::vector<int32_t> cell_tile_off, cell_shared_off;
@@ -221,6 +226,25 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
         (rc = h->alloc(&tile_acc_b, 3 * (size_t)h->n_tiles)) ||
         (rc = h->alloc(&tile_ninv, (size_t)h->n_tiles)))
       return bail(rc);
+    // 256 x 256 node-pair blocks of every cell (row block <= column block)
+    std::vector<int4> pb;
+    for (int64_t c = 0; c < h->n_cells; ++c) {
+      const int64_t nb = (P.node_off[c + 1] - P.node_off[c] + 255) / 256;
+      for (int64_t i = 0; i < nb; ++i)
+        for (int64_t j = i; j < nb; ++j)
+          pb.push_back(make_int4((int)c, (int)i, (int)j, 0));
+    }
+    int4* pbd;
+    double* mom;
+    unsigned long long* d2;
+    if ((rc = h->upload(&pbd, pb, stream)) ||
+        (rc = h->alloc(&mom, 10 * (size_t)h->n_tiles)) ||
+        (rc = h->alloc(&d2, (size_t)h->n_cells)))
+      return bail(rc);
+    h->pair_blocks = pbd;
+    h->n_pair_blocks = (int64_t)pb.size();
+    h->shape_mom = mom;
+    h->d2max = d2;
     T.params = params;
     T.part = part;
     T.tile_acc = tile_acc;
@@ -654,6 +678,18 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
                                   y, lam_next, ybar_el, plate, k_plate, mobility,
                                   F_meas, F_target, scale, thetabar_el,
                                   thetabar_acc, h->n_regions, lam, stream));
+  return CM_OK;
+}
+
+int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
+             hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !out) return fail(CM_EINVAL, "y and out must be device pointers");
+  if (cm::shape_lds(h->T.nloc) > 65536)
+    return fail(CM_EINVAL, "tiles too large for the shape kernel's LDS");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->pair_blocks, h->n_pair_blocks, y,
+                          d_ref, h->shape_mom, h->d2max, out, stream));
   return CM_OK;
 }
 

@@ -1,0 +1,261 @@
+// Cell-shape diagnostics for gfx950: the Taylor deformation parameter from
+// the discretised inertia tensor (Sec. "Taylor deformation parameter", eqs.
+// inertia-tensor-discretized, inertia-tensor-ellipsoid-semiaxes and
+// taylor-deformation-parameter-definition) and the cell strain (eq.
+// cell-strain).
+//
+//   shape_moments_kernel  one wavefront per tile: the current signed volume
+//                         V of every tetrahedron and its centroid r, summed
+//                         as V, V r and V r r^T (float64) about a per-cell
+//                         origin (the cell's first node), one record per tile;
+//   pair_max_kernel       the largest squared distance between two nodes of
+//                         a cell, over 256 x 256 blocks of node pairs (float64
+//                         differences of the float32 positions are exact; the
+//                         maximum of non-negative doubles is an order-free
+//                         integer maximum of their bit patterns);
+//   shape_finalize_kernel per cell: tile records summed in tile order, the
+//                         inertia tensor about the centre of mass, its
+//                         eigenvalues by cyclic Jacobi rotations, semi-axes,
+//                         D, d_max and the strain.
+// Readings: the tensor is taken about the centre of mass; V is the current
+// volume with the reference orientation (negative when inverted); the
+// paper's semi-axis formula gives squared semi-axes of a solid ellipsoid, so
+// a_i is its square root (0 for a negative radicand); d_ref is the caller's.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_util.h"
+#include "kernels.h"
+
+namespace cm {
+namespace {
+
+constexpr int kMom = 10;  // V, V r (3), V r r^T (xx yy zz xy xz yz)
+
+struct MomArgs {
+  DeviceTables T;
+  const int64_t* node_off;
+  const float* y;
+  double* mom;  // kMom per tile
+};
+
+__global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
+  extern __shared__ float4 ys[];
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x;
+  const TileDesc d = a.T.tiles[t];
+  const int64_t N = a.T.n_nodes;
+  const int64_t o = a.node_off[d.cell];
+  const double ox = a.y[o], oy = a.y[N + o], oz = a.y[2 * N + o];
+  for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
+    const int64_t g = l < d.n_own ? (int64_t)d.own_begin + l
+                                  : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
+    ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], 0.f);
+  }
+  wave_sync();
+  double m[kMom];
+#pragma unroll
+  for (int j = 0; j < kMom; ++j) m[j] = 0.0;
+  const TetChunk* ch = a.T.chunks + d.chunk_begin;
+  for (int k = 0; k < d.n_chunks; ++k) {
+    const uint2 q = *reinterpret_cast<const uint2*>(ch[k].idx[lane]);
+    if (q.x == kEmptyLane) continue;
+    const float4 p[4] = {ys[q.x & 0xffff], ys[q.x >> 16], ys[q.y & 0xffff],
+                         ys[q.y >> 16]};
+    double e[3][3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      e[v][0] = (double)p[v].x - (double)p[3].x;
+      e[v][1] = (double)p[v].y - (double)p[3].y;
+      e[v][2] = (double)p[v].z - (double)p[3].z;
+    }
+    const double det_s = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                         e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                         e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    double b[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) b[j] = (double)ch[k].B[j][lane];
+    const double det_b = b[0] * (b[4] * b[8] - b[5] * b[7]) -
+                         b[1] * (b[3] * b[8] - b[5] * b[6]) +
+                         b[2] * (b[3] * b[7] - b[4] * b[6]);
+    // current volume with the orientation of the reference vertex order
+    // (det B = 1 / det of the reference edges)
+    const double V = (det_b > 0.0 ? det_s : -det_s) * (1.0 / 6.0);
+    const double rx = 0.25 * (((double)p[0].x + (double)p[1].x) +
+                              ((double)p[2].x + (double)p[3].x)) - ox;
+    const double ry = 0.25 * (((double)p[0].y + (double)p[1].y) +
+                              ((double)p[2].y + (double)p[3].y)) - oy;
+    const double rz = 0.25 * (((double)p[0].z + (double)p[1].z) +
+                              ((double)p[2].z + (double)p[3].z)) - oz;
+    m[0] += V;
+    m[1] += V * rx; m[2] += V * ry; m[3] += V * rz;
+    m[4] += V * rx * rx; m[5] += V * ry * ry; m[6] += V * rz * rz;
+    m[7] += V * rx * ry; m[8] += V * rx * rz; m[9] += V * ry * rz;
+  }
+#pragma unroll
+  for (int j = 0; j < kMom; ++j) m[j] = wave_sum(m[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < kMom; ++j) a.mom[(int64_t)kMom * t + j] = m[j];
+  }
+}
+
+struct PairArgs {
+  const int4* blocks;  // (cell, row block, column block, 0)
+  const int64_t* node_off;
+  const float* y;
+  int64_t N;
+  unsigned long long* d2max;  // per cell, bits of a non-negative double
+};
+
+__global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
+  __shared__ double cx[256], cy[256], cz[256];
+  __shared__ double red[4];
+  const int4 b = a.blocks[blockIdx.x];
+  const int64_t n0 = a.node_off[b.x], n1 = a.node_off[b.x + 1];
+  const int tid = threadIdx.x;
+  const int64_t j0 = n0 + (int64_t)b.z * 256;
+  const int ncol = n1 - j0 < 256 ? (int)(n1 - j0) : 256;
+  if (tid < ncol) {
+    cx[tid] = a.y[j0 + tid];
+    cy[tid] = a.y[a.N + j0 + tid];
+    cz[tid] = a.y[2 * a.N + j0 + tid];
+  }
+  __syncthreads();
+  const int64_t i = n0 + (int64_t)b.y * 256 + tid;
+  double best = 0.0;
+  if (i < n1) {
+    const double xi = a.y[i], yi = a.y[a.N + i], zi = a.y[2 * a.N + i];
+    for (int k = 0; k < ncol; ++k) {
+      const double dx = xi - cx[k], dy = yi - cy[k], dz = zi - cz[k];
+      best = fmax(best, dx * dx + dy * dy + dz * dz);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+  if ((tid & 63) == 0) red[tid >> 6] = best;
+  __syncthreads();
+  if (tid == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(&a.d2max[b.x], (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Eigenvalues of a symmetric 3x3 matrix (A00 A11 A22 A01 A02 A12) by cyclic
+// Jacobi rotations; at most 32 sweeps (convergence is quadratic).
+__device__ void sym3_eigenvalues(const double s[6], double ev[3]) {
+  double A[3][3] = {{s[0], s[3], s[4]}, {s[3], s[1], s[5]}, {s[4], s[5], s[2]}};
+  for (int sweep = 0; sweep < 32; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+        for (int k = 0; k < 3; ++k) {  // A <- A G (columns p, q)
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {  // A <- G^T A (rows p, q)
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        A[p][q] = A[q][p] = 0.0;
+      }
+  }
+  ev[0] = A[0][0]; ev[1] = A[1][1]; ev[2] = A[2][2];
+}
+
+struct ShapeFinArgs {
+  DeviceTables T;
+  const int64_t* node_off;
+  const float* y;
+  const double* mom;
+  const unsigned long long* d2max;
+  const double* d_ref;  // nullable
+  double* out;          // kShapeFields per cell
+};
+
+__global__ __launch_bounds__(256) void shape_finalize_kernel(ShapeFinArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.T.n_cells) return;
+  double m[kMom];
+  for (int j = 0; j < kMom; ++j) m[j] = 0.0;
+  const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
+  for (int k = 0; k < nt; ++k) {
+    const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
+    for (int j = 0; j < kMom; ++j) m[j] += a.mom[kMom * t + j];
+  }
+  const int64_t N = a.T.n_nodes, o = a.node_off[c];
+  const double M = m[0];
+  const double cx = m[1] / M, cy = m[2] / M, cz = m[3] / M;
+  // second moments about the centre of mass, then the inertia tensor
+  const double Sxx = m[4] - m[1] * cx, Syy = m[5] - m[2] * cy, Szz = m[6] - m[3] * cz;
+  const double Sxy = m[7] - m[1] * cy, Sxz = m[8] - m[1] * cz, Syz = m[9] - m[2] * cz;
+  const double tr = Sxx + Syy + Szz;
+  const double I[6] = {tr - Sxx, tr - Syy, tr - Szz, -Sxy, -Sxz, -Syz};
+  double th[3];
+  sym3_eigenvalues(I, th);
+  // theta_1 >= theta_2 >= theta_3
+  if (th[0] < th[1]) { const double s = th[0]; th[0] = th[1]; th[1] = s; }
+  if (th[1] < th[2]) { const double s = th[1]; th[1] = th[2]; th[2] = s; }
+  if (th[0] < th[1]) { const double s = th[0]; th[0] = th[1]; th[1] = s; }
+  const double f = 5.0 / (2.0 * M);
+  const double a1 = sqrt(fmax(f * (-th[0] + th[1] + th[2]), 0.0));
+  const double a2 = sqrt(fmax(f * (th[0] - th[1] + th[2]), 0.0));
+  const double a3 = sqrt(fmax(f * (th[0] + th[1] - th[2]), 0.0));
+  const double dmax = sqrt(__longlong_as_double((long long)a.d2max[c]));
+  double* r = a.out + (int64_t)kShapeFields * c;
+  r[0] = M;
+  r[1] = (double)a.y[o] + cx;
+  r[2] = (double)a.y[N + o] + cy;
+  r[3] = (double)a.y[2 * N + o] + cz;
+  r[4] = a1; r[5] = a2; r[6] = a3;
+  r[7] = (a3 - a1) / (a3 + a1);
+  r[8] = dmax;
+  r[9] = a.d_ref ? (dmax - a.d_ref[c]) / a.d_ref[c] : __builtin_nan("");
+}
+
+}  // namespace
+
+size_t shape_lds(int nloc) { return (size_t)16 * nloc; }
+
+hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
+                        const int4* pair_blocks, int64_t n_pair_blocks,
+                        const float* y, const double* d_ref, double* mom,
+                        unsigned long long* d2max, double* out,
+                        hipStream_t st) {
+  const int nc = T.n_cells;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((nc + 255) / 256), dim3(256), 0, st,
+                     d2max, (int64_t)nc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n_pair_blocks > 0) {
+    PairArgs p{pair_blocks, node_off, y, T.n_nodes, d2max};
+    hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_pair_blocks), dim3(256), 0,
+                       st, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (T.n_tiles > 0) {
+    MomArgs m{T, node_off, y, mom};
+    hipLaunchKernelGGL(shape_moments_kernel, dim3((unsigned)T.n_tiles), dim3(64),
+                       shape_lds(T.nloc), st, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ShapeFinArgs f{T, node_off, y, mom, d2max, d_ref, out};
+  hipLaunchKernelGGL(shape_finalize_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
+}  // namespace cm
