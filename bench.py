@@ -43,18 +43,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 FWD_BYTES = (56, 24)    # 16 idx + 36 B + 4 V0 per tet; y in + f out per node
 BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
 F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
-DEVICE_HEADERS = ("device_util.h", "kernels.h", "layout.h", "mr_tet.h")
+TILE_KERNEL_SOURCES = ("kernels.hip", "backward.hip", "device_util.h",
+                       "kernels.h", "layout.h", "mr_tet.h")
 
 
 def kernel_source_hash():
-    """sha256 of the device-code sources (kernels and the headers they
-    include); a stored counter record applies only to the kernels it was
-    measured on.  Host-only sources (api.cpp, prep.*) are not part of it."""
+    """sha256 of the sources of the forward and backward kernels (their .hip
+    files and the headers they include); a stored counter record applies
+    only to the kernels it was measured on.  Host code and the auxiliary
+    kernels (plates, quasi-static, shape) are not part of it."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_03130_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
-        if fn.endswith(".hip") or fn in DEVICE_HEADERS:
+        if fn in TILE_KERNEL_SOURCES:
             with open(os.path.join(csrc, fn), "rb") as fh:
                 h.update(fn.encode() + fh.read())
     return h.hexdigest()

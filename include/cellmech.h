@@ -302,6 +302,45 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
                           hipStream_t stream);
 
 /*
+ * Quasi-static plate compression (the compression setup of Sec. "Simulation
+ * setup" solved for equilibrium instead of stepped in time).  At plate
+ * positions plate[2c] = top, plate[2c + 1] = bottom the state of cell c
+ * minimises Pi(y) = E(y) + sum_nodes (k/3) [max(0, y_z - top)^3 +
+ * max(0, bottom - y_z)^3] (the potential of the penalty of cm_plate_step), so
+ * that f + p = 0.  A Newton step solves Hess(Pi) dx = f + p per cell by
+ * conjugate gradients whose Hessian-vector products are cm_forces_backward
+ * calls (ybar = (df/dy)^T v = -Hess(E) v) plus the diagonal penalty
+ * Hessian; the caller drives the loop:
+ *   cm_forces(y -> f); cm_qs_residual;  repeat: cm_forces_backward(y, fbar = p
+ *   -> ybar); cm_qs_cg_step;  then cm_qs_update.
+ * Arrays (device, SoA float32[3 n_nodes]): r (residual), p (search
+ * direction), x (Newton step), Ap (scratch); state: float64[8 n_cells] =
+ * |r|^2, |r_0|^2, active (1/0), |f + p|^2, last step scale, |penalty|^2, 2
+ * spare.
+ *   cm_qs_residual: r = p = f + penalty, x = 0; active iff |f + p|_2 >
+ *     max(abs_tol, rel_tol |penalty|_2); force (nullable) float64[2 n_cells]
+ *     = top and bottom plate forces k sum max(0, .)^2.
+ *   cm_qs_cg_step: one CG iteration for every active cell; a cell stops at
+ *     |r| <= rel_tol |r_0| or at non-positive curvature.
+ *   cm_qs_update: y += s x, s = min(1, cap / max_i |x_i|) per cell.
+ *   cm_qs_predict: z -> b' + (z - b)(t' - b') / (t - b) for a new plate pair
+ *     (t', b') (affine prediction between the plates).
+ * Errors: CM_EINVAL for null pointers, negative or non-finite k_plate or
+ * tolerances, cap <= 0.
+ */
+int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* plate,
+                   double k_plate, double abs_tol, double rel_tol, float* r,
+                   float* p, float* x, double* state, double* force,
+                   hipStream_t stream);
+int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
+                  double rel_tol, const float* ybar, float* x, float* r, float* p,
+                  float* Ap, double* state, hipStream_t stream);
+int cm_qs_update(cm_batch h, const float* x, double cap, float* y, double* state,
+                 hipStream_t stream);
+int cm_qs_predict(cm_batch h, const double* plate_old, const double* plate_new,
+                  float* y, hipStream_t stream);
+
+/*
  * cm_shape: deformation diagnostics of every cell at positions y.
  *   Taylor deformation parameter D = (a3 - a1) / (a3 + a1) (Sec. "Taylor
  *   deformation parameter", eq. taylor-deformation-parameter-definition)

@@ -100,6 +100,13 @@ SIGNATURES = {
                                         ctypes.POINTER(_vp)]),
     "cm_layout_export_regions": (_int, [_vp, _vp, _vp, _vp]),
     "cm_shape": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
+                              _vp, _vp, _vp]),
+    "cm_qs_cg_step": (_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                             _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cm_qs_update": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
+    "cm_qs_predict": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "cm_layout_sizes": (_int, [_vp, _p64]),
     "cm_layout_export": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "cellmech.h"
+#include "aux_kernels.h"
 #include "kernels.h"
 #include "prep.h"
 
@@ -653,6 +654,58 @@ int cm_plate_step(cm_batch h, const float* y, const float* f,
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_plate_step(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y,
                                f, plate, k_plate, mobility, y_next, force, stream));
+  return CM_OK;
+}
+
+int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* plate,
+                   double k_plate, double abs_tol, double rel_tol, float* r,
+                   float* p, float* x, double* state, double* force,
+                   hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !f || !plate || !r || !p || !x || !state)
+    return fail(CM_EINVAL, "y, f, plate, r, p, x and state must be device pointers");
+  if (!std::isfinite(k_plate) || k_plate < 0 || !(abs_tol >= 0) || !(rel_tol >= 0))
+    return fail(CM_EINVAL, "k_plate and tolerances must be finite and >= 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_residual(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, f,
+                                plate, k_plate, abs_tol, rel_tol, r, p, x, state,
+                                force, stream));
+  return CM_OK;
+}
+
+int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
+                  double rel_tol, const float* ybar, float* x, float* r, float* p,
+                  float* Ap, double* state, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !plate || !ybar || !x || !r || !p || !Ap || !state)
+    return fail(CM_EINVAL, "all arrays must be device pointers");
+  if (!std::isfinite(k_plate) || k_plate < 0 || !(rel_tol >= 0))
+    return fail(CM_EINVAL, "k_plate and rel_tol must be finite and >= 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_cg(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
+                          k_plate, rel_tol, ybar, x, r, p, Ap, state, stream));
+  return CM_OK;
+}
+
+int cm_qs_update(cm_batch h, const float* x, double cap, float* y, double* state,
+                 hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !y || !state) return fail(CM_EINVAL, "x, y and state must be device pointers");
+  if (!(cap > 0) || !std::isfinite(cap)) return fail(CM_EINVAL, "cap must be finite and > 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_update(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, x, cap, y,
+                              state, stream));
+  return CM_OK;
+}
+
+int cm_qs_predict(cm_batch h, const double* plate_old, const double* plate_new,
+                  float* y, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!plate_old || !plate_new || !y)
+    return fail(CM_EINVAL, "plate_old, plate_new and y must be device pointers");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_predict(h->d_node_off, h->n_nodes, (int32_t)h->n_cells,
+                               plate_old, plate_new, y, stream));
   return CM_OK;
 }
 

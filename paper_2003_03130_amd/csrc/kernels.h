@@ -76,31 +76,4 @@ hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const float* fbar, const double* ebar, float* ybar,
                            double* thetabar, hipStream_t st);
 
-// Shape diagnostics (Taylor deformation, cell strain): kShapeFields float64
-// per cell = volume, centre of mass (3), semi-axes a1 <= a2 <= a3, D, d_max,
-// strain.  mom: 10 float64 per tile; d2max: one uint64 per cell;
-// pair_blocks: (cell, row block, column block, 0) over the 256-node blocks
-// of every cell with row <= column.
-constexpr int kShapeFields = 10;
-size_t shape_lds(int nloc);
-hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
-                        const int4* pair_blocks, int64_t n_pair_blocks,
-                        const float* y, const double* d_ref, double* mom,
-                        unsigned long long* d2max, double* out,
-                        hipStream_t st);
-
-// Plate compression step and its adjoint (one workgroup per cell).
-hipError_t launch_plate_step(const int64_t* node_off, int64_t N, int32_t n_cells,
-                             const float* y, const float* f, const double* plate,
-                             double k, double m, float* y_next, double* force,
-                             hipStream_t st);
-hipError_t launch_plate_adjoint(const int64_t* node_off, int64_t N,
-                                int32_t n_cells, const float* y,
-                                const float* lam_next, const float* ybar_el,
-                                const double* plate, double k, double m,
-                                const double* F_meas, const double* F_target,
-                                double scale, const double* thetabar_el,
-                                double* thetabar_acc, int n_regions, float* lam,
-                                hipStream_t st);
-
 }  // namespace cm

@@ -1,0 +1,249 @@
+// Quasi-static plate compression for gfx950: Newton steps on the total
+// potential Pi(y) = E(y) + sum_nodes phi(y_z), with the plate penalty
+// phi(z) = (k/3) [max(0, z - top)^3 + max(0, bottom - z)^3] (its force is the
+// penalty of the plate-compression steps), each Newton system
+// Hess(Pi) dx = f + p solved by conjugate gradients per cell.  Hessian-vector
+// products of E come from the backward kernels (ybar = (df/dy)^T v =
+// -Hess(E) v); the penalty Hessian is diagonal, 2k (max(0, z - top) +
+// max(0, bottom - z)) on the z entries.
+//
+// One workgroup per cell (cells are independent systems); per-cell scalars
+// live in a float64 state of kQsState entries per cell, so a whole Newton
+// step runs without host synchronisation.  Reductions are block sums in a
+// fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include "aux_kernels.h"
+
+namespace cm {
+namespace {
+
+constexpr int kThreads = 1024;
+
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+struct ResArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* y;
+  const float* f;
+  const double* plate;  // per cell: top, bottom
+  double k, abs_tol, rel_tol;
+  float *r, *p, *x;
+  double* st;     // kQsState per cell
+  double* force;  // per cell: top, bottom plate force (nullable)
+};
+
+// r = f + p (the negative gradient of Pi), CG start x = 0, p = r; a cell is
+// active (not yet in equilibrium) when |r|_2 > max(abs_tol, rel_tol |pen|_2)
+// with pen the plate penalty forces.
+__global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  double rr = 0.0, ft = 0.0, fb = 0.0, pp = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    const double z = a.y[2 * N + i];
+    const double dt = fmax(z - top, 0.0), db = fmax(bot - z, 0.0);
+    const float rx = a.f[i], ry = a.f[N + i];
+    const double pz = a.k * (db * db - dt * dt);
+    const float rz = (float)((double)a.f[2 * N + i] + pz);
+    pp += pz * pz;
+    a.r[i] = rx; a.r[N + i] = ry; a.r[2 * N + i] = rz;
+    a.p[i] = rx; a.p[N + i] = ry; a.p[2 * N + i] = rz;
+    a.x[i] = 0.f; a.x[N + i] = 0.f; a.x[2 * N + i] = 0.f;
+    rr += (double)rx * rx + (double)ry * ry + (double)rz * rz;
+    ft += a.k * dt * dt;
+    fb += a.k * db * db;
+  }
+  rr = block_sum(rr, red);
+  ft = block_sum(ft, red);
+  fb = block_sum(fb, red);
+  pp = block_sum(pp, red);
+  if (threadIdx.x == 0) {
+    double* s = a.st + kQsState * c;
+    const double tol2 = fmax(a.abs_tol * a.abs_tol, a.rel_tol * a.rel_tol * pp);
+    s[0] = rr;                      // CG residual |r|^2
+    s[1] = rr;                      // its start value
+    s[2] = rr > tol2 ? 1.0 : 0.0;   // active: not yet in equilibrium
+    s[3] = rr;                      // Newton residual |f + p|^2
+    s[5] = pp;                      // |penalty forces|^2
+    if (a.force) { a.force[2 * c] = ft; a.force[2 * c + 1] = fb; }
+  }
+}
+
+struct CgArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* y;
+  const double* plate;
+  double k, rel_tol;
+  const float* ybar;  // (df/dy)^T p
+  float *x, *r, *p, *Ap;
+  double* st;
+};
+
+// One CG iteration per active cell: Ap = Hess(Pi) p, alpha = |r|^2 / p.Ap,
+// x += alpha p, r -= alpha Ap, beta = |r_new|^2 / |r|^2, p = r + beta p.  A
+// cell stops at |r| <= rel_tol |r_0| or on non-positive curvature.
+__global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  double* s = a.st + kQsState * c;
+  if (s[2] == 0.0) return;  // uniform over the workgroup
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  double pap = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    const double z = a.y[2 * N + i];
+    const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+    const float ax = -a.ybar[i], ay = -a.ybar[N + i];
+    const float az = (float)(-(double)a.ybar[2 * N + i] + h * (double)a.p[2 * N + i]);
+    a.Ap[i] = ax; a.Ap[N + i] = ay; a.Ap[2 * N + i] = az;
+    pap += (double)a.p[i] * ax + (double)a.p[N + i] * ay + (double)a.p[2 * N + i] * az;
+  }
+  pap = block_sum(pap, red);
+  const double rs = s[0];
+  if (!(pap > 0.0)) {
+    if (threadIdx.x == 0) s[2] = 0.0;
+    return;
+  }
+  const float alpha = (float)(rs / pap);
+  double rn = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t q = d * N + i;
+      a.x[q] += alpha * a.p[q];
+      const float rq = a.r[q] - alpha * a.Ap[q];
+      a.r[q] = rq;
+      rn += (double)rq * rq;
+    }
+  }
+  rn = block_sum(rn, red);
+  const float beta = (float)(rn / rs);
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t q = d * N + i;
+      a.p[q] = a.r[q] + beta * a.p[q];
+    }
+  }
+  if (threadIdx.x == 0) {
+    s[0] = rn;
+    if (rn <= a.rel_tol * a.rel_tol * s[1]) s[2] = 0.0;
+  }
+}
+
+struct UpdArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* x;
+  double cap;
+  float* y;
+  double* st;
+};
+
+// y += s x with s = min(1, cap / max |x_i|) per cell (a bounded Newton step);
+// the applied scale goes to the state.
+__global__ __launch_bounds__(kThreads) void qs_update_kernel(UpdArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  double mx = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+    mx = fmax(mx, fmax(fabs((double)a.x[i]),
+                       fmax(fabs((double)a.x[N + i]), fabs((double)a.x[2 * N + i]))));
+  mx = block_max(mx, red);
+  const float sc = (float)(mx > a.cap ? a.cap / mx : 1.0);
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    a.y[i] += sc * a.x[i];
+    a.y[N + i] += sc * a.x[N + i];
+    a.y[2 * N + i] += sc * a.x[2 * N + i];
+  }
+  if (threadIdx.x == 0) a.st[kQsState * c + 4] = sc;
+}
+
+struct PredArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const double* plate_old;
+  const double* plate_new;
+  float* y;
+};
+
+// Predictor for a new plate position: z -> b + (z - b) (t' - b') / (t - b)
+// with the bottom b moved to b' (affine in z between the plates).
+__global__ __launch_bounds__(kThreads) void qs_predict_kernel(PredArgs a) {
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  const double t0 = a.plate_old[2 * c], b0 = a.plate_old[2 * c + 1];
+  const double t1 = a.plate_new[2 * c], b1 = a.plate_new[2 * c + 1];
+  const double sc = (t1 - b1) / (t0 - b0);
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+    a.y[2 * N + i] = (float)(b1 + ((double)a.y[2 * N + i] - b0) * sc);
+}
+
+}  // namespace
+
+hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cells,
+                              const float* y, const float* f, const double* plate,
+                              double k, double abs_tol, double rel_tol, float* r,
+                              float* p, float* x, double* st, double* force,
+                              hipStream_t s) {
+  ResArgs a{node_off, N, y, f, plate, k, abs_tol, rel_tol, r, p, x, st, force};
+  hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
+                        const float* y, const double* plate, double k,
+                        double rel_tol, const float* ybar, float* x, float* r,
+                        float* p, float* Ap, double* st, hipStream_t s) {
+  CgArgs a{node_off, N, y, plate, k, rel_tol, ybar, x, r, p, Ap, st};
+  hipLaunchKernelGGL(qs_cg_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_update(const int64_t* node_off, int64_t N, int32_t n_cells,
+                            const float* x, double cap, float* y, double* st,
+                            hipStream_t s) {
+  UpdArgs a{node_off, N, x, cap, y, st};
+  hipLaunchKernelGGL(qs_update_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_predict(const int64_t* node_off, int64_t N, int32_t n_cells,
+                             const double* plate_old, const double* plate_new,
+                             float* y, hipStream_t s) {
+  PredArgs a{node_off, N, plate_old, plate_new, y};
+  hipLaunchKernelGGL(qs_predict_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace cm

@@ -12,7 +12,7 @@
 // result is deterministic.
 #include <hip/hip_runtime.h>
 
-#include "kernels.h"
+#include "aux_kernels.h"
 
 namespace cm {
 namespace {

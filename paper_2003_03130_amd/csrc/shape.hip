@@ -26,7 +26,7 @@
 #include <cmath>
 
 #include "device_util.h"
-#include "kernels.h"
+#include "aux_kernels.h"
 
 namespace cm {
 namespace {
