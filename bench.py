@@ -346,6 +346,50 @@ def run_shape(args, cb, b, y):
     return res
 
 
+def run_quasistatic(args):
+    """Quasi-static force-indentation curves: oblate cells (~2k nodes,
+    ~11k tets each) between plates closing in steps of 0.02 R up to 20 %
+    of the height, every step brought to equilibrium by Newton-CG on the
+    device; reports wall time, Newton/CG counts and Hessian-vector-product
+    throughput (the CG's hot kernel)."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    from synth.configs import K_PLATE, oblate_batch
+    t = time.time()
+    b = oblate_batch(args.qs_cells, 2000, 7000)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets, tile_tets=args.tile_tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    top0 = np.array([b.x[b.node_off[c]:b.node_off[c + 1], 2].max()
+                     for c in range(b.n_cells)])
+    bot = np.array([b.x[b.node_off[c]:b.node_off[c + 1], 2].min()
+                    for c in range(b.n_cells)])
+    delta = np.linspace(0.02, 0.2, 10)
+    tops = top0[None, :] - 2.0 * delta[:, None] * 0.8
+    log(f"quasi-static workload: {b.n_cells} cells, {b.n_tets} tets "
+        f"({time.time() - t:.1f} s)")
+    qs = QuasiStaticCompression(cb, K_PLATE)
+    y0 = cb.to_device(b.y)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Ft, Fb, ok, _ = qs.curve(y0, tops, bot)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    hvp = qs.stats["cg"]
+    out = {
+        "workload": f"{b.n_cells} oblate cells, {b.n_tets} tets, plates "
+                    f"closing to 20 % of the height in 10 steps",
+        "wall_s": wall, "newton": qs.stats["newton"], "cg": hvp,
+        "converged_steps": int(ok.sum()), "steps": len(ok),
+        "hvp_tets_per_s": hvp * b.n_tets / wall,
+        "max_force_mean": float(Ft[-1].mean()),
+        "plate_balance": float(np.max(np.abs(Ft - Fb) / np.maximum(Ft, 1e-30))),
+    }
+    log(f"quasi-static: {out}")
+    cb.close()
+    return out
+
+
 def run_regions(args, b):
     """The main workload with three material regions per cell (nucleus,
     cytoplasm, cortex shell by reference radius), each (cell, region) with
@@ -444,6 +488,8 @@ def main():
     ap.add_argument("--no-template", action="store_true")
     ap.add_argument("--no-regions", action="store_true")
     ap.add_argument("--no-shape", action="store_true")
+    ap.add_argument("--qs-cells", type=int, default=256)
+    ap.add_argument("--no-qs", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
@@ -577,6 +623,9 @@ def main():
     regions = None
     if not args.no_regions:
         regions = run_regions(args, b)
+    quasistatic = None
+    if not args.no_qs:
+        quasistatic = run_quasistatic(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -619,6 +668,7 @@ def main():
         "template": template,
         "regions": regions,
         "shape": shape,
+        "quasistatic": quasistatic,
     }
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)

@@ -315,11 +315,15 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  *   -> ybar); cm_qs_cg_step;  then cm_qs_update.
  * Arrays (device, SoA float32[3 n_nodes]): r (residual), p (search
  * direction), x (Newton step), Ap (scratch); state: float64[8 n_cells] =
- * |r|^2, |r_0|^2, active (1/0), |f + p|^2, last step scale, |penalty|^2, 2
- * spare.
- *   cm_qs_residual: r = p = f + penalty, x = 0; active iff |f + p|_2 >
- *     max(abs_tol, rel_tol |penalty|_2); force (nullable) float64[2 n_cells]
- *     = top and bottom plate forces k sum max(0, .)^2.
+ * |r|^2, |r_0|^2, active (1/0), |r_N|^2, last step scale, |penalty|^2,
+ * largest node move of the last step, spare.
+ *   cm_qs_residual: r = p = r_N, x = 0, with r_N = f + penalty minus its
+ *     components along the exact symmetries of the plates (translations in
+ *     x and y, rotation about z through the centroid); active iff |r_N|_2 >
+ *     max(abs_tol, rel_tol |penalty|_2) and the last step moved some node by
+ *     more than step_tol (restart != 0: no last step, at a new plate
+ *     position); force (nullable) float64[2 n_cells] = top and bottom plate
+ *     forces k sum max(0, .)^2.
  *   cm_qs_cg_step: one CG iteration for every active cell; a cell stops at
  *     |r| <= rel_tol |r_0| or at non-positive curvature.
  *   cm_qs_update: y += s x, s = min(1, cap / max_i |x_i|) per cell.
@@ -329,9 +333,9 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  * tolerances, cap <= 0.
  */
 int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* plate,
-                   double k_plate, double abs_tol, double rel_tol, float* r,
-                   float* p, float* x, double* state, double* force,
-                   hipStream_t stream);
+                   double k_plate, double abs_tol, double rel_tol, double step_tol,
+                   int32_t restart, float* r, float* p, float* x, double* state,
+                   double* force, hipStream_t stream);
 int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
                   double rel_tol, const float* ybar, float* x, float* r, float* p,
                   float* Ap, double* state, hipStream_t stream);

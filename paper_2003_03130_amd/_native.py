@@ -101,8 +101,8 @@ SIGNATURES = {
     "cm_layout_export_regions": (_int, [_vp, _vp, _vp, _vp]),
     "cm_shape": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, ctypes.c_double,
-                              ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
-                              _vp, _vp, _vp]),
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_cg_step": (_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                              _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_update": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),

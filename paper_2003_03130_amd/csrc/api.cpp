@@ -658,18 +658,19 @@ int cm_plate_step(cm_batch h, const float* y, const float* f,
 }
 
 int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* plate,
-                   double k_plate, double abs_tol, double rel_tol, float* r,
-                   float* p, float* x, double* state, double* force,
-                   hipStream_t stream) {
+                   double k_plate, double abs_tol, double rel_tol, double step_tol,
+                   int32_t restart, float* r, float* p, float* x, double* state,
+                   double* force, hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !f || !plate || !r || !p || !x || !state)
     return fail(CM_EINVAL, "y, f, plate, r, p, x and state must be device pointers");
-  if (!std::isfinite(k_plate) || k_plate < 0 || !(abs_tol >= 0) || !(rel_tol >= 0))
+  if (!std::isfinite(k_plate) || k_plate < 0 || !(abs_tol >= 0) || !(rel_tol >= 0) ||
+      !(step_tol >= 0))
     return fail(CM_EINVAL, "k_plate and tolerances must be finite and >= 0");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_residual(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, f,
-                                plate, k_plate, abs_tol, rel_tol, r, p, x, state,
-                                force, stream));
+                                plate, k_plate, abs_tol, rel_tol, step_tol,
+                                restart ? 1 : 0, r, p, x, state, force, stream));
   return CM_OK;
 }
 

@@ -26,13 +26,13 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
 // Quasi-static plate compression (one workgroup per cell): Newton residual,
 // one conjugate-gradient iteration, bounded Newton update, plate predictor.
 // Per-cell state: kQsState float64 = |r|^2, |r_0|^2, active, |f + p|^2,
-// applied step scale, |penalty|^2, 2 spare.
+// applied step scale, |penalty|^2, largest node move of the last step, spare.
 constexpr int kQsState = 8;
 hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cells,
                               const float* y, const float* f, const double* plate,
-                              double k, double abs_tol, double rel_tol, float* r,
-                              float* p, float* x, double* st, double* force,
-                              hipStream_t s);
+                              double k, double abs_tol, double rel_tol,
+                              double step_tol, int restart, float* r, float* p,
+                              float* x, double* st, double* force, hipStream_t s);
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,

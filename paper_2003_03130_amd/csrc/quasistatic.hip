@@ -52,27 +52,65 @@ struct ResArgs {
   const float* y;
   const float* f;
   const double* plate;  // per cell: top, bottom
-  double k, abs_tol, rel_tol;
+  double k, abs_tol, rel_tol, step_tol;
+  int restart;  // 1: first call at this plate position (forget the last step)
   float *r, *p, *x;
   double* st;     // kQsState per cell
   double* force;  // per cell: top, bottom plate force (nullable)
 };
 
-// r = f + p (the negative gradient of Pi), CG start x = 0, p = r; a cell is
-// active (not yet in equilibrium) when |r|_2 > max(abs_tol, rel_tol |pen|_2)
-// with pen the plate penalty forces.
+// r = f + p (the negative gradient of Pi) with its components along the
+// exact symmetries of the plate problem removed: translations along x and y
+// and the rotation about the z axis through the centroid (the plates are
+// invariant under them, so Hess(Pi) annihilates them and the forces have no
+// net component along them up to rounding).  CG start x = 0, p = r.  A cell
+// is active (not yet in equilibrium) when |r|_2 > max(abs_tol,
+// rel_tol |pen|_2), pen the plate penalty forces, and its last Newton step
+// moved no node by more than step_tol (float32 positions bound how small
+// the residual can get, so a step below a few units in the last place ends
+// the iteration).
 __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  const double inv_n = 1.0 / (double)(n1 - n0);
+  auto rz_of = [&](int64_t i, double& dt, double& db, double& pz) {
+    const double z = a.y[2 * N + i];
+    dt = fmax(z - top, 0.0);
+    db = fmax(bot - z, 0.0);
+    pz = a.k * (db * db - dt * dt);
+    return (double)a.f[2 * N + i] + pz;
+  };
+  // centroid (x, y) and mean residual (x, y)
+  double sx = 0.0, sy = 0.0, mx = 0.0, my = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    sx += a.y[i];
+    sy += a.y[N + i];
+    mx += a.f[i];
+    my += a.f[N + i];
+  }
+  const double cx = block_sum(sx, red) * inv_n, cy = block_sum(sy, red) * inv_n;
+  mx = block_sum(mx, red) * inv_n;
+  my = block_sum(my, red) * inv_n;
+  // torque about the z axis through the centroid and |w|^2, w = e_z x (y - c)
+  double tq = 0.0, ww = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
+    tq += dx * a.f[N + i] - dy * a.f[i];
+    ww += dx * dx + dy * dy;
+  }
+  tq = block_sum(tq, red);
+  ww = block_sum(ww, red);
+  const double om = ww > 0.0 ? tq / ww : 0.0;
   double rr = 0.0, ft = 0.0, fb = 0.0, pp = 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
-    const double z = a.y[2 * N + i];
-    const double dt = fmax(z - top, 0.0), db = fmax(bot - z, 0.0);
-    const float rx = a.f[i], ry = a.f[N + i];
-    const double pz = a.k * (db * db - dt * dt);
-    const float rz = (float)((double)a.f[2 * N + i] + pz);
+    double dt, db, pz;
+    const double rzd = rz_of(i, dt, db, pz);
+    const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
+    const float rx = (float)((double)a.f[i] - mx + om * dy);
+    const float ry = (float)((double)a.f[N + i] - my - om * dx);
+    const float rz = (float)rzd;
     pp += pz * pz;
     a.r[i] = rx; a.r[N + i] = ry; a.r[2 * N + i] = rz;
     a.p[i] = rx; a.p[N + i] = ry; a.p[2 * N + i] = rz;
@@ -88,10 +126,11 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   if (threadIdx.x == 0) {
     double* s = a.st + kQsState * c;
     const double tol2 = fmax(a.abs_tol * a.abs_tol, a.rel_tol * a.rel_tol * pp);
+    if (a.restart) s[6] = __builtin_inf();
     s[0] = rr;                      // CG residual |r|^2
     s[1] = rr;                      // its start value
-    s[2] = rr > tol2 ? 1.0 : 0.0;   // active: not yet in equilibrium
-    s[3] = rr;                      // Newton residual |f + p|^2
+    s[2] = (rr > tol2 && s[6] > a.step_tol) ? 1.0 : 0.0;  // not yet in equilibrium
+    s[3] = rr;                      // Newton residual |f + p|^2 (projected)
     s[5] = pp;                      // |penalty forces|^2
     if (a.force) { a.force[2 * c] = ft; a.force[2 * c + 1] = fb; }
   }
@@ -181,12 +220,17 @@ __global__ __launch_bounds__(kThreads) void qs_update_kernel(UpdArgs a) {
                        fmax(fabs((double)a.x[N + i]), fabs((double)a.x[2 * N + i]))));
   mx = block_max(mx, red);
   const float sc = (float)(mx > a.cap ? a.cap / mx : 1.0);
+  // a cell that took no step (converged) keeps its last step size
+  const bool moved = mx > 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     a.y[i] += sc * a.x[i];
     a.y[N + i] += sc * a.x[N + i];
     a.y[2 * N + i] += sc * a.x[2 * N + i];
   }
-  if (threadIdx.x == 0) a.st[kQsState * c + 4] = sc;
+  if (threadIdx.x == 0 && moved) {
+    a.st[kQsState * c + 4] = sc;
+    a.st[kQsState * c + 6] = mx * sc;  // largest node move of this step
+  }
 }
 
 struct PredArgs {
@@ -213,10 +257,11 @@ __global__ __launch_bounds__(kThreads) void qs_predict_kernel(PredArgs a) {
 
 hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cells,
                               const float* y, const float* f, const double* plate,
-                              double k, double abs_tol, double rel_tol, float* r,
-                              float* p, float* x, double* st, double* force,
-                              hipStream_t s) {
-  ResArgs a{node_off, N, y, f, plate, k, abs_tol, rel_tol, r, p, x, st, force};
+                              double k, double abs_tol, double rel_tol,
+                              double step_tol, int restart, float* r, float* p,
+                              float* x, double* st, double* force, hipStream_t s) {
+  ResArgs a{node_off, N, y, f, plate, k, abs_tol, rel_tol, step_tol, restart,
+            r, p, x, st, force};
   hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -281,6 +281,24 @@ def plate_schedule(n_steps, radius=1.0, compression=0.8):
     return top, -radius
 
 
+def oblate_batch(n_cells, n_target, seed, n_meshes=8):
+    """Undeformed oblate ellipsoids for quasi-static compression: semi-axes
+    U[1.05, 1.25] x U[1.0, 1.2] x U[0.75, 0.85] R (shortest on z, the
+    compression axis, so the cell cannot roll between frictionless plates),
+    meshes from ``n_meshes`` sphere seeds, theta drawn like random_theta."""
+    meshes = [sphere_mesh(n_target, seed + 31 * k) for k in range(n_meshes)]
+    rng = np.random.default_rng(seed)
+    cells = []
+    for c in range(n_cells):
+        x0, tets = meshes[c % n_meshes]
+        ax = np.array([rng.uniform(1.05, 1.25), rng.uniform(1.0, 1.2),
+                       rng.uniform(0.75, 0.85)])
+        x = ellipsoid(x0, ax)
+        cells.append(Cell(x, tets.copy(), x.astype(np.float32),
+                          random_theta(rng)))
+    return batch_from_cells(cells)
+
+
 def compression_batch(n_cells, n_target, seed, n_meshes=None):
     """Spheres (R = 1) for the plate-compression runs, each with a hidden
     parameter set theta* (seed) and a start theta0 (seed + 1), both drawn

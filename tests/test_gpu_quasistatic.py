@@ -1,0 +1,99 @@
+"""Quasi-static plate compression on the GPU (cm_qs_* with Newton-CG on the
+backward kernels' Hessian-vector products) against the FP64 oracle's
+minimiser of the same potential, along the same loading path.
+
+Tolerance: the device stops at |f + p|_2 <= 1e-3 |p|_2 (projected residual,
+float32 positions: the floor is about 5e-6 absolute, 3e-4 |p| at the
+smallest compression), the oracle at a float64 gradient norm of 1e-10; the
+plate force moves by well under the relative residual (measured 1e-5 to
+2e-4), so the bar on the top-plate force is 2e-3 relative, and the plates
+balance to 1e-3."""
+import warnings
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import require_gpu
+from oracle import quasistatic as oqs
+from synth.configs import batch_from_cells, Cell
+from synth.mesh import ellipsoid, sphere_mesh
+
+pytestmark = pytest.mark.gpu
+K = 100.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _cells():
+    """Ellipsoids with their shortest axis along the compression axis: a
+    sphere between frictionless plates can roll at almost no energy cost
+    (its discrete equilibria differ by orientation), an oblate cell cannot,
+    so both solvers reach the same equilibrium."""
+    thetas = [(1.0, 20.0, 0.5), (0.7, 30.0, 0.9), (1.5, 12.0, 0.1)]
+    axes = [(1.2, 1.05, 0.8), (1.1, 1.3, 0.75), (1.25, 1.0, 0.85)]
+    cells = []
+    for k, (th, ax) in enumerate(zip(thetas, axes)):
+        x, tets = sphere_mesh(300 + 100 * k, 5 + k)
+        x = ellipsoid(x, np.array(ax))
+        cells.append(Cell(x, tets, x.astype(np.float32), th))
+    return batch_from_cells(cells)
+
+
+def test_force_curve_against_oracle():
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b = _cells()
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    top0 = np.array([b.cell(c).x[:, 2].max() for c in range(b.n_cells)])
+    bot = np.array([b.cell(c).x[:, 2].min() for c in range(b.n_cells)])
+    delta = np.array([0.02, 0.05, 0.1, 0.2])
+    tops = top0[None, :] - 2.0 * delta[:, None]
+    qs = QuasiStaticCompression(cb, K)
+    Ft, Fb, ok, y = qs.curve(cb.to_device(b.y), tops, bot)
+    assert ok.all(), qs.stats
+    print("newton / cg iterations:", qs.stats)
+    worst = 0.0
+    for c in range(b.n_cells):
+        cell = b.cell(c)
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        yo = cell.x.copy()
+        for s in range(len(delta)):
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore", RuntimeWarning)
+                yo, Fo, Fbo, g = oqs.equilibrium(m, yo, cell.theta, tops[s, c],
+                                                 bot[c], K)
+            err = abs(Ft[s, c] - Fo) / Fo
+            worst = max(worst, err)
+            assert err <= 2e-3, (c, s, Ft[s, c], Fo)
+            assert abs(Ft[s, c] - Fb[s, c]) <= 1e-3 * Ft[s, c]
+    print("worst relative top-plate force difference:", worst)
+    assert np.all(np.diff(Ft, axis=0) > 0)
+
+
+def test_restart_from_equilibrium():
+    """Solving again at the same plate position from an equilibrium takes at
+    most a few Newton steps of float32 size and keeps the plate forces."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b = _cells()
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    top0 = np.array([b.cell(c).x[:, 2].max() for c in range(b.n_cells)])
+    bot = np.array([b.cell(c).x[:, 2].min() for c in range(b.n_cells)])
+    qs = QuasiStaticCompression(cb, K)
+    Ft, _, ok, y = qs.curve(cb.to_device(b.y), (top0 - 0.1)[None, :], bot)
+    assert ok.all()
+    plate = torch.tensor(np.stack([top0 - 0.1, bot], axis=1), device=cb.device)
+    n0 = qs.stats["newton"]
+    y1 = y.clone()
+    assert qs.equilibrate(y1, plate)
+    assert qs.stats["newton"] - n0 <= 3
+    assert (y1 - y).abs().max().item() <= 1e-5
+    assert np.abs(qs.force[:, 0].cpu().numpy() - Ft[0]).max() <= 1e-4 * Ft[0].max()
