@@ -62,16 +62,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, info):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     record (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration),
-    or None if absent or taken on other kernel sources."""
+    or None if absent, taken on other kernel sources or on another layout of
+    the workload (tiles, slots, chunks)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_hash") != kernel_source_hash():
+        return None
+    lay = rec.get("layout", {})
+    if not lay or any(info.get(k) != v for k, v in lay.items()):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes")
@@ -381,6 +385,7 @@ def run_quasistatic(args):
                     f"closing to 20 % of the height in 10 steps",
         "wall_s": wall, "newton": qs.stats["newton"], "cg": hvp,
         "converged_steps": int(ok.sum()), "steps": len(ok),
+        "unconverged_cells_last": int((qs.state[:, 2] > 0).sum().item()),
         "hvp_tets_per_s": hvp * b.n_tets / wall,
         "max_force_mean": float(Ft[-1].mean()),
         "plate_balance": float(np.max(np.abs(Ft - Fb) / np.maximum(Ft, 1e-30))),
@@ -472,6 +477,9 @@ def main():
     ap.add_argument("--cells", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--tile-tets", type=int, default=768)
+    ap.add_argument("--order", type=int, default=None,
+                    help="tile order (0 input, 1 RCM, 2 Morton, 3 bisection; "
+                         "default: the library's)")
     ap.add_argument("--parity-cells", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -515,7 +523,7 @@ def main():
         f"({time.time() - t:.1f} s)")
     t = time.time()
     cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets,
-                   tile_tets=args.tile_tets)
+                   tile_tets=args.tile_tets, order=args.order)
     log(f"prepared + uploaded in {time.time() - t:.1f} s: {cb.info}")
     cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
     dev = cb.device
@@ -598,7 +606,7 @@ def main():
     }
     dom = "backward_tile" if ms[2] >= ms[0] else "forward_tile"
     kd = kern[dom]
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, cb.info)
     if kd["alu_frac"] > kd["hbm_frac"]:
         roofline = {"bound": "alu", "kernel": dom,
                     "achieved": round(kd["TFLOPs"], 2),
@@ -651,6 +659,8 @@ def main():
                         f"{N} nodes; one step = batched forward + backward",
             "n_cells": b.n_cells, "n_tets": M, "n_nodes": N,
             "tile_tets": cb.info["tile_tets"], "launch": list(launch),
+            "tile_order": {0: "input", 1: "rcm", 2: "morton", 3: "bisection",
+                           None: "bisection"}[args.order],
             "parallelism": "single GPU",
         },
         "fwd_tets_per_s": M / (res["fwd"] * 1e-3),

@@ -67,10 +67,12 @@ enum {
 };
 
 /* Node / tetrahedron ordering used to form tiles. */
-enum { CM_ORDER_INPUT = 0, CM_ORDER_RCM = 1, CM_ORDER_MORTON = 2 };
+/* CM_ORDER_BISECT: tiles by recursive inertial bisection of the reference
+ * centroids (compact tiles, fewer shared nodes), Morton order inside a tile. */
+enum { CM_ORDER_INPUT = 0, CM_ORDER_RCM = 1, CM_ORDER_MORTON = 2, CM_ORDER_BISECT = 3 };
 
 typedef struct {
-  int32_t order;          /* CM_ORDER_*; default CM_ORDER_MORTON             */
+  int32_t order;          /* CM_ORDER_*; default CM_ORDER_BISECT             */
   int32_t tile_tets;      /* tetrahedra per tile, a multiple of 64 in        */
                           /* [64, 4096]; 0 = default (768)                    */
   double degenerate_tol;  /* reject |det J| <= tol * h^3 with h the cell's   */
@@ -311,31 +313,58 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  * conjugate gradients whose Hessian-vector products are cm_forces_backward
  * calls (ybar = (df/dy)^T v = -Hess(E) v) plus the diagonal penalty
  * Hessian; the caller drives the loop:
- *   cm_forces(y -> f); cm_qs_residual;  repeat: cm_forces_backward(y, fbar = p
- *   -> ybar); cm_qs_cg_step;  then cm_qs_update.
+ *   cm_forces(y -> f, E); cm_qs_residual;  repeat: cm_forces_backward(y,
+ *   fbar = p -> ybar); cm_qs_cg_step;  then either cm_qs_update (bounded
+ *   step) or a line search on Pi: cm_qs_ls_start, then repeat cm_forces(
+ *   y_trial -> E_trial); cm_qs_ls_accept while some cell is pending.
  * Arrays (device, SoA float32[3 n_nodes]): r (residual), p (search
- * direction), x (Newton step), Ap (scratch); state: float64[8 n_cells] =
- * |r|^2, |r_0|^2, active (1/0), |r_N|^2, last step scale, |penalty|^2,
- * largest node move of the last step, spare.
+ * direction), x (Newton step), Ap (scratch), r_newton (copy of r_N,
+ * nullable), y_trial; state: float64[16 n_cells] = CG |r|^2, CG |r_0|^2, CG
+ * active, |r_N|^2, accepted step scale, |penalty|^2, largest node move of
+ * the last step, float32 floor rho, Pi(y), line-search scale, slope
+ * r_N . x, not in equilibrium (1/0), line search pending (1/0), max |x|,
+ * 2 spare.
  *   cm_qs_residual: r = p = r_N, x = 0, with r_N = f + penalty minus its
  *     components along the exact symmetries of the plates (translations in
  *     x and y, rotation about z through the centroid); active iff |r_N|_2 >
- *     max(abs_tol, rel_tol |penalty|_2) and the last step moved some node by
- *     more than step_tol (restart != 0: no last step, at a new plate
- *     position); force (nullable) float64[2 n_cells] = top and bottom plate
- *     forces k sum max(0, .)^2.
+ *     max(abs_tol, rel_tol |penalty|_2, floor_factor rho) and the last step
+ *     moved some node by more than step_tol (restart != 0: no last step, at
+ *     a new plate position); force (nullable) float64[2 n_cells] = top and
+ *     bottom plate forces k sum max(0, .)^2; energy (nullable) E(y) per cell
+ *     from cm_forces, giving Pi(y) in the state.
+ *   cm_qs_ls_start: s = min(1, cap / max_i |x_i|), slope r_N . x; y_trial =
+ *     y + s x for cells not in equilibrium whose step descends, y otherwise.
+ *   cm_qs_ls_accept (energy_trial = E(y_trial) from cm_forces): a pending
+ *     cell accepts y_trial (copied into y) if Pi(y_trial) <= Pi(y) - armijo
+ *     s (r_N . x), else halves s and forms the next trial; it gives up (no
+ *     move, last step 0) once s max|x| < min_move.
+ *   cm_qs_noise / cm_qs_floor: the float32 floor rho of the residual: e =
+ *     +-|y| 2^-24 per coordinate (half a unit in the last place, signs from
+ *     a fixed hash of the index), then after ybar = cm_forces_backward(y,
+ *     fbar = e), rho = |Hess(Pi) e|_2 per cell, stored in the state.
  *   cm_qs_cg_step: one CG iteration for every active cell; a cell stops at
  *     |r| <= rel_tol |r_0| or at non-positive curvature.
  *   cm_qs_update: y += s x, s = min(1, cap / max_i |x_i|) per cell.
- *   cm_qs_predict: z -> b' + (z - b)(t' - b') / (t - b) for a new plate pair
- *     (t', b') (affine prediction between the plates).
+ *   cm_qs_predict: z -> b' + (z - b) s, s = (t' - b') / (t - b), for a new
+ *     plate pair (t', b'), and x, y stretched by 1/sqrt(s) about the cell's
+ *     centroid (a volume-preserving affine prediction).
  * Errors: CM_EINVAL for null pointers, negative or non-finite k_plate or
  * tolerances, cap <= 0.
  */
-int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* plate,
-                   double k_plate, double abs_tol, double rel_tol, double step_tol,
-                   int32_t restart, float* r, float* p, float* x, double* state,
-                   double* force, hipStream_t stream);
+int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* energy,
+                   const double* plate, double k_plate, double abs_tol,
+                   double rel_tol, double step_tol, double floor_factor,
+                   int32_t restart, float* r, float* p, float* x, float* r_newton,
+                   double* state, double* force, hipStream_t stream);
+int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
+                   const float* y, float* y_trial, double* state,
+                   hipStream_t stream);
+int cm_qs_ls_accept(cm_batch h, const float* x, const double* plate, double k_plate,
+                    const double* energy_trial, double armijo, double min_move,
+                    float* y, float* y_trial, double* state, hipStream_t stream);
+int cm_qs_noise(cm_batch h, const float* y, float* e, hipStream_t stream);
+int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
+                const float* e, const float* ybar, double* state, hipStream_t stream);
 int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
                   double rel_tol, const float* ybar, float* x, float* r, float* p,
                   float* Ap, double* state, hipStream_t stream);

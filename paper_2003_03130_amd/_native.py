@@ -100,9 +100,18 @@ SIGNATURES = {
                                         ctypes.POINTER(_vp)]),
     "cm_layout_export_regions": (_int, [_vp, _vp, _vp, _vp]),
     "cm_shape": (_int, [_vp, _vp, _vp, _vp, _vp]),
-    "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, ctypes.c_double,
+    "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                              _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+                              ctypes.c_double, _i32, _vp, _vp, _vp, _vp, _vp,
+                              _vp, _vp]),
+    "cm_qs_ls_start": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
+                              _vp]),
+    "cm_qs_ls_accept": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp,
+                               ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
+                               _vp]),
+    "cm_qs_noise": (_int, [_vp, _vp, _vp, _vp]),
+    "cm_qs_floor": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
+                           _vp]),
     "cm_qs_cg_step": (_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                              _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_update": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),

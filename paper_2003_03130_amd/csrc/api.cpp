@@ -136,7 +136,7 @@ int cm_version(void) { return 1; }
 
 void cm_options_default(cm_options* opt) {
   if (!opt) return;
-  opt->order = CM_ORDER_MORTON;
+  opt->order = CM_ORDER_BISECT;
   opt->tile_tets = 768;
   opt->degenerate_tol = 1e-12;
 }
@@ -657,20 +657,74 @@ int cm_plate_step(cm_batch h, const float* y, const float* f,
   return CM_OK;
 }
 
-int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* plate,
-                   double k_plate, double abs_tol, double rel_tol, double step_tol,
-                   int32_t restart, float* r, float* p, float* x, double* state,
-                   double* force, hipStream_t stream) {
+int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* energy,
+                   const double* plate, double k_plate, double abs_tol,
+                   double rel_tol, double step_tol, double floor_factor,
+                   int32_t restart, float* r, float* p, float* x, float* r_newton,
+                   double* state, double* force, hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !f || !plate || !r || !p || !x || !state)
     return fail(CM_EINVAL, "y, f, plate, r, p, x and state must be device pointers");
   if (!std::isfinite(k_plate) || k_plate < 0 || !(abs_tol >= 0) || !(rel_tol >= 0) ||
-      !(step_tol >= 0))
+      !(step_tol >= 0) || !(floor_factor >= 0))
     return fail(CM_EINVAL, "k_plate and tolerances must be finite and >= 0");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_residual(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, f,
-                                plate, k_plate, abs_tol, rel_tol, step_tol,
-                                restart ? 1 : 0, r, p, x, state, force, stream));
+                                energy, plate, k_plate, abs_tol, rel_tol, step_tol,
+                                floor_factor, restart ? 1 : 0, r, p, x, r_newton,
+                                state, force, stream));
+  return CM_OK;
+}
+
+int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
+                   const float* y, float* y_trial, double* state,
+                   hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !r_newton || !y || !y_trial || !state || y_trial == y)
+    return fail(CM_EINVAL, "x, r_newton, y, y_trial (distinct from y) and state "
+                           "must be device pointers");
+  if (!(cap > 0) || !std::isfinite(cap)) return fail(CM_EINVAL, "cap must be finite and > 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_ls_start(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, x,
+                                r_newton, cap, y, y_trial, state, stream));
+  return CM_OK;
+}
+
+int cm_qs_ls_accept(cm_batch h, const float* x, const double* plate, double k_plate,
+                    const double* energy_trial, double armijo, double min_move,
+                    float* y, float* y_trial, double* state, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !plate || !energy_trial || !y || !y_trial || !state || y_trial == y)
+    return fail(CM_EINVAL, "x, plate, energy_trial, y, y_trial (distinct from y) "
+                           "and state must be device pointers");
+  if (!std::isfinite(k_plate) || k_plate < 0 || !(armijo >= 0) || !(armijo < 1) ||
+      !(min_move >= 0))
+    return fail(CM_EINVAL, "k_plate >= 0, 0 <= armijo < 1 and min_move >= 0 required");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_ls_accept(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, x,
+                                 plate, k_plate, energy_trial, armijo, min_move, y,
+                                 y_trial, state, stream));
+  return CM_OK;
+}
+
+int cm_qs_noise(cm_batch h, const float* y, float* e, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !e || e == y) return fail(CM_EINVAL, "y and e must be distinct device pointers");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_noise(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, e, stream));
+  return CM_OK;
+}
+
+int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
+                const float* e, const float* ybar, double* state, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !plate || !e || !ybar || !state)
+    return fail(CM_EINVAL, "y, plate, e, ybar and state must be device pointers");
+  if (!std::isfinite(k_plate) || k_plate < 0)
+    return fail(CM_EINVAL, "k_plate must be finite and >= 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_floor(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
+                             k_plate, e, ybar, state, stream));
   return CM_OK;
 }
 

@@ -25,14 +25,32 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
 
 // Quasi-static plate compression (one workgroup per cell): Newton residual,
 // one conjugate-gradient iteration, bounded Newton update, plate predictor.
-// Per-cell state: kQsState float64 = |r|^2, |r_0|^2, active, |f + p|^2,
-// applied step scale, |penalty|^2, largest node move of the last step, spare.
-constexpr int kQsState = 8;
+// Per-cell state: kQsState float64 = 0 CG |r|^2, 1 CG |r_0|^2, 2 CG active,
+// 3 Newton |r_N|^2, 4 accepted step scale, 5 |penalty|^2, 6 largest node move
+// of the last step, 7 float32 floor of the residual, 8 Pi(y), 9 line-search
+// scale, 10 slope r_N . x, 11 not in equilibrium, 12 line search pending,
+// 13 max |x|, 14-15 spare.
+constexpr int kQsState = 16;
 hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cells,
-                              const float* y, const float* f, const double* plate,
-                              double k, double abs_tol, double rel_tol,
-                              double step_tol, int restart, float* r, float* p,
-                              float* x, double* st, double* force, hipStream_t s);
+                              const float* y, const float* f, const double* energy,
+                              const double* plate, double k, double abs_tol,
+                              double rel_tol, double step_tol, double floor_factor,
+                              int restart, float* r, float* p, float* x, float* rn,
+                              double* st, double* force, hipStream_t s);
+hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
+                              const float* x, const float* rn, double cap,
+                              const float* y, float* yt, double* st, hipStream_t s);
+hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cells,
+                               const float* x, const double* plate, double k,
+                               const double* energy_t, double armijo,
+                               double min_move, float* y, float* yt, double* st,
+                               hipStream_t s);
+hipError_t launch_qs_noise(const int64_t* node_off, int64_t N, int32_t n_cells,
+                           const float* y, float* e, hipStream_t s);
+hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
+                           const float* y, const double* plate, double k,
+                           const float* e, const float* ybar, double* st,
+                           hipStream_t s);
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,

@@ -42,6 +42,94 @@ inline uint32_t spread3(uint32_t v) {
   return v;
 }
 
+// Reference centroids of the tetrahedra (xyz per tet).
+void centroids(int64_t m, const int32_t* T, const double* X, std::vector<double>& cen) {
+  cen.resize(3 * m);
+  for (int64_t t = 0; t < m; ++t)
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+      for (int a = 0; a < 4; ++a) s += X[3 * (int64_t)T[4 * t + a] + i];
+      cen[3 * t + i] = 0.25 * s;
+    }
+}
+
+// Recursive inertial bisection state of one cell.
+struct Bisector {
+  const int32_t* T;
+  const std::vector<double>& cen;     // reference centroids
+  const std::vector<int64_t>& rank;   // locality (Morton) rank of every tet
+  int64_t tt;                         // tets per tile
+  int64_t node_cap;                   // most distinct nodes per tile
+  std::vector<int64_t>& perm;
+  std::vector<int64_t> ends;          // tile ends (positions in perm)
+  std::vector<int32_t> stamp;         // per node: last leaf that counted it
+  int32_t gen = 0;
+
+  // Sorts perm[a, b) along the principal axis of the centroids (power
+  // iteration on their covariance; ties by rank, so deterministic).
+  void sort_principal(int64_t a, int64_t b) {
+    const int64_t n = b - a;
+    double mu[3] = {0, 0, 0}, cv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int64_t q = a; q < b; ++q)
+      for (int i = 0; i < 3; ++i) mu[i] += cen[3 * perm[q] + i];
+    for (int i = 0; i < 3; ++i) mu[i] /= (double)n;
+    for (int64_t q = a; q < b; ++q) {
+      double d[3];
+      for (int i = 0; i < 3; ++i) d[i] = cen[3 * perm[q] + i] - mu[i];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) cv[i][j] += d[i] * d[j];
+    }
+    double v[3] = {0.6, 0.5, 0.4};
+    for (int it = 0; it < 40; ++it) {
+      double w[3] = {0, 0, 0};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) w[i] += cv[i][j] * v[j];
+      const double nw = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+      if (!(nw > 0)) break;
+      for (int i = 0; i < 3; ++i) v[i] = w[i] / nw;
+    }
+    std::vector<std::pair<double, int64_t>> key(n);
+    for (int64_t q = 0; q < n; ++q) {
+      const double* c = &cen[3 * perm[a + q]];
+      key[q] = {c[0] * v[0] + c[1] * v[1] + c[2] * v[2], rank[perm[a + q]]};
+    }
+    std::vector<int64_t> idx(perm.begin() + a, perm.begin() + b), ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+    for (int64_t q = 0; q < n; ++q) perm[a + q] = idx[ord[q]];
+  }
+
+  int64_t distinct_nodes(int64_t a, int64_t b) {
+    ++gen;
+    int64_t cnt = 0;
+    for (int64_t q = a; q < b; ++q)
+      for (int k = 0; k < 4; ++k) {
+        const int32_t v = T[4 * perm[q] + k];
+        if (stamp[v] != gen) { stamp[v] = gen; ++cnt; }
+      }
+    return cnt;
+  }
+
+  // perm[a, b) into tiles: whole tiles of tt tets (the last one ragged) by
+  // halving along the principal axis, the first part taking floor(k/2)
+  // tiles; a tile touching more than node_cap nodes (thin or boundary-heavy
+  // parts) is halved again.  Tets keep their locality order inside a tile.
+  void split(int64_t a, int64_t b) {
+    const int64_t n = b - a;
+    const int64_t k = (n + tt - 1) / tt;
+    if (k <= 1 && (n <= kChunk || distinct_nodes(a, b) <= node_cap)) {
+      std::sort(perm.begin() + a, perm.begin() + b,
+                [&](int64_t x, int64_t y) { return rank[x] < rank[y]; });
+      ends.push_back(b);
+      return;
+    }
+    sort_principal(a, b);
+    const int64_t mid = k > 1 ? a + (k / 2) * tt : a + n / 2;
+    split(a, mid);
+    split(mid, b);
+  }
+};
+
 // Tet order by the Morton (Z-order) code of the reference centroid.
 void morton_order(int64_t m, const int32_t* T, const double* X,
                   std::vector<int64_t>& perm) {
@@ -257,7 +345,7 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
 
   // Locality order of the tetrahedra.
   std::vector<int64_t> perm;
-  if (opt.order == CM_ORDER_MORTON) {
+  if (opt.order == CM_ORDER_MORTON || opt.order == CM_ORDER_BISECT) {
     morton_order(m, T, X, perm);
   } else if (opt.order == CM_ORDER_RCM) {
     rcm_order(n, m, T, perm);
@@ -277,15 +365,37 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
   std::vector<int64_t> tlo, thi;  // tet range [tlo, thi) of every tile in the order
   out.region_tile_first.assign(n_regions, 0);
   out.region_tile_count.assign(n_regions, 0);
+  std::vector<double> cen;
+  std::vector<int64_t> rank;
+  if (opt.order == CM_ORDER_BISECT) {
+    centroids(m, T, X, cen);
+    rank.resize(m);
+    for (int64_t p = 0; p < m; ++p) rank[perm[p]] = p;
+  }
   for (int64_t p = 0; p < m;) {
     const int32_t r = region ? (int32_t)region[perm[p]] : 0;
     int64_t e = p;
     while (e < m && (region ? (int32_t)region[perm[e]] : 0) == r) ++e;
     out.region_tile_first[r] = (int32_t)tlo.size();
-    for (int64_t a = p; a < e; a += TT) {
-      tlo.push_back(a);
-      thi.push_back(std::min(e, a + TT));
-      out.tile_region.push_back(r);
+    if (opt.order == CM_ORDER_BISECT) {
+      // compact tiles by recursive bisection inside the region, Morton
+      // order inside every tile; at most 5/12 tile_tets nodes per tile
+      Bisector bs{T, cen, rank, TT, std::max<int64_t>(TT * 5 / 12, 4 * kChunk), perm, {},
+                  std::vector<int32_t>(n, -1)};
+      bs.split(p, e);
+      int64_t a = p;
+      for (int64_t b : bs.ends) {
+        tlo.push_back(a);
+        thi.push_back(b);
+        out.tile_region.push_back(r);
+        a = b;
+      }
+    } else {
+      for (int64_t a = p; a < e; a += TT) {
+        tlo.push_back(a);
+        thi.push_back(std::min(e, a + TT));
+        out.tile_region.push_back(r);
+      }
     }
     out.region_tile_count[r] = (int32_t)tlo.size() - out.region_tile_first[r];
     p = e;
@@ -462,7 +572,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
     *err = "tile_tets must be a multiple of 64 in [64, 4096]";
     return CM_EINVAL;
   }
-  if (opt.order < 0 || opt.order > 2) {
+  if (opt.order < 0 || opt.order > 3) {
     *err = "unknown order";
     return CM_EINVAL;
   }

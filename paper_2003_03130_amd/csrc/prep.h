@@ -9,7 +9,7 @@
 namespace cm {
 
 struct PrepOptions {
-  int order = 2;                // 0 input, 1 RCM, 2 Morton
+  int order = 3;                // 0 input, 1 RCM, 2 Morton, 3 bisection
   int tile_tets = 768;         // multiple of 64, <= kMaxTileTets
   double degenerate_tol = 1e-12;
 };

@@ -51,10 +51,12 @@ struct ResArgs {
   int64_t N;
   const float* y;
   const float* f;
-  const double* plate;  // per cell: top, bottom
-  double k, abs_tol, rel_tol, step_tol;
+  const double* energy;  // per cell E(y), nullable (no potential recorded)
+  const double* plate;   // per cell: top, bottom
+  double k, abs_tol, rel_tol, step_tol, floor_factor;
   int restart;  // 1: first call at this plate position (forget the last step)
   float *r, *p, *x;
+  float* rn;      // copy of the Newton residual (nullable)
   double* st;     // kQsState per cell
   double* force;  // per cell: top, bottom plate force (nullable)
 };
@@ -65,10 +67,9 @@ struct ResArgs {
 // invariant under them, so Hess(Pi) annihilates them and the forces have no
 // net component along them up to rounding).  CG start x = 0, p = r.  A cell
 // is active (not yet in equilibrium) when |r|_2 > max(abs_tol,
-// rel_tol |pen|_2), pen the plate penalty forces, and its last Newton step
-// moved no node by more than step_tol (float32 positions bound how small
-// the residual can get, so a step below a few units in the last place ends
-// the iteration).
+// rel_tol |pen|_2, floor_factor rho), pen the plate penalty forces and rho
+// the cell's float32 floor (qs_floor_kernel), and its last Newton step moved
+// some node by more than step_tol.
 __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -103,10 +104,11 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   tq = block_sum(tq, red);
   ww = block_sum(ww, red);
   const double om = ww > 0.0 ? tq / ww : 0.0;
-  double rr = 0.0, ft = 0.0, fb = 0.0, pp = 0.0;
+  double rr = 0.0, ft = 0.0, fb = 0.0, pp = 0.0, phi = 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     double dt, db, pz;
     const double rzd = rz_of(i, dt, db, pz);
+    phi += dt * dt * dt + db * db * db;
     const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
     const float rx = (float)((double)a.f[i] - mx + om * dy);
     const float ry = (float)((double)a.f[N + i] - my - om * dx);
@@ -115,6 +117,7 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
     a.r[i] = rx; a.r[N + i] = ry; a.r[2 * N + i] = rz;
     a.p[i] = rx; a.p[N + i] = ry; a.p[2 * N + i] = rz;
     a.x[i] = 0.f; a.x[N + i] = 0.f; a.x[2 * N + i] = 0.f;
+    if (a.rn) { a.rn[i] = rx; a.rn[N + i] = ry; a.rn[2 * N + i] = rz; }
     rr += (double)rx * rx + (double)ry * ry + (double)rz * rz;
     ft += a.k * dt * dt;
     fb += a.k * db * db;
@@ -123,15 +126,20 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   ft = block_sum(ft, red);
   fb = block_sum(fb, red);
   pp = block_sum(pp, red);
+  phi = block_sum(phi, red) * (a.k / 3.0);
   if (threadIdx.x == 0) {
     double* s = a.st + kQsState * c;
-    const double tol2 = fmax(a.abs_tol * a.abs_tol, a.rel_tol * a.rel_tol * pp);
+    const double fl = a.floor_factor * s[7];
+    const double tol2 = fmax(fmax(a.abs_tol * a.abs_tol, a.rel_tol * a.rel_tol * pp), fl * fl);
     if (a.restart) s[6] = __builtin_inf();
     s[0] = rr;                      // CG residual |r|^2
     s[1] = rr;                      // its start value
-    s[2] = (rr > tol2 && s[6] > a.step_tol) ? 1.0 : 0.0;  // not yet in equilibrium
+    const double act = (rr > tol2 && s[6] > a.step_tol) ? 1.0 : 0.0;
+    s[2] = act;                     // CG active
+    s[11] = act;                    // not yet in equilibrium
     s[3] = rr;                      // Newton residual |f + p|^2 (projected)
     s[5] = pp;                      // |penalty forces|^2
+    if (a.energy) s[8] = a.energy[c] + phi;  // Pi(y)
     if (a.force) { a.force[2 * c] = ft; a.force[2 * c + 1] = fb; }
   }
 }
@@ -199,6 +207,55 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   }
 }
 
+// Float32 floor of the residual.  Positions held in float32 carry rounding
+// errors of up to half a unit in the last place, so the residual of a
+// float32 state cannot be resolved below |Hess(Pi) e| for such an error e.
+// qs_noise_kernel writes e_q = +-|y_q| 2^-24 with a sign from a fixed hash of
+// the index; after the Hessian-vector product ybar = (df/dy)^T e,
+// qs_floor_kernel stores rho = |-ybar + penalty diagonal e|_2 per cell.
+__global__ __launch_bounds__(kThreads) void qs_noise_kernel(const int64_t* node_off,
+                                                            int64_t N, const float* y,
+                                                            float* e) {
+  const int c = blockIdx.x;
+  const int64_t n0 = node_off[c], n1 = node_off[c + 1];
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t q = d * N + i;
+      const uint32_t hsh = (uint32_t)q * 2654435761u;
+      const float mag = fabsf(y[q]) * 5.9604645e-8f;  // 2^-24
+      e[q] = (hsh >> 16) & 1u ? mag : -mag;
+    }
+}
+
+struct FloorArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* y;
+  const double* plate;
+  double k;
+  const float* e;
+  const float* ybar;
+  double* st;
+};
+
+__global__ __launch_bounds__(kThreads) void qs_floor_kernel(FloorArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  double acc = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    const double z = a.y[2 * N + i];
+    const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+    const double hx = -(double)a.ybar[i], hy = -(double)a.ybar[N + i];
+    const double hz = -(double)a.ybar[2 * N + i] + h * (double)a.e[2 * N + i];
+    acc += hx * hx + hy * hy + hz * hz;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) a.st[kQsState * c + 7] = sqrt(acc);
+}
+
 struct UpdArgs {
   const int64_t* node_off;
   int64_t N;
@@ -233,6 +290,106 @@ __global__ __launch_bounds__(kThreads) void qs_update_kernel(UpdArgs a) {
   }
 }
 
+struct LsArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* x;
+  const float* rn;         // Newton residual (-grad Pi, projected)
+  const double* plate;
+  const double* energy_t;  // E at the trial positions (accept)
+  double k, cap, armijo, min_move;
+  float* y;
+  float* yt;               // trial positions
+  double* st;
+};
+
+// Start of the line search on Pi along the Newton step x: s = min(1, cap /
+// max |x_i|), slope r_N . x (> 0 for a descent direction), y_t = y + s x for
+// the cells in equilibrium-search, y_t = y for the others.
+__global__ __launch_bounds__(kThreads) void qs_ls_start_kernel(LsArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  double* s = a.st + kQsState * c;
+  const bool act = s[11] != 0.0;
+  double mx = 0.0, rx = 0.0;
+  if (act)
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int64_t q = d * N + i;
+        mx = fmax(mx, fabs((double)a.x[q]));
+        rx += (double)a.rn[q] * a.x[q];
+      }
+  mx = block_max(mx, red);
+  rx = block_sum(rx, red);
+  const bool go = act && mx > 0.0 && rx > 0.0;
+  const double sc = mx > a.cap ? a.cap / mx : 1.0;
+  const float scf = go ? (float)sc : 0.f;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t q = d * N + i;
+      a.yt[q] = a.y[q] + scf * a.x[q];
+    }
+  if (threadIdx.x == 0) {
+    s[9] = sc;
+    s[10] = rx;
+    s[12] = go ? 1.0 : 0.0;  // line search pending
+    s[13] = mx;
+    if (act && !go) s[6] = 0.0;  // no descent step: nothing left to gain
+  }
+}
+
+// Armijo test per pending cell: accept y_t if Pi(y_t) <= Pi(y) - armijo s
+// (r_N . x), copying y_t into y; else halve s and form the next trial, giving
+// up (no move) once s max|x| < min_move.
+__global__ __launch_bounds__(kThreads) void qs_ls_accept_kernel(LsArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  double* s = a.st + kQsState * c;
+  if (s[12] == 0.0) return;  // uniform over the workgroup
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  double phi = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    const double z = a.yt[2 * N + i];
+    const double dt = fmax(z - top, 0.0), db = fmax(bot - z, 0.0);
+    phi += dt * dt * dt + db * db * db;
+  }
+  phi = block_sum(phi, red) * (a.k / 3.0);
+  const double pit = a.energy_t[c] + phi;
+  const double sc = s[9];
+  const bool ok = pit <= s[8] - a.armijo * sc * s[10];
+  const bool give_up = !ok && 0.5 * sc * s[13] < a.min_move;
+  if (ok) {
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.y[d * N + i] = a.yt[d * N + i];
+  } else {
+    const float scf = give_up ? 0.f : (float)(0.5 * sc);
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int64_t q = d * N + i;
+        a.yt[q] = a.y[q] + scf * a.x[q];
+      }
+  }
+  if (threadIdx.x == 0) {
+    if (ok) {
+      s[8] = pit;
+      s[4] = sc;
+      s[6] = sc * s[13];  // largest node move of this step
+      s[12] = 0.0;
+    } else if (give_up) {
+      s[6] = 0.0;
+      s[12] = 0.0;
+    } else {
+      s[9] = 0.5 * sc;
+    }
+  }
+}
+
 struct PredArgs {
   const int64_t* node_off;
   int64_t N;
@@ -241,27 +398,42 @@ struct PredArgs {
   float* y;
 };
 
-// Predictor for a new plate position: z -> b + (z - b) (t' - b') / (t - b)
-// with the bottom b moved to b' (affine in z between the plates).
+// Predictor for a new plate position: z -> b' + (z - b) s with s = (t' - b')
+// / (t - b), and x, y stretched by 1/sqrt(s) about the cell's centroid, an
+// affine map of unit determinant (cells are nearly incompressible: a z-only
+// compression would start Newton from a large volumetric stress).
 __global__ __launch_bounds__(kThreads) void qs_predict_kernel(PredArgs a) {
+  __shared__ double red[kThreads];
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double t0 = a.plate_old[2 * c], b0 = a.plate_old[2 * c + 1];
   const double t1 = a.plate_new[2 * c], b1 = a.plate_new[2 * c + 1];
   const double sc = (t1 - b1) / (t0 - b0);
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
+  const double lat = sc > 0.0 ? 1.0 / sqrt(sc) : 1.0;
+  double sx = 0.0, sy = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    sx += a.y[i];
+    sy += a.y[N + i];
+  }
+  const double inv_n = 1.0 / (double)(n1 - n0);
+  const double cx = block_sum(sx, red) * inv_n, cy = block_sum(sy, red) * inv_n;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    a.y[i] = (float)(cx + ((double)a.y[i] - cx) * lat);
+    a.y[N + i] = (float)(cy + ((double)a.y[N + i] - cy) * lat);
     a.y[2 * N + i] = (float)(b1 + ((double)a.y[2 * N + i] - b0) * sc);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cells,
-                              const float* y, const float* f, const double* plate,
-                              double k, double abs_tol, double rel_tol,
-                              double step_tol, int restart, float* r, float* p,
-                              float* x, double* st, double* force, hipStream_t s) {
-  ResArgs a{node_off, N, y, f, plate, k, abs_tol, rel_tol, step_tol, restart,
-            r, p, x, st, force};
+                              const float* y, const float* f, const double* energy,
+                              const double* plate, double k, double abs_tol,
+                              double rel_tol, double step_tol, double floor_factor,
+                              int restart, float* r, float* p, float* x, float* rn,
+                              double* st, double* force, hipStream_t s) {
+  ResArgs a{node_off, N, y, f, energy, plate, k, abs_tol, rel_tol, step_tol,
+            floor_factor, restart, r, p, x, rn, st, force};
   hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -280,6 +452,42 @@ hipError_t launch_qs_update(const int64_t* node_off, int64_t N, int32_t n_cells,
                             hipStream_t s) {
   UpdArgs a{node_off, N, x, cap, y, st};
   hipLaunchKernelGGL(qs_update_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_noise(const int64_t* node_off, int64_t N, int32_t n_cells,
+                           const float* y, float* e, hipStream_t s) {
+  hipLaunchKernelGGL(qs_noise_kernel, dim3(n_cells), dim3(kThreads), 0, s, node_off, N,
+                     y, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
+                           const float* y, const double* plate, double k,
+                           const float* e, const float* ybar, double* st,
+                           hipStream_t s) {
+  FloorArgs a{node_off, N, y, plate, k, e, ybar, st};
+  hipLaunchKernelGGL(qs_floor_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
+                              const float* x, const float* rn, double cap,
+                              const float* y, float* yt, double* st, hipStream_t s) {
+  LsArgs a{node_off, N, x, rn, nullptr, nullptr, 0.0, cap, 0.0, 0.0,
+           const_cast<float*>(y), yt, st};
+  hipLaunchKernelGGL(qs_ls_start_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cells,
+                               const float* x, const double* plate, double k,
+                               const double* energy_t, double armijo,
+                               double min_move, float* y, float* yt, double* st,
+                               hipStream_t s) {
+  LsArgs a{node_off, N, x, nullptr, plate, energy_t, k, 0.0, armijo, min_move, y, yt,
+           st};
+  hipLaunchKernelGGL(qs_ls_accept_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 """Quasi-static plate compression of a batch of cells (force-indentation
 curves): each plate position is brought to equilibrium by Newton steps whose
 systems are solved per cell by conjugate gradients on the device (cm_qs_*;
-Hessian-vector products from cm_forces_backward).  Python only orders the
-calls and checks convergence flags between Newton steps."""
+Hessian-vector products from cm_forces_backward), each step globalised by a
+backtracking (Armijo) line search on the total potential.  Python only
+orders the calls and checks convergence flags between Newton steps."""
 from __future__ import annotations
 
 import numpy as np
@@ -14,18 +15,24 @@ from .cells import _ptr, _stream
 class QuasiStaticCompression:
     """batch: CellBatch with parameters set; k_plate: plate penalty;
     rel_tol / abs_tol: equilibrium when |f + p|_2 <= max(abs_tol,
-    rel_tol |p|_2) per cell (p the plate forces) or when a Newton step
-    moves no node by more than step_tol (the float32 floor of the residual);
-    cg_tol: relative CG residual; cap: largest node move per Newton step."""
+    rel_tol |p|_2, floor_factor rho) per cell (p the plate forces, rho the
+    float32 floor of the residual, estimated at every plate position) or
+    when a Newton step moves no node by more than step_tol; cg_tol: relative
+    CG residual; cap: largest node move per Newton step; armijo: sufficient
+    decrease of the line search, which gives up below min_move."""
 
     def __init__(self, batch, k_plate, rel_tol=1e-3, abs_tol=1e-9,
-                 step_tol=1e-6, cg_tol=1e-3, max_newton=40, max_cg=400,
-                 cap=0.05):
+                 step_tol=1e-6, floor_factor=2.0, cg_tol=1e-3, max_newton=40,
+                 max_cg=400, cap=0.05, armijo=1e-4, min_move=1e-7,
+                 max_backtrack=12):
         import torch
         self.cb = batch
         self.k = float(k_plate)
         self.rel_tol, self.abs_tol = float(rel_tol), float(abs_tol)
         self.step_tol = float(step_tol)
+        self.floor_factor = float(floor_factor)
+        self.armijo, self.min_move = float(armijo), float(min_move)
+        self.max_backtrack = int(max_backtrack)
         self.cg_tol, self.cap = float(cg_tol), float(cap)
         self.max_newton, self.max_cg = int(max_newton), int(max_cg)
         dev = batch.device
@@ -35,32 +42,46 @@ class QuasiStaticCompression:
         self._x = batch.empty_nodes()
         self._Ap = batch.empty_nodes()
         self._ybar = batch.empty_nodes()
+        self._rn = batch.empty_nodes()
+        self._yt = batch.empty_nodes()
+        self._ft = batch.empty_nodes()
+        self._Et = torch.empty(batch.n_cells, dtype=torch.float64, device=dev)
         self._E = torch.empty(batch.n_cells, dtype=torch.float64, device=dev)
         self._tb = torch.empty(3 * batch.n_mat, dtype=torch.float64,
                                device=dev)
-        self.state = torch.zeros(batch.n_cells, 8, dtype=torch.float64,
+        self.state = torch.zeros(batch.n_cells, 16, dtype=torch.float64,
                                  device=dev)
         self.force = torch.zeros(batch.n_cells, 2, dtype=torch.float64,
                                  device=dev)
-        self.stats = {"newton": 0, "cg": 0}
+        self.stats = {"newton": 0, "cg": 0, "trials": 0}
 
     def _residual(self, y, plate, restart=False):
         cb = self.cb
         cb.forces(y, self._f, self._E)
         nat.check(nat.lib().cm_qs_residual(
-            cb._h, _ptr(y), _ptr(self._f), _ptr(plate), self.k, self.abs_tol,
-            self.rel_tol, self.step_tol, int(restart), _ptr(self._r),
-            _ptr(self._p), _ptr(self._x), _ptr(self.state), _ptr(self.force),
-            _stream(None)))
+            cb._h, _ptr(y), _ptr(self._f), _ptr(self._E), _ptr(plate), self.k,
+            self.abs_tol, self.rel_tol, self.step_tol, self.floor_factor,
+            int(restart), _ptr(self._r), _ptr(self._p), _ptr(self._x),
+            _ptr(self._rn), _ptr(self.state), _ptr(self.force), _stream(None)))
+
+    def _active(self, col):
+        return bool((self.state[:, col] > 0).any())
 
     def equilibrate(self, y, plate):
         """Newton iterations at one plate position (plate: float64 device
         tensor (n_cells, 2) = top, bottom); y (device SoA) is updated in
         place.  Returns True when every cell met the tolerance."""
         cb = self.cb
+        # float32 floor of the residual at this plate position
+        nat.check(nat.lib().cm_qs_noise(cb._h, _ptr(y), _ptr(self._Ap),
+                                        _stream(None)))
+        cb.backward(y, self._Ap, None, self._ybar, self._tb)
+        nat.check(nat.lib().cm_qs_floor(
+            cb._h, _ptr(y), _ptr(plate), self.k, _ptr(self._Ap),
+            _ptr(self._ybar), _ptr(self.state), _stream(None)))
         for it in range(self.max_newton):
             self._residual(y, plate, restart=(it == 0))
-            if not bool((self.state[:, 2] > 0).any()):
+            if not self._active(11):
                 return True
             self.stats["newton"] += 1
             for j in range(self.max_cg):
@@ -71,13 +92,26 @@ class QuasiStaticCompression:
                     _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
                     _stream(None)))
                 self.stats["cg"] += 1
-                if j % 8 == 7 and not bool((self.state[:, 2] > 0).any()):
+                if j % 8 == 7 and not self._active(2):
                     break
-            nat.check(nat.lib().cm_qs_update(
-                cb._h, _ptr(self._x), self.cap, _ptr(y), _ptr(self.state),
-                _stream(None)))
+            self._line_search(y, plate)
         self._residual(y, plate)
-        return not bool((self.state[:, 2] > 0).any())
+        return not self._active(11)
+
+    def _line_search(self, y, plate):
+        cb = self.cb
+        nat.check(nat.lib().cm_qs_ls_start(
+            cb._h, _ptr(self._x), _ptr(self._rn), self.cap, _ptr(y),
+            _ptr(self._yt), _ptr(self.state), _stream(None)))
+        for _ in range(self.max_backtrack):
+            if not self._active(12):
+                return
+            cb.forces(self._yt, self._ft, self._Et)
+            nat.check(nat.lib().cm_qs_ls_accept(
+                cb._h, _ptr(self._x), _ptr(plate), self.k, _ptr(self._Et),
+                self.armijo, self.min_move, _ptr(y), _ptr(self._yt),
+                _ptr(self.state), _stream(None)))
+            self.stats["trials"] += 1
 
     def curve(self, y0, tops, bottom):
         """Top-plate force of every cell at each plate height (tops: (S,) or

@@ -66,7 +66,8 @@ def _decode_tets(L, b):
     return np.array(out, dtype=np.int64)
 
 
-@pytest.mark.parametrize("order,tile", [(0, 64), (1, 256), (2, 1024), (2, 128)])
+@pytest.mark.parametrize("order,tile", [(0, 64), (1, 256), (2, 1024), (2, 128),
+                                        (3, 768), (3, 192)])
 def test_layout_is_a_relabelling_of_the_input(order, tile):
     from paper_2003_03130_amd import HostLayout
     b = _batch()
@@ -109,10 +110,12 @@ def test_layout_is_a_relabelling_of_the_input(order, tile):
     assert np.allclose(V0, np.abs(np.linalg.det(Dm)) / 6, rtol=2e-7, atol=0)
 
 
-def test_owned_and_shared_tables_partition_the_nodes():
+@pytest.mark.parametrize("order", [2, 3])
+def test_owned_and_shared_tables_partition_the_nodes(order):
     from paper_2003_03130_amd import HostLayout
     b = _batch(4)
-    L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256)
+    L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256,
+                   order=order)
     owner = np.full(b.n_nodes, -1)
     for t in range(L.n_tiles):
         ob, no = L.tiles[t, 2], L.tiles[t, 3]
@@ -141,13 +144,15 @@ def test_owned_and_shared_tables_partition_the_nodes():
         assert touch[int(g)] == {int(owner[g])}
 
 
-def test_layout_scatter_matches_direct_assembly():
+@pytest.mark.parametrize("order", [2, 3])
+def test_layout_scatter_matches_direct_assembly(order):
     """Summing per-tetrahedron corner values through the tile tables (LDS
     accumulation, owned stores, slot partials, finalize) equals a direct
     scatter-add: checks the reduction plumbing independently of the physics."""
     from paper_2003_03130_amd import HostLayout
     b = _batch(3)
-    L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=192)
+    L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=192,
+                   order=order)
     rng = np.random.default_rng(0)
     rec = _decode_tets(L, b)
     vals = rng.normal(size=(len(rec), 4))
@@ -245,7 +250,8 @@ def test_template_layout_replicates_one_cell():
     assert np.allclose(got, direct, rtol=0, atol=1e-12)
 
 
-def test_region_layout_tiles_one_region_each():
+@pytest.mark.parametrize("order", [2, 3])
+def test_region_layout_tiles_one_region_each(order):
     """cm_layout_create_regions: still a relabelling of every cell's
     tetrahedra; every tile holds tetrahedra of one region only, the one its
     material slot names; the tiles of each slot are its first/count range; a
@@ -257,7 +263,7 @@ def test_region_layout_tiles_one_region_each():
                                          b.tets[b.tet_off[c]:b.tet_off[c + 1]])
                           for c in range(b.n_cells)])
     L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256,
-                   regions=reg, n_regions=R)
+                   regions=reg, n_regions=R, order=order)
     rec = _decode_tets(L, b)
     # region of every decoded tetrahedron, by matching its sorted vertices
     key = {}
