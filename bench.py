@@ -153,12 +153,17 @@ def parity(cb, b, f, E, ybar, tb, vbar, ebar, cells):
     return worst
 
 
-def cpu_baseline(b, vbar, ebar, seconds):
-    """The FP64 oracle (forward + backward) on the first cells of the same
-    workload until about `seconds` of single-thread CPU time."""
+def cpu_baseline(b, vbar, ebar, seconds, threads=16):
+    """The FP64 oracle (forward + backward) on the host: first a single
+    thread on the first cells for about seconds/3, then `threads` threads
+    (the oracle's C routines run outside the Python lock, one cell per call)
+    on the following cells for about `seconds` of wall time."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
-    tets, spent, ncell = 0, 0.0, 0
-    for c in range(b.n_cells):
+
+    def run_cell(c):
         cell = b.cell(c)
         n0, n1 = b.node_off[c], b.node_off[c + 1]
         m = oracle.OracleMesh(cell.x, cell.tets)
@@ -167,16 +172,48 @@ def cpu_baseline(b, vbar, ebar, seconds):
         t0 = time.perf_counter()
         m.forces(y64, cell.theta)
         m.backward(y64, cell.theta, v64, float(ebar[c]))
-        spent += time.perf_counter() - t0
-        tets += cell.n_tets
-        ncell += 1
-        if spent >= seconds:
-            break
-    return {"value": tets / spent, "unit": "tets/s", "cores": 1,
+        return cell.n_tets, time.perf_counter() - t0
+
+    # single thread
+    tets1, spent, c = 0, 0.0, 0
+    while spent < seconds / 3 and c < b.n_cells:
+        n, dt = run_cell(c)
+        tets1, spent, c = tets1 + n, spent + dt, c + 1
+    single = tets1 / spent
+    first_multi = c
+    # many threads, wall clock
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    nxt = [first_multi]
+    lock = threading.Lock()
+    done = [0, 0]
+    t_end = time.perf_counter() + seconds
+
+    def worker():
+        while time.perf_counter() < t_end:
+            with lock:
+                c = nxt[0]
+                nxt[0] += 1
+            if c >= b.n_cells:
+                return
+            n, _ = run_cell(c)
+            with lock:
+                done[0] += n
+                done[1] += 1
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        for f in [ex.submit(worker) for _ in range(threads)]:
+            f.result()
+    wall = time.perf_counter() - t0
+    return {"value": done[0] / wall, "unit": "tets/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {ncell} cells of the workload ({tets} tets), "
-                      f"FP64 oracle forward (derivative-table path) + backward "
-                      f"(dual-number JVPs), single thread, {spent:.1f} s"}
+            "single_thread_value": single,
+            "sample": f"FP64 oracle forward (derivative-table path) + backward "
+                      f"(dual-number JVPs) on cells of the workload: {threads} "
+                      f"threads, one cell per call, cells {first_multi}.."
+                      f"{first_multi + done[1] - 1} ({done[0]} tets) in "
+                      f"{wall:.1f} s wall; single thread on cells 0..{c - 1} "
+                      f"({tets1} tets, {spent:.1f} s)"}
 
 
 def hertz_targets(theta, top, radius=1.0):
@@ -537,6 +574,24 @@ def main():
     tb = torch.empty(3 * b.n_cells, dtype=torch.float64, device=dev)
     ninv = torch.empty(b.n_cells, dtype=torch.int32, device=dev)
 
+    # device-to-device copy bandwidth (context for the HBM roof): 1 GiB
+    # read + 1 GiB written, best of 5
+    src = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    copy_ms = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_ms.append(e0.elapsed_time(e1))
+    copy_gbps = 2 * src.numel() * 4 / min(copy_ms) / 1e6
+    del src, dst
+    log(f"device copy: {copy_gbps:.0f} GB/s")
+
     if args.calibrate_copy:
         nf = args.calibrate_copy * 2 ** 20 // 4
         src = torch.ones(nf, dtype=torch.float32, device=dev)
@@ -665,6 +720,7 @@ def main():
         },
         "fwd_tets_per_s": M / (res["fwd"] * 1e-3),
         "fwd_bwd_tets_per_s": M / (step_ms * 1e-3),
+        "hbm_copy_GBps": copy_gbps,
         "hbm_frac_fwd": fwd_b / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "hbm_frac_fwd_bwd": (fwd_b + bwd_b) / (step_ms * 1e-3)
         / (HBM_PEAK_GBS * 1e9),

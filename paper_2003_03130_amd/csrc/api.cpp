@@ -44,6 +44,9 @@ struct cm_batch_s {
   // shape diagnostics scratch
   const int4* pair_blocks = nullptr;
   int64_t n_pair_blocks = 0;
+  const int2* node_blocks = nullptr;
+  int64_t n_node_blocks = 0;
+  double* shape_bbox = nullptr;
   double* shape_mom = nullptr;
   unsigned long long* d2max = nullptr;
   int32_t tile_tets = 0, max_tile_nodes = 0;
@@ -229,21 +232,31 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
       return bail(rc);
     // 256 x 256 node-pair blocks of every cell (row block <= column block)
     std::vector<int4> pb;
+    std::vector<int2> nbk;
     for (int64_t c = 0; c < h->n_cells; ++c) {
       const int64_t nb = (P.node_off[c + 1] - P.node_off[c] + 255) / 256;
-      for (int64_t i = 0; i < nb; ++i)
+      const int base = (int)nbk.size();
+      for (int64_t i = 0; i < nb; ++i) {
+        nbk.push_back(make_int2((int)c, (int)i));
         for (int64_t j = i; j < nb; ++j)
-          pb.push_back(make_int4((int)c, (int)i, (int)j, 0));
+          pb.push_back(make_int4((int)c, (int)i, (int)j, base));
+      }
     }
     int4* pbd;
-    double* mom;
+    int2* nbd;
+    double *mom, *bbox;
     unsigned long long* d2;
     if ((rc = h->upload(&pbd, pb, stream)) ||
+        (rc = h->upload(&nbd, nbk, stream)) ||
+        (rc = h->alloc(&bbox, 6 * nbk.size())) ||
         (rc = h->alloc(&mom, 10 * (size_t)h->n_tiles)) ||
         (rc = h->alloc(&d2, (size_t)h->n_cells)))
       return bail(rc);
     h->pair_blocks = pbd;
     h->n_pair_blocks = (int64_t)pb.size();
+    h->node_blocks = nbd;
+    h->n_node_blocks = (int64_t)nbk.size();
+    h->shape_bbox = bbox;
     h->shape_mom = mom;
     h->d2max = d2;
     T.params = params;
@@ -796,8 +809,9 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
   if (cm::shape_lds(h->T.nloc) > 65536)
     return fail(CM_EINVAL, "tiles too large for the shape kernel's LDS");
   if (int rc = select_device(h)) return rc;
-  CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->pair_blocks, h->n_pair_blocks, y,
-                          d_ref, h->shape_mom, h->d2max, out, stream));
+  CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->pair_blocks, h->n_pair_blocks,
+                          h->node_blocks, h->n_node_blocks, y, d_ref, h->shape_mom,
+                          h->shape_bbox, h->d2max, out, stream));
   return CM_OK;
 }
 

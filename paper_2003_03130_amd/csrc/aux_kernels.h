@@ -12,15 +12,17 @@ namespace cm {
 
 // Shape diagnostics (Taylor deformation, cell strain): kShapeFields float64
 // per cell = volume, centre of mass (3), semi-axes a1 <= a2 <= a3, D, d_max,
-// strain.  mom: 10 float64 per tile; d2max: one uint64 per cell;
-// pair_blocks: (cell, row block, column block, 0) over the 256-node blocks
-// of every cell with row <= column.
+// strain.  mom: 10 float64 per tile; d2max: one uint64 per cell; node
+// blocks: (cell, block) for every block of 256 nodes, with a bounding box
+// (6 float64) each; pair_blocks: (cell, row block, column block, first node
+// block of the cell) over the node blocks of every cell with row <= column.
 constexpr int kShapeFields = 10;
 size_t shape_lds(int nloc);
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* pair_blocks, int64_t n_pair_blocks,
+                        const int2* node_blocks, int64_t n_node_blocks,
                         const float* y, const double* d_ref, double* mom,
-                        unsigned long long* d2max, double* out,
+                        double* bbox, unsigned long long* d2max, double* out,
                         hipStream_t st);
 
 // Quasi-static plate compression (one workgroup per cell): Newton residual,

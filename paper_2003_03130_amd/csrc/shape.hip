@@ -8,11 +8,19 @@
 //                         V of every tetrahedron and its centroid r, summed
 //                         as V, V r and V r r^T (float64) about a per-cell
 //                         origin (the cell's first node), one record per tile;
+//   shape_extreme_kernel  per cell, the nodes extreme along the three axes and
+//                         the four body diagonals; the largest distance among
+//                         these pairs is a lower bound L of d_max (the
+//                         distance of two actual nodes) and starts the maximum;
+//   shape_bbox_kernel     the bounding box of every block of 256 nodes;
 //   pair_max_kernel       the largest squared distance between two nodes of
 //                         a cell, over 256 x 256 blocks of node pairs (float64
 //                         differences of the float32 positions are exact; the
 //                         maximum of non-negative doubles is an order-free
-//                         integer maximum of their bit patterns);
+//                         integer maximum of their bit patterns); a block pair
+//                         whose bounding boxes are closer than the current
+//                         maximum cannot hold a larger distance and is skipped
+//                         (the result is the same, only the work changes);
 //   shape_finalize_kernel per cell: tile records summed in tile order, the
 //                         inertia tensor about the centre of mass, its
 //                         eigenvalues by cyclic Jacobi rotations, semi-axes,
@@ -102,19 +110,132 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
 }
 
 struct PairArgs {
-  const int4* blocks;  // (cell, row block, column block, 0)
+  const int4* blocks;  // (cell, row block, column block, first node block of the cell)
   const int64_t* node_off;
   const float* y;
   int64_t N;
+  const double* bbox;         // per node block: min x y z, max x y z
   unsigned long long* d2max;  // per cell, bits of a non-negative double
 };
+
+// Directions of the extreme-node search: the axes and the body diagonals.
+__constant__ float kDirs[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 1},
+                                  {1, 1, -1}, {1, -1, 1}, {-1, 1, 1}};
+
+struct ExtArgs {
+  const int64_t* node_off;
+  const float* y;
+  int64_t N;
+  unsigned long long* d2max;
+};
+
+// Per cell: for every direction the node of smallest and of largest
+// projection (ties to the smaller index), then d2max = the largest squared
+// distance among those pairs.
+__global__ __launch_bounds__(256) void shape_extreme_kernel(ExtArgs a) {
+  __shared__ double rv[256];
+  __shared__ int64_t ri[256];
+  __shared__ int64_t ext[14];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  for (int d = 0; d < 7; ++d)
+    for (int side = 0; side < 2; ++side) {  // 0: min, 1: max
+      double best = side ? -INFINITY : INFINITY;
+      int64_t arg = -1;
+      for (int64_t i = n0 + tid; i < n1; i += 256) {
+        const double pr = (double)kDirs[d][0] * a.y[i] + (double)kDirs[d][1] * a.y[N + i] +
+                          (double)kDirs[d][2] * a.y[2 * N + i];
+        if (side ? pr > best : pr < best) { best = pr; arg = i; }
+      }
+      rv[tid] = best;
+      ri[tid] = arg;
+      __syncthreads();
+      for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+          const double v2 = rv[tid + s];
+          const int64_t i2 = ri[tid + s];
+          const bool better = side ? v2 > rv[tid] : v2 < rv[tid];
+          if (i2 >= 0 && (ri[tid] < 0 || better || (v2 == rv[tid] && i2 < ri[tid]))) {
+            rv[tid] = v2;
+            ri[tid] = i2;
+          }
+        }
+        __syncthreads();
+      }
+      if (tid == 0) ext[2 * d + side] = ri[0];
+      __syncthreads();
+    }
+  if (tid == 0) {
+    double m = 0.0;
+    for (int d = 0; d < 7; ++d) {
+      const int64_t p = ext[2 * d], q = ext[2 * d + 1];
+      if (p < 0 || q < 0) continue;
+      const double dx = (double)a.y[p] - a.y[q], dy = (double)a.y[N + p] - a.y[N + q],
+                   dz = (double)a.y[2 * N + p] - a.y[2 * N + q];
+      m = fmax(m, dx * dx + dy * dy + dz * dz);
+    }
+    a.d2max[c] = (unsigned long long)__double_as_longlong(m);
+  }
+}
+
+struct BoxArgs {
+  const int2* node_blocks;  // (cell, block of the cell)
+  const int64_t* node_off;
+  const float* y;
+  int64_t N;
+  double* bbox;
+};
+
+__global__ __launch_bounds__(256) void shape_bbox_kernel(BoxArgs a) {
+  __shared__ double red[6][4];
+  const int2 nb = a.node_blocks[blockIdx.x];
+  const int64_t n1 = a.node_off[nb.x + 1];
+  const int64_t i = a.node_off[nb.x] + (int64_t)nb.y * 256 + threadIdx.x;
+  const bool in = i < n1;
+  double v[6];
+  for (int d = 0; d < 3; ++d) {
+    const double q = in ? (double)a.y[d * a.N + i] : 0.0;
+    v[d] = in ? q : INFINITY;
+    v[3 + d] = in ? q : -INFINITY;
+  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      v[d] = fmin(v[d], __shfl_xor(v[d], off));
+      v[3 + d] = fmax(v[3 + d], __shfl_xor(v[3 + d], off));
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    const double r = k < 3 ? fmin(fmin(red[k][0], red[k][1]), fmin(red[k][2], red[k][3]))
+                           : fmax(fmax(red[k][0], red[k][1]), fmax(red[k][2], red[k][3]));
+    a.bbox[6 * (int64_t)blockIdx.x + k] = r;
+  }
+}
 
 __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
   __shared__ double cx[256], cy[256], cz[256];
   __shared__ double red[4];
+  __shared__ int skip;
   const int4 b = a.blocks[blockIdx.x];
-  const int64_t n0 = a.node_off[b.x], n1 = a.node_off[b.x + 1];
   const int tid = threadIdx.x;
+  if (tid == 0) {
+    // farthest points of the two bounding boxes vs the current maximum
+    const double* r = a.bbox + 6 * (int64_t)(b.w + b.y);
+    const double* q = a.bbox + 6 * (int64_t)(b.w + b.z);
+    double u = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double e = fmax(r[3 + d] - q[d], q[3 + d] - r[d]);
+      u += e * e;
+    }
+    const unsigned long long cur = __hip_atomic_load(&a.d2max[b.x], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+    skip = u < __longlong_as_double((long long)cur);
+  }
+  __syncthreads();
+  if (skip) return;  // uniform over the workgroup
+  const int64_t n0 = a.node_off[b.x], n1 = a.node_off[b.x + 1];
   const int64_t j0 = n0 + (int64_t)b.z * 256;
   const int ncol = n1 - j0 < 256 ? (int)(n1 - j0) : 256;
   if (tid < ncol) {
@@ -140,11 +261,6 @@ __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
     const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     atomicMax(&a.d2max[b.x], (unsigned long long)__double_as_longlong(m));
   }
-}
-
-__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ull;
 }
 
 // Eigenvalues of a symmetric 3x3 matrix (A00 A11 A22 A01 A02 A12) by cyclic
@@ -233,16 +349,23 @@ size_t shape_lds(int nloc) { return (size_t)16 * nloc; }
 
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* pair_blocks, int64_t n_pair_blocks,
+                        const int2* node_blocks, int64_t n_node_blocks,
                         const float* y, const double* d_ref, double* mom,
-                        unsigned long long* d2max, double* out,
+                        double* bbox, unsigned long long* d2max, double* out,
                         hipStream_t st) {
   const int nc = T.n_cells;
-  hipLaunchKernelGGL(zero_u64_kernel, dim3((nc + 255) / 256), dim3(256), 0, st,
-                     d2max, (int64_t)nc);
+  ExtArgs x{node_off, y, T.n_nodes, d2max};
+  hipLaunchKernelGGL(shape_extreme_kernel, dim3(nc), dim3(256), 0, st, x);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (n_node_blocks > 0) {
+    BoxArgs bx{node_blocks, node_off, y, T.n_nodes, bbox};
+    hipLaunchKernelGGL(shape_bbox_kernel, dim3((unsigned)n_node_blocks), dim3(256), 0,
+                       st, bx);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (n_pair_blocks > 0) {
-    PairArgs p{pair_blocks, node_off, y, T.n_nodes, d2max};
+    PairArgs p{pair_blocks, node_off, y, T.n_nodes, bbox, d2max};
     hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_pair_blocks), dim3(256), 0,
                        st, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
