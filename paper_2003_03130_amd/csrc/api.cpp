@@ -46,6 +46,7 @@ struct cm_batch_s {
   int64_t n_pair_blocks = 0;
   const int2* node_blocks = nullptr;
   int64_t n_node_blocks = 0;
+  const int32_t* space_order = nullptr;
   double* shape_bbox = nullptr;
   double* shape_mom = nullptr;
   unsigned long long* d2max = nullptr;
@@ -244,9 +245,11 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     }
     int4* pbd;
     int2* nbd;
+    int32_t* sord;
     double *mom, *bbox;
     unsigned long long* d2;
     if ((rc = h->upload(&pbd, pb, stream)) ||
+        (rc = h->upload(&sord, P.space_order, stream)) ||
         (rc = h->upload(&nbd, nbk, stream)) ||
         (rc = h->alloc(&bbox, 6 * nbk.size())) ||
         (rc = h->alloc(&mom, 10 * (size_t)h->n_tiles)) ||
@@ -257,6 +260,7 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     h->node_blocks = nbd;
     h->n_node_blocks = (int64_t)nbk.size();
     h->shape_bbox = bbox;
+    h->space_order = sord;
     h->shape_mom = mom;
     h->d2max = d2;
     T.params = params;
@@ -810,7 +814,8 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
     return fail(CM_EINVAL, "tiles too large for the shape kernel's LDS");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->pair_blocks, h->n_pair_blocks,
-                          h->node_blocks, h->n_node_blocks, y, d_ref, h->shape_mom,
+                          h->node_blocks, h->n_node_blocks, h->space_order, y, d_ref,
+                          h->shape_mom,
                           h->shape_bbox, h->d2max, out, stream));
   return CM_OK;
 }

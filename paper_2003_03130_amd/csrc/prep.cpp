@@ -26,6 +26,7 @@ struct CellOut {
   std::vector<int32_t> shared_slot_ptr;
   std::vector<int32_t> shared_slots;  // local slot ids
   std::vector<int64_t> new_to_old;    // local
+  std::vector<int32_t> space_order;   // local internal ids by Morton code of the node
   std::vector<int32_t> tile_region;   // region of every tile
   std::vector<int32_t> region_tile_first, region_tile_count;  // local tiles
   int32_t max_tile_nodes = 0;
@@ -435,6 +436,30 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
 
   out.new_to_old.resize(n);
   for (int64_t v = 0; v < n; ++v) out.new_to_old[newid[v]] = v;
+  {
+    // nodes in Morton order of their reference position (spatially compact
+    // blocks of nodes for the shape kernels' pair search)
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t v = 0; v < n; ++v)
+      for (int i = 0; i < 3; ++i) {
+        lo[i] = std::min(lo[i], X[3 * v + i]);
+        hi[i] = std::max(hi[i], X[3 * v + i]);
+      }
+    std::vector<uint32_t> code(n);
+    for (int64_t v = 0; v < n; ++v) {
+      uint32_t cd = 0;
+      for (int i = 0; i < 3; ++i) {
+        const double span = hi[i] - lo[i];
+        const double q = span > 0 ? (X[3 * v + i] - lo[i]) / span : 0.0;
+        cd |= spread3((uint32_t)std::min(1023.0, std::max(0.0, std::floor(q * 1024.0)))) << i;
+      }
+      code[newid[v]] = cd;
+    }
+    out.space_order.resize(n);
+    std::iota(out.space_order.begin(), out.space_order.end(), 0);
+    std::stable_sort(out.space_order.begin(), out.space_order.end(),
+                     [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+  }
 
   // Tiles, slots and chunks.
   out.tiles.resize(n_tiles);
@@ -639,6 +664,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
   P->cell_shared_off.resize(n_cells + 1);
   P->node_off.assign(node_off, node_off + n_cells + 1);
   P->new_to_old.resize(P->n_nodes);
+  P->space_order.resize(P->n_nodes);
   P->n_regions = n_regions;
   P->tile_mat.resize(n_tiles);
   P->mat_tile_first.resize((size_t)n_cells * n_regions);
@@ -678,6 +704,8 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
     }
     for (size_t v = 0; v < cell.new_to_old.size(); ++v)
       P->new_to_old[nb + v] = cell.new_to_old[v] + nb;
+    for (size_t v = 0; v < cell.space_order.size(); ++v)
+      P->space_order[nb + v] = cell.space_order[v] + nb;
     P->volume += cell.volume;
     P->min_v0 = std::min(P->min_v0, cell.min_v0);
     P->max_cond = std::max(P->max_cond, cell.max_cond);
@@ -750,6 +778,7 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   P->shared_node.resize(C * H1);
   P->shared_slot_ptr.resize(C * H1 + 1);
   P->new_to_old.resize(C * N);
+  P->space_order.resize(C * N);
   P->node_off.resize(C + 1);
   P->cell_shared_off.resize(C + 1);
   P->cell_tile_first.resize(C);
@@ -765,6 +794,8 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
       P->shared_slot_ptr[c * H1 + h + 1] = one.shared_slot_ptr[h + 1] + (int32_t)(c * S1);
     }
     for (int64_t v = 0; v < N; ++v) P->new_to_old[c * N + v] = one.new_to_old[v] + c * N;
+    for (int64_t v = 0; v < N; ++v)
+      P->space_order[c * N + v] = one.space_order[v] + (int32_t)(c * N);
     P->node_off[c] = c * N;
     P->cell_shared_off[c] = (int32_t)(c * H1);
     P->cell_tile_first[c] = (int32_t)c;

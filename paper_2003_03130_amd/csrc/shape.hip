@@ -12,7 +12,9 @@
 //                         the four body diagonals; the largest distance among
 //                         these pairs is a lower bound L of d_max (the
 //                         distance of two actual nodes) and starts the maximum;
-//   shape_bbox_kernel     the bounding box of every block of 256 nodes;
+//   shape_bbox_kernel     the bounding box of every block of 256 nodes, the
+//                         nodes of a cell taken in Morton order of their
+//                         reference positions (compact blocks);
 //   pair_max_kernel       the largest squared distance between two nodes of
 //                         a cell, over 256 x 256 blocks of node pairs (float64
 //                         differences of the float32 positions are exact; the
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
 struct PairArgs {
   const int4* blocks;  // (cell, row block, column block, first node block of the cell)
   const int64_t* node_off;
+  const int32_t* order;  // per cell, node ids in spatial (Morton) order
   const float* y;
   int64_t N;
   const double* bbox;         // per node block: min x y z, max x y z
@@ -181,6 +184,7 @@ __global__ __launch_bounds__(256) void shape_extreme_kernel(ExtArgs a) {
 struct BoxArgs {
   const int2* node_blocks;  // (cell, block of the cell)
   const int64_t* node_off;
+  const int32_t* order;
   const float* y;
   int64_t N;
   double* bbox;
@@ -192,9 +196,10 @@ __global__ __launch_bounds__(256) void shape_bbox_kernel(BoxArgs a) {
   const int64_t n1 = a.node_off[nb.x + 1];
   const int64_t i = a.node_off[nb.x] + (int64_t)nb.y * 256 + threadIdx.x;
   const bool in = i < n1;
+  const int64_t g = in ? (int64_t)a.order[i] : 0;
   double v[6];
   for (int d = 0; d < 3; ++d) {
-    const double q = in ? (double)a.y[d * a.N + i] : 0.0;
+    const double q = in ? (double)a.y[d * a.N + g] : 0.0;
     v[d] = in ? q : INFINITY;
     v[3 + d] = in ? q : -INFINITY;
   }
@@ -239,15 +244,17 @@ __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
   const int64_t j0 = n0 + (int64_t)b.z * 256;
   const int ncol = n1 - j0 < 256 ? (int)(n1 - j0) : 256;
   if (tid < ncol) {
-    cx[tid] = a.y[j0 + tid];
-    cy[tid] = a.y[a.N + j0 + tid];
-    cz[tid] = a.y[2 * a.N + j0 + tid];
+    const int64_t g = a.order[j0 + tid];
+    cx[tid] = a.y[g];
+    cy[tid] = a.y[a.N + g];
+    cz[tid] = a.y[2 * a.N + g];
   }
   __syncthreads();
   const int64_t i = n0 + (int64_t)b.y * 256 + tid;
   double best = 0.0;
   if (i < n1) {
-    const double xi = a.y[i], yi = a.y[a.N + i], zi = a.y[2 * a.N + i];
+    const int64_t g = a.order[i];
+    const double xi = a.y[g], yi = a.y[a.N + g], zi = a.y[2 * a.N + g];
     for (int k = 0; k < ncol; ++k) {
       const double dx = xi - cx[k], dy = yi - cy[k], dz = zi - cz[k];
       best = fmax(best, dx * dx + dy * dy + dz * dz);
@@ -350,22 +357,22 @@ size_t shape_lds(int nloc) { return (size_t)16 * nloc; }
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* pair_blocks, int64_t n_pair_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
-                        const float* y, const double* d_ref, double* mom,
-                        double* bbox, unsigned long long* d2max, double* out,
-                        hipStream_t st) {
+                        const int32_t* order, const float* y, const double* d_ref,
+                        double* mom, double* bbox, unsigned long long* d2max,
+                        double* out, hipStream_t st) {
   const int nc = T.n_cells;
   ExtArgs x{node_off, y, T.n_nodes, d2max};
   hipLaunchKernelGGL(shape_extreme_kernel, dim3(nc), dim3(256), 0, st, x);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (n_node_blocks > 0) {
-    BoxArgs bx{node_blocks, node_off, y, T.n_nodes, bbox};
+    BoxArgs bx{node_blocks, node_off, order, y, T.n_nodes, bbox};
     hipLaunchKernelGGL(shape_bbox_kernel, dim3((unsigned)n_node_blocks), dim3(256), 0,
                        st, bx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (n_pair_blocks > 0) {
-    PairArgs p{pair_blocks, node_off, y, T.n_nodes, bbox, d2max};
+    PairArgs p{pair_blocks, node_off, order, y, T.n_nodes, bbox, d2max};
     hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_pair_blocks), dim3(256), 0,
                        st, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
