@@ -61,7 +61,9 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     }
     wave_sync();
 
-    double acc[3] = {0.0, 0.0, 0.0};
+    // per tile: sum V0 gp and sum V0 ge (the parameter gradient is
+    // -sum V0 gp + ebar/2 sum V0 ge)
+    double acc[3] = {0.0, 0.0, 0.0}, acce[3] = {0.0, 0.0, 0.0};
     const TetChunk* ch = a.T.chunks + d.chunk_begin;
     TetRegs nxt;
     load_tet(ch, lane, nxt);
@@ -81,12 +83,15 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
         const float4 v2 = make_float4(p2.w, w2.x, w2.y, 0.f);
         const float4 v3 = make_float4(p3.w, w3.x, w3.y, 0.f);
         float h[3][3];
-        double gt[3];
-        tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, B, V0, mat, eb, h, gt);
+        double gp[3], ge[3];
+        tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, B, V0, mat, eb, h, gp, ge);
         lds_accumulate(gs, i0, i1, i2, i3, h);
-        acc[0] += gt[0];
-        acc[1] += gt[1];
-        acc[2] += gt[2];
+        const double vol = (double)V0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          acc[q] = fma(vol, gp[q], acc[q]);
+          acce[q] = fma(vol, ge[q], acce[q]);
+        }
       }
     }
     wave_sync();
@@ -102,9 +107,9 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
       float* pp = a.T.part + 3 * s;
       pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
     }
-    acc[0] = wave_sum(acc[0]);
-    acc[1] = wave_sum(acc[1]);
-    acc[2] = wave_sum(acc[2]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      acc[q] = -wave_sum(acc[q]) + 0.5 * eb * wave_sum(acce[q]);
     if (lane == 0) {
       a.T.tile_acc[3 * (int64_t)t] = acc[0];
       a.T.tile_acc[3 * (int64_t)t + 1] = acc[1];

@@ -194,15 +194,15 @@ __device__ __forceinline__ void cofactor_dir(const float F[3][3],
 //   are -grad E, so (df/dy)^T fbar = d/de f(y + e fbar));
 //   h[k][i] = (-V0 (dP[dF] - ebar P) B^T)_ik, the contribution to ybar of
 //   vertices k = 0..2 (vertex 3 takes the negative sum);
-//   g = dL/d(mu1, mu2, kappa) of this tetrahedron.  P is linear in
-//   (mu1, mu2, kappa): P = mu1 P_I + mu2 P_K + kappa P_J, so
-//   g_I = V0 (-<P_I, dF> + ebar (I - 3)/2), g_K likewise with K, and
-//   g_J = V0 (-(J - 1) <cof F, dF> + ebar (J - 1)^2 / 2).
+//   dL/d(mu1, mu2, kappa) of this tetrahedron is V0 (-gp + ebar ge / 2):
+//   P is linear in (mu1, mu2, kappa), P = mu1 P_I + mu2 P_K + kappa P_J, so
+//   gp = (<P_I, dF>, <P_K, dF>, (J - 1) <cof F, dF>) and
+//   ge = (I - 3, K - 3, (J - 1)^2) (twice the energy parts).
 __device__ __forceinline__ void tet_backward(
     const float4& p0, const float4& p1, const float4& p2, const float4& p3,
     const float4& v0, const float4& v1, const float4& v2, const float4& v3,
     const float B[9], float V0, const Material& m, double ebar, float h[3][3],
-    double g[3]) {
+    double gp[3], double ge[3]) {
   double Fd[3][3];
   float F[3][3], dF[3][3], Cf[6];
   deformation_gradient(p0, p1, p2, p3, B, Fd, F);
@@ -231,24 +231,23 @@ __device__ __forceinline__ void tet_backward(
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) fK = fmaf(K[i][j], dF[i][j], fK);
-  // directional derivatives of tr C, tr C^2, J and I2 = (trC^2 - trC2)/2
-  const double dTC = 2.0 * (double)fF;
-  const double dTC2 = 4.0 * (double)fFC;
+  // directional derivatives of tr C, tr C^2, J and I2 = (trC^2 - trC2)/2;
+  // with t = dJ / J: d J^-2/3 = -(2/3) J^-2/3 t, d J^-4/3 = -(4/3) J^-4/3 t
+  const double fFd = (double)fF, fFCd = (double)fFC;
+  const double dTC = 2.0 * fFd;
   const double dJ = (double)fK;
-  const double dI2 = s.TC * dTC - 0.5 * dTC2;
+  const double dI2 = 2.0 * (s.TC * fFd - fFCd);
   const double r3 = s.r2 * s.r;          // 1/J
-  const double r5 = s.r4 * s.r, r7 = r5 * s.r2;
-  const double dr2 = -(2.0 / 3.0) * r5 * dJ;   // d J^-2/3
-  const double dr4 = -(4.0 / 3.0) * r7 * dJ;   // d J^-4/3
+  const double tq = r3 * dJ;
   const double a = m.mu1 * s.r2, b = m.mu2 * s.r4;
-  const double da = m.mu1 * dr2, db = m.mu2 * dr4;
+  const double da = (-2.0 / 3.0) * a * tq, db = (-4.0 / 3.0) * b * tq;
   const double c1 = a + b * s.TC, dc1 = da + db * s.TC + b * dTC;
   const double c2 = -b, dc2 = -db;
   const double q = -(a * s.TC + 2.0 * b * s.I2) * (1.0 / 3.0);
   const double dq = -(da * s.TC + a * dTC + 2.0 * (db * s.I2 + b * dI2)) * (1.0 / 3.0);
   const double Jm1 = s.J - 1.0;
   const double c3 = q * r3 + m.kappa * Jm1;
-  const double dc3 = dq * r3 - q * (r3 * r3) * dJ + m.kappa * dJ;
+  const double dc3 = r3 * (dq - q * tq) + m.kappa * dJ;
   const double nv = -(double)V0;
   const float s1 = (float)(nv * (dc1 - ebar * c1)), t1 = (float)(nv * c1);
   const float s2 = (float)(nv * (dc2 - ebar * c2)), t2 = (float)(nv * c2);
@@ -281,13 +280,15 @@ __device__ __forceinline__ void tet_backward(
     for (int i = 0; i < 3; ++i)
       h[k][i] = Q[i][0] * B[3 * k] + Q[i][1] * B[3 * k + 1] + Q[i][2] * B[3 * k + 2];
 
-  const double vol = (double)V0;
-  const double pI = s.r2 * (0.5 * dTC - r3 * s.TC * dJ * (1.0 / 3.0));
-  const double pK = s.r4 * (0.5 * s.TC * dTC - 0.25 * dTC2 - (2.0 / 3.0) * s.I2 * r3 * dJ);
-  const double pJ = Jm1 * dJ;
-  g[0] = vol * (-pI + 0.5 * ebar * (s.TC * s.r2 - 3.0));
-  g[1] = vol * (-pK + 0.5 * ebar * (s.I2 * s.r4 - 3.0));
-  g[2] = vol * (-pJ + 0.5 * ebar * Jm1 * Jm1);
+  // parameter gradient: per unit V0, the directional derivatives p of the
+  // energy parts along dF and the energy parts e themselves, so that
+  // g = V0 (-p + ebar e / 2) is formed once per tile
+  gp[0] = s.r2 * (fFd - s.TC * tq * (1.0 / 3.0));
+  gp[1] = s.r4 * (s.TC * fFd - fFCd - (2.0 / 3.0) * s.I2 * tq);
+  gp[2] = Jm1 * dJ;
+  ge[0] = s.TC * s.r2 - 3.0;
+  ge[1] = s.I2 * s.r4 - 3.0;
+  ge[2] = Jm1 * Jm1;
 }
 
 }  // namespace cm
