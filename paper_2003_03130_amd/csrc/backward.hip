@@ -2,11 +2,11 @@
 // fbar = dL/df (per node) and ebar = dL/dE (per cell),
 //   ybar     = (df/dy)^T fbar - ebar f  (a Hessian-vector product of E),
 //   thetabar = dL/d(mu, kappa, w) per material slot (cell and region).
-// Same tiling as the forward kernel: one wavefront per tile; positions and
-// fbar of the tile's nodes are staged in LDS, ybar is accumulated in LDS slot
-// by slot without atomics (see layout.h), owned nodes are stored directly and
-// shared nodes go through the slot partials and the finalize kernel, in a
-// fixed order (deterministic).
+// Same tiling as the forward kernel: one wavefront per tile; position, fbar
+// and ybar accumulator of each tile node form one LDS record; ybar is
+// accumulated in LDS slot by slot without atomics (see layout.h), owned
+// nodes are stored directly and shared nodes go through the slot partials
+// and the finalize kernel, in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -61,18 +61,12 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     }
     wave_sync();
 
-    // per tile: sum V0 gp and sum V0 ge (the parameter gradient is
+    // per lane: sum V0 gp and sum V0 ge (the tile's parameter gradient is
     // -sum V0 gp + ebar/2 sum V0 ge)
     double acc[3] = {0.0, 0.0, 0.0}, acce[3] = {0.0, 0.0, 0.0};
-    const TetChunk* ch = a.T.chunks + d.chunk_begin;
-    TetRegs nxt;
-    load_tet(ch, lane, nxt);
-    for (int k = 0; k < d.n_chunks; ++k) {
-      const TetRegs cur = nxt;
-      if (k + 1 < d.n_chunks) load_tet(ch + k + 1, lane, nxt);
+    for_each_chunk(a.T.chunks + d.chunk_begin, d.n_chunks, lane,
+                   [&](const TetRegs& cur) {
       const uint2 q = cur.q;
-      const float* B = cur.B;
-      const float V0 = cur.V0;
       if (q.x != kEmptyLane) {
         const int i0 = q.x & 0xffff, i1 = q.x >> 16;
         const int i2 = q.y & 0xffff, i3 = q.y >> 16;
@@ -84,16 +78,17 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
         const float4 v3 = make_float4(p3.w, w3.x, w3.y, 0.f);
         float h[3][3];
         double gp[3], ge[3];
-        tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, B, V0, mat, eb, h, gp, ge);
-        lds_accumulate(gs, i0, i1, i2, i3, h);
-        const double vol = (double)V0;
+        tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, cur.B, cur.V0, mat, eb, h,
+                     gp, ge);
+        lds_accumulate([&](int i) { return &gs[i].x; }, i0, i1, i2, i3, h);
+        const double vol = (double)cur.V0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          acc[q] = fma(vol, gp[q], acc[q]);
-          acce[q] = fma(vol, ge[q], acce[q]);
+        for (int c = 0; c < 3; ++c) {
+          acc[c] = fma(vol, gp[c], acc[c]);
+          acce[c] = fma(vol, ge[c], acce[c]);
         }
       }
-    }
+    });
     wave_sync();
 
     for (int i = lane; i < d.n_own; i += 64) {
@@ -108,8 +103,7 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
       pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-      acc[q] = -wave_sum(acc[q]) + 0.5 * eb * wave_sum(acce[q]);
+    for (int c = 0; c < 3; ++c) acc[c] = wave_sum(fma(0.5 * eb, acce[c], -acc[c]));
     if (lane == 0) {
       a.T.tile_acc[3 * (int64_t)t] = acc[0];
       a.T.tile_acc[3 * (int64_t)t + 1] = acc[1];

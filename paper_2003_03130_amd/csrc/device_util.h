@@ -32,27 +32,52 @@ __device__ __forceinline__ void load_tet(const TetChunk* ch, int lane,
 }
 
 // Adds the contributions h[0..2] of vertex slots 0..2 and -(h0 + h1 + h2) of
-// slot 3 to the float4 accumulators acc[i_s].  The layout guarantees that
-// the active lanes of the wave name distinct nodes within each slot, so each
-// slot is one LDS read and one LDS write per lane with no races; slots are
-// processed in order (LDS instructions of a wavefront execute in order).
-__device__ __forceinline__ void lds_accumulate(float4* acc, int i0, int i1,
-                                               int i2, int i3,
-                                               const float h[3][3]) {
-  float4 v = acc[i0];
-  v.x += h[0][0]; v.y += h[0][1]; v.z += h[0][2];
-  acc[i0] = v;
-  v = acc[i1];
-  v.x += h[1][0]; v.y += h[1][1]; v.z += h[1][2];
-  acc[i1] = v;
-  v = acc[i2];
-  v.x += h[2][0]; v.y += h[2][1]; v.z += h[2][2];
-  acc[i2] = v;
-  v = acc[i3];
-  v.x -= h[0][0] + h[1][0] + h[2][0];
-  v.y -= h[0][1] + h[1][1] + h[2][1];
-  v.z -= h[0][2] + h[1][2] + h[2][2];
-  acc[i3] = v;
+// slot 3 to the accumulators acc(i_s) (acc maps a tile-local node index to
+// its three accumulator floats).  The layout guarantees that the active
+// lanes of the wave name distinct nodes within each slot, so each slot is
+// one LDS read and one LDS write per lane with no races; slots are processed
+// in order (LDS instructions of a wavefront execute in order).
+template <class Acc>
+__device__ __forceinline__ void lds_accumulate(Acc acc, int i0, int i1, int i2,
+                                               int i3, const float h[3][3]) {
+  float* a = acc(i0);
+  a[0] += h[0][0]; a[1] += h[0][1]; a[2] += h[0][2];
+  a = acc(i1);
+  a[0] += h[1][0]; a[1] += h[1][1]; a[2] += h[1][2];
+  a = acc(i2);
+  a[0] += h[2][0]; a[1] += h[2][1]; a[2] += h[2][2];
+  a = acc(i3);
+  a[0] -= h[0][0] + h[1][0] + h[2][0];
+  a[1] -= h[0][1] + h[1][1] + h[2][1];
+  a[2] -= h[0][2] + h[1][2] + h[2][2];
+}
+
+// Runs body(regs) over the n chunks ch[0..n) with the next chunk's loads in
+// flight while the current one is evaluated; two register sets alternate, so
+// no register copies are needed between chunks.  Every call site of body is
+// reached with one fixed set of outstanding loads (one chunk in flight, or
+// none at the last chunk), so the compiler waits only for the chunk that
+// body reads.
+template <class Body>
+__device__ __forceinline__ void for_each_chunk(const TetChunk* ch, int n,
+                                               int lane, Body body) {
+  if (n <= 0) return;
+  TetRegs ra, rb;
+  load_tet(ch, lane, ra);
+  for (int k = 0;; k += 2) {
+    if (k + 1 >= n) {
+      body(ra);
+      return;
+    }
+    load_tet(ch + k + 1, lane, rb);
+    body(ra);
+    if (k + 2 >= n) {
+      body(rb);
+      return;
+    }
+    load_tet(ch + k + 2, lane, ra);
+    body(rb);
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -30,8 +30,10 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nloc = a.T.nloc;
-  float4* ys = lds + (size_t)wave * 2 * nloc;  // positions
-  float4* fs = ys + nloc;                      // force accumulators
+  // positions and force accumulators as two float4 arrays: 16-byte records
+  // spread random-index LDS accesses over all banks
+  float4* ys = lds + (size_t)wave * 2 * nloc;
+  float4* fs = ys + nloc;
   const int64_t N = a.T.n_nodes;
 
   int t0, t1;
@@ -54,17 +56,9 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
 
     double eacc = 0.0;
     int ninv = 0;
-    const TetChunk* ch = a.T.chunks + d.chunk_begin;
-    // software pipeline: the next chunk's loads are in flight while the
-    // current chunk is evaluated
-    TetRegs nxt;
-    load_tet(ch, lane, nxt);
-    for (int k = 0; k < d.n_chunks; ++k) {
-      const TetRegs cur = nxt;
-      if (k + 1 < d.n_chunks) load_tet(ch + k + 1, lane, nxt);
+    for_each_chunk(a.T.chunks + d.chunk_begin, d.n_chunks, lane,
+                   [&](const TetRegs& cur) {
       const uint2 q = cur.q;
-      const float* B = cur.B;
-      const float V0 = cur.V0;
       if (q.x != kEmptyLane) {
         const int i0 = q.x & 0xffff, i1 = q.x >> 16;
         const int i2 = q.y & 0xffff, i3 = q.y >> 16;
@@ -72,12 +66,12 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
         float h[3][3];
         double vU;
         bool inv;
-        tet_forward(p0, p1, p2, p3, B, V0, mat, h, vU, inv);
-        lds_accumulate(fs, i0, i1, i2, i3, h);
+        tet_forward(p0, p1, p2, p3, cur.B, cur.V0, mat, h, vU, inv);
+        lds_accumulate([&](int i) { return &fs[i].x; }, i0, i1, i2, i3, h);
         eacc += vU;
         ninv += inv ? 1 : 0;
       }
-    }
+    });
     wave_sync();
 
     for (int i = lane; i < d.n_own; i += 64) {

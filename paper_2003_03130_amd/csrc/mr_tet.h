@@ -44,7 +44,7 @@ __device__ __forceinline__ double inv_cbrt(double J) {
 
 // Scalar part shared by the forward and backward passes.
 struct Scalars {
-  double TC, TC2, J, r, r2, r4, I2;
+  double TC, J, r, r2, r4, I2;
 };
 
 // Float64 invariants of the float64 deformation gradient f; Cf receives
@@ -60,15 +60,14 @@ __device__ __forceinline__ void invariants(const double f[3][3], float Cf[6],
   Cf[0] = (float)C00; Cf[1] = (float)C11; Cf[2] = (float)C22;
   Cf[3] = (float)C01; Cf[4] = (float)C02; Cf[5] = (float)C12;
   s.TC = C00 + C11 + C22;
-  s.TC2 = C00 * C00 + C11 * C11 + C22 * C22 +
-          2.0 * (C01 * C01 + C02 * C02 + C12 * C12);
   s.J = f[0][0] * (f[1][1] * f[2][2] - f[1][2] * f[2][1]) -
         f[0][1] * (f[1][0] * f[2][2] - f[1][2] * f[2][0]) +
         f[0][2] * (f[1][0] * f[2][1] - f[1][1] * f[2][0]);
   s.r = inv_cbrt(s.J);
   s.r2 = s.r * s.r;
   s.r4 = s.r2 * s.r2;
-  s.I2 = 0.5 * (s.TC * s.TC - s.TC2);
+  // I2 = (T_C^2 - T_C2) / 2, the sum of the principal 2x2 minors of C
+  s.I2 = C00 * C11 + C00 * C22 + C11 * C22 - C01 * C01 - C02 * C02 - C12 * C12;
 }
 
 // Cofactor matrix cof F = det(F) F^-T (columns are cross products of the
@@ -211,21 +210,22 @@ __device__ __forceinline__ void tet_backward(
   invariants(Fd, Cf, s);
   float K[3][3];
   cofactor(F, K);
-  // dC = dF^T F + F^T dF (symmetric: 00 11 22 01 02 12)
-  float dC[6];
-  dC[0] = 2.f * (dF[0][0] * F[0][0] + dF[1][0] * F[1][0] + dF[2][0] * F[2][0]);
-  dC[1] = 2.f * (dF[0][1] * F[0][1] + dF[1][1] * F[1][1] + dF[2][1] * F[2][1]);
-  dC[2] = 2.f * (dF[0][2] * F[0][2] + dF[1][2] * F[1][2] + dF[2][2] * F[2][2]);
-  dC[3] = dF[0][0] * F[0][1] + dF[1][0] * F[1][1] + dF[2][0] * F[2][1] +
-          F[0][0] * dF[0][1] + F[1][0] * dF[1][1] + F[2][0] * dF[2][1];
-  dC[4] = dF[0][0] * F[0][2] + dF[1][0] * F[1][2] + dF[2][0] * F[2][2] +
-          F[0][0] * dF[0][2] + F[1][0] * dF[1][2] + F[2][0] * dF[2][2];
-  dC[5] = dF[0][1] * F[0][2] + dF[1][1] * F[1][2] + dF[2][1] * F[2][2] +
-          F[0][1] * dF[0][2] + F[1][1] * dF[1][2] + F[2][1] * dF[2][2];
+  // dC = dF^T F + F^T dF (symmetric): diagonal dC_jj = 2 u_j with
+  // u_j = <F e_j, dF e_j>; off-diagonal 01 02 12
+  float u[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    u[j] = dF[0][j] * F[0][j] + dF[1][j] * F[1][j] + dF[2][j] * F[2][j];
+  const float dC01 = dF[0][0] * F[0][1] + dF[1][0] * F[1][1] + dF[2][0] * F[2][1] +
+                     F[0][0] * dF[0][1] + F[1][0] * dF[1][1] + F[2][0] * dF[2][1];
+  const float dC02 = dF[0][0] * F[0][2] + dF[1][0] * F[1][2] + dF[2][0] * F[2][2] +
+                     F[0][0] * dF[0][2] + F[1][0] * dF[1][2] + F[2][0] * dF[2][2];
+  const float dC12 = dF[0][1] * F[0][2] + dF[1][1] * F[1][2] + dF[2][1] * F[2][2] +
+                     F[0][1] * dF[0][2] + F[1][1] * dF[1][2] + F[2][1] * dF[2][2];
   // <F, dF> = tr(dC)/2, <F C, dF> = <C, F^T dF> = <C, dC>/2, <cof F, dF> = dJ
-  const float fF = 0.5f * (dC[0] + dC[1] + dC[2]);
-  const float fFC = 0.5f * (Cf[0] * dC[0] + Cf[1] * dC[1] + Cf[2] * dC[2]) +
-                    (Cf[3] * dC[3] + Cf[4] * dC[4] + Cf[5] * dC[5]);
+  const float fF = u[0] + u[1] + u[2];
+  const float fFC = Cf[0] * u[0] + Cf[1] * u[1] + Cf[2] * u[2] +
+                    Cf[3] * dC01 + Cf[4] * dC02 + Cf[5] * dC12;
   float fK = 0.f;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -256,11 +256,12 @@ __device__ __forceinline__ void tet_backward(
   // -V0 (dP - ebar P) with P = c1 F + c2 F C + c3 cof F:
   //   s1 F + t1 dF + s2 F C + t2 (dF C + F dC) + s3 cof F + t3 d(cof F)
   //   = F (s1 I + s2 C + t2 dC) + dF (t1 I + t2 C) + s3 cof F + t3 d(cof F)
-  const float M[6] = {fmaf(t2, dC[0], fmaf(s2, Cf[0], s1)),
-                      fmaf(t2, dC[1], fmaf(s2, Cf[1], s1)),
-                      fmaf(t2, dC[2], fmaf(s2, Cf[2], s1)),
-                      fmaf(t2, dC[3], s2 * Cf[3]), fmaf(t2, dC[4], s2 * Cf[4]),
-                      fmaf(t2, dC[5], s2 * Cf[5])};
+  const float t2x2 = 2.f * t2;
+  const float M[6] = {fmaf(t2x2, u[0], fmaf(s2, Cf[0], s1)),
+                      fmaf(t2x2, u[1], fmaf(s2, Cf[1], s1)),
+                      fmaf(t2x2, u[2], fmaf(s2, Cf[2], s1)),
+                      fmaf(t2, dC01, s2 * Cf[3]), fmaf(t2, dC02, s2 * Cf[4]),
+                      fmaf(t2, dC12, s2 * Cf[5])};
   const float Nm[6] = {fmaf(t2, Cf[0], t1), fmaf(t2, Cf[1], t1), fmaf(t2, Cf[2], t1),
                        t2 * Cf[3], t2 * Cf[4], t2 * Cf[5]};
   float dK[3][3];
