@@ -323,7 +323,7 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  * active, |r_N|^2, accepted step scale, |penalty|^2, largest node move of
  * the last step, float32 floor rho, Pi(y), line-search scale, slope
  * r_N . x, not in equilibrium (1/0), line search pending (1/0), max |x|,
- * 2 spare.
+ * CG forcing term eta, |r_N|^2 of the last residual.
  *   cm_qs_residual: r = p = r_N, x = 0, with r_N = f + penalty minus its
  *     components along the exact symmetries of the plates (translations in
  *     x and y, rotation about z through the centroid); active iff |r_N|_2 >
@@ -331,7 +331,12 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  *     moved some node by more than step_tol (restart != 0: no last step, at
  *     a new plate position); force (nullable) float64[2 n_cells] = top and
  *     bottom plate forces k sum max(0, .)^2; energy (nullable) E(y) per cell
- *     from cm_forces, giving Pi(y) in the state.
+ *     from cm_forces, giving Pi(y) in the state.  eta_max in [0, 1): with
+ *     eta_max > 0 the Newton step is inexact (Eisenstat and Walker's second
+ *     forcing term): eta = 0.9 (|r_N| / |r_N,prev|)^2, at least 0.9
+ *     eta_prev^2 when that exceeds 0.1, at least half of tolerance / |r_N|,
+ *     at most eta_max (eta_max at a new plate position); eta_max = 0 sets
+ *     eta = 0.
  *   cm_qs_ls_start: s = min(1, cap / max_i |x_i|), slope r_N . x; y_trial =
  *     y + s x for cells not in equilibrium whose step descends, y otherwise.
  *   cm_qs_ls_accept (energy_trial = E(y_trial) from cm_forces): a pending
@@ -343,19 +348,20 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  *     a fixed hash of the index), then after ybar = cm_forces_backward(y,
  *     fbar = e), rho = |Hess(Pi) e|_2 per cell, stored in the state.
  *   cm_qs_cg_step: one CG iteration for every active cell; a cell stops at
- *     |r| <= rel_tol |r_0| or at non-positive curvature.
+ *     |r| <= max(rel_tol, eta) |r_0| or at non-positive curvature.
  *   cm_qs_update: y += s x, s = min(1, cap / max_i |x_i|) per cell.
  *   cm_qs_predict: z -> b' + (z - b) s, s = (t' - b') / (t - b), for a new
  *     plate pair (t', b'), and x, y stretched by 1/sqrt(s) about the cell's
  *     centroid (a volume-preserving affine prediction).
  * Errors: CM_EINVAL for null pointers, negative or non-finite k_plate or
- * tolerances, cap <= 0.
+ * tolerances, cap <= 0, eta_max outside [0, 1).
  */
 int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* energy,
                    const double* plate, double k_plate, double abs_tol,
                    double rel_tol, double step_tol, double floor_factor,
-                   int32_t restart, float* r, float* p, float* x, float* r_newton,
-                   double* state, double* force, hipStream_t stream);
+                   double eta_max, int32_t restart, float* r, float* p, float* x,
+                   float* r_newton, double* state, double* force,
+                   hipStream_t stream);
 int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
                    const float* y, float* y_trial, double* state,
                    hipStream_t stream);

@@ -102,8 +102,8 @@ SIGNATURES = {
     "cm_shape": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                              ctypes.c_double, _i32, _vp, _vp, _vp, _vp, _vp,
-                              _vp, _vp]),
+                              ctypes.c_double, ctypes.c_double, _i32, _vp, _vp,
+                              _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_ls_start": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
                               _vp]),
     "cm_qs_ls_accept": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp,

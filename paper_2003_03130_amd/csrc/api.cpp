@@ -677,19 +677,22 @@ int cm_plate_step(cm_batch h, const float* y, const float* f,
 int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* energy,
                    const double* plate, double k_plate, double abs_tol,
                    double rel_tol, double step_tol, double floor_factor,
-                   int32_t restart, float* r, float* p, float* x, float* r_newton,
-                   double* state, double* force, hipStream_t stream) {
+                   double eta_max, int32_t restart, float* r, float* p, float* x,
+                   float* r_newton, double* state, double* force,
+                   hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !f || !plate || !r || !p || !x || !state)
     return fail(CM_EINVAL, "y, f, plate, r, p, x and state must be device pointers");
   if (!std::isfinite(k_plate) || k_plate < 0 || !(abs_tol >= 0) || !(rel_tol >= 0) ||
       !(step_tol >= 0) || !(floor_factor >= 0))
     return fail(CM_EINVAL, "k_plate and tolerances must be finite and >= 0");
+  if (!(eta_max >= 0 && eta_max < 1))
+    return fail(CM_EINVAL, "eta_max must lie in [0, 1)");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_residual(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, f,
                                 energy, plate, k_plate, abs_tol, rel_tol, step_tol,
-                                floor_factor, restart ? 1 : 0, r, p, x, r_newton,
-                                state, force, stream));
+                                floor_factor, eta_max, restart ? 1 : 0, r, p, x,
+                                r_newton, state, force, stream));
   return CM_OK;
 }
 

@@ -31,14 +31,16 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
 // 3 Newton |r_N|^2, 4 accepted step scale, 5 |penalty|^2, 6 largest node move
 // of the last step, 7 float32 floor of the residual, 8 Pi(y), 9 line-search
 // scale, 10 slope r_N . x, 11 not in equilibrium, 12 line search pending,
-// 13 max |x|, 14-15 spare.
+// 13 max |x|, 14 CG forcing term eta of the Newton step, 15 |r_N|^2 of the
+// last residual (for the next forcing term).
 constexpr int kQsState = 16;
 hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cells,
                               const float* y, const float* f, const double* energy,
                               const double* plate, double k, double abs_tol,
                               double rel_tol, double step_tol, double floor_factor,
-                              int restart, float* r, float* p, float* x, float* rn,
-                              double* st, double* force, hipStream_t s);
+                              double eta_max, int restart, float* r, float* p,
+                              float* x, float* rn, double* st, double* force,
+                              hipStream_t s);
 hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
                               const float* x, const float* rn, double cap,
                               const float* y, float* yt, double* st, hipStream_t s);

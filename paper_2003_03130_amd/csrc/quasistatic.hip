@@ -54,6 +54,7 @@ struct ResArgs {
   const double* energy;  // per cell E(y), nullable (no potential recorded)
   const double* plate;   // per cell: top, bottom
   double k, abs_tol, rel_tol, step_tol, floor_factor;
+  double eta_max;  // largest CG forcing term (0: fixed CG tolerance)
   int restart;  // 1: first call at this plate position (forget the last step)
   float *r, *p, *x;
   float* rn;      // copy of the Newton residual (nullable)
@@ -70,6 +71,13 @@ struct ResArgs {
 // rel_tol |pen|_2, floor_factor rho), pen the plate penalty forces and rho
 // the cell's float32 floor (qs_floor_kernel), and its last Newton step moved
 // some node by more than step_tol.
+//
+// Inexact Newton: with eta_max > 0 the CG of this Newton step stops at a
+// relative residual eta (Eisenstat and Walker's second choice of forcing
+// term, gamma = 0.9, exponent 2): eta = 0.9 (|r_N| / |r_N,prev|)^2, kept at
+// least 0.9 eta_prev^2 when that exceeds 0.1, at most eta_max (eta_max at a
+// new plate position), and at least half the ratio of the equilibrium
+// tolerance to |r_N| (no more accuracy than the test needs).
 __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -135,6 +143,21 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
     s[0] = rr;                      // CG residual |r|^2
     s[1] = rr;                      // its start value
     const double act = (rr > tol2 && s[6] > a.step_tol) ? 1.0 : 0.0;
+    double eta = 0.0;
+    if (a.eta_max > 0.0) {
+      const double prev = s[15], eta_prev = s[14];
+      if (a.restart || !(prev > 0.0)) {
+        eta = a.eta_max;
+      } else {
+        eta = 0.9 * rr / prev;
+        const double sg = 0.9 * eta_prev * eta_prev;
+        if (sg > 0.1) eta = fmax(eta, sg);
+      }
+      if (rr > 0.0) eta = fmax(eta, 0.5 * sqrt(tol2 / rr));
+      eta = fmin(eta, a.eta_max);
+    }
+    s[14] = eta;                    // CG forcing term of this Newton step
+    s[15] = rr;                     // |r_N|^2 for the next forcing term
     s[2] = act;                     // CG active
     s[11] = act;                    // not yet in equilibrium
     s[3] = rr;                      // Newton residual |f + p|^2 (projected)
@@ -157,7 +180,8 @@ struct CgArgs {
 
 // One CG iteration per active cell: Ap = Hess(Pi) p, alpha = |r|^2 / p.Ap,
 // x += alpha p, r -= alpha Ap, beta = |r_new|^2 / |r|^2, p = r + beta p.  A
-// cell stops at |r| <= rel_tol |r_0| or on non-positive curvature.
+// cell stops at |r| <= max(rel_tol, eta) |r_0| (eta the forcing term of the
+// Newton step, 0 without forcing) or on non-positive curvature.
 __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -203,7 +227,8 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   }
   if (threadIdx.x == 0) {
     s[0] = rn;
-    if (rn <= a.rel_tol * a.rel_tol * s[1]) s[2] = 0.0;
+    const double tol = fmax(a.rel_tol, s[14]);
+    if (rn <= tol * tol * s[1]) s[2] = 0.0;
   }
 }
 
@@ -430,10 +455,11 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               const float* y, const float* f, const double* energy,
                               const double* plate, double k, double abs_tol,
                               double rel_tol, double step_tol, double floor_factor,
-                              int restart, float* r, float* p, float* x, float* rn,
-                              double* st, double* force, hipStream_t s) {
+                              double eta_max, int restart, float* r, float* p,
+                              float* x, float* rn, double* st, double* force,
+                              hipStream_t s) {
   ResArgs a{node_off, N, y, f, energy, plate, k, abs_tol, rel_tol, step_tol,
-            floor_factor, restart, r, p, x, rn, st, force};
+            floor_factor, eta_max, restart, r, p, x, rn, st, force};
   hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

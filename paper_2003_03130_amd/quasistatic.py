@@ -2,7 +2,9 @@
 curves): each plate position is brought to equilibrium by Newton steps whose
 systems are solved per cell by conjugate gradients on the device (cm_qs_*;
 Hessian-vector products from cm_forces_backward), each step globalised by a
-backtracking (Armijo) line search on the total potential.  Python only
+backtracking (Armijo) line search on the total potential and solved only as
+accurately as the Newton residual's progress asks for (inexact Newton with
+Eisenstat and Walker's forcing term, per cell on the device).  Python only
 orders the calls and checks convergence flags between Newton steps."""
 from __future__ import annotations
 
@@ -17,14 +19,16 @@ class QuasiStaticCompression:
     rel_tol / abs_tol: equilibrium when |f + p|_2 <= max(abs_tol,
     rel_tol |p|_2, floor_factor rho) per cell (p the plate forces, rho the
     float32 floor of the residual, estimated at every plate position) or
-    when a Newton step moves no node by more than step_tol; cg_tol: relative
-    CG residual; cap: largest node move per Newton step; armijo: sufficient
-    decrease of the line search, which gives up below min_move."""
+    when a Newton step moves no node by more than step_tol; cg_tol: smallest
+    relative CG residual; eta_max: largest forcing term of the inexact Newton
+    steps (0: every CG solve to cg_tol); cap: largest node move per Newton
+    step; armijo: sufficient decrease of the line search, which gives up
+    below min_move."""
 
     def __init__(self, batch, k_plate, rel_tol=1e-3, abs_tol=1e-9,
                  step_tol=1e-6, floor_factor=2.0, cg_tol=1e-3, max_newton=40,
                  max_cg=400, cap=0.05, armijo=1e-4, min_move=1e-7,
-                 max_backtrack=12):
+                 max_backtrack=12, eta_max=0.5):
         import torch
         self.cb = batch
         self.k = float(k_plate)
@@ -34,6 +38,7 @@ class QuasiStaticCompression:
         self.armijo, self.min_move = float(armijo), float(min_move)
         self.max_backtrack = int(max_backtrack)
         self.cg_tol, self.cap = float(cg_tol), float(cap)
+        self.eta_max = float(eta_max)
         self.max_newton, self.max_cg = int(max_newton), int(max_cg)
         dev = batch.device
         self._f = batch.empty_nodes()
@@ -61,7 +66,7 @@ class QuasiStaticCompression:
         nat.check(nat.lib().cm_qs_residual(
             cb._h, _ptr(y), _ptr(self._f), _ptr(self._E), _ptr(plate), self.k,
             self.abs_tol, self.rel_tol, self.step_tol, self.floor_factor,
-            int(restart), _ptr(self._r), _ptr(self._p), _ptr(self._x),
+            self.eta_max, int(restart), _ptr(self._r), _ptr(self._p), _ptr(self._x),
             _ptr(self._rn), _ptr(self.state), _ptr(self.force), _stream(None)))
 
     def _active(self, col):

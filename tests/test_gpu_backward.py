@@ -49,6 +49,27 @@ def test_small_sphere_backward(seed):
     assert _max_rel(tb, to) <= TOL
 
 
+@pytest.mark.parametrize("order,tile", [(0, 64), (3, 128), (3, 192), (1, 320),
+                                        (3, 1024), (2, 4096)])
+def test_backward_orders_and_tile_sizes(order, tile):
+    """Tiles of 1, 2, 3, 5, 16 and 64 chunks (one, even and odd chunk counts
+    in the kernel's two-register-set chunk pipeline) under every tile order."""
+    c = small_sphere_case(1003)
+    v = cotangent(c.n_nodes, 1004)
+    try:
+        _, yb, tb = _gpu_backward(c, v, -0.7, tile_tets=tile, order=order)
+    except RuntimeError as e:
+        if "LDS" not in str(e):
+            raise
+        pytest.skip(str(e))  # tile does not fit the LDS budget
+    m = oracle.OracleMesh(c.x, c.tets)
+    yo, to = m.backward(c.y.astype(np.float64), c.theta, v, -0.7)
+    print(f"order {order} tile {tile}: ybar {_max_rel(yb, yo):.2e} "
+          f"thetabar {_max_rel(tb, to):.2e}", flush=True)
+    assert _max_rel(yb, yo) <= TOL
+    assert _max_rel(tb, to) <= TOL
+
+
 def test_differentiation_config_against_oracle_and_fd():
     """One ~110k-tet sphere, L = sum v.f with v ~ N(0, 1): ybar and
     dL/d(mu, kappa, w) against the oracle and FP64 central differences

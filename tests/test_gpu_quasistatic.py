@@ -100,3 +100,29 @@ def test_restart_from_equilibrium():
     assert qs.stats["newton"] - n0 <= 3
     assert (y1 - y).abs().max().item() <= 1e-5
     assert np.abs(qs.force[:, 0].cpu().numpy() - Ft[0]).max() <= 1e-4 * Ft[0].max()
+
+
+def test_inexact_newton_matches_exact_solves():
+    """The forcing term changes only how accurately each Newton system is
+    solved, not the equilibrium test: eta_max = 0 (every CG solve to cg_tol)
+    and the default inexact Newton steps give the same plate forces within
+    the equilibrium tolerance.  eta_max outside [0, 1) is refused."""
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b = _cells()
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    top0 = np.array([b.cell(c).x[:, 2].max() for c in range(b.n_cells)])
+    bot = np.array([b.cell(c).x[:, 2].min() for c in range(b.n_cells)])
+    tops = top0[None, :] - 2.0 * np.array([0.05, 0.1, 0.2])[:, None]
+    out = {}
+    for eta in (0.0, 0.5):
+        qs = QuasiStaticCompression(cb, K, eta_max=eta)
+        Ft, Fb, ok, _ = qs.curve(cb.to_device(b.y), tops, bot)
+        assert ok.all(), (eta, qs.stats)
+        out[eta] = Ft
+        print(f"eta_max {eta}: {qs.stats}")
+    assert np.abs(out[0.5] - out[0.0]).max() <= 2e-3 * np.abs(out[0.0]).max()
+    with pytest.raises(RuntimeError, match="eta_max"):
+        QuasiStaticCompression(cb, K, eta_max=1.0).curve(
+            cb.to_device(b.y), tops[:1], bot)
