@@ -221,6 +221,23 @@ int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
                        hipStream_t stream);
 
 /*
+ * cm_forces_backward_cells: cm_forces_backward restricted to the cells c
+ * with cell_flags[c * flag_stride] != 0 (for iterative solvers in which
+ * cells finish at different times, e.g. the conjugate gradients of
+ * cm_qs_cg_step, whose state column 2 can serve as the flags).
+ *   cell_flags  : device float64, read at c * flag_stride for c < n_cells.
+ *   flag_stride : >= 1, in elements.
+ * For a selected cell, ybar and thetabar are bitwise those of
+ * cm_forces_backward; tiles of other cells are not evaluated and their
+ * ybar and thetabar entries are left unchanged.  Errors: as
+ * cm_forces_backward, and CM_EINVAL for a null cell_flags or a stride < 1.
+ */
+int cm_forces_backward_cells(cm_batch h, const float* y, const float* fbar,
+                             const double* ebar, const double* cell_flags,
+                             int64_t flag_stride, float* ybar, double* thetabar,
+                             hipStream_t stream);
+
+/*
  * Same results as cm_forces / cm_forces_backward, but one kernel launch per
  * cell (the plain single-cell path).  Used as the comparison baseline of the
  * batched persistent launch.

@@ -100,6 +100,8 @@ SIGNATURES = {
                                         ctypes.POINTER(_vp)]),
     "cm_layout_export_regions": (_int, [_vp, _vp, _vp, _vp]),
     "cm_shape": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "cm_forces_backward_cells": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp,
+                                        _vp, _vp]),
     "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, _i32, _vp, _vp,

@@ -220,13 +220,28 @@ class CellBatch:
         return f, energy
 
     def backward(self, y, fbar=None, ebar=None, ybar=None, thetabar=None,
-                 stream=None, percell=False):
+                 stream=None, percell=False, cells=None):
+        """cells: optional float64 device tensor of shape (n_cells,) (a
+        strided view such as a column of a state array is fine): only cells
+        with a nonzero entry are evaluated, the others' ybar and thetabar
+        entries are left unchanged (cm_forces_backward_cells)."""
         import torch
         if ybar is None:
             ybar = self.empty_nodes()
         if thetabar is None:
             thetabar = torch.empty(3 * self.n_mat, dtype=torch.float64,
                                    device=self.device)
+        if cells is not None:
+            if percell:
+                raise ValueError("cells and percell cannot be combined")
+            if (cells.dtype != torch.float64 or cells.dim() != 1
+                    or cells.shape[0] != self.n_cells or not cells.is_cuda):
+                raise ValueError("cells must be a float64 device tensor of "
+                                 "shape (n_cells,)")
+            nat.check(nat.lib().cm_forces_backward_cells(
+                self._h, _ptr(y), _ptr(fbar), _ptr(ebar), _ptr(cells),
+                cells.stride(0), _ptr(ybar), _ptr(thetabar), _stream(stream)))
+            return ybar, thetabar
         fn = (nat.lib().cm_forces_backward_percell if percell
               else nat.lib().cm_forces_backward)
         nat.check(fn(self._h, _ptr(y), _ptr(fbar), _ptr(ebar), _ptr(ybar),

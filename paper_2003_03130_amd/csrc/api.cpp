@@ -461,7 +461,8 @@ static int forces_impl(cm_batch h, const float* y, float* f, double* energy,
 
 static int backward_impl(cm_batch h, const float* y, const float* fbar,
                          const double* ebar, float* ybar, double* thetabar,
-                         hipStream_t st, bool percell) {
+                         hipStream_t st, bool percell,
+                         const cm::CellMask& mask = cm::CellMask{}) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !ybar) return fail(CM_EINVAL, "y and ybar must be device pointers");
   if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
@@ -472,7 +473,7 @@ static int backward_impl(cm_batch h, const float* y, const float* fbar,
     return fail(CM_EINVAL, "per-cell launches need contiguous tiles (not a template batch)");
   if (!percell) {
     CM_HIP(cm::launch_backward(h->Tb, full_range(h), h->cfg, y, fbar, ebar, ybar,
-                               thetabar, st));
+                               thetabar, st, mask));
   } else {
     cm::LaunchCfg one{h->cfg.waves, 0};
     for (int32_t c = 0; c < (int32_t)h->n_cells; ++c)
@@ -502,6 +503,17 @@ int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
                                const double* ebar, float* ybar,
                                double* thetabar, hipStream_t stream) {
   return backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, true);
+}
+
+int cm_forces_backward_cells(cm_batch h, const float* y, const float* fbar,
+                             const double* ebar, const double* cell_flags,
+                             int64_t flag_stride, float* ybar, double* thetabar,
+                             hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!cell_flags) return fail(CM_EINVAL, "cell_flags must be a device pointer");
+  if (flag_stride < 1) return fail(CM_EINVAL, "flag_stride must be >= 1");
+  cm::CellMask mask{cell_flags, flag_stride, h->d_node_off, (int32_t)h->n_cells};
+  return backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, false, mask);
 }
 
 int cm_set_launch(cm_batch h, int32_t waves, int32_t blocks_per_cu) {

@@ -23,6 +23,7 @@ struct BwdArgs {
   const float* fbar;    // nullable
   const double* ebar;   // nullable
   float* ybar;
+  CellMask mask;
 };
 
 template <int W>
@@ -43,6 +44,8 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   block_tiles(a.r, t0, t1);
   for (int t = t0 + wave; t < t1; t += W) {
     const TileDesc d = a.T.tiles[t];
+    if (a.mask.flags && a.mask.flags[(int64_t)d.cell * a.mask.stride] == 0.0)
+      continue;  // cell not selected (uniform over the wave)
     const int mt = a.T.tile_mat[t], nm = a.T.n_mat;
     const double mu = a.T.params[mt];
     const double kappa = a.T.params[nm + mt];
@@ -118,7 +121,18 @@ struct BwdFinArgs {
   Range r;
   float* ybar;
   double* thetabar;  // nullable
+  CellMask mask;
 };
+
+// Cell of internal node g (cells keep contiguous node ranges).
+__device__ int cell_of_node(const int64_t* node_off, int n_cells, int64_t g) {
+  int lo = 0, hi = n_cells;  // node_off[lo] <= g < node_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (node_off[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 
 // Shared-node slot sums in tile order, and per material slot
 //   dL/dmu = w g_I + (1 - w) g_K, dL/dkappa = g_J, dL/dw = mu (g_I - g_K)
@@ -126,22 +140,27 @@ struct BwdFinArgs {
 __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = a.T.n_nodes;
+  const CellMask& m = a.mask;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
-      const int64_t sl = a.T.shared_slots[q];
-      const float* pp = a.T.part + 3 * sl;
-      sx += pp[0];
-      sy += pp[1];
-      sz += pp[2];
-    }
     const int64_t g = a.T.shared_node[s];
-    a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
+    if (!m.flags ||
+        m.flags[(int64_t)cell_of_node(m.node_off, m.n_cells, g) * m.stride] != 0.0) {
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+      for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
+        const int64_t sl = a.T.shared_slots[q];
+        const float* pp = a.T.part + 3 * sl;
+        sx += pp[0];
+        sy += pp[1];
+        sz += pp[2];
+      }
+      a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
+    }
   }
   const int R = a.T.n_regions;
   if (a.thetabar && gid < (int64_t)(a.r.cell_end - a.r.cell_begin) * R) {
     const int mt = a.r.cell_begin * R + (int)gid;  // material slot
+    if (m.flags && m.flags[(int64_t)(mt / R) * m.stride] == 0.0) return;
     double gI = 0.0, gK = 0.0, gJ = 0.0;
     const int t0 = a.T.mat_tile_first[mt], nt = a.T.mat_tile_count[mt];
     for (int k = 0; k < nt; ++k) {
@@ -171,9 +190,9 @@ size_t backward_lds_per_wave(int nloc) { return (size_t)40 * nloc; }
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
-                                float* ybar, hipStream_t st) {
+                                float* ybar, hipStream_t st, const CellMask& mask) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
-  BwdArgs a{T, r, y, fbar, ebar, ybar};
+  BwdArgs a{T, r, y, fbar, ebar, ybar, mask};
   const int grid = grid_for(r, cfg);
   const size_t lds = backward_lds_per_wave(T.nloc) * cfg.waves;
   switch (cfg.waves) {
@@ -187,11 +206,11 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
 
 hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
                                     float* ybar, double* thetabar,
-                                    hipStream_t st) {
+                                    hipStream_t st, const CellMask& mask) {
   const int64_t work = std::max<int64_t>(
       r.shared_end - r.shared_begin, (int64_t)(r.cell_end - r.cell_begin) * T.n_regions);
   if (work <= 0) return hipSuccess;
-  BwdFinArgs b{T, r, ybar, thetabar};
+  BwdFinArgs b{T, r, ybar, thetabar, mask};
   hipLaunchKernelGGL(backward_finalize_kernel,
                      dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, b);
   return hipGetLastError();
@@ -200,10 +219,10 @@ hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
 hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const LaunchCfg& cfg, const float* y,
                            const float* fbar, const double* ebar, float* ybar,
-                           double* thetabar, hipStream_t st) {
-  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st);
+                           double* thetabar, hipStream_t st, const CellMask& mask) {
+  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st, mask);
   if (e != hipSuccess) return e;
-  return launch_backward_finalize(T, r, ybar, thetabar, st);
+  return launch_backward_finalize(T, r, ybar, thetabar, st, mask);
 }
 
 }  // namespace cm

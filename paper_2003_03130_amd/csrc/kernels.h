@@ -43,6 +43,16 @@ struct Range {
   int32_t cell_begin, cell_end;
 };
 
+// Restricts a backward pass to the cells c with flags[c * stride] != 0 (all
+// cells when flags is null); node_off (device, n_cells + 1 entries) finds
+// the cell of a shared node.
+struct CellMask {
+  const double* flags = nullptr;
+  int64_t stride = 1;
+  const int64_t* node_off = nullptr;
+  int32_t n_cells = 0;
+};
+
 struct LaunchCfg {
   int waves = 1;   // tiles (wavefronts) per workgroup: 1, 2, 4 or 8
   int blocks = 0;  // persistent workgroups; 0 = one workgroup per W tiles
@@ -62,10 +72,12 @@ hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
-                                float* ybar, hipStream_t st);
+                                float* ybar, hipStream_t st,
+                                const CellMask& mask = CellMask{});
 hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
                                     float* ybar, double* thetabar,
-                                    hipStream_t st);
+                                    hipStream_t st,
+                                    const CellMask& mask = CellMask{});
 
 hipError_t launch_forward(const DeviceTables& T, const Range& r,
                           const LaunchCfg& cfg, const float* y, float* f,
@@ -74,6 +86,7 @@ hipError_t launch_forward(const DeviceTables& T, const Range& r,
 hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const LaunchCfg& cfg, const float* y,
                            const float* fbar, const double* ebar, float* ybar,
-                           double* thetabar, hipStream_t st);
+                           double* thetabar, hipStream_t st,
+                           const CellMask& mask = CellMask{});
 
 }  // namespace cm

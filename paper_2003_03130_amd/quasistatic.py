@@ -90,7 +90,9 @@ class QuasiStaticCompression:
                 return True
             self.stats["newton"] += 1
             for j in range(self.max_cg):
-                cb.backward(y, self._p, None, self._ybar, self._tb)
+                # Hessian-vector products only for cells still in CG
+                cb.backward(y, self._p, None, self._ybar, self._tb,
+                            cells=self.state[:, 2])
                 nat.check(nat.lib().cm_qs_cg_step(
                     cb._h, _ptr(y), _ptr(plate), self.k, self.cg_tol,
                     _ptr(self._ybar), _ptr(self._x), _ptr(self._r),

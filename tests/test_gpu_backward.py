@@ -192,6 +192,58 @@ def test_batched_backward_deterministic_and_equal_percell():
         assert _max_rel(tb[c], to) <= TOL
 
 
+@pytest.mark.parametrize("n_regions", [1, 3])
+def test_backward_restricted_to_flagged_cells(n_regions):
+    """cm_forces_backward_cells: selected cells bitwise equal to the full
+    backward, the others' ybar / thetabar entries untouched (sentinels),
+    flags read through a strided column; with material regions the
+    thetabar slots of a cell follow its flag."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import radial_regions
+    b = uneven_batch(n_cells=12, seed=23, tet_lo=500, tet_hi=8000, ladder=5)
+    kw = {}
+    if n_regions > 1:
+        kw = dict(regions=np.concatenate([
+            radial_regions(b.x[b.node_off[c]:b.node_off[c + 1]],
+                           b.tets[b.tet_off[c]:b.tet_off[c + 1]])
+            for c in range(b.n_cells)]), n_regions=n_regions)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets, **kw)
+    th = np.repeat(b.theta, n_regions, axis=0)
+    cb.set_params(th[:, 0], th[:, 1], th[:, 2])
+    y = cb.to_device(b.y)
+    v = cb.to_device(cotangent(b.n_nodes, 29))
+    eb = torch.linspace(-0.5, 0.8, b.n_cells, dtype=torch.float64,
+                        device=cb.device)
+    y0, t0 = cb.backward(y, v, eb)
+    y0, t0 = cb.to_host(y0), t0.cpu().numpy().reshape(b.n_cells, -1)
+    sel = np.array([1, 0, 0, 1, 1, 0, 1, 0, 0, 0, 1, 1], np.float64)
+    state = torch.zeros(b.n_cells, 5, dtype=torch.float64, device=cb.device)
+    state[:, 3] = torch.from_numpy(sel).to(cb.device)
+    yb = torch.full_like(cb.empty_nodes(), 7.0)
+    tb = torch.full((3 * cb.n_mat,), -3.0, dtype=torch.float64,
+                    device=cb.device)
+    cb.backward(y, v, eb, yb, tb, cells=state[:, 3])
+    y1, t1 = cb.to_host(yb), tb.cpu().numpy().reshape(b.n_cells, -1)
+    for c in range(b.n_cells):
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        if sel[c]:
+            assert np.array_equal(y1[n0:n1], y0[n0:n1]), c
+            assert np.array_equal(t1[c], t0[c]), c
+        else:
+            assert np.all(y1[n0:n1] == 7.0), c
+            assert np.all(t1[c] == -3.0), c
+    with pytest.raises(ValueError):
+        cb.backward(y, v, eb, yb, tb, cells=state[:4, 3])
+    from paper_2003_03130_amd import _native as nat
+    from paper_2003_03130_amd.cells import _ptr, _stream
+    fn = nat.lib().cm_forces_backward_cells
+    assert fn(cb._h, _ptr(y), _ptr(v), None, None, 1, _ptr(yb), None,
+              _stream(None)) != 0
+    assert fn(cb._h, _ptr(y), _ptr(v), None, _ptr(state), 0, _ptr(yb), None,
+              _stream(None)) != 0
+
+
 def test_graph_forward_backward_replay():
     import torch
     from paper_2003_03130_amd import CellBatch
