@@ -134,13 +134,43 @@ __device__ int cell_of_node(const int64_t* node_off, int n_cells, int64_t g) {
   return lo;
 }
 
-// Shared-node slot sums in tile order, and per material slot
+// The first slot_blocks workgroups form, one wavefront per material slot,
 //   dL/dmu = w g_I + (1 - w) g_K, dL/dkappa = g_J, dL/dw = mu (g_I - g_K)
-// from the per-tile sums of dL/d(mu1, mu2, kappa) (mu1 = w mu, mu2 = (1-w) mu).
-__global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = a.T.n_nodes;
+// from the per-tile sums of dL/d(mu1, mu2, kappa) (mu1 = w mu, mu2 = (1-w) mu;
+// lane l takes tiles l, l + 64, ..., then a fixed butterfly); the others sum
+// the slot partials of every shared node in tile order.
+__global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
+                                                                int slot_blocks) {
   const CellMask& m = a.mask;
+  const int R = a.T.n_regions;
+  if ((int)blockIdx.x < slot_blocks) {
+    const int wv = ((int)blockIdx.x * 256 + (int)threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (!a.thetabar || wv >= (a.r.cell_end - a.r.cell_begin) * R) return;
+    const int mt = a.r.cell_begin * R + wv;  // material slot
+    if (m.flags && m.flags[(int64_t)(mt / R) * m.stride] == 0.0) return;
+    double gI = 0.0, gK = 0.0, gJ = 0.0;
+    const int t0 = a.T.mat_tile_first[mt], nt = a.T.mat_tile_count[mt];
+    for (int k = lane; k < nt; k += 64) {
+      const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
+      gI += a.T.tile_acc[3 * t];
+      gK += a.T.tile_acc[3 * t + 1];
+      gJ += a.T.tile_acc[3 * t + 2];
+    }
+    gI = wave_sum(gI);
+    gK = wave_sum(gK);
+    gJ = wave_sum(gJ);
+    if (lane == 0) {
+      const int nm = a.T.n_mat;
+      const double mu = a.T.params[mt], w = a.T.params[2 * nm + mt];
+      a.thetabar[3 * (int64_t)mt] = w * gI + (1.0 - w) * gK;
+      a.thetabar[3 * (int64_t)mt + 1] = gJ;
+      a.thetabar[3 * (int64_t)mt + 2] = mu * (gI - gK);
+    }
+    return;
+  }
+  const int64_t gid = (int64_t)(blockIdx.x - slot_blocks) * blockDim.x + threadIdx.x;
+  const int64_t N = a.T.n_nodes;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
     const int64_t g = a.T.shared_node[s];
@@ -156,24 +186,6 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a) {
       }
       a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
     }
-  }
-  const int R = a.T.n_regions;
-  if (a.thetabar && gid < (int64_t)(a.r.cell_end - a.r.cell_begin) * R) {
-    const int mt = a.r.cell_begin * R + (int)gid;  // material slot
-    if (m.flags && m.flags[(int64_t)(mt / R) * m.stride] == 0.0) return;
-    double gI = 0.0, gK = 0.0, gJ = 0.0;
-    const int t0 = a.T.mat_tile_first[mt], nt = a.T.mat_tile_count[mt];
-    for (int k = 0; k < nt; ++k) {
-      const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
-      gI += a.T.tile_acc[3 * t];
-      gK += a.T.tile_acc[3 * t + 1];
-      gJ += a.T.tile_acc[3 * t + 2];
-    }
-    const int nm = a.T.n_mat;
-    const double mu = a.T.params[mt], w = a.T.params[2 * nm + mt];
-    a.thetabar[3 * (int64_t)mt] = w * gI + (1.0 - w) * gK;
-    a.thetabar[3 * (int64_t)mt + 1] = gJ;
-    a.thetabar[3 * (int64_t)mt + 2] = mu * (gI - gK);
   }
 }
 
@@ -207,12 +219,14 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
 hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
                                     float* ybar, double* thetabar,
                                     hipStream_t st, const CellMask& mask) {
-  const int64_t work = std::max<int64_t>(
-      r.shared_end - r.shared_begin, (int64_t)(r.cell_end - r.cell_begin) * T.n_regions);
-  if (work <= 0) return hipSuccess;
+  const int64_t n_shr = r.shared_end - r.shared_begin;
+  const int64_t n_slots = thetabar ? (int64_t)(r.cell_end - r.cell_begin) * T.n_regions : 0;
+  if (n_shr <= 0 && n_slots <= 0) return hipSuccess;
+  const int slot_blocks = (int)((n_slots + 3) / 4);  // four waves per block
+  const int64_t blocks = slot_blocks + (n_shr + 255) / 256;
   BwdFinArgs b{T, r, ybar, thetabar, mask};
-  hipLaunchKernelGGL(backward_finalize_kernel,
-                     dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(backward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     st, b, slot_blocks);
   return hipGetLastError();
 }
 

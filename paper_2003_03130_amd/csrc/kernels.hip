@@ -103,10 +103,35 @@ struct FinArgs {
   int32_t* ninv;
 };
 
-// Sums the slot partials of every shared node in tile order, and the tile
-// energies / inverted counts of every cell.
-__global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The first cell_blocks workgroups sum the tile energies / inverted counts
+// of every cell, one wavefront per cell (lane l takes tiles l, l + 64, ...,
+// then a fixed butterfly: deterministic, and the cells' long chains of
+// loads run in parallel); the others sum the slot partials of every shared
+// node in tile order.
+__global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
+                                                               int cell_blocks) {
+  if ((int)blockIdx.x < cell_blocks) {
+    const int wv = ((int)blockIdx.x * 256 + (int)threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wv >= a.r.cell_end - a.r.cell_begin) return;  // uniform per wave
+    const int c = a.r.cell_begin + wv;
+    double e = 0.0;
+    int ni = 0;
+    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
+    for (int k = lane; k < nt; k += 64) {
+      const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
+      e += a.T.tile_acc[t];
+      ni += a.T.tile_ninv[t];
+    }
+    e = wave_sum(e);
+    ni = wave_sum(ni);
+    if (lane == 0) {
+      if (a.energy) a.energy[c] = e;
+      if (a.ninv) a.ninv[c] = ni;
+    }
+    return;
+  }
+  const int64_t gid = (int64_t)(blockIdx.x - cell_blocks) * blockDim.x + threadIdx.x;
   const int64_t N = a.T.n_nodes;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
@@ -120,19 +145,6 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a) {
     }
     const int64_t g = a.T.shared_node[s];
     a.f[g] = sx; a.f[N + g] = sy; a.f[2 * N + g] = sz;
-  }
-  if (gid < a.r.cell_end - a.r.cell_begin) {
-    const int c = a.r.cell_begin + (int)gid;
-    double e = 0.0;
-    int ni = 0;
-    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
-    for (int k = 0; k < nt; ++k) {
-      const int t = t0 + k * a.T.tile_stride;
-      e += a.T.tile_acc[t];
-      ni += a.T.tile_ninv[t];
-    }
-    if (a.energy) a.energy[c] = e;
-    if (a.ninv) a.ninv[c] = ni;
   }
 }
 
@@ -165,12 +177,14 @@ hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
 hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
                                    float* f, double* energy, int32_t* ninv,
                                    hipStream_t st) {
-  const int64_t work = std::max<int64_t>(r.shared_end - r.shared_begin,
-                                         r.cell_end - r.cell_begin);
-  if (work <= 0) return hipSuccess;
+  const int64_t n_shr = r.shared_end - r.shared_begin;
+  const int64_t n_cells = r.cell_end - r.cell_begin;
+  if (n_shr <= 0 && n_cells <= 0) return hipSuccess;
+  const int cell_blocks = (int)((n_cells + 3) / 4);  // four waves per block
+  const int64_t blocks = cell_blocks + (n_shr + 255) / 256;
   FinArgs b{T, r, f, energy, ninv};
-  hipLaunchKernelGGL(forward_finalize_kernel, dim3((unsigned)((work + 255) / 256)),
-                     dim3(256), 0, st, b);
+  hipLaunchKernelGGL(forward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     st, b, cell_blocks);
   return hipGetLastError();
 }
 
