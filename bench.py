@@ -539,6 +539,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
+    ap.add_argument("--only", choices=["relax", "qs", "template"], default=None,
+                    help="run one self-contained leg alone (for profiling it) "
+                         "and print its JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -554,6 +557,12 @@ def main():
     torch.cuda.set_device(0)
     from paper_2003_03130_amd import CellBatch
     from synth.configs import cotangent, uneven_batch
+
+    if args.only:
+        leg = {"relax": run_relax, "qs": run_quasistatic,
+               "template": run_template}[args.only](args)
+        print(json.dumps({"leg": args.only, **leg}), flush=True)
+        return
 
     t = time.time()
     b = uneven_batch(n_cells=args.cells, seed=args.seed)

@@ -127,3 +127,29 @@ def test_template_graph_replay_and_percell_rejected():
         with pytest.raises(CellmechError) as ei:
             call()
         assert ei.value.status == nat.CM_EINVAL
+
+
+def test_template_backward_restricted_to_flagged_cells():
+    """cm_forces_backward_cells on a shared-mesh batch (tiles interleaved by
+    copy): flagged copies bitwise equal to the full backward, the others
+    untouched."""
+    import torch
+    b = template_batch(6, 800, seed=93)
+    tp, _ = _pair(b, tile_tets=128)
+    y = tp.to_device(b.y)
+    v = tp.to_device(cotangent(b.n_nodes, 94))
+    eb = torch.linspace(-1.0, 1.0, b.n_cells, dtype=torch.float64, device=tp.device)
+    y0, t0 = tp.backward(y, v, eb)
+    y0, t0 = tp.to_host(y0), t0.cpu().numpy().reshape(b.n_cells, 3)
+    sel = torch.tensor([0.0, 1.0, 1.0, 0.0, 0.0, 1.0], dtype=torch.float64,
+                       device=tp.device)
+    yb = torch.full_like(tp.empty_nodes(), 5.0)
+    tb = torch.full((3 * b.n_cells,), 9.0, dtype=torch.float64, device=tp.device)
+    tp.backward(y, v, eb, yb, tb, cells=sel)
+    y1, t1 = tp.to_host(yb), tb.cpu().numpy().reshape(b.n_cells, 3)
+    for c in range(b.n_cells):
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        if sel[c] != 0:
+            assert np.array_equal(y1[n0:n1], y0[n0:n1]) and np.array_equal(t1[c], t0[c])
+        else:
+            assert np.all(y1[n0:n1] == 5.0) and np.all(t1[c] == 9.0)
