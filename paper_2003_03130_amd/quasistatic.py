@@ -84,20 +84,24 @@ class QuasiStaticCompression:
         nat.check(nat.lib().cm_qs_floor(
             cb._h, _ptr(y), _ptr(plate), self.k, _ptr(self._Ap),
             _ptr(self._ybar), _ptr(self.state), _stream(None)))
+        # the CG loop's two calls with their arguments fixed once: Hessian-
+        # vector products only for the cells still in CG (state column 2 as
+        # the cell flags; no parameter gradient), then one CG iteration
+        lib, st = nat.lib(), _stream(None)
+        flags = self.state[:, 2]
+        hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
+                    flags.stride(0), _ptr(self._ybar), None, st)
+        cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, self.cg_tol,
+                   _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
+                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state), st)
         for it in range(self.max_newton):
             self._residual(y, plate, restart=(it == 0))
             if not self._active(11):
                 return True
             self.stats["newton"] += 1
             for j in range(self.max_cg):
-                # Hessian-vector products only for cells still in CG
-                cb.backward(y, self._p, None, self._ybar, self._tb,
-                            cells=self.state[:, 2])
-                nat.check(nat.lib().cm_qs_cg_step(
-                    cb._h, _ptr(y), _ptr(plate), self.k, self.cg_tol,
-                    _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
-                    _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
-                    _stream(None)))
+                nat.check(lib.cm_forces_backward_cells(*hvp_args))
+                nat.check(lib.cm_qs_cg_step(*cg_args))
                 self.stats["cg"] += 1
                 if j % 8 == 7 and not self._active(2):
                     break
