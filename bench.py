@@ -399,7 +399,7 @@ def run_quasistatic(args):
     from synth.configs import K_PLATE, oblate_batch
     t = time.time()
     b = oblate_batch(args.qs_cells, 2000, 7000)
-    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets, tile_tets=args.tile_tets)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets, tile_tets=args.qs_tile_tets)
     cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
     top0 = np.array([b.x[b.node_off[c]:b.node_off[c + 1], 2].max()
                      for c in range(b.n_cells)])
@@ -419,7 +419,8 @@ def run_quasistatic(args):
     hvp = qs.stats["cg"]
     out = {
         "workload": f"{b.n_cells} oblate cells, {b.n_tets} tets, plates "
-                    f"closing to 20 % of the height in 10 steps",
+                    f"closing to 20 % of the height in 10 steps, "
+                    f"{args.qs_tile_tets}-tet tiles",
         "wall_s": wall, "newton": qs.stats["newton"], "cg": hvp,
         "converged_steps": int(ok.sum()), "steps": len(ok),
         "unconverged_cells_last": int((qs.state[:, 2] > 0).sum().item()),
@@ -535,6 +536,10 @@ def main():
     ap.add_argument("--no-regions", action="store_true")
     ap.add_argument("--no-shape", action="store_true")
     ap.add_argument("--qs-cells", type=int, default=256)
+    ap.add_argument("--qs-tile-tets", type=int, default=512,
+                    help="tile size of the quasi-static leg (its masked "
+                         "Hessian-vector products are bound by the latency "
+                         "of single tiles once few cells are left in CG)")
     ap.add_argument("--no-qs", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
