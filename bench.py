@@ -256,10 +256,22 @@ def run_relax(args):
     F, yN, _ = pc.forward(y0)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t
+    pc.gradient(y0, Ft, scale)  # warm-up (allocations)
+    torch.cuda.synchronize()
     t = time.perf_counter()
     loss, g, _ = pc.gradient(y0, Ft, scale)
     torch.cuda.synchronize()
     t_bptt = time.perf_counter() - t
+    # the same gradient with every state kept (no recomputation; the states
+    # of this workload take a few GB of the 288 GB of HBM)
+    pc_all = PlateCompression(cb, top, bot, K_PLATE, STOKES_DT / DRAG,
+                              checkpoint=args.relax_steps)
+    pc_all.gradient(y0, Ft, scale)  # warm-up (allocations)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, g_all, _ = pc_all.gradient(y0, Ft, scale)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t
     M, N, S = b.n_tets, b.n_nodes, args.relax_steps
     step_bytes = FWD_BYTES[0] * M + FWD_BYTES[1] * N + 36 * N
     out = {
@@ -268,6 +280,9 @@ def run_relax(args):
         "fwd_s": t_fwd, "bptt_s": t_bptt,
         "fwd_tet_steps_per_s": M * S / t_fwd,
         "bptt_tet_steps_per_s": M * S / t_bptt,
+        "bptt_all_states_s": t_all,
+        "bptt_all_states_GB": S * 12 * N / 1e9,
+        "bptt_all_states_same_gradient": bool(torch.equal(g_all, g)),
         "fwd_step_hbm_frac": step_bytes * S / t_fwd / (HBM_PEAK_GBS * 1e9),
         "loss": loss, "grad_finite": bool(torch.isfinite(g).all()),
         "max_plate_force": float(F.max()),

@@ -17,9 +17,11 @@ Reverse mode: lam_N = 0 and, for n = N-1 .. 0,
     lam_n = lam_{n+1} + m ((df/dy)^T + dp/dy) lam_{n+1} + dL/dy_n,
     dL/dtheta += m (df/dtheta)^T lam_{n+1},
 where (df/dy)^T lam and (df/dtheta)^T lam come from cm_forces_backward.  Only
-every `checkpoint`-th state is kept during the forward sweep; each segment is
-recomputed from its checkpoint during the reverse sweep (the recomputation is
-bitwise identical, so the gradient equals the one with every state stored).
+every `checkpoint`-th state is kept during the forward sweep, plus the states
+of the last segment; every other segment is recomputed from its checkpoint
+during the reverse sweep (the recomputation is bitwise identical, so the
+gradient equals the one with every state stored; the plate forces of the
+loss come from the forward sweep).
 Every arithmetic step runs in libcellmech's kernels; this module only
 orders the calls and owns the buffers.
 """
@@ -78,9 +80,11 @@ class PlateCompression:
         cb.forces(y, self._f, self._E)
         cb.plate_step(y, self._f, self.plates[n], self.k, self.m, y_next, force)
 
-    def forward(self, y0, keep_every=None):
+    def forward(self, y0, keep_every=None, tail=None):
         """Runs all steps from y0 (device SoA).  Returns (F (N, n_cells)
-        float64 device tensor, final positions, kept states dict n -> y_n)."""
+        float64 device tensor, final positions, kept states dict n -> y_n).
+        tail = (n0, buffers): the states y_n, n >= n0, are also copied into
+        buffers[n - n0]."""
         import torch
         N = self.n_steps
         F = torch.empty(N, self.cb.n_cells, dtype=torch.float64,
@@ -91,6 +95,8 @@ class PlateCompression:
         for n in range(N):
             if keep_every and n % keep_every == 0:
                 kept[n] = y.clone()
+            if tail is not None and n >= tail[0]:
+                tail[1][n - tail[0]].copy_(y)
             self._step(n, y, nxt, F[n])
             y, nxt = nxt, y
         return F, y, kept
@@ -100,30 +106,34 @@ class PlateCompression:
         F_target: (N, n_cells) float64 device tensor."""
         import torch
         N, C = self.n_steps, self.checkpoint
-        F, _, kept = self.forward(y0, keep_every=C)
-        loss = float(scale * ((F - F_target) ** 2).sum())
         cb = self.cb
         lam = torch.zeros(3 * cb.n_nodes, dtype=torch.float32, device=cb.device)
+        seg_states = [torch.empty_like(lam) for _ in range(C)]
+        # the forward sweep leaves the last segment's states in seg_states,
+        # so only the earlier segments are recomputed
+        last0 = ((N - 1) // C) * C
+        F, _, kept = self.forward(y0, keep_every=C, tail=(last0, seg_states))
+        loss = float(scale * ((F - F_target) ** 2).sum())
         lam_new = torch.empty_like(lam)
         tacc = torch.zeros(3 * cb.n_mat, dtype=torch.float64,
                            device=cb.device)
-        seg_states = [torch.empty_like(lam) for _ in range(C)]
-        spare = torch.empty_like(lam)
-        Fseg = torch.empty(C, cb.n_cells, dtype=torch.float64, device=cb.device)
         for s0 in reversed(range(0, N, C)):
             s1 = min(N, s0 + C)
-            # recompute the segment's states from its checkpoint
-            seg_states[0].copy_(kept[s0])
-            for j in range(s1 - s0):
-                n = s0 + j
-                nxt = seg_states[j + 1] if j + 1 < s1 - s0 else spare
-                self._step(n, seg_states[j], nxt, Fseg[j])
+            if s0 != last0:
+                # recompute the segment's states y_s0 .. y_{s1-1} from its
+                # checkpoint (bitwise the states of the forward sweep; the
+                # plate forces F_n come from the forward sweep)
+                seg_states[0].copy_(kept[s0])
+                for j in range(s1 - s0 - 1):
+                    cb.forces(seg_states[j], self._f, self._E)
+                    cb.plate_step(seg_states[j], self._f, self.plates[s0 + j],
+                                  self.k, self.m, seg_states[j + 1], None)
             for j in reversed(range(s1 - s0)):
                 n = s0 + j
                 y_n = seg_states[j]
                 cb.backward(y_n, lam, None, self._ybar, self._tb)
                 cb.plate_step_adjoint(y_n, lam, self._ybar, self.plates[n],
-                                      self.k, self.m, lam_new, Fseg[j],
+                                      self.k, self.m, lam_new, F[n],
                                       F_target[n], scale, self._tb, tacc)
                 lam, lam_new = lam_new, lam
         return loss, tacc.view(-1, 3), F
