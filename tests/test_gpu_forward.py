@@ -158,3 +158,57 @@ def test_state_and_parameter_errors():
         assert ei.value.status == nat.CM_EINVAL
     with pytest.raises(CellmechError):
         cb.set_launch(3, 0)
+
+
+def _tiny_cells():
+    """A 1-tetrahedron cell, two tetrahedra sharing a face, a 5-tetrahedron
+    cube split, and a 1,000-node sphere: tiles of one chunk with mostly empty
+    lanes beside full tiles."""
+    from synth.configs import Cell
+    rng = np.random.default_rng(77)
+    cube = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0],
+                     [1, 0, 1], [0, 1, 1], [1, 1, 1]], np.float64)
+    meshes = [
+        (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], np.float64),
+         np.array([[0, 1, 2, 3]], np.int32)),
+        (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]],
+                  np.float64),
+         np.array([[0, 1, 2, 3], [1, 2, 3, 4]], np.int32)),
+        (cube, np.array([[0, 1, 2, 3], [1, 4, 2, 7], [1, 3, 5, 7],
+                         [2, 3, 6, 7], [1, 2, 3, 7]], np.int32)),
+    ]
+    cells = []
+    for k, (x, tets) in enumerate(meshes):
+        A = np.eye(3) + 0.2 * rng.standard_normal((3, 3))
+        y = x @ A.T + 0.02 * rng.standard_normal(x.shape)
+        cells.append(Cell(x, tets, y.astype(np.float32), (1.0 + k, 15.0, 0.3)))
+    cells.append(small_sphere_case(1007))
+    return cells
+
+
+def test_tiny_and_ragged_cells_against_the_oracle():
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import batch_from_cells
+    cells = _tiny_cells()
+    b = batch_from_cells(cells)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    y = cb.to_device(b.y)
+    ninv = torch.zeros(b.n_cells, dtype=torch.int32, device=cb.device)
+    f, E = cb.forces(y, n_inverted=ninv)
+    from synth.configs import cotangent
+    v = cotangent(b.n_nodes, 78)
+    eb = torch.tensor([0.4, -0.2, 0.9, 0.1], dtype=torch.float64, device=cb.device)
+    yb, tb = cb.backward(y, cb.to_device(v), eb)
+    f, E, yb = cb.to_host(f), E.cpu().numpy(), cb.to_host(yb)
+    tb = tb.cpu().numpy().reshape(-1, 3)
+    for c, cell in enumerate(cells):
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        m, (fo, Eo, _) = oracle_cell(cell)
+        assert force_rel_err(f[n0:n1], fo) <= F_TOL, c
+        assert rel_err(E[c], Eo) <= E_TOL, c
+        yo, to = m.backward(cell.y.astype(np.float64), cell.theta,
+                            v[n0:n1].astype(np.float64), float(eb[c]))
+        assert force_rel_err(yb[n0:n1], yo) <= F_TOL, c
+        assert force_rel_err(tb[c], to) <= F_TOL, c
