@@ -85,3 +85,63 @@ def test_full_workload_graph_replay_against_oracle():
         assert err[0] <= TOL and err[1] <= E_TOL, (c, err)
         assert err[2] <= TOL and err[3] <= TOL, (c, err)
     print("worst force, energy, ybar, thetabar:", worst.tolist(), flush=True)
+
+
+def _hertz(theta, top, radius=1.0):
+    """Hertz force of a sphere between two plates for parameters theta
+    (n, 3), d = R - top: F = (4/3) E / (1 - nu^2) sqrt(R/2) (d/2)^(3/2), with
+    E, nu from mu, kappa by the small-strain relations."""
+    mu, kappa = theta[:, 0], theta[:, 1]
+    E = 9 * kappa * mu / (3 * kappa + mu)
+    nu = (3 * kappa - 2 * mu) / (2 * (3 * kappa + mu))
+    d = np.clip(radius - np.asarray(top), 0, None)[:, None]
+    return (4.0 / 3.0 * (E / (1 - nu ** 2))[None, :] * np.sqrt(radius / 2)
+            * (d / 2) ** 1.5)
+
+
+@pytest.mark.timeout(900)
+def test_plate_compression_full_workload_against_oracle():
+    """256 spheres of ~51k tetrahedra, 200 plate steps to 20 % compression,
+    checkpoint every 20 (the benchmark's plate-compression run): sampled
+    cells' plate-force trajectories and final positions against the
+    oracle's FP64 replay, and one cell's BPTT gradient against the oracle's
+    forward-mode duals through all steps."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.relax import PlateCompression
+    from synth.configs import (DRAG, K_PLATE, STOKES_DT, compression_batch,
+                               plate_schedule)
+    b = compression_batch(256, 9000, 5000, n_meshes=8)
+    mob = STOKES_DT / DRAG
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    top, bot = plate_schedule(200, compression=0.2)
+    pc = PlateCompression(cb, top, bot, K_PLATE, mob, checkpoint=20)
+    theta0 = b.info["theta0"]
+    pc.set_theta(theta0)
+    y0 = cb.to_device(b.y)
+    F, yN, _ = pc.forward(y0)
+    Fh, yh = F.cpu().numpy(), cb.to_host(yN)
+    for c in (0, 255):
+        cell = b.cell(c)
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        Fo, yo = m.relax_forward(cell.y.astype(np.float64), tuple(theta0[c]),
+                                 top, bot, K_PLATE, mob)
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        ferr = np.abs(Fh[:, c] - Fo).max() / np.abs(Fo).max()
+        yerr = np.abs(yh[n0:n1] - yo).max() / np.abs(yo).max()
+        print(f"cell {c}: plate force {ferr:.2e}, final positions {yerr:.2e}",
+              flush=True)
+        assert ferr <= TOL and yerr <= TOL, c
+    Ft = _hertz(b.info["theta_star"], top)
+    scale = 1.0 / (200 * b.n_cells)
+    loss, g, _ = pc.gradient(y0, torch.from_numpy(Ft).to(cb.device), scale)
+    g = g.cpu().numpy()
+    assert np.isfinite(g).all() and np.isfinite(loss)
+    c = 128
+    cell = b.cell(c)
+    m = oracle.OracleMesh(cell.x, cell.tets)
+    _, gc, _ = m.relax_grad(cell.y.astype(np.float64), tuple(theta0[c]), top,
+                            bot, K_PLATE, mob, Ft[:, c], scale)
+    err = np.abs(g[c] - gc).max() / np.abs(gc).max()
+    print(f"cell {c}: gradient {g[c]} oracle {gc} err {err:.2e}", flush=True)
+    assert err <= TOL
