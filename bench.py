@@ -34,8 +34,10 @@ HBM_PEAK_GBS = 8000.0
 # Vector FMA issue rate with packed FP32 disabled: 256 CUs x 4 SIMDs x 16
 # lanes x 2 flops x 2.4 GHz (FP32 and FP64 alike).
 ALU_PEAK_TFLOPS = 78.6
-# Algorithmic flops per tetrahedron (survey estimate: forward ~350, backward
-# ~2.5x forward ~900).
+# Algorithmic flops per tetrahedron, counted on the method's operations:
+# forward ~350 (deformation gradient, invariants, closed-form stress, P B^T),
+# backward ~900 (the same plus the stress derivative along the direction and
+# the parameter terms, ~2.5x the forward).
 FWD_FLOPS, BWD_FLOPS = 350, 900
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # Algorithmic bytes per tetrahedron and per node (int32 indices, float32
