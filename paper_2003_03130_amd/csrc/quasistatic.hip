@@ -20,28 +20,29 @@ namespace {
 
 constexpr int kThreads = 1024;
 
+// Workgroup sum in a fixed order: a butterfly inside each wavefront (every
+// lane ends with the same bits), then every thread adds the wavefront totals
+// in wavefront order.  red: at least kThreads / 64 doubles of LDS.
 __device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < kThreads / 64; ++w) r += red[w];
+  __syncthreads();  // red is reused by the next reduction
   return r;
 }
 
 __device__ double block_max(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = fmax(red[t], red[t + s]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < kThreads / 64; ++w) r = fmax(r, red[w]);
   __syncthreads();
   return r;
 }

@@ -8,7 +8,7 @@
 // with f the elastic forces (cm_forces), k the plate penalty and m the
 // mobility (time step over drag).  One workgroup per cell: the cell's nodes
 // are contiguous in the internal order; each thread walks a fixed strided
-// subset and the per-cell force is reduced in a fixed tree order, so the
+// subset and the per-cell force is reduced in a fixed order, so the
 // result is deterministic.
 #include <hip/hip_runtime.h>
 
@@ -30,15 +30,17 @@ struct StepArgs {
   double* force;
 };
 
+// Workgroup sum in a fixed order: a butterfly inside each wavefront, then
+// the wavefront totals in wavefront order (deterministic).
 __device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kRelaxThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  return red[0];
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < kRelaxThreads / 64; ++w) r += red[w];
+  return r;
 }
 
 __global__ __launch_bounds__(kRelaxThreads) void plate_step_kernel(StepArgs a) {
