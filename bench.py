@@ -568,8 +568,9 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the batched cell-force path "
-              "has no multi-GPU mode (cells shard independently; see the "
-              "design notes). Run with --gpus 1.", file=sys.stderr)
+              "has no multi-GPU mode (cells are independent, so a batch would "
+              "shard by cell, one process per GPU). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
