@@ -42,8 +42,12 @@ struct cm_batch_s {
   int32_t n_regions = 1;
   int64_t n_mat = 0;  // material slots: n_cells * n_regions
   // shape diagnostics scratch
-  const int4* pair_blocks = nullptr;
-  int64_t n_pair_blocks = 0;
+  const int4* cand_blocks = nullptr;  // block pairs among candidate nodes
+  int64_t n_cand_blocks = 0;
+  const int4* rest_blocks = nullptr;  // the other block pairs
+  int64_t n_rest_blocks = 0;
+  int32_t* shape_tile_inv = nullptr;
+  int32_t* shape_cell_inv = nullptr;
   const int2* node_blocks = nullptr;
   int64_t n_node_blocks = 0;
   const int32_t* space_order = nullptr;
@@ -231,32 +235,42 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
         (rc = h->alloc(&tile_acc_b, 3 * (size_t)h->n_tiles)) ||
         (rc = h->alloc(&tile_ninv, (size_t)h->n_tiles)))
       return bail(rc);
-    // 256 x 256 node-pair blocks of every cell (row block <= column block)
-    std::vector<int4> pb;
+    // 256 x 256 node-pair blocks of every cell (row block <= column block);
+    // the cell's nodes are ordered candidates first, so the pairs of the
+    // first ceil(candidates / 256) blocks hold every candidate pair
+    std::vector<int4> pc, pr;
     std::vector<int2> nbk;
     for (int64_t c = 0; c < h->n_cells; ++c) {
       const int64_t nb = (P.node_off[c + 1] - P.node_off[c] + 255) / 256;
+      int64_t bc = ((int64_t)P.cell_candidates[c] + 255) / 256;
+      if (bc <= 0) bc = nb;
       const int base = (int)nbk.size();
       for (int64_t i = 0; i < nb; ++i) {
         nbk.push_back(make_int2((int)c, (int)i));
         for (int64_t j = i; j < nb; ++j)
-          pb.push_back(make_int4((int)c, (int)i, (int)j, base));
+          (j < bc ? pc : pr).push_back(make_int4((int)c, (int)i, (int)j, base));
       }
     }
-    int4* pbd;
+    int4 *pcd, *prd;
     int2* nbd;
-    int32_t* sord;
+    int32_t *sord, *tinv, *cinv;
     double *mom, *bbox;
     unsigned long long* d2;
-    if ((rc = h->upload(&pbd, pb, stream)) ||
+    if ((rc = h->upload(&pcd, pc, stream)) || (rc = h->upload(&prd, pr, stream)) ||
         (rc = h->upload(&sord, P.space_order, stream)) ||
         (rc = h->upload(&nbd, nbk, stream)) ||
         (rc = h->alloc(&bbox, 6 * nbk.size())) ||
         (rc = h->alloc(&mom, 10 * (size_t)h->n_tiles)) ||
+        (rc = h->alloc(&tinv, (size_t)h->n_tiles)) ||
+        (rc = h->alloc(&cinv, (size_t)h->n_cells)) ||
         (rc = h->alloc(&d2, (size_t)h->n_cells)))
       return bail(rc);
-    h->pair_blocks = pbd;
-    h->n_pair_blocks = (int64_t)pb.size();
+    h->cand_blocks = pcd;
+    h->n_cand_blocks = (int64_t)pc.size();
+    h->rest_blocks = prd;
+    h->n_rest_blocks = (int64_t)pr.size();
+    h->shape_tile_inv = tinv;
+    h->shape_cell_inv = cinv;
     h->node_blocks = nbd;
     h->n_node_blocks = (int64_t)nbk.size();
     h->shape_bbox = bbox;
@@ -828,9 +842,10 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
   if (cm::shape_lds(h->T.nloc) > 65536)
     return fail(CM_EINVAL, "tiles too large for the shape kernel's LDS");
   if (int rc = select_device(h)) return rc;
-  CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->pair_blocks, h->n_pair_blocks,
+  CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->cand_blocks, h->n_cand_blocks,
+                          h->rest_blocks, h->n_rest_blocks,
                           h->node_blocks, h->n_node_blocks, h->space_order, y, d_ref,
-                          h->shape_mom,
+                          h->shape_mom, h->shape_tile_inv, h->shape_cell_inv,
                           h->shape_bbox, h->d2max, out, stream));
   return CM_OK;
 }

@@ -19,11 +19,13 @@ namespace cm {
 constexpr int kShapeFields = 10;
 size_t shape_lds(int nloc);
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
-                        const int4* pair_blocks, int64_t n_pair_blocks,
+                        const int4* cand_blocks, int64_t n_cand_blocks,
+                        const int4* rest_blocks, int64_t n_rest_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
                         const int32_t* order, const float* y, const double* d_ref,
-                        double* mom, double* bbox, unsigned long long* d2max,
-                        double* out, hipStream_t st);
+                        double* mom, int32_t* tile_inv, int32_t* cell_inv,
+                        double* bbox, unsigned long long* d2max, double* out,
+                        hipStream_t st);
 
 // Quasi-static plate compression (one workgroup per cell): Newton residual,
 // one conjugate-gradient iteration, bounded Newton update, plate predictor.

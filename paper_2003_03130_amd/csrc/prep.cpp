@@ -5,6 +5,7 @@
 #include "prep.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -26,7 +27,10 @@ struct CellOut {
   std::vector<int32_t> shared_slot_ptr;
   std::vector<int32_t> shared_slots;  // local slot ids
   std::vector<int64_t> new_to_old;    // local
-  std::vector<int32_t> space_order;   // local internal ids by Morton code of the node
+  std::vector<int32_t> space_order;   // local internal ids: candidates of the
+                                      // largest node distance first, each part
+                                      // in Morton order of the node
+  int32_t n_candidates = 0;           // leading entries of space_order
   std::vector<int32_t> tile_region;   // region of every tile
   std::vector<int32_t> region_tile_first, region_tile_count;  // local tiles
   int32_t max_tile_nodes = 0;
@@ -455,10 +459,47 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
       }
       code[newid[v]] = cd;
     }
+    // Candidates for the largest node distance: the two nodes of a cell that
+    // are farthest apart are vertices of the convex hull of its nodes, and a
+    // node whose faces are each shared by exactly two tetrahedra (its link is
+    // a closed surface) lies inside the image of its star while all those
+    // tetrahedra keep their orientation, so it is no hull vertex.  The others
+    // (on a boundary or non-manifold face, or in no tetrahedron) come first.
+    std::vector<uint8_t> cand(n, 0);
+    {
+      std::vector<std::array<int32_t, 3>> faces((size_t)4 * m);
+      for (int64_t t = 0; t < m; ++t)
+        for (int f = 0; f < 4; ++f) {
+          std::array<int32_t, 3> k;
+          for (int a = 0, q = 0; a < 4; ++a)
+            if (a != f) k[q++] = T[4 * t + a];
+          std::sort(k.begin(), k.end());
+          faces[(size_t)4 * t + f] = k;
+        }
+      std::sort(faces.begin(), faces.end());
+      std::vector<uint8_t> referenced(n, 0);
+      for (int64_t q = 0; q < 4 * m; ++q) referenced[T[q]] = 1;
+      for (size_t i = 0; i < faces.size();) {
+        size_t j = i + 1;
+        while (j < faces.size() && faces[j] == faces[i]) ++j;
+        if (j - i != 2)
+          for (int a = 0; a < 3; ++a) cand[faces[i][a]] = 1;
+        i = j;
+      }
+      for (int64_t v = 0; v < n; ++v)
+        if (!referenced[v]) cand[v] = 1;
+    }
+    std::vector<uint8_t> cand_new(n);
+    for (int64_t v = 0; v < n; ++v) cand_new[newid[v]] = cand[v];
     out.space_order.resize(n);
     std::iota(out.space_order.begin(), out.space_order.end(), 0);
     std::stable_sort(out.space_order.begin(), out.space_order.end(),
-                     [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+                     [&](int32_t a, int32_t b) {
+                       if (cand_new[a] != cand_new[b]) return cand_new[a] > cand_new[b];
+                       return code[a] < code[b];
+                     });
+    out.n_candidates = 0;
+    for (int64_t v = 0; v < n; ++v) out.n_candidates += cand[v];
   }
 
   // Tiles, slots and chunks.
@@ -665,6 +706,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
   P->node_off.assign(node_off, node_off + n_cells + 1);
   P->new_to_old.resize(P->n_nodes);
   P->space_order.resize(P->n_nodes);
+  P->cell_candidates.resize(n_cells);
   P->n_regions = n_regions;
   P->tile_mat.resize(n_tiles);
   P->mat_tile_first.resize((size_t)n_cells * n_regions);
@@ -706,6 +748,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
       P->new_to_old[nb + v] = cell.new_to_old[v] + nb;
     for (size_t v = 0; v < cell.space_order.size(); ++v)
       P->space_order[nb + v] = cell.space_order[v] + nb;
+    P->cell_candidates[c] = cell.n_candidates;
     P->volume += cell.volume;
     P->min_v0 = std::min(P->min_v0, cell.min_v0);
     P->max_cond = std::max(P->max_cond, cell.max_cond);
@@ -779,6 +822,7 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   P->shared_slot_ptr.resize(C * H1 + 1);
   P->new_to_old.resize(C * N);
   P->space_order.resize(C * N);
+  P->cell_candidates.assign(C, one.cell_candidates[0]);
   P->node_off.resize(C + 1);
   P->cell_shared_off.resize(C + 1);
   P->cell_tile_first.resize(C);

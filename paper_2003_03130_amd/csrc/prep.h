@@ -37,8 +37,12 @@ struct Prepared {
   std::vector<int32_t> cell_shared_off;  // n_cells + 1
   std::vector<int64_t> node_off;         // n_cells + 1 (same as input)
   std::vector<int64_t> new_to_old;       // n_nodes
-  std::vector<int32_t> space_order;      // n_nodes: per cell, internal ids in
-                                         // Morton order of the reference node
+  std::vector<int32_t> space_order;      // n_nodes: per cell, internal ids,
+                                         // the cell's candidates for the
+                                         // largest node distance first, each
+                                         // part in Morton order of the
+                                         // reference node
+  std::vector<int32_t> cell_candidates;  // n_cells: leading candidates
   int32_t max_tile_nodes = 0;
   double volume = 0.0, min_v0 = 0.0, max_cond = 0.0;
 };

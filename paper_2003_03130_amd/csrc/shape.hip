@@ -7,14 +7,16 @@
 //   shape_moments_kernel  one wavefront per tile: the current signed volume
 //                         V of every tetrahedron and its centroid r, summed
 //                         as V, V r and V r r^T (float64) about a per-cell
-//                         origin (the cell's first node), one record per tile;
+//                         origin (the cell's first node), one record per tile,
+//                         and the tile's count of tetrahedra with V not > 0;
 //   shape_extreme_kernel  per cell, the nodes extreme along the three axes and
 //                         the four body diagonals; the largest distance among
 //                         these pairs is a lower bound L of d_max (the
 //                         distance of two actual nodes) and starts the maximum;
+//                         and the cell's count of inverted tetrahedra;
 //   shape_bbox_kernel     the bounding box of every block of 256 nodes, the
-//                         nodes of a cell taken in Morton order of their
-//                         reference positions (compact blocks);
+//                         nodes of a cell taken candidates first (below), each
+//                         part in Morton order of the reference positions;
 //   pair_max_kernel       the largest squared distance between two nodes of
 //                         a cell, over 256 x 256 blocks of node pairs (float64
 //                         differences of the float32 positions are exact; the
@@ -22,7 +24,16 @@
 //                         integer maximum of their bit patterns); a block pair
 //                         whose bounding boxes are closer than the current
 //                         maximum cannot hold a larger distance and is skipped
-//                         (the result is the same, only the work changes);
+//                         (the result is the same, only the work changes).
+//                         It runs over the block pairs of the candidate nodes
+//                         (leading blocks), then over the other block pairs
+//                         only for cells with an inverted tetrahedron: the
+//                         farthest two nodes are convex-hull vertices, and a
+//                         node whose faces are all shared by two tetrahedra
+//                         lies inside the image of its star while those keep
+//                         their orientation (their solid angles at the node
+//                         sum to a positive multiple of 4 pi, so no direction
+//                         has the node strictly beyond all its neighbours);
 //   shape_finalize_kernel per cell: tile records summed in tile order, the
 //                         inertia tensor about the centre of mass, its
 //                         eigenvalues by cyclic Jacobi rotations, semi-axes,
@@ -47,7 +58,8 @@ struct MomArgs {
   DeviceTables T;
   const int64_t* node_off;
   const float* y;
-  double* mom;  // kMom per tile
+  double* mom;        // kMom per tile
+  int32_t* tile_inv;  // per tile: tetrahedra whose current volume is not > 0
 };
 
 __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
@@ -67,6 +79,7 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
   double m[kMom];
 #pragma unroll
   for (int j = 0; j < kMom; ++j) m[j] = 0.0;
+  int ninv = 0;
   const TetChunk* ch = a.T.chunks + d.chunk_begin;
   for (int k = 0; k < d.n_chunks; ++k) {
     const uint2 q = *reinterpret_cast<const uint2*>(ch[k].idx[lane]);
@@ -92,6 +105,7 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
     // current volume with the orientation of the reference vertex order
     // (det B = 1 / det of the reference edges)
     const double V = (det_b > 0.0 ? det_s : -det_s) * (1.0 / 6.0);
+    ninv += V > 0.0 ? 0 : 1;
     const double rx = 0.25 * (((double)p[0].x + (double)p[1].x) +
                               ((double)p[2].x + (double)p[3].x)) - ox;
     const double ry = 0.25 * (((double)p[0].y + (double)p[1].y) +
@@ -105,9 +119,11 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
   }
 #pragma unroll
   for (int j = 0; j < kMom; ++j) m[j] = wave_sum(m[j]);
+  ninv = wave_sum(ninv);
   if (lane == 0) {
 #pragma unroll
     for (int j = 0; j < kMom; ++j) a.mom[(int64_t)kMom * t + j] = m[j];
+    a.tile_inv[t] = ninv;
   }
 }
 
@@ -119,6 +135,7 @@ struct PairArgs {
   int64_t N;
   const double* bbox;         // per node block: min x y z, max x y z
   unsigned long long* d2max;  // per cell, bits of a non-negative double
+  const int32_t* gate;        // nullable: only cells with gate[c] != 0
 };
 
 // Directions of the extreme-node search: the axes and the body diagonals.
@@ -126,21 +143,35 @@ __constant__ float kDirs[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 1},
                                   {1, 1, -1}, {1, -1, 1}, {-1, 1, 1}};
 
 struct ExtArgs {
+  DeviceTables T;
   const int64_t* node_off;
   const float* y;
   int64_t N;
   unsigned long long* d2max;
+  const int32_t* tile_inv;
+  int32_t* cell_inv;  // per cell: tetrahedra whose current volume is not > 0
 };
 
 // Per cell: for every direction the node of smallest and of largest
 // projection (ties to the smaller index), then d2max = the largest squared
-// distance among those pairs.
+// distance among those pairs; and the cell's count of tetrahedra that are
+// inverted (or degenerate) in the current positions.
 __global__ __launch_bounds__(256) void shape_extreme_kernel(ExtArgs a) {
   __shared__ double rv[256];
   __shared__ int64_t ri[256];
   __shared__ int64_t ext[14];
+  __shared__ int inv[4];
   const int c = blockIdx.x, tid = threadIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  {
+    int s = 0;
+    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
+    for (int k = tid; k < nt; k += 256) s += a.tile_inv[t0 + (int64_t)k * a.T.tile_stride];
+    s = wave_sum(s);
+    if ((tid & 63) == 0) inv[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) a.cell_inv[c] = inv[0] + inv[1] + inv[2] + inv[3];
+  }
   for (int d = 0; d < 7; ++d)
     for (int side = 0; side < 2; ++side) {  // 0: min, 1: max
       double best = side ? -INFINITY : INFINITY;
@@ -225,6 +256,7 @@ __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
   __shared__ int skip;
   const int4 b = a.blocks[blockIdx.x];
   const int tid = threadIdx.x;
+  if (a.gate && a.gate[b.x] == 0) return;  // uniform over the workgroup
   if (tid == 0) {
     // farthest points of the two bounding boxes vs the current maximum
     const double* r = a.bbox + 6 * (int64_t)(b.w + b.y);
@@ -355,32 +387,40 @@ __global__ __launch_bounds__(256) void shape_finalize_kernel(ShapeFinArgs a) {
 size_t shape_lds(int nloc) { return (size_t)16 * nloc; }
 
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
-                        const int4* pair_blocks, int64_t n_pair_blocks,
+                        const int4* cand_blocks, int64_t n_cand_blocks,
+                        const int4* rest_blocks, int64_t n_rest_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
                         const int32_t* order, const float* y, const double* d_ref,
-                        double* mom, double* bbox, unsigned long long* d2max,
-                        double* out, hipStream_t st) {
+                        double* mom, int32_t* tile_inv, int32_t* cell_inv,
+                        double* bbox, unsigned long long* d2max, double* out,
+                        hipStream_t st) {
   const int nc = T.n_cells;
-  ExtArgs x{node_off, y, T.n_nodes, d2max};
+  hipError_t e;
+  if (T.n_tiles > 0) {
+    MomArgs m{T, node_off, y, mom, tile_inv};
+    hipLaunchKernelGGL(shape_moments_kernel, dim3((unsigned)T.n_tiles), dim3(64),
+                       shape_lds(T.nloc), st, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  ExtArgs x{T, node_off, y, T.n_nodes, d2max, tile_inv, cell_inv};
   hipLaunchKernelGGL(shape_extreme_kernel, dim3(nc), dim3(256), 0, st, x);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (n_node_blocks > 0) {
     BoxArgs bx{node_blocks, node_off, order, y, T.n_nodes, bbox};
     hipLaunchKernelGGL(shape_bbox_kernel, dim3((unsigned)n_node_blocks), dim3(256), 0,
                        st, bx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (n_pair_blocks > 0) {
-    PairArgs p{pair_blocks, node_off, order, y, T.n_nodes, bbox, d2max};
-    hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_pair_blocks), dim3(256), 0,
+  if (n_cand_blocks > 0) {
+    PairArgs p{cand_blocks, node_off, order, y, T.n_nodes, bbox, d2max, nullptr};
+    hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_cand_blocks), dim3(256), 0,
                        st, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (T.n_tiles > 0) {
-    MomArgs m{T, node_off, y, mom};
-    hipLaunchKernelGGL(shape_moments_kernel, dim3((unsigned)T.n_tiles), dim3(64),
-                       shape_lds(T.nloc), st, m);
+  if (n_rest_blocks > 0) {
+    PairArgs p{rest_blocks, node_off, order, y, T.n_nodes, bbox, d2max, cell_inv};
+    hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_rest_blocks), dim3(256), 0,
+                       st, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   ShapeFinArgs f{T, node_off, y, mom, d2max, d_ref, out};

@@ -86,3 +86,39 @@ def test_large_cell_many_pair_blocks():
     assert abs(out[0] - ref["volume"]) <= 1e-12 * ref["volume"]
     assert np.abs(out[4:7] - ref["axes"]).max() <= 1e-10
     assert abs(out[8] - ref["d_max"]) <= 1e-12 * ref["d_max"]
+
+
+def _interior_nodes(tets, n):
+    """Nodes of a cell none of whose faces lies on the boundary (every face
+    shared by exactly two tetrahedra)."""
+    f = np.sort(np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]],
+                                tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]]), axis=1)
+    _, inv, cnt = np.unique(f, axis=0, return_inverse=True, return_counts=True)
+    bad = np.zeros(n, bool)
+    bad[f[cnt[inv.ravel()] != 2].ravel()] = True
+    used = np.zeros(n, bool)
+    used[tets.ravel()] = True
+    return np.flatnonzero(used & ~bad)
+
+
+def test_inverted_cell_searches_all_node_pairs():
+    """The pair search takes only boundary (and non-manifold or unused)
+    nodes while a cell has no inverted tetrahedron; two interior nodes moved
+    far out on opposite sides invert their tetrahedra and become the
+    farthest pair, which the search must still find (the other cells keep
+    the restricted search)."""
+    from paper_2003_03130_amd import CellBatch
+    b = uneven_batch(n_cells=3, seed=83, tet_lo=8000, tet_hi=12000, ladder=3)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    y = b.y.copy()
+    c = 1
+    n0, n1 = b.node_off[c], b.node_off[c + 1]
+    t0, t1 = b.tet_off[c], b.tet_off[c + 1]
+    inner = _interior_nodes(b.tets[t0:t1], n1 - n0)
+    centre = b.x[n0:n1].mean(axis=0)
+    near = inner[np.argsort(np.linalg.norm(b.x[n0:n1][inner] - centre, axis=1))[:2]]
+    y[n0 + near[0]] = centre + np.array([5.0, 0.0, 0.0])
+    y[n0 + near[1]] = centre - np.array([5.0, 0.0, 0.0])
+    d_ref = np.full(b.n_cells, 2.0)
+    out = _check(cb, b, y, d_ref)
+    assert abs(out[c, 8] - 10.0) <= 1e-5
