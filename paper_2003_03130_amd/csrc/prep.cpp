@@ -461,29 +461,48 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
     }
     // Candidates for the largest node distance: the two nodes of a cell that
     // are farthest apart are vertices of the convex hull of its nodes, and a
-    // node whose faces are each shared by exactly two tetrahedra (its link is
-    // a closed surface) lies inside the image of its star while all those
-    // tetrahedra keep their orientation, so it is no hull vertex.  The others
-    // (on a boundary or non-manifold face, or in no tetrahedron) come first.
+    // node whose faces are each shared by exactly two tetrahedra on opposite
+    // sides (its link is a closed, consistently oriented surface) lies inside
+    // the image of its star while all those tetrahedra keep their
+    // orientation, so it is no hull vertex.  The others (on a boundary face,
+    // a face of one orientation shared more than once, or in no tetrahedron)
+    // come first.
     std::vector<uint8_t> cand(n, 0);
     {
-      std::vector<std::array<int32_t, 3>> faces((size_t)4 * m);
-      for (int64_t t = 0; t < m; ++t)
+      // per face: sorted vertex triple and its orientation induced by the
+      // tetrahedron (the reference orientation of the tetrahedron, the sign
+      // of the face in its boundary, and the parity of the sort)
+      struct Face { std::array<int32_t, 3> k; int8_t o; };
+      std::vector<Face> faces((size_t)4 * m);
+      for (int64_t t = 0; t < m; ++t) {
+        const int32_t* v = T + 4 * t;
+        double e[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int i = 0; i < 3; ++i) e[a][i] = X[3 * v[a + 1] + i] - X[3 * v[0] + i];
+        const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                           e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+        const int so = det > 0 ? 1 : -1;
         for (int f = 0; f < 4; ++f) {
           std::array<int32_t, 3> k;
           for (int a = 0, q = 0; a < 4; ++a)
-            if (a != f) k[q++] = T[4 * t + a];
-          std::sort(k.begin(), k.end());
-          faces[(size_t)4 * t + f] = k;
+            if (a != f) k[q++] = v[a];
+          int par = 1;  // parity of the sort of three entries
+          if (k[0] > k[1]) { std::swap(k[0], k[1]); par = -par; }
+          if (k[1] > k[2]) { std::swap(k[1], k[2]); par = -par; }
+          if (k[0] > k[1]) { std::swap(k[0], k[1]); par = -par; }
+          faces[(size_t)4 * t + f] = Face{k, (int8_t)(so * (f % 2 ? -1 : 1) * par)};
         }
-      std::sort(faces.begin(), faces.end());
+      }
+      std::sort(faces.begin(), faces.end(),
+                [](const Face& a, const Face& b) { return a.k < b.k; });
       std::vector<uint8_t> referenced(n, 0);
       for (int64_t q = 0; q < 4 * m; ++q) referenced[T[q]] = 1;
       for (size_t i = 0; i < faces.size();) {
         size_t j = i + 1;
-        while (j < faces.size() && faces[j] == faces[i]) ++j;
-        if (j - i != 2)
-          for (int a = 0; a < 3; ++a) cand[faces[i][a]] = 1;
+        while (j < faces.size() && faces[j].k == faces[i].k) ++j;
+        if (!(j - i == 2 && faces[i].o != faces[i + 1].o))
+          for (int a = 0; a < 3; ++a) cand[faces[i].k[a]] = 1;
         i = j;
       }
       for (int64_t v = 0; v < n; ++v)

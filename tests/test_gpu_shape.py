@@ -122,3 +122,19 @@ def test_inverted_cell_searches_all_node_pairs():
     d_ref = np.full(b.n_cells, 2.0)
     out = _check(cb, b, y, d_ref)
     assert abs(out[c, 8] - 10.0) <= 1e-5
+
+
+def test_duplicated_tetrahedron_keeps_its_nodes_in_the_search():
+    """A face shared by two tetrahedra on the same side (a duplicated
+    tetrahedron) does not make its nodes interior: a cell of a doubled unit
+    tetrahedron and a separate one 3 R away, nothing inverted, has its
+    farthest pair between the two parts."""
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import batch_from_cells, Cell
+    unit = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], np.float64)
+    x = np.concatenate([unit, unit + np.array([3.0, 0.0, 0.0])])
+    tets = np.array([[0, 1, 2, 3], [0, 1, 2, 3], [4, 5, 6, 7]], np.int32)
+    b = batch_from_cells([Cell(x, tets, x.astype(np.float32), (1.0, 10.0, 0.5))])
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    out = _check(cb, b, b.y, np.array([2.0]))
+    assert abs(out[0, 8] - np.sqrt(17.0)) <= 1e-12 * np.sqrt(17.0)
