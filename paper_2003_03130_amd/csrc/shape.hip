@@ -30,14 +30,15 @@
 //                         only for cells with an inverted tetrahedron: the
 //                         farthest two nodes are convex-hull vertices, and a
 //                         node whose faces are all shared by two tetrahedra
-//                         lies inside the image of its star while those keep
-//                         their orientation (their solid angles at the node
-//                         sum to a positive multiple of 4 pi, so no direction
-//                         has the node strictly beyond all its neighbours);
-//   shape_finalize_kernel per cell: tile records summed in tile order, the
-//                         inertia tensor about the centre of mass, its
-//                         eigenvalues by cyclic Jacobi rotations, semi-axes,
-//                         D, d_max and the strain.
+//                         on opposite sides lies inside the image of its star
+//                         while those keep their orientation (their solid
+//                         angles at the node sum to a positive multiple of
+//                         4 pi, so no direction has the node strictly beyond
+//                         all its neighbours);
+//   shape_finalize_kernel per cell (one wavefront): tile records summed in a
+//                         fixed order, the inertia tensor about the centre of
+//                         mass, its eigenvalues by cyclic Jacobi rotations,
+//                         semi-axes, D, d_max and the strain.
 // Readings: the tensor is taken about the centre of mass; V is the current
 // volume with the reference orientation (negative when inverted); the
 // paper's semi-axis formula gives squared semi-axes of a solid ellipsoid, so
@@ -342,16 +343,24 @@ struct ShapeFinArgs {
   double* out;          // kShapeFields per cell
 };
 
+// One wavefront per cell: lane l sums the tile records l, l + 64, ...,
+// then a fixed butterfly; lane 0 finishes the cell.
 __global__ __launch_bounds__(256) void shape_finalize_kernel(ShapeFinArgs a) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.T.n_cells) return;
+  const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= a.T.n_cells) return;  // uniform per wavefront
   double m[kMom];
+#pragma unroll
   for (int j = 0; j < kMom; ++j) m[j] = 0.0;
   const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
-  for (int k = 0; k < nt; ++k) {
+  for (int k = lane; k < nt; k += 64) {
     const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
+#pragma unroll
     for (int j = 0; j < kMom; ++j) m[j] += a.mom[kMom * t + j];
   }
+#pragma unroll
+  for (int j = 0; j < kMom; ++j) m[j] = wave_sum(m[j]);
+  if (lane != 0) return;
   const int64_t N = a.T.n_nodes, o = a.node_off[c];
   const double M = m[0];
   const double cx = m[1] / M, cy = m[2] / M, cz = m[3] / M;
@@ -424,7 +433,7 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   ShapeFinArgs f{T, node_off, y, mom, d2max, d_ref, out};
-  hipLaunchKernelGGL(shape_finalize_kernel, dim3((nc + 255) / 256), dim3(256), 0, st, f);
+  hipLaunchKernelGGL(shape_finalize_kernel, dim3((nc + 3) / 4), dim3(256), 0, st, f);
   return hipGetLastError();
 }
 
