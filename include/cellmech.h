@@ -336,7 +336,8 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  *   y_trial -> E_trial); cm_qs_ls_accept while some cell is pending.
  * Arrays (device, SoA float32[3 n_nodes]): r (residual), p (search
  * direction), x (Newton step), Ap (scratch), r_newton (copy of r_N,
- * nullable), y_trial; state: float64[16 n_cells] = CG |r|^2, CG |r_0|^2, CG
+ * nullable), y_trial; state: float64[16 n_cells] = CG r . z (|r|^2 without
+ * preconditioner), CG |r_0|^2, CG
  * active, |r_N|^2, accepted step scale, |penalty|^2, largest node move of
  * the last step, float32 floor rho, Pi(y), line-search scale, slope
  * r_N . x, not in equilibrium (1/0), line search pending (1/0), max |x|,
@@ -364,8 +365,23 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  *     +-|y| 2^-24 per coordinate (half a unit in the last place, signs from
  *     a fixed hash of the index), then after ybar = cm_forces_backward(y,
  *     fbar = e), rho = |Hess(Pi) e|_2 per cell, stored in the state.
- *   cm_qs_cg_step: one CG iteration for every active cell; a cell stops at
- *     |r| <= max(rel_tol, eta) |r_0| or at non-positive curvature.
+ *   cm_qs_stiffness: k_el (device float32[6 n_nodes] SoA: xx, yy, zz, xy,
+ *     xz, yz) = per node the sum over its tetrahedra of the diagonal 3x3
+ *     block of the small-strain stiffness, V0 (mu |b|^2 I + (kappa + mu/3)
+ *     b b^T) with b the node's row of the tetrahedron's gradient operator
+ *     (B's rows, minus their sum for vertex 4) and (mu, kappa) of its
+ *     material slot: the small-strain limit of the energy (shear modulus
+ *     mu, bulk modulus kappa), used as a block-Jacobi preconditioner.
+ *     Uses the forward scratch (do not overlap with cm_forces); CM_ESTATE
+ *     before cm_set_params.
+ *   cm_qs_residual with k_el and minv (device float32[6 n_nodes], both or
+ *     neither): minv = the inverse of k_el plus the penalty Hessian per
+ *     node (identity where that block is not positive definite), and the
+ *     CG starts from p = minv r (preconditioned CG).
+ *   cm_qs_cg_step: one CG iteration for every active cell, preconditioned
+ *     by minv (nullable: plain CG; pass the array cm_qs_residual filled); a
+ *     cell stops at |r| <= max(rel_tol, eta) |r_0| or at non-positive
+ *     curvature.
  *   cm_qs_update: y += s x, s = min(1, cap / max_i |x_i|) per cell.
  *   cm_qs_predict: z -> b' + (z - b) s, s = (t' - b') / (t - b), for a new
  *     plate pair (t', b'), and x, y stretched by 1/sqrt(s) about the cell's
@@ -377,8 +393,9 @@ int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* ene
                    const double* plate, double k_plate, double abs_tol,
                    double rel_tol, double step_tol, double floor_factor,
                    double eta_max, int32_t restart, float* r, float* p, float* x,
-                   float* r_newton, double* state, double* force,
-                   hipStream_t stream);
+                   float* r_newton, double* state, double* force, const float* k_el,
+                   float* minv, hipStream_t stream);
+int cm_qs_stiffness(cm_batch h, float* k_el, hipStream_t stream);
 int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
                    const float* y, float* y_trial, double* state,
                    hipStream_t stream);
@@ -390,7 +407,7 @@ int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
                 const float* e, const float* ybar, double* state, hipStream_t stream);
 int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
                   double rel_tol, const float* ybar, float* x, float* r, float* p,
-                  float* Ap, double* state, hipStream_t stream);
+                  float* Ap, double* state, const float* minv, hipStream_t stream);
 int cm_qs_update(cm_batch h, const float* x, double cap, float* y, double* state,
                  hipStream_t stream);
 int cm_qs_predict(cm_batch h, const double* plate_old, const double* plate_new,

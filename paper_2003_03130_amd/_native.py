@@ -105,7 +105,8 @@ SIGNATURES = {
     "cm_qs_residual": (_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, _i32, _vp, _vp,
-                              _vp, _vp, _vp, _vp, _vp]),
+                              _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cm_qs_stiffness": (_int, [_vp, _vp, _vp]),
     "cm_qs_ls_start": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
                               _vp]),
     "cm_qs_ls_accept": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp,
@@ -115,7 +116,7 @@ SIGNATURES = {
     "cm_qs_floor": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
                            _vp]),
     "cm_qs_cg_step": (_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
-                             _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_update": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "cm_qs_predict": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "cm_layout_sizes": (_int, [_vp, _p64]),

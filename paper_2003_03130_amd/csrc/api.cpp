@@ -704,11 +704,13 @@ int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* ene
                    const double* plate, double k_plate, double abs_tol,
                    double rel_tol, double step_tol, double floor_factor,
                    double eta_max, int32_t restart, float* r, float* p, float* x,
-                   float* r_newton, double* state, double* force,
-                   hipStream_t stream) {
+                   float* r_newton, double* state, double* force, const float* k_el,
+                   float* minv, hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !f || !plate || !r || !p || !x || !state)
     return fail(CM_EINVAL, "y, f, plate, r, p, x and state must be device pointers");
+  if ((k_el == nullptr) != (minv == nullptr))
+    return fail(CM_EINVAL, "k_el and minv must both be given or both be null");
   if (!std::isfinite(k_plate) || k_plate < 0 || !(abs_tol >= 0) || !(rel_tol >= 0) ||
       !(step_tol >= 0) || !(floor_factor >= 0))
     return fail(CM_EINVAL, "k_plate and tolerances must be finite and >= 0");
@@ -718,7 +720,7 @@ int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* ene
   CM_HIP(cm::launch_qs_residual(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, f,
                                 energy, plate, k_plate, abs_tol, rel_tol, step_tol,
                                 floor_factor, eta_max, restart ? 1 : 0, r, p, x,
-                                r_newton, state, force, stream));
+                                r_newton, state, force, k_el, minv, stream));
   return CM_OK;
 }
 
@@ -774,9 +776,20 @@ int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
   return CM_OK;
 }
 
+int cm_qs_stiffness(cm_batch h, float* k_el, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!k_el) return fail(CM_EINVAL, "k_el must be a device pointer");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if ((size_t)16 * h->T.nloc > 65536)
+    return fail(CM_EINVAL, "tiles too large for the stiffness kernel's LDS");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_stiffness(h->T, full_range(h), k_el, stream));
+  return CM_OK;
+}
+
 int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
                   double rel_tol, const float* ybar, float* x, float* r, float* p,
-                  float* Ap, double* state, hipStream_t stream) {
+                  float* Ap, double* state, const float* minv, hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !plate || !ybar || !x || !r || !p || !Ap || !state)
     return fail(CM_EINVAL, "all arrays must be device pointers");
@@ -784,7 +797,7 @@ int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plat
     return fail(CM_EINVAL, "k_plate and rel_tol must be finite and >= 0");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_cg(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
-                          k_plate, rel_tol, ybar, x, r, p, Ap, state, stream));
+                          k_plate, rel_tol, ybar, x, r, p, Ap, state, minv, stream));
   return CM_OK;
 }
 

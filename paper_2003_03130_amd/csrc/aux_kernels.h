@@ -29,7 +29,8 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
 
 // Quasi-static plate compression (one workgroup per cell): Newton residual,
 // one conjugate-gradient iteration, bounded Newton update, plate predictor.
-// Per-cell state: kQsState float64 = 0 CG |r|^2, 1 CG |r_0|^2, 2 CG active,
+// Per-cell state: kQsState float64 = 0 CG r . z (|r|^2 without
+// preconditioner), 1 CG |r_0|^2, 2 CG active,
 // 3 Newton |r_N|^2, 4 accepted step scale, 5 |penalty|^2, 6 largest node move
 // of the last step, 7 float32 floor of the residual, 8 Pi(y), 9 line-search
 // scale, 10 slope r_N . x, 11 not in equilibrium, 12 line search pending,
@@ -42,7 +43,7 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               double rel_tol, double step_tol, double floor_factor,
                               double eta_max, int restart, float* r, float* p,
                               float* x, float* rn, double* st, double* force,
-                              hipStream_t s);
+                              const float* kel, float* minv, hipStream_t s);
 hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
                               const float* x, const float* rn, double cap,
                               const float* y, float* yt, double* st, hipStream_t s);
@@ -60,7 +61,12 @@ hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
-                        float* p, float* Ap, double* st, hipStream_t s);
+                        float* p, float* Ap, double* st, const float* minv,
+                        hipStream_t s);
+// Small-strain stiffness blocks (the Newton preconditioner), 6 n_nodes
+// floats SoA: xx yy zz xy xz yz; uses the forward scratch.
+hipError_t launch_qs_stiffness(const DeviceTables& T, const Range& r, float* kel,
+                               hipStream_t s);
 hipError_t launch_qs_update(const int64_t* node_off, int64_t N, int32_t n_cells,
                             const float* x, double cap, float* y, double* st,
                             hipStream_t s);

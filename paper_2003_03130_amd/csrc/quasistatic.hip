@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include "aux_kernels.h"
+#include "device_util.h"
+#include "kernels.h"
 
 namespace cm {
 namespace {
@@ -47,6 +49,34 @@ __device__ double block_max(double v, double* red) {
   return r;
 }
 
+// Inverse of the symmetric 3x3 block (xx yy zz xy xz yz) in float64; the
+// identity where the block is not positive definite (unused nodes).
+__device__ void sym3_inverse(const double m[6], float o[6]) {
+  const double c00 = m[1] * m[2] - m[5] * m[5], c11 = m[0] * m[2] - m[4] * m[4];
+  const double c22 = m[0] * m[1] - m[3] * m[3], c01 = m[4] * m[5] - m[3] * m[2];
+  const double c02 = m[3] * m[5] - m[4] * m[1], c12 = m[3] * m[4] - m[0] * m[5];
+  const double det = m[0] * c00 + m[3] * c01 + m[4] * c02;
+  if (!(det > 0.0 && m[0] > 0.0 && c22 > 0.0) || !isfinite(det)) {
+    o[0] = o[1] = o[2] = 1.f;
+    o[3] = o[4] = o[5] = 0.f;
+    return;
+  }
+  const double r = 1.0 / det;
+  o[0] = (float)(c00 * r); o[1] = (float)(c11 * r); o[2] = (float)(c22 * r);
+  o[3] = (float)(c01 * r); o[4] = (float)(c02 * r); o[5] = (float)(c12 * r);
+}
+
+// z = Minv r for node i (Minv SoA: xx yy zz xy xz yz, 6 n_nodes floats).
+__device__ __forceinline__ void apply_minv(const float* mi, int64_t N, int64_t i,
+                                           float rx, float ry, float rz, float& zx,
+                                           float& zy, float& zz) {
+  const float xx = mi[i], yy = mi[N + i], z2 = mi[2 * N + i];
+  const float xy = mi[3 * N + i], xz = mi[4 * N + i], yz = mi[5 * N + i];
+  zx = xx * rx + xy * ry + xz * rz;
+  zy = xy * rx + yy * ry + yz * rz;
+  zz = xz * rx + yz * ry + z2 * rz;
+}
+
 struct ResArgs {
   const int64_t* node_off;
   int64_t N;
@@ -61,6 +91,8 @@ struct ResArgs {
   float* rn;      // copy of the Newton residual (nullable)
   double* st;     // kQsState per cell
   double* force;  // per cell: top, bottom plate force (nullable)
+  const float* kel;  // small-strain stiffness blocks (6 n_nodes), nullable
+  float* minv;       // out with kel: inverse preconditioner blocks (6 n_nodes)
 };
 
 // r = f + p (the negative gradient of Pi) with its components along the
@@ -113,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   tq = block_sum(tq, red);
   ww = block_sum(ww, red);
   const double om = ww > 0.0 ? tq / ww : 0.0;
-  double rr = 0.0, ft = 0.0, fb = 0.0, pp = 0.0, phi = 0.0;
+  double rr = 0.0, rzs = 0.0, ft = 0.0, fb = 0.0, pp = 0.0, phi = 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     double dt, db, pz;
     const double rzd = rz_of(i, dt, db, pz);
@@ -123,8 +155,22 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
     const float ry = (float)((double)a.f[N + i] - my - om * dx);
     const float rz = (float)rzd;
     pp += pz * pz;
+    // preconditioned start direction p = z = M^-1 r, M = stiffness block +
+    // penalty Hessian (2 k (max(0, z - top) + max(0, bottom - z)) on zz)
+    float zx = rx, zy = ry, zz = rz;
+    if (a.kel) {
+      const double blk[6] = {a.kel[i], a.kel[N + i],
+                             a.kel[2 * N + i] + 2.0 * a.k * (dt + db),
+                             a.kel[3 * N + i], a.kel[4 * N + i], a.kel[5 * N + i]};
+      float o[6];
+      sym3_inverse(blk, o);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) a.minv[q * N + i] = o[q];
+      apply_minv(a.minv, N, i, rx, ry, rz, zx, zy, zz);
+    }
     a.r[i] = rx; a.r[N + i] = ry; a.r[2 * N + i] = rz;
-    a.p[i] = rx; a.p[N + i] = ry; a.p[2 * N + i] = rz;
+    a.p[i] = zx; a.p[N + i] = zy; a.p[2 * N + i] = zz;
+    rzs += (double)rx * zx + (double)ry * zy + (double)rz * zz;
     a.x[i] = 0.f; a.x[N + i] = 0.f; a.x[2 * N + i] = 0.f;
     if (a.rn) { a.rn[i] = rx; a.rn[N + i] = ry; a.rn[2 * N + i] = rz; }
     rr += (double)rx * rx + (double)ry * ry + (double)rz * rz;
@@ -132,6 +178,7 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
     fb += a.k * db * db;
   }
   rr = block_sum(rr, red);
+  rzs = block_sum(rzs, red);
   ft = block_sum(ft, red);
   fb = block_sum(fb, red);
   pp = block_sum(pp, red);
@@ -141,8 +188,8 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
     const double fl = a.floor_factor * s[7];
     const double tol2 = fmax(fmax(a.abs_tol * a.abs_tol, a.rel_tol * a.rel_tol * pp), fl * fl);
     if (a.restart) s[6] = __builtin_inf();
-    s[0] = rr;                      // CG residual |r|^2
-    s[1] = rr;                      // its start value
+    s[0] = rzs;                     // CG r . z (|r|^2 without preconditioner)
+    s[1] = rr;                      // |r_0|^2
     const double act = (rr > tol2 && s[6] > a.step_tol) ? 1.0 : 0.0;
     double eta = 0.0;
     if (a.eta_max > 0.0) {
@@ -168,6 +215,80 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   }
 }
 
+// Preconditioner of the Newton systems: the diagonal 3x3 blocks of the
+// small-strain (linear-elastic) stiffness, shear modulus mu and bulk modulus
+// kappa being the small-strain limit of the energy.  Per tetrahedron and
+// vertex a with gradient row b_a (row a of B, b_4 = -(b_1 + b_2 + b_3)) the
+// block is V0 (mu |b_a|^2 I + (kappa + mu/3) b_a b_a^T); one wavefront per
+// tile adds them per node in LDS (the chunk colouring keeps the lanes of a
+// vertex slot on distinct nodes), pass 0 the (xx, yy, zz) entries, pass 1
+// (xy, xz, yz); owned nodes are stored, shared nodes go through the slot
+// partials and the forward finalize pass.
+struct StiffArgs {
+  DeviceTables T;
+  int pass;
+  float* out;  // 3 n_nodes floats (SoA) of this pass
+};
+
+__global__ __launch_bounds__(64) void qs_stiffness_kernel(StiffArgs a) {
+  extern __shared__ float4 acc[];
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x;
+  const TileDesc d = a.T.tiles[t];
+  const int mt = a.T.tile_mat[t], nm = a.T.n_mat;
+  const float mu = (float)a.T.params[mt];
+  const float cb = (float)a.T.params[nm + mt] + mu * (1.f / 3.f);
+  const int64_t N = a.T.n_nodes;
+  for (int l = lane; l < d.n_own + d.n_shr; l += 64) acc[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+  wave_sync();
+  const TetChunk* ch = a.T.chunks + d.chunk_begin;
+  for (int k = 0; k < d.n_chunks; ++k) {
+    const uint2 q = *reinterpret_cast<const uint2*>(ch[k].idx[lane]);
+    if (q.x != kEmptyLane) {
+      const int idx[4] = {(int)(q.x & 0xffff), (int)(q.x >> 16), (int)(q.y & 0xffff),
+                          (int)(q.y >> 16)};
+      float b[4][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) b[r][j] = ch[k].B[3 * r + j][lane];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) b[3][j] = -(b[0][j] + b[1][j] + b[2][j]);
+      const float v0 = ch[k].V0[lane];
+      // vertex slots in order: the lanes of one slot name distinct nodes
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const float* g = b[s];
+        float e0, e1, e2;
+        if (a.pass == 0) {
+          const float nb = mu * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+          e0 = v0 * (nb + cb * g[0] * g[0]);
+          e1 = v0 * (nb + cb * g[1] * g[1]);
+          e2 = v0 * (nb + cb * g[2] * g[2]);
+        } else {
+          e0 = v0 * cb * g[0] * g[1];
+          e1 = v0 * cb * g[0] * g[2];
+          e2 = v0 * cb * g[1] * g[2];
+        }
+        float4 v = acc[idx[s]];
+        v.x += e0; v.y += e1; v.z += e2;
+        acc[idx[s]] = v;
+      }
+    }
+  }
+  wave_sync();
+  for (int i = lane; i < d.n_own; i += 64) {
+    const int64_t g = d.own_begin + i;
+    const float4 v = acc[i];
+    a.out[g] = v.x; a.out[N + g] = v.y; a.out[2 * N + g] = v.z;
+  }
+  for (int j = lane; j < d.n_shr; j += 64) {
+    const float4 v = acc[d.n_own + j];
+    float* pp = a.T.part + 3 * ((int64_t)d.shr_begin + j);
+    pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
+  }
+}
+
 struct CgArgs {
   const int64_t* node_off;
   int64_t N;
@@ -177,12 +298,14 @@ struct CgArgs {
   const float* ybar;  // (df/dy)^T p
   float *x, *r, *p, *Ap;
   double* st;
+  const float* minv;  // preconditioner blocks (6 n_nodes), nullable
 };
 
-// One CG iteration per active cell: Ap = Hess(Pi) p, alpha = |r|^2 / p.Ap,
-// x += alpha p, r -= alpha Ap, beta = |r_new|^2 / |r|^2, p = r + beta p.  A
-// cell stops at |r| <= max(rel_tol, eta) |r_0| (eta the forcing term of the
-// Newton step, 0 without forcing) or on non-positive curvature.
+// One (preconditioned) CG iteration per active cell, z = M^-1 r (z = r
+// without preconditioner): Ap = Hess(Pi) p, alpha = r.z / p.Ap, x += alpha p,
+// r -= alpha Ap, beta = r_new.z_new / r.z, p = z_new + beta p.  A cell stops
+// at |r| <= max(rel_tol, eta) |r_0| (eta the forcing term of the Newton
+// step, 0 without forcing) or on non-positive curvature.
 __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -206,28 +329,35 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
     return;
   }
   const float alpha = (float)(rs / pap);
-  double rn = 0.0;
+  double rn = 0.0, rzn = 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    float rq[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int64_t q = d * N + i;
       a.x[q] += alpha * a.p[q];
-      const float rq = a.r[q] - alpha * a.Ap[q];
-      a.r[q] = rq;
-      rn += (double)rq * rq;
+      rq[d] = a.r[q] - alpha * a.Ap[q];
+      a.r[q] = rq[d];
+      rn += (double)rq[d] * rq[d];
     }
+    float z[3] = {rq[0], rq[1], rq[2]};
+    if (a.minv) apply_minv(a.minv, N, i, rq[0], rq[1], rq[2], z[0], z[1], z[2]);
+    rzn += (double)rq[0] * z[0] + (double)rq[1] * z[1] + (double)rq[2] * z[2];
   }
   rn = block_sum(rn, red);
-  const float beta = (float)(rn / rs);
+  rzn = block_sum(rzn, red);
+  const float beta = (float)(rzn / rs);
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    float z[3] = {a.r[i], a.r[N + i], a.r[2 * N + i]};
+    if (a.minv) apply_minv(a.minv, N, i, z[0], z[1], z[2], z[0], z[1], z[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int64_t q = d * N + i;
-      a.p[q] = a.r[q] + beta * a.p[q];
+      a.p[q] = z[d] + beta * a.p[q];
     }
   }
   if (threadIdx.x == 0) {
-    s[0] = rn;
+    s[0] = rzn;
     const double tol = fmax(a.rel_tol, s[14]);
     if (rn <= tol * tol * s[1]) s[2] = 0.0;
   }
@@ -458,9 +588,9 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               double rel_tol, double step_tol, double floor_factor,
                               double eta_max, int restart, float* r, float* p,
                               float* x, float* rn, double* st, double* force,
-                              hipStream_t s) {
+                              const float* kel, float* minv, hipStream_t s) {
   ResArgs a{node_off, N, y, f, energy, plate, k, abs_tol, rel_tol, step_tol,
-            floor_factor, eta_max, restart, r, p, x, rn, st, force};
+            floor_factor, eta_max, restart, r, p, x, rn, st, force, kel, minv};
   hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -468,10 +598,27 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
-                        float* p, float* Ap, double* st, hipStream_t s) {
-  CgArgs a{node_off, N, y, plate, k, rel_tol, ybar, x, r, p, Ap, st};
+                        float* p, float* Ap, double* st, const float* minv,
+                        hipStream_t s) {
+  CgArgs a{node_off, N, y, plate, k, rel_tol, ybar, x, r, p, Ap, st, minv};
   hipLaunchKernelGGL(qs_cg_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_qs_stiffness(const DeviceTables& T, const Range& r, float* kel,
+                               hipStream_t s) {
+  if (T.n_tiles <= 0) return hipSuccess;
+  for (int pass = 0; pass < 2; ++pass) {
+    float* out = kel + (int64_t)pass * 3 * T.n_nodes;
+    StiffArgs a{T, pass, out};
+    hipLaunchKernelGGL(qs_stiffness_kernel, dim3((unsigned)T.n_tiles), dim3(64),
+                       (size_t)16 * T.nloc, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_forward_finalize(T, r, out, nullptr, nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_qs_update(const int64_t* node_off, int64_t N, int32_t n_cells,

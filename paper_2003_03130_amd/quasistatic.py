@@ -4,7 +4,9 @@ systems are solved per cell by conjugate gradients on the device (cm_qs_*;
 Hessian-vector products from cm_forces_backward), each step globalised by a
 backtracking (Armijo) line search on the total potential and solved only as
 accurately as the Newton residual's progress asks for (inexact Newton with
-Eisenstat and Walker's forcing term, per cell on the device).  Python only
+Eisenstat and Walker's forcing term, per cell on the device), the conjugate
+gradients preconditioned by the inverse 3x3 node blocks of the small-strain
+stiffness plus the penalty Hessian (block Jacobi).  Python only
 orders the calls and checks convergence flags between Newton steps."""
 from __future__ import annotations
 
@@ -21,14 +23,14 @@ class QuasiStaticCompression:
     float32 floor of the residual, estimated at every plate position) or
     when a Newton step moves no node by more than step_tol; cg_tol: smallest
     relative CG residual; eta_max: largest forcing term of the inexact Newton
-    steps (0: every CG solve to cg_tol); cap: largest node move per Newton
-    step; armijo: sufficient decrease of the line search, which gives up
-    below min_move."""
+    steps (0: every CG solve to cg_tol); precondition: block-Jacobi CG;
+    cap: largest node move per Newton step; armijo: sufficient decrease of
+    the line search, which gives up below min_move."""
 
     def __init__(self, batch, k_plate, rel_tol=1e-3, abs_tol=1e-9,
                  step_tol=1e-6, floor_factor=2.0, cg_tol=1e-3, max_newton=40,
                  max_cg=400, cap=0.05, armijo=1e-4, min_move=1e-7,
-                 max_backtrack=12, eta_max=0.5):
+                 max_backtrack=12, eta_max=0.5, precondition=True):
         import torch
         self.cb = batch
         self.k = float(k_plate)
@@ -39,6 +41,13 @@ class QuasiStaticCompression:
         self.max_backtrack = int(max_backtrack)
         self.cg_tol, self.cap = float(cg_tol), float(cap)
         self.eta_max = float(eta_max)
+        self.precondition = bool(precondition)
+        if self.precondition:
+            self._kel = torch.empty(6 * batch.n_nodes, dtype=torch.float32,
+                                    device=batch.device)
+            self._minv = torch.empty_like(self._kel)
+        else:
+            self._kel = self._minv = None
         self.max_newton, self.max_cg = int(max_newton), int(max_cg)
         dev = batch.device
         self._f = batch.empty_nodes()
@@ -67,7 +76,8 @@ class QuasiStaticCompression:
             cb._h, _ptr(y), _ptr(self._f), _ptr(self._E), _ptr(plate), self.k,
             self.abs_tol, self.rel_tol, self.step_tol, self.floor_factor,
             self.eta_max, int(restart), _ptr(self._r), _ptr(self._p), _ptr(self._x),
-            _ptr(self._rn), _ptr(self.state), _ptr(self.force), _stream(None)))
+            _ptr(self._rn), _ptr(self.state), _ptr(self.force), _ptr(self._kel),
+            _ptr(self._minv), _stream(None)))
 
     def _active(self, col):
         return bool((self.state[:, col] > 0).any())
@@ -77,6 +87,9 @@ class QuasiStaticCompression:
         tensor (n_cells, 2) = top, bottom); y (device SoA) is updated in
         place.  Returns True when every cell met the tolerance."""
         cb = self.cb
+        if self.precondition:  # for the current parameters
+            nat.check(nat.lib().cm_qs_stiffness(cb._h, _ptr(self._kel),
+                                                _stream(None)))
         # float32 floor of the residual at this plate position
         nat.check(nat.lib().cm_qs_noise(cb._h, _ptr(y), _ptr(self._Ap),
                                         _stream(None)))
@@ -93,7 +106,8 @@ class QuasiStaticCompression:
                     flags.stride(0), _ptr(self._ybar), None, st)
         cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, self.cg_tol,
                    _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
-                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state), st)
+                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
+                   _ptr(self._minv), st)
         for it in range(self.max_newton):
             self._residual(y, plate, restart=(it == 0))
             if not self._active(11):
@@ -129,7 +143,8 @@ class QuasiStaticCompression:
         (S, n_cells); bottom: scalar or (n_cells,)), starting from y0 and
         each position from the previous equilibrium (affine predictor).
         Returns (forces (S, n_cells) top, (S, n_cells) bottom, converged (S,),
-        final positions)."""
+        final positions); self.residuals (S, n_cells) holds the final
+        projected Newton residual norms |f + p|_2."""
         import torch
         cb = self.cb
         tops = np.asarray(tops, dtype=np.float64)
@@ -139,7 +154,7 @@ class QuasiStaticCompression:
         y = y0.clone()
         plates = torch.from_numpy(np.stack([tops, np.broadcast_to(
             bot, tops.shape)], axis=2).copy()).to(cb.device)
-        Ft, Fb, ok = [], [], []
+        Ft, Fb, ok, res = [], [], [], []
         for s in range(len(tops)):
             if s > 0:
                 nat.check(nat.lib().cm_qs_predict(
@@ -148,4 +163,6 @@ class QuasiStaticCompression:
             ok.append(self.equilibrate(y, plates[s]))
             Ft.append(self.force[:, 0].cpu().numpy().copy())
             Fb.append(self.force[:, 1].cpu().numpy().copy())
+            res.append(self.state[:, 3].sqrt().cpu().numpy())
+        self.residuals = np.array(res)
         return np.array(Ft), np.array(Fb), np.array(ok), y
