@@ -2,10 +2,11 @@
 // potential Pi(y) = E(y) + sum_nodes phi(y_z), with the plate penalty
 // phi(z) = (k/3) [max(0, z - top)^3 + max(0, bottom - z)^3] (its force is the
 // penalty of the plate-compression steps), each Newton system
-// Hess(Pi) dx = f + p solved by conjugate gradients per cell.  Hessian-vector
-// products of E come from the backward kernels (ybar = (df/dy)^T v =
-// -Hess(E) v); the penalty Hessian is diagonal, 2k (max(0, z - top) +
-// max(0, bottom - z)) on the z entries.
+// Hess(Pi) dx = f + p solved by conjugate gradients per cell, preconditioned
+// by the inverse 3x3 node blocks of the small-strain stiffness plus the
+// penalty Hessian (block Jacobi).  Hessian-vector products of E come from the
+// backward kernels (ybar = (df/dy)^T v = -Hess(E) v); the penalty Hessian is
+// diagonal, 2k (max(0, z - top) + max(0, bottom - z)) on the z entries.
 //
 // One workgroup per cell (cells are independent systems); per-cell scalars
 // live in a float64 state of kQsState entries per cell, so a whole Newton
