@@ -137,8 +137,11 @@ def test_inexact_newton_matches_exact_solves():
 def _stiffness_blocks(x, tets, mu, kappa):
     """Per node, the summed diagonal 3x3 blocks V0 (mu |b|^2 I + (kappa +
     mu/3) b b^T) of the small-strain stiffness (b: the node's row of the
-    tetrahedron's gradient operator), in float64."""
+    tetrahedron's gradient operator; mu, kappa scalars or per tetrahedron),
+    in float64."""
     D = np.zeros((len(x), 3, 3))
+    mu = np.broadcast_to(np.asarray(mu, np.float64), (len(tets),))[:, None, None]
+    kappa = np.broadcast_to(np.asarray(kappa, np.float64), (len(tets),))[:, None, None]
     e = x[tets[:, :3]] - x[tets[:, [3]]]
     Bt = np.linalg.inv(np.transpose(e, (0, 2, 1)))       # rows b_1, b_2, b_3
     V0 = np.abs(np.linalg.det(e)) / 6.0
@@ -188,3 +191,32 @@ def test_stiffness_blocks_and_preconditioned_cg():
         out[pre] = Ft
         print(f"precondition {pre}: {qs.stats}")
     assert np.abs(out[True] - out[False]).max() <= 2e-3 * np.abs(out[False]).max()
+
+
+def test_stiffness_blocks_with_material_regions():
+    """Every tetrahedron's block takes the (mu, kappa) of its region."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd import _native as nat
+    from paper_2003_03130_amd.cells import _ptr, _stream
+    from synth.configs import radial_regions
+    b = _cells()
+    reg = np.concatenate([radial_regions(b.cell(c).x, b.cell(c).tets)
+                          for c in range(b.n_cells)])
+    th = np.array([[1.0, 20.0, 0.5], [3.0, 5.0, 0.2], [0.4, 40.0, 0.9]] * b.n_cells)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets, regions=reg, n_regions=3)
+    cb.set_params(th[:, 0], th[:, 1], th[:, 2])
+    kel = torch.empty(6 * b.n_nodes, dtype=torch.float32, device=cb.device)
+    nat.check(nat.lib().cm_qs_stiffness(cb._h, _ptr(kel), _stream(None)))
+    kh = kel.view(6, -1).cpu().numpy()
+    got = np.zeros((b.n_nodes, 3, 3))
+    for q, (i, j) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        got[cb.new_to_old, i, j] = kh[q]
+        got[cb.new_to_old, j, i] = kh[q]
+    for c in range(b.n_cells):
+        cell = b.cell(c)
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        r = reg[b.tet_off[c]:b.tet_off[c + 1]]
+        want = _stiffness_blocks(cell.x, cell.tets, th[3 * c + r, 0], th[3 * c + r, 1])
+        err = np.abs(got[n0:n1] - want).max() / np.abs(want).max()
+        assert err <= 1e-5, (c, err)
