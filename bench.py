@@ -559,9 +559,11 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
-    ap.add_argument("--only", choices=["relax", "qs", "template"], default=None,
-                    help="run one self-contained leg alone (for profiling it) "
-                         "and print its JSON line")
+    ap.add_argument("--only", choices=["relax", "qs", "template", "shape",
+                                       "regions"], default=None,
+                    help="run one leg alone (for profiling it) and print its "
+                         "JSON line; shape and regions build the main "
+                         "workload first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -579,7 +581,7 @@ def main():
     from paper_2003_03130_amd import CellBatch
     from synth.configs import cotangent, uneven_batch
 
-    if args.only:
+    if args.only in ("relax", "qs", "template"):
         leg = {"relax": run_relax, "qs": run_quasistatic,
                "template": run_template}[args.only](args)
         print(json.dumps({"leg": args.only, **leg}), flush=True)
@@ -596,6 +598,10 @@ def main():
     cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
     dev = cb.device
     y = cb.to_device(b.y)
+    if args.only:
+        leg = run_shape(args, cb, b, y) if args.only == "shape" else run_regions(args, b)
+        print(json.dumps({"leg": args.only, **leg}), flush=True)
+        return
     vbar = cotangent(b.n_nodes, args.seed + 1)
     fbar = cb.to_device(vbar)
     ebar_h = np.random.default_rng(args.seed + 2).uniform(0.0, 1.0, b.n_cells)

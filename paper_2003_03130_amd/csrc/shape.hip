@@ -156,55 +156,72 @@ struct ExtArgs {
 // Per cell: for every direction the node of smallest and of largest
 // projection (ties to the smaller index), then d2max = the largest squared
 // distance among those pairs; and the cell's count of tetrahedra that are
-// inverted (or degenerate) in the current positions.
+// inverted (or degenerate) in the current positions.  One pass over the
+// nodes: every thread keeps the 14 extremes of its nodes (a largest
+// projection as the smallest negated one), then a (value, index)
+// lexicographic minimum over the wavefront (butterfly) and the 4 wavefronts.
 __global__ __launch_bounds__(256) void shape_extreme_kernel(ExtArgs a) {
-  __shared__ double rv[256];
-  __shared__ int64_t ri[256];
-  __shared__ int64_t ext[14];
+  __shared__ double wv[4][14];
+  __shared__ int wi[4][14];
   __shared__ int inv[4];
-  const int c = blockIdx.x, tid = threadIdx.x;
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   {
     int s = 0;
     const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
     for (int k = tid; k < nt; k += 256) s += a.tile_inv[t0 + (int64_t)k * a.T.tile_stride];
     s = wave_sum(s);
-    if ((tid & 63) == 0) inv[tid >> 6] = s;
-    __syncthreads();
-    if (tid == 0) a.cell_inv[c] = inv[0] + inv[1] + inv[2] + inv[3];
+    if (lane == 0) inv[w] = s;
   }
-  for (int d = 0; d < 7; ++d)
-    for (int side = 0; side < 2; ++side) {  // 0: min, 1: max
-      double best = side ? -INFINITY : INFINITY;
-      int64_t arg = -1;
-      for (int64_t i = n0 + tid; i < n1; i += 256) {
-        const double pr = (double)kDirs[d][0] * a.y[i] + (double)kDirs[d][1] * a.y[N + i] +
-                          (double)kDirs[d][2] * a.y[2 * N + i];
-        if (side ? pr > best : pr < best) { best = pr; arg = i; }
-      }
-      rv[tid] = best;
-      ri[tid] = arg;
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-          const double v2 = rv[tid + s];
-          const int64_t i2 = ri[tid + s];
-          const bool better = side ? v2 > rv[tid] : v2 < rv[tid];
-          if (i2 >= 0 && (ri[tid] < 0 || better || (v2 == rv[tid] && i2 < ri[tid]))) {
-            rv[tid] = v2;
-            ri[tid] = i2;
-          }
-        }
-        __syncthreads();
-      }
-      if (tid == 0) ext[2 * d + side] = ri[0];
-      __syncthreads();
+  double best[14];
+  int arg[14];
+#pragma unroll
+  for (int k = 0; k < 14; ++k) {
+    best[k] = INFINITY;
+    arg[k] = -1;
+  }
+  for (int64_t i = n0 + tid; i < n1; i += 256) {
+    const double px = a.y[i], py = a.y[N + i], pz = a.y[2 * N + i];
+    const int li = (int)(i - n0);
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+      const double pr = (double)kDirs[d][0] * px + (double)kDirs[d][1] * py +
+                        (double)kDirs[d][2] * pz;
+      // indices grow along a thread's nodes: strict < keeps the smaller one
+      if (pr < best[2 * d]) { best[2 * d] = pr; arg[2 * d] = li; }
+      if (-pr < best[2 * d + 1]) { best[2 * d + 1] = -pr; arg[2 * d + 1] = li; }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 14; ++k) {
+    double v = best[k];
+    int ix = arg[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(v, off);
+      const int i2 = __shfl_xor(ix, off);
+      if (i2 >= 0 && (ix < 0 || v2 < v || (v2 == v && i2 < ix))) { v = v2; ix = i2; }
+    }
+    if (lane == 0) { wv[w][k] = v; wi[w][k] = ix; }
+  }
+  __syncthreads();
   if (tid == 0) {
+    a.cell_inv[c] = inv[0] + inv[1] + inv[2] + inv[3];
+    int ext[14];
+    for (int k = 0; k < 14; ++k) {
+      double v = wv[0][k];
+      int ix = wi[0][k];
+      for (int q = 1; q < 4; ++q) {
+        const double v2 = wv[q][k];
+        const int i2 = wi[q][k];
+        if (i2 >= 0 && (ix < 0 || v2 < v || (v2 == v && i2 < ix))) { v = v2; ix = i2; }
+      }
+      ext[k] = ix;
+    }
     double m = 0.0;
     for (int d = 0; d < 7; ++d) {
-      const int64_t p = ext[2 * d], q = ext[2 * d + 1];
-      if (p < 0 || q < 0) continue;
+      if (ext[2 * d] < 0 || ext[2 * d + 1] < 0) continue;
+      const int64_t p = n0 + ext[2 * d], q = n0 + ext[2 * d + 1];
       const double dx = (double)a.y[p] - a.y[q], dy = (double)a.y[N + p] - a.y[N + q],
                    dz = (double)a.y[2 * N + p] - a.y[2 * N + q];
       m = fmax(m, dx * dx + dy * dy + dz * dz);
