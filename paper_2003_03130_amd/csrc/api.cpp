@@ -47,6 +47,7 @@ struct cm_batch_s {
   const int4* rest_blocks = nullptr;  // the other block pairs
   int64_t n_rest_blocks = 0;
   int32_t* shape_tile_inv = nullptr;
+  const uint64_t* chunk_neg = nullptr;  // per chunk: lanes of negative orientation
   int32_t* shape_cell_inv = nullptr;
   const int2* node_blocks = nullptr;
   int64_t n_node_blocks = 0;
@@ -254,10 +255,12 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     int4 *pcd, *prd;
     int2* nbd;
     int32_t *sord, *tinv, *cinv;
+    uint64_t* cneg;
     double *mom, *bbox;
     unsigned long long* d2;
     if ((rc = h->upload(&pcd, pc, stream)) || (rc = h->upload(&prd, pr, stream)) ||
         (rc = h->upload(&sord, P.space_order, stream)) ||
+        (rc = h->upload(&cneg, P.chunk_neg, stream)) ||
         (rc = h->upload(&nbd, nbk, stream)) ||
         (rc = h->alloc(&bbox, 6 * nbk.size())) ||
         (rc = h->alloc(&mom, 10 * (size_t)h->n_tiles)) ||
@@ -270,6 +273,7 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     h->rest_blocks = prd;
     h->n_rest_blocks = (int64_t)pr.size();
     h->shape_tile_inv = tinv;
+    h->chunk_neg = cneg;
     h->shape_cell_inv = cinv;
     h->node_blocks = nbd;
     h->n_node_blocks = (int64_t)nbk.size();
@@ -858,7 +862,7 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
   CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->cand_blocks, h->n_cand_blocks,
                           h->rest_blocks, h->n_rest_blocks,
                           h->node_blocks, h->n_node_blocks, h->space_order, y, d_ref,
-                          h->shape_mom, h->shape_tile_inv, h->shape_cell_inv,
+                          h->chunk_neg, h->shape_mom, h->shape_tile_inv, h->shape_cell_inv,
                           h->shape_bbox, h->d2max, out, stream));
   return CM_OK;
 }

@@ -23,7 +23,8 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* rest_blocks, int64_t n_rest_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
                         const int32_t* order, const float* y, const double* d_ref,
-                        double* mom, int32_t* tile_inv, int32_t* cell_inv,
+                        const uint64_t* chunk_neg, double* mom, int32_t* tile_inv,
+                        int32_t* cell_inv,
                         double* bbox, unsigned long long* d2max, double* out,
                         hipStream_t st);
 

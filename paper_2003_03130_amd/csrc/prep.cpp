@@ -22,6 +22,8 @@ struct CellOut {
   std::string err;
   std::vector<TileDesc> tiles;       // chunk_begin, own_begin, shr_begin local
   std::vector<TetChunk> chunks;
+  std::vector<uint64_t> chunk_neg;   // per chunk: lanes whose reference
+                                     // orientation (det of the edges) is < 0
   std::vector<int32_t> slot_node;    // local internal ids
   std::vector<int32_t> shared_node;  // local internal ids
   std::vector<int32_t> shared_slot_ptr;
@@ -605,6 +607,7 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
     d.n_chunks = (int32_t)used.size();
     const size_t base = out.chunks.size();
     out.chunks.resize(base + used.size());
+    out.chunk_neg.resize(base + used.size(), 0);
     for (size_t q = base; q < out.chunks.size(); ++q) {
       TetChunk& ch = out.chunks[q];
       std::memset(&ch, 0, sizeof(TetChunk));
@@ -618,6 +621,7 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
       const double det = reference_inverse(X, pl.v, Bt, nullptr);
       for (int q = 0; q < 9; ++q) ch.B[q][pl.lane] = (float)Bt[q];
       ch.V0[pl.lane] = (float)(std::fabs(det) / 6.0);
+      if (det < 0) out.chunk_neg[base + pl.chunk] |= 1ull << pl.lane;
     }
   }
   // Shared node -> its slots, in tile order.
@@ -716,6 +720,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
   P->n_tets = tet_off[n_cells];
   P->tiles.resize(n_tiles);
   P->chunks.resize(n_chunks);
+  P->chunk_neg.resize(n_chunks);
   P->slot_node.resize(n_slots);
   P->shared_node.resize(n_shared);
   P->shared_slot_ptr.resize(n_shared + 1);
@@ -753,6 +758,7 @@ int prepare_batch(int32_t n_cells, const int64_t* node_off,
       P->mat_tile_first[(size_t)c * n_regions + r] = (int32_t)tb + cell.region_tile_first[r];
       P->mat_tile_count[(size_t)c * n_regions + r] = cell.region_tile_count[r];
     }
+    std::copy(cell.chunk_neg.begin(), cell.chunk_neg.end(), P->chunk_neg.begin() + cb);
     std::memcpy(P->chunks.data() + cb, cell.chunks.data(),
                 sizeof(TetChunk) * cell.chunks.size());
     for (size_t q = 0; q < cell.slot_node.size(); ++q) {
@@ -816,6 +822,7 @@ int prepare_template(int32_t n_cells, int64_t n_nodes, int64_t n_tets,
   P->n_nodes = C * N;
   P->n_tets = C * n_tets;
   P->chunks = std::move(one.chunks);
+  P->chunk_neg = std::move(one.chunk_neg);
   P->tiles.resize(C * T1);
   P->tile_mat.resize(C * T1);
   for (int64_t k = 0; k < T1; ++k)

@@ -19,6 +19,8 @@ struct Prepared {
   int64_t n_cells = 0, n_nodes = 0, n_tets = 0;
   std::vector<TileDesc> tiles;
   std::vector<TetChunk> chunks;
+  std::vector<uint64_t> chunk_neg;       // per chunk: bit l set when lane l's
+                                         // reference orientation is negative
   std::vector<int32_t> slot_node;        // internal node id of every slot
   std::vector<int32_t> shared_node;      // internal node id of every shared node
   std::vector<int32_t> shared_slot_ptr;  // CSR (n_shared + 1) into shared_slots

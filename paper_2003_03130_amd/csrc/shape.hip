@@ -61,6 +61,7 @@ struct MomArgs {
   const float* y;
   double* mom;        // kMom per tile
   int32_t* tile_inv;  // per tile: tetrahedra whose current volume is not > 0
+  const uint64_t* chunk_neg;  // per chunk: lanes of negative reference orientation
 };
 
 __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
   const TetChunk* ch = a.T.chunks + d.chunk_begin;
   for (int k = 0; k < d.n_chunks; ++k) {
     const uint2 q = *reinterpret_cast<const uint2*>(ch[k].idx[lane]);
+    const uint64_t neg = a.chunk_neg[d.chunk_begin + k];  // wave-uniform
     if (q.x == kEmptyLane) continue;
     const float4 p[4] = {ys[q.x & 0xffff], ys[q.x >> 16], ys[q.y & 0xffff],
                          ys[q.y >> 16]};
@@ -97,15 +99,9 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
     const double det_s = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
                          e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
                          e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
-    double b[9];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) b[j] = (double)ch[k].B[j][lane];
-    const double det_b = b[0] * (b[4] * b[8] - b[5] * b[7]) -
-                         b[1] * (b[3] * b[8] - b[5] * b[6]) +
-                         b[2] * (b[3] * b[7] - b[4] * b[6]);
-    // current volume with the orientation of the reference vertex order
-    // (det B = 1 / det of the reference edges)
-    const double V = (det_b > 0.0 ? det_s : -det_s) * (1.0 / 6.0);
+    // current volume with the orientation of the reference vertex order (the
+    // sign of the reference edges' determinant for the stored vertex order)
+    const double V = (((neg >> lane) & 1ull) ? -det_s : det_s) * (1.0 / 6.0);
     ninv += V > 0.0 ? 0 : 1;
     const double rx = 0.25 * (((double)p[0].x + (double)p[1].x) +
                               ((double)p[2].x + (double)p[3].x)) - ox;
@@ -417,13 +413,14 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* rest_blocks, int64_t n_rest_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
                         const int32_t* order, const float* y, const double* d_ref,
-                        double* mom, int32_t* tile_inv, int32_t* cell_inv,
+                        const uint64_t* chunk_neg, double* mom, int32_t* tile_inv,
+                        int32_t* cell_inv,
                         double* bbox, unsigned long long* d2max, double* out,
                         hipStream_t st) {
   const int nc = T.n_cells;
   hipError_t e;
   if (T.n_tiles > 0) {
-    MomArgs m{T, node_off, y, mom, tile_inv};
+    MomArgs m{T, node_off, y, mom, tile_inv, chunk_neg};
     hipLaunchKernelGGL(shape_moments_kernel, dim3((unsigned)T.n_tiles), dim3(64),
                        shape_lds(T.nloc), st, m);
     if ((e = hipGetLastError()) != hipSuccess) return e;
