@@ -44,8 +44,6 @@ struct cm_batch_s {
   // shape diagnostics scratch
   const int4* cand_blocks = nullptr;  // block pairs among candidate nodes
   int64_t n_cand_blocks = 0;
-  const int4* rest_blocks = nullptr;  // the other block pairs
-  int64_t n_rest_blocks = 0;
   int32_t* shape_tile_inv = nullptr;
   const uint64_t* chunk_neg = nullptr;  // per chunk: lanes of negative orientation
   int32_t* shape_cell_inv = nullptr;
@@ -239,26 +237,26 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     // 256 x 256 node-pair blocks of every cell (row block <= column block);
     // the cell's nodes are ordered candidates first, so the pairs of the
     // first ceil(candidates / 256) blocks hold every candidate pair
-    std::vector<int4> pc, pr;
-    std::vector<int2> nbk;
+    std::vector<int4> pc;
+    std::vector<int2> nbk;  // the candidate node blocks of every cell
     for (int64_t c = 0; c < h->n_cells; ++c) {
       const int64_t nb = (P.node_off[c + 1] - P.node_off[c] + 255) / 256;
       int64_t bc = ((int64_t)P.cell_candidates[c] + 255) / 256;
       if (bc <= 0) bc = nb;
       const int base = (int)nbk.size();
-      for (int64_t i = 0; i < nb; ++i) {
+      for (int64_t i = 0; i < bc; ++i) {
         nbk.push_back(make_int2((int)c, (int)i));
-        for (int64_t j = i; j < nb; ++j)
-          (j < bc ? pc : pr).push_back(make_int4((int)c, (int)i, (int)j, base));
+        for (int64_t j = i; j < bc; ++j)
+          pc.push_back(make_int4((int)c, (int)i, (int)j, base));
       }
     }
-    int4 *pcd, *prd;
+    int4* pcd;
     int2* nbd;
     int32_t *sord, *tinv, *cinv;
     uint64_t* cneg;
     double *mom, *bbox;
     unsigned long long* d2;
-    if ((rc = h->upload(&pcd, pc, stream)) || (rc = h->upload(&prd, pr, stream)) ||
+    if ((rc = h->upload(&pcd, pc, stream)) ||
         (rc = h->upload(&sord, P.space_order, stream)) ||
         (rc = h->upload(&cneg, P.chunk_neg, stream)) ||
         (rc = h->upload(&nbd, nbk, stream)) ||
@@ -270,8 +268,6 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
       return bail(rc);
     h->cand_blocks = pcd;
     h->n_cand_blocks = (int64_t)pc.size();
-    h->rest_blocks = prd;
-    h->n_rest_blocks = (int64_t)pr.size();
     h->shape_tile_inv = tinv;
     h->chunk_neg = cneg;
     h->shape_cell_inv = cinv;
@@ -860,7 +856,6 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
     return fail(CM_EINVAL, "tiles too large for the shape kernel's LDS");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_shape(h->T, h->d_node_off, h->cand_blocks, h->n_cand_blocks,
-                          h->rest_blocks, h->n_rest_blocks,
                           h->node_blocks, h->n_node_blocks, h->space_order, y, d_ref,
                           h->chunk_neg, h->shape_mom, h->shape_tile_inv, h->shape_cell_inv,
                           h->shape_bbox, h->d2max, out, stream));

@@ -13,14 +13,15 @@ namespace cm {
 // Shape diagnostics (Taylor deformation, cell strain): kShapeFields float64
 // per cell = volume, centre of mass (3), semi-axes a1 <= a2 <= a3, D, d_max,
 // strain.  mom: 10 float64 per tile; d2max: one uint64 per cell; node
-// blocks: (cell, block) for every block of 256 nodes, with a bounding box
-// (6 float64) each; pair_blocks: (cell, row block, column block, first node
-// block of the cell) over the node blocks of every cell with row <= column.
+// blocks: (cell, block) for every candidate block of 256 nodes (a cell's
+// nodes ordered candidates first), with a bounding box (6 float64) each;
+// cand_blocks: (cell, row block, column block, first node block of the cell)
+// over the candidate blocks of every cell with row <= column; chunk_neg: per
+// chunk, the lanes of negative reference orientation.
 constexpr int kShapeFields = 10;
 size_t shape_lds(int nloc);
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* cand_blocks, int64_t n_cand_blocks,
-                        const int4* rest_blocks, int64_t n_rest_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
                         const int32_t* order, const float* y, const double* d_ref,
                         const uint64_t* chunk_neg, double* mom, int32_t* tile_inv,

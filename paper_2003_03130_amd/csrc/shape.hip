@@ -14,27 +14,27 @@
 //                         these pairs is a lower bound L of d_max (the
 //                         distance of two actual nodes) and starts the maximum;
 //                         and the cell's count of inverted tetrahedra;
-//   shape_bbox_kernel     the bounding box of every block of 256 nodes, the
-//                         nodes of a cell taken candidates first (below), each
-//                         part in Morton order of the reference positions;
-//   pair_max_kernel       the largest squared distance between two nodes of
-//                         a cell, over 256 x 256 blocks of node pairs (float64
-//                         differences of the float32 positions are exact; the
-//                         maximum of non-negative doubles is an order-free
-//                         integer maximum of their bit patterns); a block pair
-//                         whose bounding boxes are closer than the current
-//                         maximum cannot hold a larger distance and is skipped
-//                         (the result is the same, only the work changes).
-//                         It runs over the block pairs of the candidate nodes
-//                         (leading blocks), then over the other block pairs
-//                         only for cells with an inverted tetrahedron: the
-//                         farthest two nodes are convex-hull vertices, and a
-//                         node whose faces are all shared by two tetrahedra
-//                         on opposite sides lies inside the image of its star
-//                         while those keep their orientation (their solid
-//                         angles at the node sum to a positive multiple of
-//                         4 pi, so no direction has the node strictly beyond
-//                         all its neighbours);
+//   shape_bbox_kernel     the bounding box of every candidate block of 256
+//                         nodes (below), the nodes of a cell taken candidates
+//                         first, each part in Morton order of the reference
+//                         positions;
+//   pair_max_kernel       the largest squared distance between two candidate
+//                         nodes of a cell, over 256 x 256 blocks of node pairs
+//                         (float64 differences of the float32 positions are
+//                         exact; the maximum of non-negative doubles is an
+//                         order-free integer maximum of their bit patterns); a
+//                         block pair whose bounding boxes are closer than the
+//                         current maximum cannot hold a larger distance and is
+//                         skipped (the result is the same, only the work
+//                         changes).  The farthest two nodes are convex-hull
+//                         vertices, and a node whose faces are all shared by
+//                         two tetrahedra on opposite sides lies inside the
+//                         image of its star while those keep their orientation
+//                         (their solid angles at the node sum to a positive
+//                         multiple of 4 pi, so no direction has the node
+//                         strictly beyond all its neighbours): the other nodes
+//                         are the candidates;
+//   pair_all_kernel       cells with an inverted tetrahedron: all node pairs;
 //   shape_finalize_kernel per cell (one wavefront): tile records summed in a
 //                         fixed order, the inertia tensor about the centre of
 //                         mass, its eigenvalues by cyclic Jacobi rotations,
@@ -132,8 +132,41 @@ struct PairArgs {
   int64_t N;
   const double* bbox;         // per node block: min x y z, max x y z
   unsigned long long* d2max;  // per cell, bits of a non-negative double
-  const int32_t* gate;        // nullable: only cells with gate[c] != 0
 };
+
+struct AllArgs {
+  const int64_t* node_off;
+  const float* y;
+  int64_t N;
+  const int32_t* cell_inv;
+  unsigned long long* d2max;
+};
+
+// Cells with an inverted (or degenerate) tetrahedron, which the candidate
+// search does not cover: one workgroup per such cell takes the largest
+// squared distance over all its node pairs (other cells return at once).
+__global__ __launch_bounds__(256) void pair_all_kernel(AllArgs a) {
+  __shared__ double red[4];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  if (a.cell_inv[c] == 0) return;  // uniform over the workgroup
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  double best = 0.0;
+  for (int64_t p = n0 + tid; p < n1; p += 256) {
+    const double xp = a.y[p], yp = a.y[N + p], zp = a.y[2 * N + p];
+    for (int64_t q = p + 1; q < n1; ++q) {
+      const double dx = xp - a.y[q], dy = yp - a.y[N + q], dz = zp - a.y[2 * N + q];
+      best = fmax(best, dx * dx + dy * dy + dz * dz);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+  if ((tid & 63) == 0) red[tid >> 6] = best;
+  __syncthreads();
+  if (tid == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(&a.d2max[c], (unsigned long long)__double_as_longlong(m));
+  }
+}
 
 // Directions of the extreme-node search: the axes and the body diagonals.
 __constant__ float kDirs[7][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 1},
@@ -268,9 +301,9 @@ __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
   __shared__ double cx[256], cy[256], cz[256];
   __shared__ double red[4];
   __shared__ int skip;
+  __shared__ double cur_d2;
   const int4 b = a.blocks[blockIdx.x];
   const int tid = threadIdx.x;
-  if (a.gate && a.gate[b.x] == 0) return;  // uniform over the workgroup
   if (tid == 0) {
     // farthest points of the two bounding boxes vs the current maximum
     const double* r = a.bbox + 6 * (int64_t)(b.w + b.y);
@@ -282,7 +315,9 @@ __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
     }
     const unsigned long long cur = __hip_atomic_load(&a.d2max[b.x], __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
-    skip = u < __longlong_as_double((long long)cur);
+    cur_d2 = __longlong_as_double((long long)cur);
+    // (with a relative margin far above the rounding of the two sums)
+    skip = u < cur_d2 * (1.0 - 1e-12);
   }
   __syncthreads();
   if (skip) return;  // uniform over the workgroup
@@ -301,7 +336,13 @@ __global__ __launch_bounds__(256) void pair_max_kernel(PairArgs a) {
   if (i < n1) {
     const int64_t g = a.order[i];
     const double xi = a.y[g], yi = a.y[a.N + g], zi = a.y[2 * a.N + g];
-    for (int k = 0; k < ncol; ++k) {
+    // the column block's box cannot hold a node farther from this one than
+    // the current maximum: nothing to find for this row
+    const double* q = a.bbox + 6 * (int64_t)(b.w + b.z);
+    const double ex = fmax(xi - q[0], q[3] - xi), ey = fmax(yi - q[1], q[4] - yi),
+                 ez = fmax(zi - q[2], q[5] - zi);
+    const int ncheck = ex * ex + ey * ey + ez * ez < cur_d2 * (1.0 - 1e-12) ? 0 : ncol;
+    for (int k = 0; k < ncheck; ++k) {
       const double dx = xi - cx[k], dy = yi - cy[k], dz = zi - cz[k];
       best = fmax(best, dx * dx + dy * dy + dz * dz);
     }
@@ -410,7 +451,6 @@ size_t shape_lds(int nloc) { return (size_t)16 * nloc; }
 
 hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
                         const int4* cand_blocks, int64_t n_cand_blocks,
-                        const int4* rest_blocks, int64_t n_rest_blocks,
                         const int2* node_blocks, int64_t n_node_blocks,
                         const int32_t* order, const float* y, const double* d_ref,
                         const uint64_t* chunk_neg, double* mom, int32_t* tile_inv,
@@ -435,17 +475,14 @@ hipError_t launch_shape(const DeviceTables& T, const int64_t* node_off,
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (n_cand_blocks > 0) {
-    PairArgs p{cand_blocks, node_off, order, y, T.n_nodes, bbox, d2max, nullptr};
+    PairArgs p{cand_blocks, node_off, order, y, T.n_nodes, bbox, d2max};
     hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_cand_blocks), dim3(256), 0,
                        st, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (n_rest_blocks > 0) {
-    PairArgs p{rest_blocks, node_off, order, y, T.n_nodes, bbox, d2max, cell_inv};
-    hipLaunchKernelGGL(pair_max_kernel, dim3((unsigned)n_rest_blocks), dim3(256), 0,
-                       st, p);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  AllArgs al{node_off, y, T.n_nodes, cell_inv, d2max};
+  hipLaunchKernelGGL(pair_all_kernel, dim3(nc), dim3(256), 0, st, al);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   ShapeFinArgs f{T, node_off, y, mom, d2max, d_ref, out};
   hipLaunchKernelGGL(shape_finalize_kernel, dim3((nc + 3) / 4), dim3(256), 0, st, f);
   return hipGetLastError();
