@@ -321,6 +321,35 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
                           hipStream_t stream);
 
 /*
+ * The same plate-compression steps with the elastic forces computed inside
+ * the step (one force pass whose epilogue applies the step, instead of
+ * cm_forces followed by cm_plate_step, and one adjoint pass instead of
+ * cm_forces_backward followed by cm_plate_step_adjoint): the intermediate f,
+ * ybar_el and thetabar_el are never stored.  Same reading and arguments as
+ * above; the per-node arithmetic and the reduction orders are those of the
+ * two-call route, and the results are bitwise equal to it.
+ *   cm_plate_forces_step: y_next, force (nullable) and, if given, the
+ *     per-cell energy and inverted count of cm_forces at y.
+ *   cm_plate_backward_step: lam from lam_next (the cotangent of the forces
+ *     pass is lam_next, with no energy cotangent); if thetabar_acc is given,
+ *     thetabar_acc[q] += m thetabar_el[q] for the 3 n_regions entries of
+ *     every cell.
+ * y_next and lam must not alias the inputs.  Errors: CM_EINVAL for null or
+ * aliased pointers, negative or non-finite k_plate / mobility, non-finite
+ * scale, F_target without F_meas, a launch configuration beyond the LDS;
+ * CM_ESTATE before cm_set_params.
+ */
+int cm_plate_forces_step(cm_batch h, const float* y, const double* plate,
+                         double k_plate, double mobility, float* y_next,
+                         double* force, double* energy, int32_t* n_inverted,
+                         hipStream_t stream);
+int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
+                           const double* plate, double k_plate, double mobility,
+                           const double* F_meas, const double* F_target,
+                           double scale, double* thetabar_acc, float* lam,
+                           hipStream_t stream);
+
+/*
  * Quasi-static plate compression (the compression setup of Sec. "Simulation
  * setup" solved for equilibrium instead of stepped in time).  At plate
  * positions plate[2c] = top, plate[2c + 1] = bottom the state of cell c

@@ -90,6 +90,11 @@ SIGNATURES = {
                                      ctypes.c_double, ctypes.c_double, _vp,
                                      _vp, ctypes.c_double, _vp, _vp, _vp,
                                      _vp]),
+    "cm_plate_forces_step": (_int, [_vp, _vp, _vp, ctypes.c_double,
+                                    ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "cm_plate_backward_step": (_int, [_vp, _vp, _vp, _vp, ctypes.c_double,
+                                      ctypes.c_double, _vp, _vp,
+                                      ctypes.c_double, _vp, _vp, _vp]),
     "cm_layout_create": (_int, [_i32, _vp, _vp, _vp, _vp,
                                 ctypes.POINTER(Options), ctypes.POINTER(_vp)]),
     "cm_layout_create_template": (_int, [_i32, _i64, _i64, _vp, _vp,

@@ -282,6 +282,27 @@ class CellBatch:
             float(scale), _ptr(thetabar_el), _ptr(thetabar_acc), _ptr(lam),
             _stream(stream)))
 
+    def plate_forces_step(self, y, plate, k_plate, mobility, y_next,
+                          force=None, energy=None, n_inverted=None,
+                          stream=None):
+        """One plate step with the elastic forces computed inside it
+        (cm_plate_forces_step): y_next, and optionally the per-cell top
+        force, energy and inverted count at y."""
+        nat.check(nat.lib().cm_plate_forces_step(
+            self._h, _ptr(y), _ptr(plate), float(k_plate), float(mobility),
+            _ptr(y_next), _ptr(force), _ptr(energy), _ptr(n_inverted),
+            _stream(stream)))
+
+    def plate_backward_step(self, y, lam_next, plate, k_plate, mobility, lam,
+                            F_meas=None, F_target=None, scale=0.0,
+                            thetabar_acc=None, stream=None):
+        """The reverse plate step with the adjoint of the forces computed
+        inside it (cm_plate_backward_step)."""
+        nat.check(nat.lib().cm_plate_backward_step(
+            self._h, _ptr(y), _ptr(lam_next), _ptr(plate), float(k_plate),
+            float(mobility), _ptr(F_meas), _ptr(F_target), float(scale),
+            _ptr(thetabar_acc), _ptr(lam), _stream(stream)))
+
     SHAPE_FIELDS = ("volume", "com_x", "com_y", "com_z", "a1", "a2", "a3",
                     "D", "d_max", "strain")
 

@@ -848,6 +848,65 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
   return CM_OK;
 }
 
+int cm_plate_forces_step(cm_batch h, const float* y, const double* plate,
+                         double k_plate, double mobility, float* y_next,
+                         double* force, double* energy, int32_t* n_inverted,
+                         hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !plate || !y_next)
+    return fail(CM_EINVAL, "y, plate and y_next must be device pointers");
+  if (y_next == y) return fail(CM_EINVAL, "y_next may not alias y");
+  if (!std::isfinite(k_plate) || !std::isfinite(mobility) || k_plate < 0 || mobility < 0)
+    return fail(CM_EINVAL, "k_plate and mobility must be finite and >= 0");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (!lds_fits(h, h->cfg.waves, false))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  cm::PlateFwd pl;
+  pl.plate = plate;
+  pl.node_off = h->d_node_off;
+  pl.k = (float)k_plate;
+  pl.m = (float)mobility;
+  pl.y_next = y_next;
+  pl.force = force;
+  CM_HIP(cm::launch_forward(h->T, full_range(h), h->cfg, y, nullptr, energy, n_inverted,
+                            stream, pl));
+  return CM_OK;
+}
+
+int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
+                           const double* plate, double k_plate, double mobility,
+                           const double* F_meas, const double* F_target,
+                           double scale, double* thetabar_acc, float* lam,
+                           hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !lam_next || !plate || !lam)
+    return fail(CM_EINVAL, "y, lam_next, plate and lam must be device pointers");
+  if (lam == lam_next || lam == y) return fail(CM_EINVAL, "lam may not alias the inputs");
+  if (F_target && !F_meas) return fail(CM_EINVAL, "F_target needs F_meas");
+  if (!std::isfinite(k_plate) || !std::isfinite(mobility) || k_plate < 0 ||
+      mobility < 0 || !std::isfinite(scale))
+    return fail(CM_EINVAL, "k_plate and mobility must be finite and >= 0, scale finite");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (!lds_fits(h, h->cfg.waves, true))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  cm::PlateBwd pl;
+  pl.plate = plate;
+  pl.node_off = h->d_node_off;
+  pl.k = (float)k_plate;
+  pl.m = (float)mobility;
+  pl.m64 = mobility;
+  pl.F_meas = F_meas;
+  pl.F_target = F_target;
+  pl.scale = scale;
+  pl.thetabar_acc = thetabar_acc;
+  pl.lam = lam;
+  CM_HIP(cm::launch_backward(h->Tb, full_range(h), h->cfg, y, lam_next, nullptr, nullptr,
+                             nullptr, stream, cm::CellMask{}, pl));
+  return CM_OK;
+}
+
 int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
              hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;

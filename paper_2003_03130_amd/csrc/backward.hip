@@ -6,12 +6,15 @@
 // and ybar accumulator of each tile node form one LDS record; ybar is
 // accumulated in LDS slot by slot without atomics (see layout.h), owned
 // nodes are stored directly and shared nodes go through the slot partials
-// and the finalize kernel, in a fixed order (deterministic).
+// and the finalize kernel, in a fixed order (deterministic).  With the
+// reverse plate step fused in (plate.h), the same passes write the adjoint
+// state of the previous step instead of ybar.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
 #include "kernels.h"
 #include "mr_tet.h"
+#include "plate.h"
 
 namespace cm {
 namespace {
@@ -24,9 +27,10 @@ struct BwdArgs {
   const double* ebar;   // nullable
   float* ybar;
   CellMask mask;
+  PlateBwd pl;  // used when PL
 };
 
-template <int W>
+template <int W, bool PL>
 __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   extern __shared__ float4 lds[];
   const int lane = threadIdx.x & 63;
@@ -94,10 +98,22 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     });
     wave_sync();
 
-    for (int i = lane; i < d.n_own; i += 64) {
-      const int64_t g = d.own_begin + i;
-      const float4 v = gs[i];
-      a.ybar[g] = v.x; a.ybar[N + g] = v.y; a.ybar[2 * N + g] = v.z;
+    if constexpr (PL) {
+      const float top = (float)a.pl.plate[2 * d.cell];
+      const float bot = (float)a.pl.plate[2 * d.cell + 1];
+      const float gw = plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, d.cell);
+      for (int i = lane; i < d.n_own; i += 64) {
+        const float4 p = ys[i], v = gs[i];
+        const float2 l = vs[i];
+        plate_node_adjoint(p.z, p.w, l.x, l.y, v.x, v.y, v.z, top, bot, a.pl.k,
+                           a.pl.m, gw, a.pl.lam, N, (int64_t)d.own_begin + i);
+      }
+    } else {
+      for (int i = lane; i < d.n_own; i += 64) {
+        const int64_t g = d.own_begin + i;
+        const float4 v = gs[i];
+        a.ybar[g] = v.x; a.ybar[N + g] = v.y; a.ybar[2 * N + g] = v.z;
+      }
     }
     for (int j = lane; j < d.n_shr; j += 64) {
       const int64_t s = d.shr_begin + j;
@@ -122,23 +138,18 @@ struct BwdFinArgs {
   float* ybar;
   double* thetabar;  // nullable
   CellMask mask;
+  const float* y;        // with a plate step
+  const float* lam_next;
+  PlateBwd pl;
 };
-
-// Cell of internal node g (cells keep contiguous node ranges).
-__device__ int cell_of_node(const int64_t* node_off, int n_cells, int64_t g) {
-  int lo = 0, hi = n_cells;  // node_off[lo] <= g < node_off[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (node_off[mid] <= g) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // The first slot_blocks workgroups form, one wavefront per material slot,
 //   dL/dmu = w g_I + (1 - w) g_K, dL/dkappa = g_J, dL/dw = mu (g_I - g_K)
 // from the per-tile sums of dL/d(mu1, mu2, kappa) (mu1 = w mu, mu2 = (1-w) mu;
 // lane l takes tiles l, l + 64, ..., then a fixed butterfly); the others sum
-// the slot partials of every shared node in tile order.
+// the slot partials of every shared node in tile order.  With a plate
+// step, m thetabar is added to pl.thetabar_acc instead of storing thetabar,
+// and the shared nodes take the reverse step instead of storing ybar.
 __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
                                                                 int slot_blocks) {
   const CellMask& m = a.mask;
@@ -146,7 +157,8 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
   if ((int)blockIdx.x < slot_blocks) {
     const int wv = ((int)blockIdx.x * 256 + (int)threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (!a.thetabar || wv >= (a.r.cell_end - a.r.cell_begin) * R) return;
+    double* const tb = a.pl.plate ? a.pl.thetabar_acc : a.thetabar;
+    if (!tb || wv >= (a.r.cell_end - a.r.cell_begin) * R) return;
     const int mt = a.r.cell_begin * R + wv;  // material slot
     if (m.flags && m.flags[(int64_t)(mt / R) * m.stride] == 0.0) return;
     double gI = 0.0, gK = 0.0, gJ = 0.0;
@@ -163,9 +175,14 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
     if (lane == 0) {
       const int nm = a.T.n_mat;
       const double mu = a.T.params[mt], w = a.T.params[2 * nm + mt];
-      a.thetabar[3 * (int64_t)mt] = w * gI + (1.0 - w) * gK;
-      a.thetabar[3 * (int64_t)mt + 1] = gJ;
-      a.thetabar[3 * (int64_t)mt + 2] = mu * (gI - gK);
+      const double t3[3] = {w * gI + (1.0 - w) * gK, gJ, mu * (gI - gK)};
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (a.pl.plate)
+          tb[3 * (int64_t)mt + q] += a.pl.m64 * t3[q];
+        else
+          tb[3 * (int64_t)mt + q] = t3[q];
+      }
     }
     return;
   }
@@ -184,14 +201,27 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
         sy += pp[1];
         sz += pp[2];
       }
-      a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
+      if (a.pl.plate) {
+        const int c = cell_of_node(a.pl.node_off, a.T.n_cells, g);
+        plate_node_adjoint(a.y[2 * N + g], a.lam_next[g], a.lam_next[N + g],
+                           a.lam_next[2 * N + g], sx, sy, sz,
+                           (float)a.pl.plate[2 * c], (float)a.pl.plate[2 * c + 1],
+                           a.pl.k, a.pl.m,
+                           plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, c),
+                           a.pl.lam, N, g);
+      } else {
+        a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
+      }
     }
   }
 }
 
 template <int W>
 hipError_t bwd_w(const BwdArgs& a, int grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(backward_kernel<W>, dim3(grid), dim3(64 * W), lds, st, a);
+  if (a.pl.plate)
+    hipLaunchKernelGGL((backward_kernel<W, true>), dim3(grid), dim3(64 * W), lds, st, a);
+  else
+    hipLaunchKernelGGL((backward_kernel<W, false>), dim3(grid), dim3(64 * W), lds, st, a);
   return hipGetLastError();
 }
 
@@ -202,9 +232,10 @@ size_t backward_lds_per_wave(int nloc) { return (size_t)40 * nloc; }
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
-                                float* ybar, hipStream_t st, const CellMask& mask) {
+                                float* ybar, hipStream_t st, const CellMask& mask,
+                                const PlateBwd& pl) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
-  BwdArgs a{T, r, y, fbar, ebar, ybar, mask};
+  BwdArgs a{T, r, y, fbar, ebar, ybar, mask, pl};
   const int grid = grid_for(r, cfg);
   const size_t lds = backward_lds_per_wave(T.nloc) * cfg.waves;
   switch (cfg.waves) {
@@ -218,13 +249,16 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
 
 hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
                                     float* ybar, double* thetabar,
-                                    hipStream_t st, const CellMask& mask) {
+                                    hipStream_t st, const CellMask& mask,
+                                    const float* y, const float* lam_next,
+                                    const PlateBwd& pl) {
   const int64_t n_shr = r.shared_end - r.shared_begin;
-  const int64_t n_slots = thetabar ? (int64_t)(r.cell_end - r.cell_begin) * T.n_regions : 0;
+  const bool has_tb = pl.plate ? pl.thetabar_acc != nullptr : thetabar != nullptr;
+  const int64_t n_slots = has_tb ? (int64_t)(r.cell_end - r.cell_begin) * T.n_regions : 0;
   if (n_shr <= 0 && n_slots <= 0) return hipSuccess;
   const int slot_blocks = (int)((n_slots + 3) / 4);  // four waves per block
   const int64_t blocks = slot_blocks + (n_shr + 255) / 256;
-  BwdFinArgs b{T, r, ybar, thetabar, mask};
+  BwdFinArgs b{T, r, ybar, thetabar, mask, y, lam_next, pl};
   hipLaunchKernelGGL(backward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      st, b, slot_blocks);
   return hipGetLastError();
@@ -233,10 +267,11 @@ hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
 hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const LaunchCfg& cfg, const float* y,
                            const float* fbar, const double* ebar, float* ybar,
-                           double* thetabar, hipStream_t st, const CellMask& mask) {
-  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st, mask);
+                           double* thetabar, hipStream_t st, const CellMask& mask,
+                           const PlateBwd& pl) {
+  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st, mask, pl);
   if (e != hipSuccess) return e;
-  return launch_backward_finalize(T, r, ybar, thetabar, st, mask);
+  return launch_backward_finalize(T, r, ybar, thetabar, st, mask, y, fbar, pl);
 }
 
 }  // namespace cm

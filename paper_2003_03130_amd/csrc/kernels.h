@@ -53,6 +53,31 @@ struct CellMask {
   int32_t n_cells = 0;
 };
 
+// Arguments of a force pass with the plate step fused in: the pass writes
+// y_next instead of the forces.
+struct PlateFwd {
+  const double* plate = nullptr;     // per cell: top, bottom (null: no step)
+  const int64_t* node_off = nullptr;  // n_cells + 1 node offsets
+  float k = 0.f, m = 0.f;
+  float* y_next = nullptr;
+  double* force = nullptr;           // per cell, nullable
+};
+
+// Arguments of an adjoint pass (fbar = lam_next, no energy cotangent) with
+// the reverse plate step fused in: the pass writes lam instead of ybar and
+// adds m thetabar to thetabar_acc instead of storing thetabar.
+struct PlateBwd {
+  const double* plate = nullptr;     // null: no step
+  const int64_t* node_off = nullptr;
+  float k = 0.f, m = 0.f;
+  double m64 = 0.0;
+  const double* F_meas = nullptr;    // with F_target
+  const double* F_target = nullptr;  // nullable: no loss term
+  double scale = 0.0;
+  double* thetabar_acc = nullptr;    // nullable
+  float* lam = nullptr;
+};
+
 struct LaunchCfg {
   int waves = 1;   // tiles (wavefronts) per workgroup: 1, 2, 4 or 8
   int blocks = 0;  // persistent workgroups; 0 = one workgroup per W tiles
@@ -63,30 +88,43 @@ size_t forward_lds_per_wave(int nloc);
 size_t backward_lds_per_wave(int nloc);
 
 // The two kernels of each pass, separately (for per-kernel timing).
+// With pl.plate set, the forward pass applies one plate-compression step
+// (see plate.h): it writes pl.y_next (and pl.force) instead of f, and the
+// finalize kernel needs y.
 hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
                                const LaunchCfg& cfg, const float* y, float* f,
-                               hipStream_t st);
+                               hipStream_t st, const PlateFwd& pl = PlateFwd{});
 hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
                                    float* f, double* energy, int32_t* ninv,
-                                   hipStream_t st);
+                                   hipStream_t st, const float* y = nullptr,
+                                   const PlateFwd& pl = PlateFwd{});
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
                                 float* ybar, hipStream_t st,
-                                const CellMask& mask = CellMask{});
+                                const CellMask& mask = CellMask{},
+                                const PlateBwd& pl = PlateBwd{});
+// With pl.plate set, the backward pass (fbar = lam_next, no ebar) applies
+// the reverse plate step: it writes pl.lam instead of ybar and adds m
+// thetabar to pl.thetabar_acc; the finalize kernel needs y and lam_next.
 hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
                                     float* ybar, double* thetabar,
                                     hipStream_t st,
-                                    const CellMask& mask = CellMask{});
+                                    const CellMask& mask = CellMask{},
+                                    const float* y = nullptr,
+                                    const float* lam_next = nullptr,
+                                    const PlateBwd& pl = PlateBwd{});
 
 hipError_t launch_forward(const DeviceTables& T, const Range& r,
                           const LaunchCfg& cfg, const float* y, float* f,
-                          double* energy, int32_t* ninv, hipStream_t st);
+                          double* energy, int32_t* ninv, hipStream_t st,
+                          const PlateFwd& pl = PlateFwd{});
 
 hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const LaunchCfg& cfg, const float* y,
                            const float* fbar, const double* ebar, float* ybar,
                            double* thetabar, hipStream_t st,
-                           const CellMask& mask = CellMask{});
+                           const CellMask& mask = CellMask{},
+                           const PlateBwd& pl = PlateBwd{});
 
 }  // namespace cm

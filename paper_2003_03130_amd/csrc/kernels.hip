@@ -8,11 +8,14 @@
 // The order of all additions is fixed by the layout: results are bitwise
 // repeatable.  Owned nodes are then written straight to the output; shared
 // nodes write a per-slot partial that the finalize kernel sums in tile order.
+// With a plate step fused in (plate.h), the same passes write the positions
+// after one compression step instead of the forces.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
 #include "kernels.h"
 #include "mr_tet.h"
+#include "plate.h"
 
 namespace cm {
 namespace {
@@ -22,9 +25,10 @@ struct FwdArgs {
   Range r;
   const float* y;
   float* f;
+  PlateFwd pl;  // used when PL
 };
 
-template <int W>
+template <int W, bool PL>
 __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
   extern __shared__ float4 lds[];
   const int lane = threadIdx.x & 63;
@@ -74,10 +78,20 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     });
     wave_sync();
 
-    for (int i = lane; i < d.n_own; i += 64) {
-      const int64_t g = d.own_begin + i;
-      const float4 v = fs[i];
-      a.f[g] = v.x; a.f[N + g] = v.y; a.f[2 * N + g] = v.z;
+    if constexpr (PL) {
+      const float top = (float)a.pl.plate[2 * d.cell];
+      const float bot = (float)a.pl.plate[2 * d.cell + 1];
+      for (int i = lane; i < d.n_own; i += 64) {
+        const float4 p = ys[i], v = fs[i];
+        plate_node_step(p.x, p.y, p.z, v.x, v.y, v.z, top, bot, a.pl.k, a.pl.m,
+                        a.pl.y_next, N, (int64_t)d.own_begin + i);
+      }
+    } else {
+      for (int i = lane; i < d.n_own; i += 64) {
+        const int64_t g = d.own_begin + i;
+        const float4 v = fs[i];
+        a.f[g] = v.x; a.f[N + g] = v.y; a.f[2 * N + g] = v.z;
+      }
     }
     for (int j = lane; j < d.n_shr; j += 64) {
       const int64_t s = d.shr_begin + j;
@@ -101,15 +115,20 @@ struct FinArgs {
   float* f;
   double* energy;
   int32_t* ninv;
+  const float* y;  // with a plate step
+  PlateFwd pl;
 };
 
 // The first cell_blocks workgroups sum the tile energies / inverted counts
 // of every cell, one wavefront per cell (lane l takes tiles l, l + 64, ...,
 // then a fixed butterfly: deterministic, and the cells' long chains of
 // loads run in parallel); the others sum the slot partials of every shared
-// node in tile order.
+// node in tile order.  With a plate step, the next plate_blocks workgroups
+// each reduce the top-plate force of one cell, and the shared nodes are
+// stepped instead of stored.
 __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
-                                                               int cell_blocks) {
+                                                               int cell_blocks,
+                                                               int plate_blocks) {
   if ((int)blockIdx.x < cell_blocks) {
     const int wv = ((int)blockIdx.x * 256 + (int)threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -131,8 +150,18 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
     }
     return;
   }
-  const int64_t gid = (int64_t)(blockIdx.x - cell_blocks) * blockDim.x + threadIdx.x;
   const int64_t N = a.T.n_nodes;
+  if ((int)blockIdx.x < cell_blocks + plate_blocks) {
+    __shared__ double red[16];
+    const int c = a.r.cell_begin + (int)blockIdx.x - cell_blocks;
+    const double F = plate_force_sum<256>(a.y + 2 * N, a.pl.node_off[c],
+                                          a.pl.node_off[c + 1],
+                                          (float)a.pl.plate[2 * c], a.pl.k, red);
+    if (threadIdx.x == 0) a.pl.force[c] = F;
+    return;
+  }
+  const int64_t gid =
+      (int64_t)(blockIdx.x - cell_blocks - plate_blocks) * blockDim.x + threadIdx.x;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
     float sx = 0.f, sy = 0.f, sz = 0.f;
@@ -144,13 +173,23 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
       sz += pp[2];
     }
     const int64_t g = a.T.shared_node[s];
-    a.f[g] = sx; a.f[N + g] = sy; a.f[2 * N + g] = sz;
+    if (a.pl.plate) {
+      const int c = cell_of_node(a.pl.node_off, a.T.n_cells, g);
+      plate_node_step(a.y[g], a.y[N + g], a.y[2 * N + g], sx, sy, sz,
+                      (float)a.pl.plate[2 * c], (float)a.pl.plate[2 * c + 1],
+                      a.pl.k, a.pl.m, a.pl.y_next, N, g);
+    } else {
+      a.f[g] = sx; a.f[N + g] = sy; a.f[2 * N + g] = sz;
+    }
   }
 }
 
 template <int W>
 hipError_t fwd_w(const FwdArgs& a, int grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(forward_kernel<W>, dim3(grid), dim3(64 * W), lds, st, a);
+  if (a.pl.plate)
+    hipLaunchKernelGGL((forward_kernel<W, true>), dim3(grid), dim3(64 * W), lds, st, a);
+  else
+    hipLaunchKernelGGL((forward_kernel<W, false>), dim3(grid), dim3(64 * W), lds, st, a);
   return hipGetLastError();
 }
 
@@ -160,9 +199,9 @@ size_t forward_lds_per_wave(int nloc) { return (size_t)32 * nloc; }
 
 hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
                                const LaunchCfg& cfg, const float* y, float* f,
-                               hipStream_t st) {
+                               hipStream_t st, const PlateFwd& pl) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
-  FwdArgs a{T, r, y, f};
+  FwdArgs a{T, r, y, f, pl};
   const int grid = grid_for(r, cfg);
   const size_t lds = forward_lds_per_wave(T.nloc) * cfg.waves;
   switch (cfg.waves) {
@@ -176,24 +215,27 @@ hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
 
 hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
                                    float* f, double* energy, int32_t* ninv,
-                                   hipStream_t st) {
+                                   hipStream_t st, const float* y,
+                                   const PlateFwd& pl) {
   const int64_t n_shr = r.shared_end - r.shared_begin;
   const int64_t n_cells = r.cell_end - r.cell_begin;
   if (n_shr <= 0 && n_cells <= 0) return hipSuccess;
   const int cell_blocks = (int)((n_cells + 3) / 4);  // four waves per block
-  const int64_t blocks = cell_blocks + (n_shr + 255) / 256;
-  FinArgs b{T, r, f, energy, ninv};
+  const int plate_blocks = pl.plate && pl.force ? (int)n_cells : 0;
+  const int64_t blocks = cell_blocks + plate_blocks + (n_shr + 255) / 256;
+  FinArgs b{T, r, f, energy, ninv, y, pl};
   hipLaunchKernelGGL(forward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                     st, b, cell_blocks);
+                     st, b, cell_blocks, plate_blocks);
   return hipGetLastError();
 }
 
 hipError_t launch_forward(const DeviceTables& T, const Range& r,
                           const LaunchCfg& cfg, const float* y, float* f,
-                          double* energy, int32_t* ninv, hipStream_t st) {
-  hipError_t e = launch_forward_main(T, r, cfg, y, f, st);
+                          double* energy, int32_t* ninv, hipStream_t st,
+                          const PlateFwd& pl) {
+  hipError_t e = launch_forward_main(T, r, cfg, y, f, st, pl);
   if (e != hipSuccess) return e;
-  return launch_forward_finalize(T, r, f, energy, ninv, st);
+  return launch_forward_finalize(T, r, f, energy, ninv, st, y, pl);
 }
 
 }  // namespace cm

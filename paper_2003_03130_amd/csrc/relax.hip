@@ -1,18 +1,14 @@
-// Plate compression steps for gfx950 (forward and adjoint).
-//
-// The paper compresses cells between two plates with a repulsive force that
-// keeps vertices out of the plates; the force law and the time integration
-// are in its missing supporting information.  The reading implemented here:
-//   p_z = -k max(0, y_z - top)^2 + k max(0, bottom - y_z)^2,
-//   y_next = y + m (f + p),      F = k sum max(0, y_z - top)^2,
-// with f the elastic forces (cm_forces), k the plate penalty and m the
-// mobility (time step over drag).  One workgroup per cell: the cell's nodes
-// are contiguous in the internal order; each thread walks a fixed strided
-// subset and the per-cell force is reduced in a fixed order, so the
-// result is deterministic.
+// Plate compression steps for gfx950 (forward and adjoint), stand-alone
+// passes over the nodes of every cell.  The per-node arithmetic and the
+// reading of the compression setup are in plate.h; the force and adjoint
+// passes can also apply the same steps in their epilogues.  One workgroup
+// per cell: the cell's nodes are contiguous in the internal order; each
+// thread walks a fixed strided subset and the per-cell force is reduced in
+// a fixed order, so the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "aux_kernels.h"
+#include "plate.h"
 
 namespace cm {
 namespace {
@@ -30,37 +26,17 @@ struct StepArgs {
   double* force;
 };
 
-// Workgroup sum in a fixed order: a butterfly inside each wavefront, then
-// the wavefront totals in wavefront order (deterministic).
-__device__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = red[0];
-#pragma unroll
-  for (int w = 1; w < kRelaxThreads / 64; ++w) r += red[w];
-  return r;
-}
-
 __global__ __launch_bounds__(kRelaxThreads) void plate_step_kernel(StepArgs a) {
-  __shared__ double red[kRelaxThreads];
+  __shared__ double red[16];
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1];
   const float top = (float)a.plate[2 * c], bot = (float)a.plate[2 * c + 1];
   const float k = (float)a.k, m = (float)a.m;
   const int64_t N = a.N;
-  double acc = 0.0;
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads) {
-    const float z = a.y[2 * N + i];
-    const float dt = fmaxf(z - top, 0.f), db = fmaxf(bot - z, 0.f);
-    const float pz = k * (db * db - dt * dt);
-    a.y_next[i] = a.y[i] + m * a.f[i];
-    a.y_next[N + i] = a.y[N + i] + m * a.f[N + i];
-    a.y_next[2 * N + i] = z + m * (a.f[2 * N + i] + pz);
-    acc += (double)(k * dt * dt);
-  }
-  const double s = block_sum(acc, red);
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads)
+    plate_node_step(a.y[i], a.y[N + i], a.y[2 * N + i], a.f[i], a.f[N + i],
+                    a.f[2 * N + i], top, bot, k, m, a.y_next, N, i);
+  const double s = plate_force_sum<kRelaxThreads>(a.y + 2 * N, n0, n1, top, k, red);
   if (threadIdx.x == 0 && a.force) a.force[c] = s;
 }
 
@@ -81,25 +57,18 @@ struct AdjArgs {
   float* lam;
 };
 
-// lam = lam_next + m ((df/dy)^T lam_next + dp/dy lam_next) + g dF/dy with
-// g = 2 scale (F_meas - F_target); dp_z/dy_z = -2k (max(0, z - top) +
-// max(0, bottom - z)), dF/dy_z = 2k max(0, z - top).
+// The reverse step of plate_step_kernel (plate.h).
 __global__ __launch_bounds__(kRelaxThreads) void plate_adjoint_kernel(AdjArgs a) {
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1];
   const float top = (float)a.plate[2 * c], bot = (float)a.plate[2 * c + 1];
   const float k = (float)a.k, m = (float)a.m;
-  const float g = a.F_target ? (float)(2.0 * a.scale * (a.F_meas[c] - a.F_target[c])) : 0.f;
+  const float g = plate_loss_weight(a.F_meas, a.F_target, a.scale, c);
   const int64_t N = a.N;
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads) {
-    const float z = a.y[2 * N + i];
-    const float dt = fmaxf(z - top, 0.f), db = fmaxf(bot - z, 0.f);
-    const float lz = a.lam_next[2 * N + i];
-    a.lam[i] = a.lam_next[i] + m * a.ybar_el[i];
-    a.lam[N + i] = a.lam_next[N + i] + m * a.ybar_el[N + i];
-    a.lam[2 * N + i] = lz + m * (a.ybar_el[2 * N + i] - 2.f * k * (dt + db) * lz) +
-                       g * 2.f * k * dt;
-  }
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads)
+    plate_node_adjoint(a.y[2 * N + i], a.lam_next[i], a.lam_next[N + i],
+                       a.lam_next[2 * N + i], a.ybar_el[i], a.ybar_el[N + i],
+                       a.ybar_el[2 * N + i], top, bot, k, m, g, a.lam, N, i);
   const int nq = 3 * a.n_regions;
   if ((int)threadIdx.x < nq && a.thetabar_acc) {
     const int64_t q = (int64_t)nq * c + threadIdx.x;

@@ -16,7 +16,11 @@ L = scale * sum_n sum_c (F_n,c - F*_n,c)^2.
 Reverse mode: lam_N = 0 and, for n = N-1 .. 0,
     lam_n = lam_{n+1} + m ((df/dy)^T + dp/dy) lam_{n+1} + dL/dy_n,
     dL/dtheta += m (df/dtheta)^T lam_{n+1},
-where (df/dy)^T lam and (df/dtheta)^T lam come from cm_forces_backward.  Only
+where (df/dy)^T lam and (df/dtheta)^T lam come from cm_forces_backward.  By
+default every step is one fused call (cm_plate_forces_step,
+cm_plate_backward_step: the force or adjoint pass applies the step in its
+epilogue); fused=False runs the two-call route (cm_forces + cm_plate_step,
+cm_forces_backward + cm_plate_step_adjoint).  Only
 every `checkpoint`-th state is kept during the forward sweep, plus the states
 of the last segment; every other segment is recomputed from its checkpoint
 during the reverse sweep (the recomputation is bitwise identical, so the
@@ -36,9 +40,11 @@ class PlateCompression:
     top: top-plate heights, shape (N,) (same for every cell) or (N, n_cells);
     bottom: bottom-plate height (scalar or (n_cells,)); k_plate: penalty;
     mobility: time step over drag; checkpoint: states kept every that many
-    steps during the forward sweep of gradient()."""
+    steps during the forward sweep of gradient(); fused: one library call
+    per step (else forces and plate step as two calls)."""
 
-    def __init__(self, batch, top, bottom, k_plate, mobility, checkpoint=20):
+    def __init__(self, batch, top, bottom, k_plate, mobility, checkpoint=20,
+                 fused=True):
         import torch
         self.cb = batch
         top = np.asarray(top, dtype=np.float64)
@@ -55,6 +61,7 @@ class PlateCompression:
         self.k = float(k_plate)
         self.m = float(mobility)
         self.checkpoint = int(checkpoint)
+        self.fused = bool(fused)
         if self.checkpoint < 1:
             raise ValueError("checkpoint must be >= 1")
         nn = 3 * batch.n_nodes
@@ -77,8 +84,24 @@ class PlateCompression:
 
     def _step(self, n, y, y_next, force):
         cb = self.cb
-        cb.forces(y, self._f, self._E)
-        cb.plate_step(y, self._f, self.plates[n], self.k, self.m, y_next, force)
+        if self.fused:
+            cb.plate_forces_step(y, self.plates[n], self.k, self.m, y_next,
+                                 force)
+        else:
+            cb.forces(y, self._f, self._E)
+            cb.plate_step(y, self._f, self.plates[n], self.k, self.m, y_next,
+                          force)
+
+    def _adjoint(self, n, y_n, lam, lam_new, F, F_target, scale, tacc):
+        cb = self.cb
+        if self.fused:
+            cb.plate_backward_step(y_n, lam, self.plates[n], self.k, self.m,
+                                   lam_new, F[n], F_target[n], scale, tacc)
+        else:
+            cb.backward(y_n, lam, None, self._ybar, self._tb)
+            cb.plate_step_adjoint(y_n, lam, self._ybar, self.plates[n],
+                                  self.k, self.m, lam_new, F[n], F_target[n],
+                                  scale, self._tb, tacc)
 
     def forward(self, y0, keep_every=None, tail=None):
         """Runs all steps from y0 (device SoA).  Returns (F (N, n_cells)
@@ -125,15 +148,10 @@ class PlateCompression:
                 # plate forces F_n come from the forward sweep)
                 seg_states[0].copy_(kept[s0])
                 for j in range(s1 - s0 - 1):
-                    cb.forces(seg_states[j], self._f, self._E)
-                    cb.plate_step(seg_states[j], self._f, self.plates[s0 + j],
-                                  self.k, self.m, seg_states[j + 1], None)
+                    self._step(s0 + j, seg_states[j], seg_states[j + 1], None)
             for j in reversed(range(s1 - s0)):
                 n = s0 + j
-                y_n = seg_states[j]
-                cb.backward(y_n, lam, None, self._ybar, self._tb)
-                cb.plate_step_adjoint(y_n, lam, self._ybar, self.plates[n],
-                                      self.k, self.m, lam_new, F[n],
-                                      F_target[n], scale, self._tb, tacc)
+                self._adjoint(n, seg_states[j], lam, lam_new, F, F_target,
+                              scale, tacc)
                 lam, lam_new = lam_new, lam
         return loss, tacc.view(-1, 3), F
