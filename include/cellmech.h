@@ -326,8 +326,11 @@ int cm_plate_step_adjoint(cm_batch h, const float* y, const float* lam_next,
  * cm_forces followed by cm_plate_step, and one adjoint pass instead of
  * cm_forces_backward followed by cm_plate_step_adjoint): the intermediate f,
  * ybar_el and thetabar_el are never stored.  Same reading and arguments as
- * above; the per-node arithmetic and the reduction orders are those of the
- * two-call route, and the results are bitwise equal to it.
+ * above.  The per-node arithmetic is that of the two-call route: y_next,
+ * lam, thetabar_acc, energy and inverted counts are bitwise equal to it.
+ * The top-plate force sums the same float64 node terms in another fixed
+ * order (each tile's share, then the nodes of no tetrahedron), so it agrees
+ * to rounding and is bitwise repeatable.
  *   cm_plate_forces_step: y_next, force (nullable) and, if given, the
  *     per-cell energy and inverted count of cm_forces at y.
  *   cm_plate_backward_step: lam from lam_next (the cotangent of the forces

@@ -192,17 +192,51 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
   h->new_to_old = std::move(P.new_to_old);
 
   cm::DeviceTables& T = h->T;
+  // host tables built here are copied asynchronously: they live until the
+  // stream synchronisation below
+  std::vector<int32_t> shared_cell, orphan_off, orphan, slot_first;
+  std::vector<int4> pc;
+  std::vector<int2> nbk;
   {
     cm::TileDesc* tiles;
     cm::TetChunk* chunks;
-    int32_t *slot_node, *shared_node, *ssp, *ss, *ctf, *ctc, *tmat, *mtf, *mtc;
+    int32_t *slot_node, *shared_node, *ssp, *ss, *ctf, *ctc, *tmat, *mtf, *mtc, *scell;
+    int32_t *orph_off, *orph, *sfirst;
     int64_t* noff;
+    // cell of every shared node; slot_node with bit 31 on the first slot of
+    // every shared node; shared nodes in no slot (nodes of no tetrahedron),
+    // grouped by cell
+    const size_t n_shr = P.shared_node.size();
+    shared_cell.assign(n_shr, 0);
+    orphan_off.assign(h->n_cells + 1, 0);
+    slot_first.assign(P.slot_node.begin(), P.slot_node.end());
+    for (size_t s = 0; s < n_shr; ++s) {
+      shared_cell[s] = (int32_t)(std::upper_bound(P.node_off.begin(), P.node_off.end(),
+                                                  (int64_t)P.shared_node[s]) -
+                                 P.node_off.begin() - 1);
+      if (P.shared_slot_ptr[s] < P.shared_slot_ptr[s + 1])
+        slot_first[P.shared_slots[P.shared_slot_ptr[s]]] |= INT32_MIN;
+      else
+        ++orphan_off[shared_cell[s] + 1];
+    }
+    for (int64_t c = 0; c < h->n_cells; ++c) orphan_off[c + 1] += orphan_off[c];
+    orphan.resize(orphan_off[h->n_cells]);
+    {
+      std::vector<int32_t> fill(orphan_off.begin(), orphan_off.end() - 1);
+      for (size_t s = 0; s < n_shr; ++s)
+        if (P.shared_slot_ptr[s] == P.shared_slot_ptr[s + 1])
+          orphan[fill[shared_cell[s]]++] = P.shared_node[s];
+    }
     if ((rc = h->upload(&tiles, P.tiles, stream)) ||
         (rc = h->upload(&chunks, P.chunks, stream)) ||
         (rc = h->upload(&slot_node, P.slot_node, stream)) ||
         (rc = h->upload(&shared_node, P.shared_node, stream)) ||
         (rc = h->upload(&ssp, P.shared_slot_ptr, stream)) ||
         (rc = h->upload(&ss, P.shared_slots, stream)) ||
+        (rc = h->upload(&scell, shared_cell, stream)) ||
+        (rc = h->upload(&sfirst, slot_first, stream)) ||
+        (rc = h->upload(&orph_off, orphan_off, stream)) ||
+        (rc = h->upload(&orph, orphan, stream)) ||
         (rc = h->upload(&ctf, P.cell_tile_first, stream)) ||
         (rc = h->upload(&ctc, P.cell_tile_count, stream)) ||
         (rc = h->upload(&tmat, P.tile_mat, stream)) ||
@@ -217,6 +251,10 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     T.shared_node = shared_node;
     T.shared_slot_ptr = ssp;
     T.shared_slots = ss;
+    T.shared_cell = scell;
+    T.slot_node_first = sfirst;
+    T.orphan_off = orph_off;
+    T.orphan_node = orph;
     T.cell_tile_first = ctf;
     T.cell_tile_count = ctc;
     T.tile_stride = P.tile_stride;
@@ -225,20 +263,20 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     T.mat_tile_count = mtc;
     double* params;
     float *part, *part_b;
-    double *tile_acc, *tile_acc_b;
+    double *tile_acc, *tile_acc_b, *tile_plate;
     int32_t* tile_ninv;
     if ((rc = h->alloc(&params, 3 * (size_t)h->n_mat)) ||
         (rc = h->alloc(&part, 3 * (size_t)h->n_slots)) ||
         (rc = h->alloc(&part_b, 3 * (size_t)h->n_slots)) ||
         (rc = h->alloc(&tile_acc, (size_t)h->n_tiles)) ||
         (rc = h->alloc(&tile_acc_b, 3 * (size_t)h->n_tiles)) ||
+        (rc = h->alloc(&tile_plate, (size_t)h->n_tiles)) ||
         (rc = h->alloc(&tile_ninv, (size_t)h->n_tiles)))
       return bail(rc);
     // 256 x 256 node-pair blocks of every cell (row block <= column block);
     // the cell's nodes are ordered candidates first, so the pairs of the
     // first ceil(candidates / 256) blocks hold every candidate pair
-    std::vector<int4> pc;
-    std::vector<int2> nbk;  // the candidate node blocks of every cell
+    // pc: the candidate pair blocks; nbk: the candidate node blocks of every cell
     for (int64_t c = 0; c < h->n_cells; ++c) {
       const int64_t nb = (P.node_off[c + 1] - P.node_off[c] + 255) / 256;
       int64_t bc = ((int64_t)P.cell_candidates[c] + 255) / 256;
@@ -280,6 +318,7 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     T.params = params;
     T.part = part;
     T.tile_acc = tile_acc;
+    T.tile_plate = tile_plate;
     T.tile_ninv = tile_ninv;
     h->Tb = T;
     h->Tb.part = part_b;
@@ -526,7 +565,7 @@ int cm_forces_backward_cells(cm_batch h, const float* y, const float* fbar,
   if (int rc = check_handle(h)) return rc;
   if (!cell_flags) return fail(CM_EINVAL, "cell_flags must be a device pointer");
   if (flag_stride < 1) return fail(CM_EINVAL, "flag_stride must be >= 1");
-  cm::CellMask mask{cell_flags, flag_stride, h->d_node_off, (int32_t)h->n_cells};
+  cm::CellMask mask{cell_flags, flag_stride};
   return backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, false, mask);
 }
 
@@ -864,7 +903,6 @@ int cm_plate_forces_step(cm_batch h, const float* y, const double* plate,
   if (int rc = select_device(h)) return rc;
   cm::PlateFwd pl;
   pl.plate = plate;
-  pl.node_off = h->d_node_off;
   pl.k = (float)k_plate;
   pl.m = (float)mobility;
   pl.y_next = y_next;
@@ -893,7 +931,6 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
   if (int rc = select_device(h)) return rc;
   cm::PlateBwd pl;
   pl.plate = plate;
-  pl.node_off = h->d_node_off;
   pl.k = (float)k_plate;
   pl.m = (float)mobility;
   pl.m64 = mobility;

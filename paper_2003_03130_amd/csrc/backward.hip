@@ -56,6 +56,13 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     const double w = a.T.params[2 * nm + mt];
     const Material mat{w * mu, (1.0 - w) * mu, kappa};
     const double eb = a.ebar ? a.ebar[d.cell] : 0.0;
+    // plate step: per-cell values read here, long before the epilogue
+    float top = 0.f, bot = 0.f, gw = 0.f;
+    if constexpr (PL) {
+      top = (float)a.pl.plate[2 * d.cell];
+      bot = (float)a.pl.plate[2 * d.cell + 1];
+      gw = plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, d.cell);
+    }
 
     for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
       const int64_t g = l < d.n_own ? (int64_t)d.own_begin + l
@@ -99,9 +106,6 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     wave_sync();
 
     if constexpr (PL) {
-      const float top = (float)a.pl.plate[2 * d.cell];
-      const float bot = (float)a.pl.plate[2 * d.cell + 1];
-      const float gw = plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, d.cell);
       for (int i = lane; i < d.n_own; i += 64) {
         const float4 p = ys[i], v = gs[i];
         const float2 l = vs[i];
@@ -191,8 +195,20 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
     const int64_t g = a.T.shared_node[s];
-    if (!m.flags ||
-        m.flags[(int64_t)cell_of_node(m.node_off, m.n_cells, g) * m.stride] != 0.0) {
+    if (!m.flags || m.flags[(int64_t)a.T.shared_cell[s] * m.stride] != 0.0) {
+      // plate step: the node's values are loaded before the partial sums,
+      // so that the two chains of loads overlap
+      float pz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f, top = 0.f, bot = 0.f, gw = 0.f;
+      if (a.pl.plate) {
+        const int c = a.T.shared_cell[s];
+        pz = a.y[2 * N + g];
+        lx = a.lam_next[g];
+        ly = a.lam_next[N + g];
+        lz = a.lam_next[2 * N + g];
+        top = (float)a.pl.plate[2 * c];
+        bot = (float)a.pl.plate[2 * c + 1];
+        gw = plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, c);
+      }
       float sx = 0.f, sy = 0.f, sz = 0.f;
       for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
         const int64_t sl = a.T.shared_slots[q];
@@ -202,12 +218,7 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
         sz += pp[2];
       }
       if (a.pl.plate) {
-        const int c = cell_of_node(a.pl.node_off, a.T.n_cells, g);
-        plate_node_adjoint(a.y[2 * N + g], a.lam_next[g], a.lam_next[N + g],
-                           a.lam_next[2 * N + g], sx, sy, sz,
-                           (float)a.pl.plate[2 * c], (float)a.pl.plate[2 * c + 1],
-                           a.pl.k, a.pl.m,
-                           plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, c),
+        plate_node_adjoint(pz, lx, ly, lz, sx, sy, sz, top, bot, a.pl.k, a.pl.m, gw,
                            a.pl.lam, N, g);
       } else {
         a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;

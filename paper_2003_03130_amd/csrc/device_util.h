@@ -109,17 +109,6 @@ __device__ __forceinline__ void block_tiles(const Range& r, int& t0, int& t1) {
   t1 = r.tile_begin + (int)((int64_t)(lb + 1) * ntl / G);
 }
 
-// Cell of internal node g (cells keep contiguous node ranges;
-// node_off[0] <= g < node_off[n_cells]).
-__device__ inline int cell_of_node(const int64_t* node_off, int n_cells, int64_t g) {
-  int lo = 0, hi = n_cells;  // node_off[lo] <= g < node_off[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (node_off[mid] <= g) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 inline int grid_for(const Range& r, const LaunchCfg& cfg) {
   const int64_t ntl = r.tile_end - r.tile_begin;
   const int64_t groups = (ntl + cfg.waves - 1) / cfg.waves;

@@ -16,6 +16,14 @@ struct DeviceTables {
   const int32_t* shared_node = nullptr;
   const int32_t* shared_slot_ptr = nullptr;
   const int32_t* shared_slots = nullptr;
+  const int32_t* shared_cell = nullptr;  // cell of every shared node
+  // slot_node with bit 31 set on the first slot of every shared node (the
+  // one slot whose tile adds the node's top-plate force to its sum)
+  const int32_t* slot_node_first = nullptr;
+  // shared nodes of no tetrahedron, per cell: orphan_node[orphan_off[c] ..
+  // orphan_off[c + 1])
+  const int32_t* orphan_off = nullptr;
+  const int32_t* orphan_node = nullptr;
   // tiles of cell c: cell_tile_first[c] + k * tile_stride, k < cell_tile_count[c]
   const int32_t* cell_tile_first = nullptr;
   const int32_t* cell_tile_count = nullptr;
@@ -30,6 +38,7 @@ struct DeviceTables {
   const double* params = nullptr;  // SoA: mu[n_mat], kappa[n_mat], w[n_mat]
   float* part = nullptr;           // slot partials, (x, y, z) per slot
   double* tile_acc = nullptr;      // per tile: energy (fwd) or 3 sums (bwd)
+  double* tile_plate = nullptr;    // per tile: top-plate force (fwd)
   int32_t* tile_ninv = nullptr;    // per tile
   int64_t n_nodes = 0, n_slots = 0, n_tiles = 0;
   int32_t n_cells = 0;
@@ -44,20 +53,16 @@ struct Range {
 };
 
 // Restricts a backward pass to the cells c with flags[c * stride] != 0 (all
-// cells when flags is null); node_off (device, n_cells + 1 entries) finds
-// the cell of a shared node.
+// cells when flags is null).
 struct CellMask {
   const double* flags = nullptr;
   int64_t stride = 1;
-  const int64_t* node_off = nullptr;
-  int32_t n_cells = 0;
 };
 
 // Arguments of a force pass with the plate step fused in: the pass writes
-// y_next instead of the forces.
+// y_next instead of the forces, and the top-plate force per cell.
 struct PlateFwd {
   const double* plate = nullptr;     // per cell: top, bottom (null: no step)
-  const int64_t* node_off = nullptr;  // n_cells + 1 node offsets
   float k = 0.f, m = 0.f;
   float* y_next = nullptr;
   double* force = nullptr;           // per cell, nullable
@@ -68,7 +73,6 @@ struct PlateFwd {
 // adds m thetabar to thetabar_acc instead of storing thetabar.
 struct PlateBwd {
   const double* plate = nullptr;     // null: no step
-  const int64_t* node_off = nullptr;
   float k = 0.f, m = 0.f;
   double m64 = 0.0;
   const double* F_meas = nullptr;    // with F_target

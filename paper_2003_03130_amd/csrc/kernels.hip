@@ -49,11 +49,30 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     const double kappa = a.T.params[nm + mt];
     const double w = a.T.params[2 * nm + mt];
     const Material mat{w * mu, (1.0 - w) * mu, kappa};
+    // plate step: the plates are read here, long before the epilogue needs
+    // them; the 4th LDS component flags the nodes whose top-plate force this
+    // tile adds (its owned nodes and the shared nodes of their first slot)
+    float top = 0.f, bot = 0.f;
+    if constexpr (PL) {
+      top = (float)a.pl.plate[2 * d.cell];
+      bot = (float)a.pl.plate[2 * d.cell + 1];
+    }
 
     for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
-      const int64_t g = l < d.n_own ? (int64_t)d.own_begin + l
-                                    : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
-      ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], 0.f);
+      int64_t g;
+      float flag = 0.f;
+      if constexpr (PL) {
+        // one int32 load per shared node as in the plain pass, from the copy
+        // of slot_node that carries the first-slot flag in bit 31
+        const int32_t v = l < d.n_own ? INT32_MIN | (d.own_begin + l)
+                                      : a.T.slot_node_first[d.shr_begin + l - d.n_own];
+        g = v & 0x7fffffff;
+        flag = v < 0 ? 1.f : 0.f;
+      } else {
+        g = l < d.n_own ? (int64_t)d.own_begin + l
+                        : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
+      }
+      ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], flag);
       fs[l] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     wave_sync();
@@ -79,13 +98,21 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     wave_sync();
 
     if constexpr (PL) {
-      const float top = (float)a.pl.plate[2 * d.cell];
-      const float bot = (float)a.pl.plate[2 * d.cell + 1];
+      // the step of the owned nodes, and the tile's share of the top-plate
+      // force (the flagged nodes)
+      double fp = 0.0;
       for (int i = lane; i < d.n_own; i += 64) {
         const float4 p = ys[i], v = fs[i];
         plate_node_step(p.x, p.y, p.z, v.x, v.y, v.z, top, bot, a.pl.k, a.pl.m,
                         a.pl.y_next, N, (int64_t)d.own_begin + i);
+        fp += plate_top_term(p.z, top, a.pl.k);
       }
+      for (int j = lane; j < d.n_shr; j += 64) {
+        const float4 p = ys[d.n_own + j];
+        if (p.w != 0.f) fp += plate_top_term(p.z, top, a.pl.k);
+      }
+      fp = wave_sum(fp);
+      if (lane == 0) a.T.tile_plate[t] = fp;
     } else {
       for (int i = lane; i < d.n_own; i += 64) {
         const int64_t g = d.own_begin + i;
@@ -123,12 +150,10 @@ struct FinArgs {
 // of every cell, one wavefront per cell (lane l takes tiles l, l + 64, ...,
 // then a fixed butterfly: deterministic, and the cells' long chains of
 // loads run in parallel); the others sum the slot partials of every shared
-// node in tile order.  With a plate step, the next plate_blocks workgroups
-// each reduce the top-plate force of one cell, and the shared nodes are
-// stepped instead of stored.
+// node in tile order (with a plate step, the shared nodes are stepped
+// instead of stored).
 __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
-                                                               int cell_blocks,
-                                                               int plate_blocks) {
+                                                               int cell_blocks) {
   if ((int)blockIdx.x < cell_blocks) {
     const int wv = ((int)blockIdx.x * 256 + (int)threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -148,22 +173,35 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
       if (a.energy) a.energy[c] = e;
       if (a.ninv) a.ninv[c] = ni;
     }
+    if (a.pl.force) {
+      // top-plate force: the tile shares, then the nodes of no tetrahedron
+      double fp = 0.0;
+      for (int k = lane; k < nt; k += 64)
+        fp += a.T.tile_plate[t0 + (int64_t)k * a.T.tile_stride];
+      const float top = (float)a.pl.plate[2 * c];
+      for (int o = a.T.orphan_off[c] + lane; o < a.T.orphan_off[c + 1]; o += 64)
+        fp += plate_top_term(a.y[2 * a.T.n_nodes + a.T.orphan_node[o]], top, a.pl.k);
+      fp = wave_sum(fp);
+      if (lane == 0) a.pl.force[c] = fp;
+    }
     return;
   }
   const int64_t N = a.T.n_nodes;
-  if ((int)blockIdx.x < cell_blocks + plate_blocks) {
-    __shared__ double red[16];
-    const int c = a.r.cell_begin + (int)blockIdx.x - cell_blocks;
-    const double F = plate_force_sum<256>(a.y + 2 * N, a.pl.node_off[c],
-                                          a.pl.node_off[c + 1],
-                                          (float)a.pl.plate[2 * c], a.pl.k, red);
-    if (threadIdx.x == 0) a.pl.force[c] = F;
-    return;
-  }
-  const int64_t gid =
-      (int64_t)(blockIdx.x - cell_blocks - plate_blocks) * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)(blockIdx.x - cell_blocks) * blockDim.x + threadIdx.x;
   if (gid < a.r.shared_end - a.r.shared_begin) {
     const int s = a.r.shared_begin + (int)gid;
+    const int64_t g = a.T.shared_node[s];
+    // plate step: the node's position and plates are loaded before the
+    // partial sums, so that the two chains of loads overlap
+    float px = 0.f, py = 0.f, pz = 0.f, top = 0.f, bot = 0.f;
+    if (a.pl.plate) {
+      const int c = a.T.shared_cell[s];
+      px = a.y[g];
+      py = a.y[N + g];
+      pz = a.y[2 * N + g];
+      top = (float)a.pl.plate[2 * c];
+      bot = (float)a.pl.plate[2 * c + 1];
+    }
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
       const int64_t sl = a.T.shared_slots[q];
@@ -172,12 +210,9 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
       sy += pp[1];
       sz += pp[2];
     }
-    const int64_t g = a.T.shared_node[s];
     if (a.pl.plate) {
-      const int c = cell_of_node(a.pl.node_off, a.T.n_cells, g);
-      plate_node_step(a.y[g], a.y[N + g], a.y[2 * N + g], sx, sy, sz,
-                      (float)a.pl.plate[2 * c], (float)a.pl.plate[2 * c + 1],
-                      a.pl.k, a.pl.m, a.pl.y_next, N, g);
+      plate_node_step(px, py, pz, sx, sy, sz, top, bot, a.pl.k, a.pl.m, a.pl.y_next, N,
+                      g);
     } else {
       a.f[g] = sx; a.f[N + g] = sy; a.f[2 * N + g] = sz;
     }
@@ -221,11 +256,10 @@ hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
   const int64_t n_cells = r.cell_end - r.cell_begin;
   if (n_shr <= 0 && n_cells <= 0) return hipSuccess;
   const int cell_blocks = (int)((n_cells + 3) / 4);  // four waves per block
-  const int plate_blocks = pl.plate && pl.force ? (int)n_cells : 0;
-  const int64_t blocks = cell_blocks + plate_blocks + (n_shr + 255) / 256;
+  const int64_t blocks = cell_blocks + (n_shr + 255) / 256;
   FinArgs b{T, r, f, energy, ninv, y, pl};
   hipLaunchKernelGGL(forward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                     st, b, cell_blocks, plate_blocks);
+                     st, b, cell_blocks);
   return hipGetLastError();
 }
 

@@ -51,44 +51,11 @@ __device__ inline void plate_node_adjoint(float yz, float lx, float ly, float lz
   lam[2 * N + i] = lz + m * (bz - 2.f * k * (dt + db) * lz) + g * 2.f * k * dt;
 }
 
-// Top-plate force of the nodes [n0, n1) of one cell, reduced in one fixed
-// order whatever the workgroup size NT (a divisor of 1024 and a multiple of
-// 64): virtual thread v < 1024 sums the nodes n0 + v, n0 + v + 1024, ...;
-// the 64 virtual threads of each virtual wavefront are combined by a
-// butterfly and the 16 wavefront totals in order.  red: 16 doubles of
-// LDS.  Every thread of the workgroup must call it; all get the total.
-template <int NT>
-__device__ double plate_force_sum(const float* z, int64_t n0, int64_t n1,
-                                  float top, float k, double* red) {
-  static_assert(1024 % NT == 0 && NT % 64 == 0, "workgroup size");
-  constexpr int J = 1024 / NT;
-  double acc[J];
-#pragma unroll
-  for (int j = 0; j < J; ++j) acc[j] = 0.0;
-  // the J virtual threads of a thread advance together (independent loads)
-  for (int64_t b = n0 + threadIdx.x; b < n1; b += 1024) {
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int64_t i = b + j * NT;
-      if (i < n1) {
-        const float dt = fmaxf(z[i] - top, 0.f);
-        acc[j] += (double)(k * dt * dt);
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    double v = acc[j];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) red[(threadIdx.x + j * NT) >> 6] = v;
-  }
-  __syncthreads();
-  double r = red[0];
-#pragma unroll
-  for (int w = 1; w < 16; ++w) r += red[w];
-  __syncthreads();  // red may be reused after the return
-  return r;
+// One node's term of the top-plate force, k max(0, z - top)^2 (float32
+// product, accumulated in float64 by the callers).
+__device__ inline double plate_top_term(float z, float top, float k) {
+  const float dt = fmaxf(z - top, 0.f);
+  return (double)(k * dt * dt);
 }
 
 }  // namespace cm

@@ -26,17 +26,34 @@ struct StepArgs {
   double* force;
 };
 
+// Workgroup sum in a fixed order: a butterfly inside each wavefront, then
+// the wavefront totals in wavefront order (deterministic).
+__device__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < kRelaxThreads / 64; ++w) r += red[w];
+  return r;
+}
+
 __global__ __launch_bounds__(kRelaxThreads) void plate_step_kernel(StepArgs a) {
-  __shared__ double red[16];
+  __shared__ double red[kRelaxThreads / 64];
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1];
   const float top = (float)a.plate[2 * c], bot = (float)a.plate[2 * c + 1];
   const float k = (float)a.k, m = (float)a.m;
   const int64_t N = a.N;
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads)
-    plate_node_step(a.y[i], a.y[N + i], a.y[2 * N + i], a.f[i], a.f[N + i],
-                    a.f[2 * N + i], top, bot, k, m, a.y_next, N, i);
-  const double s = plate_force_sum<kRelaxThreads>(a.y + 2 * N, n0, n1, top, k, red);
+  double acc = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kRelaxThreads) {
+    const float z = a.y[2 * N + i];
+    plate_node_step(a.y[i], a.y[N + i], z, a.f[i], a.f[N + i], a.f[2 * N + i], top,
+                    bot, k, m, a.y_next, N, i);
+    acc += plate_top_term(z, top, k);
+  }
+  const double s = block_sum(acc, red);
   if (threadIdx.x == 0 && a.force) a.force[c] = s;
 }
 
