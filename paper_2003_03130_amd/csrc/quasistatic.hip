@@ -67,6 +67,14 @@ __device__ void sym3_inverse(const double m[6], float o[6]) {
   o[3] = (float)(c01 * r); o[4] = (float)(c02 * r); o[5] = (float)(c12 * r);
 }
 
+// z = M r for one symmetric 3x3 block m = (xx yy zz xy xz yz).
+__device__ __forceinline__ void sym3_mul(const float* m, float rx, float ry, float rz,
+                                         float& zx, float& zy, float& zz) {
+  zx = m[0] * rx + m[3] * ry + m[4] * rz;
+  zy = m[3] * rx + m[1] * ry + m[5] * rz;
+  zz = m[4] * rx + m[5] * ry + m[2] * rz;
+}
+
 // z = Minv r for node i (Minv SoA: xx yy zz xy xz yz, 6 n_nodes floats).
 __device__ __forceinline__ void apply_minv(const float* mi, int64_t N, int64_t i,
                                            float rx, float ry, float rz, float& zx,
@@ -302,11 +310,104 @@ struct CgArgs {
   const float* minv;  // preconditioner blocks (6 n_nodes), nullable
 };
 
+// Nodes per thread up to which a cell's CG iteration keeps every operand in
+// registers (cells of at most kRegNodes * kThreads nodes).
+constexpr int kRegNodes = 4;
+
+__device__ __forceinline__ void cg_finish(const CgArgs& a, double* s, double rn,
+                                          double rzn) {
+  if (threadIdx.x == 0) {
+    s[0] = rzn;
+    const double tol = fmax(a.rel_tol, s[14]);
+    if (rn <= tol * tol * s[1]) s[2] = 0.0;
+  }
+}
+
+// The iteration of qs_cg_kernel for a cell of at most kRegNodes * kThreads
+// nodes: p, r, x, Hess(Pi) p and the preconditioner block of every node are
+// loaded once, in one wave of loads, and kept in registers through the
+// three phases (Ap is not stored).  Same operations in the same order as the
+// streaming version (which fused multiply-adds the compiler forms may
+// differ between the two, a last-bit difference).
+__device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
+                             double top, double bot, double* red) {
+  const int64_t N = a.N;
+  float p[kRegNodes][3], r[kRegNodes][3], ap[kRegNodes][3], x[kRegNodes][3];
+  float m[kRegNodes][6];
+  double pap = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRegNodes; ++u) {
+    const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < n1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        p[u][d] = a.p[d * N + i];
+        r[u][d] = a.r[d * N + i];
+        x[u][d] = a.x[d * N + i];
+      }
+      if (a.minv) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) m[u][q] = a.minv[q * N + i];
+      }
+      const double z = a.y[2 * N + i];
+      const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+      ap[u][0] = -a.ybar[i];
+      ap[u][1] = -a.ybar[N + i];
+      ap[u][2] = (float)(-(double)a.ybar[2 * N + i] + h * (double)p[u][2]);
+      pap += (double)p[u][0] * ap[u][0] + (double)p[u][1] * ap[u][1] +
+             (double)p[u][2] * ap[u][2];
+    }
+  }
+  pap = block_sum(pap, red);
+  const double rs = s[0];
+  if (!(pap > 0.0)) {
+    if (threadIdx.x == 0) s[2] = 0.0;
+    return;
+  }
+  const float alpha = (float)(rs / pap);
+  double rn = 0.0, rzn = 0.0;
+  float zv[kRegNodes][3];
+#pragma unroll
+  for (int u = 0; u < kRegNodes; ++u) {
+    const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < n1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int64_t q = d * N + i;
+        a.x[q] = x[u][d] + alpha * p[u][d];
+        r[u][d] = r[u][d] - alpha * ap[u][d];
+        a.r[q] = r[u][d];
+        rn += (double)r[u][d] * r[u][d];
+      }
+      zv[u][0] = r[u][0];
+      zv[u][1] = r[u][1];
+      zv[u][2] = r[u][2];
+      if (a.minv) sym3_mul(m[u], r[u][0], r[u][1], r[u][2], zv[u][0], zv[u][1], zv[u][2]);
+      rzn += (double)r[u][0] * zv[u][0] + (double)r[u][1] * zv[u][1] +
+             (double)r[u][2] * zv[u][2];
+    }
+  }
+  rn = block_sum(rn, red);
+  rzn = block_sum(rzn, red);
+  const float beta = (float)(rzn / rs);
+#pragma unroll
+  for (int u = 0; u < kRegNodes; ++u) {
+    const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < n1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.p[d * N + i] = zv[u][d] + beta * p[u][d];
+    }
+  }
+  cg_finish(a, s, rn, rzn);
+}
+
 // One (preconditioned) CG iteration per active cell, z = M^-1 r (z = r
 // without preconditioner): Ap = Hess(Pi) p, alpha = r.z / p.Ap, x += alpha p,
 // r -= alpha Ap, beta = r_new.z_new / r.z, p = z_new + beta p.  A cell stops
 // at |r| <= max(rel_tol, eta) |r_0| (eta the forcing term of the Newton
-// step, 0 without forcing) or on non-positive curvature.
+// step, 0 without forcing) or on non-positive curvature.  Cells of up to
+// kRegNodes * kThreads nodes keep their operands in registers; larger ones
+// stream them three times (Ap through memory).
 __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -314,7 +415,12 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   if (s[2] == 0.0) return;  // uniform over the workgroup
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  if (n1 - n0 <= (int64_t)kRegNodes * kThreads) {
+    cg_step_regs(a, s, n0, n1, top, bot, red);
+    return;
+  }
   double pap = 0.0;
+
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     const double z = a.y[2 * N + i];
     const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
@@ -357,11 +463,7 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
       a.p[q] = z[d] + beta * a.p[q];
     }
   }
-  if (threadIdx.x == 0) {
-    s[0] = rzn;
-    const double tol = fmax(a.rel_tol, s[14]);
-    if (rn <= tol * tol * s[1]) s[2] = 0.0;
-  }
+  cg_finish(a, s, rn, rzn);
 }
 
 // Float32 floor of the residual.  Positions held in float32 carry rounding

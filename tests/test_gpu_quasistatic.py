@@ -220,3 +220,84 @@ def test_stiffness_blocks_with_material_regions():
         want = _stiffness_blocks(cell.x, cell.tets, th[3 * c + r, 0], th[3 * c + r, 1])
         err = np.abs(got[n0:n1] - want).max() / np.abs(want).max()
         assert err <= 1e-5, (c, err)
+
+
+@pytest.mark.parametrize("precondition", [True, False])
+def test_cg_step_against_its_formula(precondition):
+    """One cm_qs_cg_step on a cell of 1,500 nodes (operands held in
+    registers) and one of 6,000 (more than 4 per thread of the 1,024-thread
+    workgroup: operands streamed), against the iteration written out in
+    float64 on the CPU from the same inputs: Ap = -ybar + penalty Hessian p,
+    alpha = r.z / p.Ap, x += alpha p, r -= alpha Ap, z = M r, beta =
+    r_new.z_new / r.z, p = z + beta p, and the stop test.  Float32 state:
+    1e-5 of the largest value."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd import _native as nat
+    from paper_2003_03130_amd.cells import _ptr, _stream
+    xs, ts = zip(*[sphere_mesh(n, 40 + n) for n in (1500, 6000)])
+    sizes = [len(x) for x in xs]
+    assert sizes[0] <= 4096 < sizes[1]
+    node_off = np.cumsum([0] + sizes)
+    tet_off = np.cumsum([0] + [len(t) for t in ts])
+    cb = CellBatch(node_off, tet_off, np.concatenate(xs), np.concatenate(ts))
+    N, C = cb.n_nodes, cb.n_cells
+    rng = np.random.default_rng(41)
+    yh = np.concatenate(xs).astype(np.float32)
+    ph, rh, xh = (rng.normal(size=(N, 3)).astype(np.float32) for _ in range(3))
+    ybh = (-(2.0 * ph + 0.1 * rng.normal(size=(N, 3)))).astype(np.float32)
+    diag = (1.0 + rng.uniform(size=(N, 3))).astype(np.float32)
+    off = (0.1 * rng.uniform(-1, 1, size=(N, 3))).astype(np.float32)
+    y, p, r, x, ybar = (cb.to_device(a) for a in (yh, ph, rh, xh, ybh))
+    minv = torch.cat([cb.to_device(diag), cb.to_device(off)]) if precondition else None
+    Ap = cb.empty_nodes()
+    k, rel_tol, top, bot = 100.0, 1e-3, 0.7, -0.7
+    plate = torch.tensor([[top, bot]] * C, dtype=torch.float64, device=cb.device)
+    # host copies in the internal order (SoA; each cell's range preserved)
+    Y, P, R, X, YB = (t.cpu().numpy().astype(np.float64).reshape(3, N)
+                      for t in (y, p, r, x, ybar))
+    M = minv.cpu().numpy().astype(np.float64).reshape(6, N) if precondition else None
+
+    def mul(v):
+        if M is None:
+            return v.copy()
+        xx, yy, zz, xy, xz, yz = M
+        return np.stack([xx * v[0] + xy * v[1] + xz * v[2],
+                         xy * v[0] + yy * v[1] + yz * v[2],
+                         xz * v[0] + yz * v[1] + zz * v[2]])
+
+    state = np.zeros((C, 16))
+    Z0 = mul(R)
+    for c in range(C):
+        sl = slice(node_off[c], node_off[c + 1])
+        state[c, 0] = (R[:, sl] * Z0[:, sl]).sum()
+        state[c, 1] = [1e-30, 1e30][c]  # cell 1 stops, cell 0 does not
+        state[c, 2] = 1.0
+        state[c, 14] = 0.1
+    st = torch.from_numpy(state).to(cb.device)
+    nat.check(nat.lib().cm_qs_cg_step(
+        cb._h, _ptr(y), _ptr(plate), k, rel_tol, _ptr(ybar), _ptr(x), _ptr(r),
+        _ptr(p), _ptr(Ap), _ptr(st), _ptr(minv), _stream(None)))
+    torch.cuda.synchronize()
+    got = {n: t.cpu().numpy().astype(np.float64).reshape(3, N)
+           for n, t in (("x", x), ("r", r), ("p", p))}
+    sg = st.cpu().numpy()
+    h = 2 * k * (np.maximum(Y[2] - top, 0) + np.maximum(bot - Y[2], 0))
+    A = -YB
+    A[2] += h * P[2]
+    for c in range(C):
+        sl = slice(node_off[c], node_off[c + 1])
+        rs = state[c, 0]
+        alpha = rs / (P[:, sl] * A[:, sl]).sum()
+        xn = X[:, sl] + alpha * P[:, sl]
+        rn = R[:, sl] - alpha * A[:, sl]
+        zn = mul(np.pad(rn, ((0, 0), (node_off[c], N - node_off[c + 1]))))[:, sl]
+        rzn = (rn * zn).sum()
+        pn = zn + (rzn / rs) * P[:, sl]
+        for name, want in (("x", xn), ("r", rn), ("p", pn)):
+            err = np.abs(got[name][:, sl] - want).max() / np.abs(want).max()
+            print(f"cell {c} ({sizes[c]} nodes) {name}: {err:.2e}", flush=True)
+            assert err <= 1e-5, (c, name)
+        assert abs(sg[c, 0] - rzn) <= 1e-5 * abs(rzn), c
+        stop = (rn ** 2).sum() <= max(rel_tol, 0.1) ** 2 * state[c, 1]
+        assert sg[c, 2] == (0.0 if stop else 1.0), c
