@@ -40,6 +40,19 @@ def test_library_exports_every_header_function():
     assert nat.lib().cm_version() == 1
 
 
+def test_binding_arity_matches_header():
+    """Every ctypes signature takes as many arguments as the C declaration
+    (a missing or extra argument would shift every pointer after it)."""
+    nat = _lib_or_skip()
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    decls = re.findall(r"\b(?:int|void|const char\*)\s+(cm_[a-z_0-9]+)\s*\(([^;]*?)\);",
+                       text, flags=re.S)
+    assert len(decls) == len(header_functions())
+    for name, params in decls:
+        n = 0 if params.strip() in ("", "void") else len(params.split(","))
+        assert len(nat.SIGNATURES[name][1]) == n, name
+
+
 def _batch(n_cells=5):
     return uneven_batch(n_cells=n_cells, seed=77, tet_lo=300, tet_hi=6000,
                         ladder=4)
