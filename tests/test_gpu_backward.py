@@ -260,7 +260,9 @@ def test_graph_forward_backward_replay():
     E = torch.empty(b.n_cells, dtype=torch.float64, device=cb.device)
     tb = torch.empty(3 * b.n_cells, dtype=torch.float64, device=cb.device)
     s = torch.cuda.Stream()
-    for mode in (1, 3):
+    # 1: forward then backward; 3: the same as per-cell launches; 4 and 5:
+    # forward and backward as parallel branches (batched, per cell)
+    for mode in (1, 3, 4, 5):
         with torch.cuda.stream(s):
             cb.graph_capture(mode, y, f, E, None, v, eb, yb, tb, stream=s)
         for _ in range(3):
