@@ -414,7 +414,9 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
  *     by minv (nullable: plain CG; pass the array cm_qs_residual filled); a
  *     cell stops at |r| <= max(rel_tol, eta) |r_0| or at non-positive
  *     curvature.
- *   cm_qs_update: y += s x, s = min(1, cap / max_i |x_i|) per cell.
+ *   cm_qs_update: y += s x per cell, s = min(1, cap / m) with m the
+ *     largest |component| of x over the cell's nodes; for a cell with m > 0,
+ *     state[4] = s and state[6] = m s (its largest coordinate move).
  *   cm_qs_predict: z -> b' + (z - b) s, s = (t' - b') / (t - b), for a new
  *     plate pair (t', b'), and x, y stretched by 1/sqrt(s) about the cell's
  *     centroid (a volume-preserving affine prediction).

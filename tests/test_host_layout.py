@@ -53,6 +53,29 @@ def test_binding_arity_matches_header():
         assert len(nat.SIGNATURES[name][1]) == n, name
 
 
+def test_layout_create_is_the_single_region_form():
+    """cm_layout_create prepares exactly what cm_layout_create_regions does
+    without regions (every exported table equal)."""
+    from paper_2003_03130_amd import HostLayout
+    from paper_2003_03130_amd.cells import _host_inputs, _options, _ptr
+    nat = _lib_or_skip()
+    b = uneven_batch(n_cells=3, seed=78, tet_lo=300, tet_hi=3000, ladder=3)
+    L = HostLayout(b.node_off, b.tet_off, b.x, b.tets, tile_tets=256)
+    node_off, tet_off, x, tets = _host_inputs(b.node_off, b.tet_off, b.x, b.tets)
+    opt = _options(None, 256, None)
+    h = ctypes.c_void_p()
+    nat.check(nat.lib().cm_layout_create(len(node_off) - 1, _ptr(node_off), _ptr(tet_off),
+                                         _ptr(x), _ptr(tets), ctypes.byref(opt),
+                                         ctypes.byref(h)))
+    L2 = HostLayout.__new__(HostLayout)
+    L2.n_regions = 1
+    L2._load(h)
+    for name in ("tiles", "slot_node", "shared_node", "shared_slot_ptr", "shared_slots",
+                 "cell_tile_off", "cell_shared_off", "new_to_old", "tile_mat", "B", "V0",
+                 "local_idx", "empty"):
+        assert np.array_equal(getattr(L, name), getattr(L2, name)), name
+
+
 def _batch(n_cells=5):
     return uneven_batch(n_cells=n_cells, seed=77, tet_lo=300, tet_hi=6000,
                         ladder=4)
