@@ -22,10 +22,14 @@ namespace cm {
 namespace {
 
 constexpr int kThreads = 1024;
+// The residual kernel keeps more values live (the FP64 block inversion):
+// 512-thread workgroups leave it 256 VGPRs instead of 128 (no spills).
+constexpr int kResThreads = 512;
 
 // Workgroup sum in a fixed order: a butterfly inside each wavefront (every
 // lane ends with the same bits), then every thread adds the wavefront totals
-// in wavefront order.  red: at least kThreads / 64 doubles of LDS.
+// in wavefront order.  red: at least NT / 64 doubles of LDS.
+template <int NT = kThreads>
 __device__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -33,7 +37,7 @@ __device__ double block_sum(double v, double* red) {
   __syncthreads();
   double r = red[0];
 #pragma unroll
-  for (int w = 1; w < kThreads / 64; ++w) r += red[w];
+  for (int w = 1; w < NT / 64; ++w) r += red[w];
   __syncthreads();  // red is reused by the next reduction
   return r;
 }
@@ -120,8 +124,8 @@ struct ResArgs {
 // least 0.9 eta_prev^2 when that exceeds 0.1, at most eta_max (eta_max at a
 // new plate position), and at least half the ratio of the equilibrium
 // tolerance to |r_N| (no more accuracy than the test needs).
-__global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
-  __shared__ double red[kThreads];
+__global__ __launch_bounds__(kResThreads) void qs_residual_kernel(ResArgs a) {
+  __shared__ double red[kResThreads / 64];
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
@@ -135,27 +139,28 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
   };
   // centroid (x, y) and mean residual (x, y)
   double sx = 0.0, sy = 0.0, mx = 0.0, my = 0.0;
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
     sx += a.y[i];
     sy += a.y[N + i];
     mx += a.f[i];
     my += a.f[N + i];
   }
-  const double cx = block_sum(sx, red) * inv_n, cy = block_sum(sy, red) * inv_n;
-  mx = block_sum(mx, red) * inv_n;
-  my = block_sum(my, red) * inv_n;
+  const double cx = block_sum<kResThreads>(sx, red) * inv_n;
+  const double cy = block_sum<kResThreads>(sy, red) * inv_n;
+  mx = block_sum<kResThreads>(mx, red) * inv_n;
+  my = block_sum<kResThreads>(my, red) * inv_n;
   // torque about the z axis through the centroid and |w|^2, w = e_z x (y - c)
   double tq = 0.0, ww = 0.0;
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
     const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
     tq += dx * a.f[N + i] - dy * a.f[i];
     ww += dx * dx + dy * dy;
   }
-  tq = block_sum(tq, red);
-  ww = block_sum(ww, red);
+  tq = block_sum<kResThreads>(tq, red);
+  ww = block_sum<kResThreads>(ww, red);
   const double om = ww > 0.0 ? tq / ww : 0.0;
   double rr = 0.0, rzs = 0.0, ft = 0.0, fb = 0.0, pp = 0.0, phi = 0.0;
-  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
     double dt, db, pz;
     const double rzd = rz_of(i, dt, db, pz);
     phi += dt * dt * dt + db * db * db;
@@ -186,12 +191,12 @@ __global__ __launch_bounds__(kThreads) void qs_residual_kernel(ResArgs a) {
     ft += a.k * dt * dt;
     fb += a.k * db * db;
   }
-  rr = block_sum(rr, red);
-  rzs = block_sum(rzs, red);
-  ft = block_sum(ft, red);
-  fb = block_sum(fb, red);
-  pp = block_sum(pp, red);
-  phi = block_sum(phi, red) * (a.k / 3.0);
+  rr = block_sum<kResThreads>(rr, red);
+  rzs = block_sum<kResThreads>(rzs, red);
+  ft = block_sum<kResThreads>(ft, red);
+  fb = block_sum<kResThreads>(fb, red);
+  pp = block_sum<kResThreads>(pp, red);
+  phi = block_sum<kResThreads>(phi, red) * (a.k / 3.0);
   if (threadIdx.x == 0) {
     double* s = a.st + kQsState * c;
     const double fl = a.floor_factor * s[7];
@@ -694,7 +699,7 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               const float* kel, float* minv, hipStream_t s) {
   ResArgs a{node_off, N, y, f, energy, plate, k, abs_tol, rel_tol, step_tol,
             floor_factor, eta_max, restart, r, p, x, rn, st, force, kel, minv};
-  hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kResThreads), 0, s, a);
   return hipGetLastError();
 }
 
