@@ -37,7 +37,9 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nloc = a.T.nloc;
   // per wave (40 bytes per tile node): (y.x, y.y, y.z, fbar.x) as float4,
-  // ybar accumulators as float4, (fbar.y, fbar.z) as float2
+  // ybar accumulators as float4, (fbar.y, fbar.z) as float2; the wave's
+  // stride of 10 nloc / 4 float4 covers the float2 array exactly because
+  // nloc is a multiple of 4 (checked at launch)
   float4* ys = lds + (size_t)wave * (10 * nloc / 4);
   float4* gs = ys + nloc;
   float2* vs = reinterpret_cast<float2*>(gs + nloc);
@@ -246,6 +248,9 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 float* ybar, hipStream_t st, const CellMask& mask,
                                 const PlateBwd& pl) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
+  // the per-wave LDS stride (10 nloc / 4 float4) needs nloc % 4 == 0, else
+  // a wave's last float2 would overlap the next wave's records
+  if (T.nloc <= 0 || T.nloc % 4 != 0) return hipErrorInvalidValue;
   BwdArgs a{T, r, y, fbar, ebar, ybar, mask, pl};
   const int grid = grid_for(r, cfg);
   const size_t lds = backward_lds_per_wave(T.nloc) * cfg.waves;
