@@ -206,6 +206,29 @@ int cm_forces(cm_batch h, const float* y, float* f, double* energy,
               int32_t* n_inverted, hipStream_t stream);
 
 /*
+ * cm_forces_noalloc: cm_forces for callers that cannot allocate device
+ * memory or must not touch the handle's scratch (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and summation order as cm_forces, so the results are
+ * bitwise those of cm_forces; the call allocates and frees nothing.  Its
+ * scratch (the shared-node slot partials, 12 B per slot, and per tile an
+ * energy and an inverted count, 12 B per tile, each part 256-byte aligned)
+ * lives in one static device array of CM_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the library's load until the process ends; its device address
+ * is looked up on the first call on each GPU.  Every call on a GPU shares
+ * that array and leaves its contents behind (every entry it reads is
+ * written first in the same call), so calls that overlap on one GPU -- on
+ * two streams, or from two threads, whatever their handles -- race.
+ * Errors: as cm_forces, and CM_EINVAL (the message states both sizes) when
+ * the handle needs more scratch than the array holds (about 1.3 million
+ * slots: a batch of a few hundred cells of the paper's size; larger batches
+ * use cm_forces).
+ */
+#define CM_NOALLOC_SCRATCH_BYTES (16u << 20)
+int cm_forces_noalloc(cm_batch h, const float* y, float* f, double* energy,
+                      int32_t* n_inverted, hipStream_t stream);
+
+/*
  * cm_forces_backward: reverse-mode cotangents of a loss L(f, E).
  *   fbar     : device float32[3 * n_nodes] = dL/df, nullable (zero).
  *   ebar     : device float64[n_cells] = dL/dE per cell, nullable (zero).

@@ -73,6 +73,7 @@ SIGNATURES = {
     "cm_permutation": (_int, [_vp, _vp]),
     "cm_set_params": (_int, [_vp, _vp, _vp, _vp, _int, _vp]),
     "cm_forces": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "cm_forces_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_percell": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_backward_percell": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
