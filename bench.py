@@ -155,67 +155,88 @@ def parity(cb, b, f, E, ybar, tb, vbar, ebar, cells):
     return worst
 
 
-def cpu_baseline(b, vbar, ebar, seconds, threads=16):
-    """The FP64 oracle (forward + backward) on the host: first a single
-    thread on the first cells for about seconds/3, then `threads` threads
-    (the oracle's C routines run outside the Python lock, one cell per call)
-    on the following cells for about `seconds` of wall time."""
-    import threading
-    from concurrent.futures import ThreadPoolExecutor
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(b, vbar, ebar, seconds, threads=None, reps=5):
+    """The FP64 oracle (forward by the derivative-table path + backward by
+    dual-number JVPs, unchanged) in its timing mode: built with -O3
+    -march=native -fopenmp for this host, OpenMP over the cells of the
+    workload (OMP_PROC_BIND=close), preparation (B, V0) outside the timed
+    calls.  A one-thread calibration sizes the samples; the reported value
+    is the median of `reps` runs on `threads` threads (OMP_NUM_THREADS, else
+    the GPU's host share of 16 cores) over a prefix of the workload's cells
+    of about seconds / (reps + 3) each, beside the median of 3 one-thread
+    runs on a shorter prefix."""
+    import tempfile
 
     import oracle
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(
+            16, os.cpu_count() or 1)
+    so = os.path.join(tempfile.gettempdir(), f"cm_oracle_omp_{os.getpid()}.so")
+    oracle.build_timing(so)
+    tets = np.diff(b.tet_off)
 
-    def run_cell(c):
-        cell = b.cell(c)
-        n0, n1 = b.node_off[c], b.node_off[c + 1]
-        m = oracle.OracleMesh(cell.x, cell.tets)
-        y64 = cell.y.astype(np.float64)
-        v64 = vbar[n0:n1].astype(np.float64)
-        t0 = time.perf_counter()
-        m.forces(y64, cell.theta)
-        m.backward(y64, cell.theta, v64, float(ebar[c]))
-        return cell.n_tets, time.perf_counter() - t0
+    def prefix(n_tets):
+        return int(min(b.n_cells, max(1, np.searchsorted(np.cumsum(tets), n_tets) + 1)))
 
-    # single thread
-    tets1, spent, c = 0, 0.0, 0
-    while spent < seconds / 3 and c < b.n_cells:
-        n, dt = run_cell(c)
-        tets1, spent, c = tets1 + n, spent + dt, c + 1
-    single = tets1 / spent
-    first_multi = c
-    # many threads, wall clock
-    threads = max(1, min(threads, os.cpu_count() or 1))
-    nxt = [first_multi]
-    lock = threading.Lock()
-    done = [0, 0]
-    t_end = time.perf_counter() + seconds
-
-    def worker():
-        while time.perf_counter() < t_end:
-            with lock:
-                c = nxt[0]
-                nxt[0] += 1
-            if c >= b.n_cells:
-                return
-            n, _ = run_cell(c)
-            with lock:
-                done[0] += n
-                done[1] += 1
-
+    # the sample cells (a prefix) with their FP64 reference data
+    per_run = seconds / (reps + 3)
+    cal = prefix(2e5)
+    ob = oracle.OracleBatch(b.node_off[:cal + 1], b.tet_off[:cal + 1],
+                            b.x[:b.node_off[cal]], b.tets[:b.tet_off[cal]],
+                            lib_path=so)
+    th = b.theta[:cal]
+    ob.threads(1)
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(threads) as ex:
-        for f in [ex.submit(worker) for _ in range(threads)]:
-            f.result()
-    wall = time.perf_counter() - t0
-    return {"value": done[0] / wall, "unit": "tets/s", "cores": threads,
-            "kind": "oracle",
-            "single_thread_value": single,
+    ob.fwd_bwd(b.y[:b.node_off[cal]], th, vbar[:b.node_off[cal]], ebar[:cal])
+    rate1 = b.tet_off[cal] / (time.perf_counter() - t0)
+    n1 = prefix(rate1 * per_run)
+    nm = prefix(rate1 * per_run * threads * 0.8)
+    c_max = max(n1, nm)
+    ob = oracle.OracleBatch(b.node_off[:c_max + 1], b.tet_off[:c_max + 1],
+                            b.x[:b.node_off[c_max]], b.tets[:b.tet_off[c_max]],
+                            lib_path=so)
+    y = b.y[:b.node_off[c_max]]
+    v = vbar[:b.node_off[c_max]]
+
+    def timed(nthreads, c1, n_reps):
+        used = ob.threads(nthreads)
+        ts = []
+        for _ in range(n_reps):
+            t0 = time.perf_counter()
+            ob.fwd_bwd(y, b.theta[:c_max], v, ebar[:c_max], 0, c1)
+            ts.append(time.perf_counter() - t0)
+        return used, float(np.median(ts)), ts
+
+    _, t1, _ = timed(1, n1, 3)
+    used, tm, all_t = timed(threads, nm, reps)
+    try:
+        os.remove(so)
+    except OSError:
+        pass
+    return {"value": float(b.tet_off[nm] / tm), "unit": "tets/s",
+            "cores": int(used), "kind": "oracle",
+            "single_thread_value": float(b.tet_off[n1] / t1),
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
             "sample": f"FP64 oracle forward (derivative-table path) + backward "
-                      f"(dual-number JVPs) on cells of the workload: {threads} "
-                      f"threads, one cell per call, cells {first_multi}.."
-                      f"{first_multi + done[1] - 1} ({done[0]} tets) in "
-                      f"{wall:.1f} s wall; single thread on cells 0..{c - 1} "
-                      f"({tets1} tets, {spent:.1f} s)"}
+                      f"(dual-number JVPs), g++ -O3 -march=native -fopenmp, "
+                      f"OpenMP over cells (OMP_PROC_BIND=close): median of "
+                      f"{reps} runs on {used} threads over cells 0..{nm - 1} "
+                      f"({int(b.tet_off[nm])} tets, {tm:.2f} s each, runs "
+                      f"{', '.join(f'{t:.2f}' for t in all_t)} s); one thread: "
+                      f"median of 3 runs over cells 0..{n1 - 1} "
+                      f"({int(b.tet_off[n1])} tets, {t1:.2f} s)"}
 
 
 def hertz_targets(theta, top, radius=1.0):

@@ -54,6 +54,17 @@ def build(force: bool = True, src: str = _SRC, out: str = _SO) -> str:
     return out
 
 
+def build_timing(out: str, src: str = _SRC) -> str:
+    """The same source built for the CPU-baseline timing mode: -O3 for the
+    host it runs on, OpenMP over cells (still no -ffast-math)."""
+    tmp = out + ".tmp"
+    subprocess.run(["g++", "-O3", "-march=native", "-fopenmp", "-std=c++17",
+                    "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, src],
+                   check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def lib(path: str = None):
     """The ctypes handle of the oracle library (built on first use)."""
     path = path or _SO
@@ -85,6 +96,12 @@ def lib(path: str = None):
         L.or_energy_density.restype = ctypes.c_double
         L.or_stress_table.argtypes = [_dp, _d, _d, _d, _dp]
         L.or_stress_table.restype = None
+        L.or_batch_fwd_bwd.argtypes = [_i64, _i64, _lp, _lp, _dp, _ip, _dp,
+                                       _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       _dp, _dp]
+        L.or_batch_fwd_bwd.restype = None
+        L.or_threads.argtypes = [ctypes.c_int]
+        L.or_threads.restype = ctypes.c_int
         _libs[path] = L
     return _libs[path]
 
@@ -217,6 +234,50 @@ class OracleMesh:
                              float(mobility), _ptr(Ft), float(scale),
                              ctypes.byref(loss), _ptr(g), _ptr(F))
         return loss.value, g, F
+
+
+class OracleBatch:
+    """Cells of a batch (concatenated arrays as in the device library) with
+    their FP64 inverse edge matrices and volumes, for the timing mode:
+    forward and backward of a range of cells, OpenMP over cells."""
+
+    def __init__(self, node_off, tet_off, x, tets, lib_path: str = None):
+        self.L = lib(lib_path)
+        self.node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+        self.tet_off = np.ascontiguousarray(tet_off, dtype=np.int64)
+        self.x = _f64(x, (-1, 3))
+        self.tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+        self.n_cells = len(self.node_off) - 1
+        m = len(self.tets)
+        self.B = np.empty((m, 3, 3))
+        self.V0 = np.empty(m)
+        for c in range(self.n_cells):
+            n0, n1 = self.node_off[c], self.node_off[c + 1]
+            t0, t1 = self.tet_off[c], self.tet_off[c + 1]
+            rc = self.L.or_prepare(n1 - n0, t1 - t0, _ptr(self.x[n0:n1]),
+                                   _ptr(self.tets[t0:t1], _ip),
+                                   _ptr(self.B[t0:t1]), _ptr(self.V0[t0:t1]),
+                                   None)
+            if rc != 0:
+                raise ValueError(f"cell {c}: bad mesh ({rc})")
+
+    def threads(self, n: int = 0) -> int:
+        return int(self.L.or_threads(int(n)))
+
+    def fwd_bwd(self, y, theta, fbar, ebar, c0=0, c1=None):
+        """Forces, energies, ybar and thetabar of cells [c0, c1)."""
+        c1 = self.n_cells if c1 is None else c1
+        y, fbar = _f64(y, (-1, 3)), _f64(fbar, (-1, 3))
+        theta, ebar = _f64(theta, (-1, 3)), _f64(ebar)
+        f, ybar = np.zeros_like(y), np.zeros_like(y)
+        E, tb = np.zeros(self.n_cells), np.zeros((self.n_cells, 3))
+        self.L.or_batch_fwd_bwd(int(c0), int(c1), _ptr(self.node_off, _lp),
+                                _ptr(self.tet_off, _lp), _ptr(self.x),
+                                _ptr(self.tets, _ip), _ptr(self.B),
+                                _ptr(self.V0), _ptr(y), _ptr(theta),
+                                _ptr(fbar), _ptr(ebar), _ptr(f), _ptr(E),
+                                _ptr(ybar), _ptr(tb))
+        return f, E, ybar, tb
 
 
 def energy_density(F, theta, lib_path: str = None) -> float:

@@ -55,6 +55,9 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -621,6 +624,46 @@ void or_relax_grad(int64_t n_nodes, int64_t n_tets, const double* x,
   }
   *loss = L;
   for (int k = 0; k < 3; ++k) dtheta[k] = g[k];
+}
+
+// Timing mode of the CPU baseline: the forward (O1) and the backward of every
+// cell c in [c0, c1) of a batch, the cells distributed over OpenMP threads
+// (a build with -fopenmp; without it the loop runs on one thread).  Per-cell
+// arrays are concatenated: node_off / tet_off are CSR offsets (n_cells + 1),
+// tets are cell-local, B / V0 come from or_prepare on each cell, theta holds
+// (mu, kappa, w) per cell; f, ybar (3 per node), energy (1 per cell) and
+// thetabar (3 per cell) are outputs.  Each cell runs or_forces_table and
+// or_backward unchanged.
+void or_batch_fwd_bwd(int64_t c0, int64_t c1, const int64_t* node_off,
+                      const int64_t* tet_off, const double* x,
+                      const int32_t* tets, const double* B, const double* V0,
+                      const double* y, const double* theta, const double* fbar,
+                      const double* ebar, double* f, double* energy,
+                      double* ybar, double* thetabar) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t c = c0; c < c1; ++c) {
+    const int64_t n0 = node_off[c], n = node_off[c + 1] - n0;
+    const int64_t t0 = tet_off[c], m = tet_off[c + 1] - t0;
+    const double* th = theta + 3 * c;
+    or_forces_table(n, m, x + 3 * n0, tets + 4 * t0, B + 9 * t0, V0 + t0,
+                    y + 3 * n0, th[0], th[1], th[2], f + 3 * n0, energy + c,
+                    nullptr);
+    or_backward(n, m, x + 3 * n0, tets + 4 * t0, B + 9 * t0, V0 + t0,
+                y + 3 * n0, th[0], th[1], th[2], fbar + 3 * n0, ebar[c],
+                ybar + 3 * n0, thetabar + 3 * c);
+  }
+}
+
+// Threads of the timing mode: sets the OpenMP thread count when n > 0 and
+// returns the count in effect (1 without OpenMP).
+int or_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 }  // extern "C"
