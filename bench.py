@@ -44,6 +44,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # inverse edge matrix and volume, float32 SoA node arrays), per pass.
 FWD_BYTES = (56, 24)    # 16 idx + 36 B + 4 V0 per tet; y in + f out per node
 BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
+# Bytes per tetrahedron of the stored chunk format (uint16 tile-local
+# indices: 8 + 36 + 4), the other denominator reported beside the canonical.
+STORED_TET_BYTES = 48
 F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
 TILE_KERNEL_SOURCES = ("kernels.hip", "backward.hip", "device_util.h",
                        "kernels.h", "layout.h", "mr_tet.h")
@@ -570,7 +573,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cells", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=3000)
-    ap.add_argument("--tile-tets", type=int, default=768)
+    ap.add_argument("--tile-tets", type=int, default=None,
+                    help="fixed tile size (default: chosen with the launch by "
+                         "cm_batch_create_tuned over 512..1024)")
     ap.add_argument("--order", type=int, default=None,
                     help="tile order (0 input, 1 RCM, 2 Morton, 3 bisection; "
                          "default: the library's)")
@@ -632,8 +637,20 @@ def main():
     log(f"workload: {b.n_cells} cells, {b.n_tets} tets, {b.n_nodes} nodes "
         f"({time.time() - t:.1f} s)")
     t = time.time()
-    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets,
-                   tile_tets=args.tile_tets, order=args.order)
+    tuning = None
+    if args.tile_tets is None and not args.launch and not args.no_autotune:
+        cand = [512, 640, 768, 896, 1024]
+        cb = CellBatch.tuned(b.node_off, b.tet_off, b.x, b.tets,
+                             tile_candidates=cand, order=args.order)
+        tuning = {"tile_candidates": cand,
+                  "candidate_ms_fwd_bwd": [round(float(v), 5) for v in cb.candidate_ms],
+                  "tile_tets": int(cb.info["tile_tets"]),
+                  "launch": list(cb.get_launch()), "s": round(time.time() - t, 1)}
+        log(f"tuned creation (tile size and launch) in {time.time() - t:.1f} s: "
+            f"{tuning}")
+    else:
+        cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets,
+                       tile_tets=args.tile_tets or 768, order=args.order)
     log(f"prepared + uploaded in {time.time() - t:.1f} s: {cb.info}")
     cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
     dev = cb.device
@@ -680,7 +697,7 @@ def main():
     if args.launch:
         w_, b_ = (int(v) for v in args.launch.split(","))
         cb.set_launch(w_, b_)
-    elif not args.no_autotune:
+    elif not args.no_autotune and tuning is None:
         t = time.time()
         launch = cb.autotune(y)
         log(f"autotuned launch (waves/block, blocks/CU) = {launch} in "
@@ -801,7 +818,14 @@ def main():
         "hbm_frac_fwd": fwd_b / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "hbm_frac_fwd_bwd": (fwd_b + bwd_b) / (step_ms * 1e-3)
         / (HBM_PEAK_GBS * 1e9),
+        # the same fractions with the stored chunk bytes per tetrahedron
+        "hbm_frac_fwd_stored": (fwd_b - (FWD_BYTES[0] - STORED_TET_BYTES) * M)
+        / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "hbm_frac_fwd_bwd_stored": (fwd_b + bwd_b - (FWD_BYTES[0] + BWD_BYTES[0]
+                                                     - 2 * STORED_TET_BYTES) * M)
+        / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "ms": {k: round(v, 5) for k, v in res.items()},
+        "autotune": tuning,
         "kernels": kern,
         "roofline": roofline,
         "parity": par,

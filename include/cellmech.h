@@ -206,6 +206,22 @@ int cm_forces(cm_batch h, const float* y, float* f, double* energy,
               int32_t* n_inverted, hipStream_t stream);
 
 /*
+ * cm_forces_checked: cm_forces plus a per-cell count of tetrahedra whose
+ * energy V0 U or force contribution is not finite (NaN or infinite: from
+ * non-finite positions, or J = 0 where J^-1/3 is singular).  A node force
+ * or a cell energy is non-finite only where such a tetrahedron exists (short
+ * of overflow in a sum), so n_nonfinite[c] > 0 flags every cell whose output
+ * cannot be used.
+ *   n_nonfinite : device int32[n_cells], required.
+ * Results (f, energy, n_inverted) are bitwise those of cm_forces; kernels
+ * run to completion on any input.  Errors as cm_forces, and CM_EINVAL for a
+ * null n_nonfinite.
+ */
+int cm_forces_checked(cm_batch h, const float* y, float* f, double* energy,
+                      int32_t* n_inverted, int32_t* n_nonfinite,
+                      hipStream_t stream);
+
+/*
  * cm_forces_noalloc: cm_forces for callers that cannot allocate device
  * memory or must not touch the handle's scratch (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
@@ -282,6 +298,31 @@ int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
  * skips the measurement, a miss appends the result.  Tuning allocates and
  * frees scratch outputs and synchronises the stream: it is not graph-safe.
  */
+/*
+ * cm_batch_create_tuned: cm_batch_create with the tile size chosen by
+ * measurement.  For every candidate tile size (tile_candidates, host
+ * int32[n_candidates], multiples of 64 in [64, 4096]; NULL = {512, 640, 768,
+ * 896, 1024}) the meshes are prepared and uploaded, and forward + backward
+ * are timed as in cm_autotune for every launch configuration, with the
+ * reference positions as input and unit parameters (the work per
+ * tetrahedron does not depend on them); the fastest tile size and launch
+ * are kept, the other handles freed as soon as they lose.  candidate_ms
+ * (host float64[n_candidates], nullable) receives each candidate's best
+ * time (infinity where skipped).  cache_path (nullable): a JSON file of the
+ * cm_autotune format keyed by device, cell / node / tetrahedron counts,
+ * ordering and candidate list; a hit prepares only the cached tile size.
+ * opt->tile_tets is ignored.  cm_set_params must still be called on the
+ * result.  Allocates and synchronises; one handle of every candidate is
+ * alive at a time beside the best so far.  Errors as cm_batch_create, and
+ * CM_EINVAL for a bad candidate list.
+ */
+int cm_batch_create_tuned(int32_t n_cells, const int64_t* node_off,
+                          const int64_t* tet_off, const double* ref_xyz,
+                          const int32_t* tets, const cm_options* opt,
+                          const int32_t* tile_candidates, int32_t n_candidates,
+                          const char* cache_path, double* candidate_ms,
+                          hipStream_t stream, cm_batch* out);
+
 int cm_set_launch(cm_batch h, int32_t waves_per_block, int32_t blocks_per_cu);
 int cm_get_launch(cm_batch h, int32_t* waves_per_block, int32_t* blocks_per_cu);
 int cm_autotune(cm_batch h, const float* y, const char* cache_path,
@@ -415,7 +456,12 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
  *   cm_qs_ls_accept (energy_trial = E(y_trial) from cm_forces): a pending
  *     cell accepts y_trial (copied into y) if Pi(y_trial) <= Pi(y) - armijo
  *     s (r_N . x), else halves s and forms the next trial; it gives up (no
- *     move, last step 0) once s max|x| < min_move.
+ *     move, last step 0) once s max|x| < min_move.  With the inverted counts
+ *     (device int32[n_cells] each, both or neither: n_inverted_trial from
+ *     cm_forces at y_trial, n_inverted those at y, updated on acceptance) a
+ *     trial that inverts more tetrahedra than y has is rejected too (the
+ *     energy density grows without bound as J -> 0 from above; a finite step
+ *     could jump over that barrier to an inverted state of finite energy).
  *   cm_qs_noise / cm_qs_floor: the float32 floor rho of the residual: e =
  *     +-|y| 2^-24 per coordinate (half a unit in the last place, signs from
  *     a fixed hash of the index), then after ybar = cm_forces_backward(y,
@@ -453,12 +499,34 @@ int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* ene
                    float* r_newton, double* state, double* force, const float* k_el,
                    float* minv, hipStream_t stream);
 int cm_qs_stiffness(cm_batch h, float* k_el, hipStream_t stream);
+/*
+ * cm_qs_adjoint_rhs: start of the adjoint solve for the derivative of the
+ * top-plate force at an equilibrium (f + p = 0) with respect to the
+ * material parameters: dF_top/dtheta = lam^T df/dtheta with
+ * Hess(Pi) lam = g, g = dF_top/dy (2 k max(0, y_z - top) on the z entries).
+ * Sets r = weight[c] g (weight: device float64[n_cells], nullable = 1),
+ * p = minv r (minv nullable: p = r; pass the blocks of the last
+ * cm_qs_residual at this y), x = 0, and the CG columns of the state (r . z,
+ * |r|^2, active iff |r| > 0, forcing term 0).  The caller then runs the CG
+ * loop of a Newton step (cm_forces_backward_cells + cm_qs_cg_step, which
+ * stop at cg_tol) and gets lam in x; cm_forces_backward(y, fbar = lam) then
+ * gives thetabar = weight dF_top/d(mu, kappa, w) per material slot.  g has
+ * z entries only, so it is orthogonal to the symmetry modes of the plates
+ * (translations in x and y, rotation about z) and the singular system is
+ * consistent.  Errors: CM_EINVAL for null pointers or a negative or
+ * non-finite k_plate.
+ */
+int cm_qs_adjoint_rhs(cm_batch h, const float* y, const double* plate, double k_plate,
+                      const double* weight, float* r, float* p, float* x, double* state,
+                      const float* minv, hipStream_t stream);
 int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
                    const float* y, float* y_trial, double* state,
                    hipStream_t stream);
 int cm_qs_ls_accept(cm_batch h, const float* x, const double* plate, double k_plate,
                     const double* energy_trial, double armijo, double min_move,
-                    float* y, float* y_trial, double* state, hipStream_t stream);
+                    float* y, float* y_trial, double* state,
+                    const int32_t* n_inverted_trial, int32_t* n_inverted,
+                    hipStream_t stream);
 int cm_qs_noise(cm_batch h, const float* y, float* e, hipStream_t stream);
 int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
                 const float* e, const float* ybar, double* state, hipStream_t stream);

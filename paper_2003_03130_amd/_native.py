@@ -74,9 +74,14 @@ SIGNATURES = {
     "cm_set_params": (_int, [_vp, _vp, _vp, _vp, _int, _vp]),
     "cm_forces": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "cm_forces_checked": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_percell": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_backward_percell": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cm_batch_create_tuned": (_int, [_i32, _vp, _vp, _vp, _vp,
+                                     ctypes.POINTER(Options), _vp, _i32,
+                                     ctypes.c_char_p, _vp, _vp,
+                                     ctypes.POINTER(_vp)]),
     "cm_set_launch": (_int, [_vp, _i32, _i32]),
     "cm_get_launch": (_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "cm_autotune": (_int, [_vp, _vp, ctypes.c_char_p, _vp]),
@@ -113,11 +118,13 @@ SIGNATURES = {
                               ctypes.c_double, ctypes.c_double, _i32, _vp, _vp,
                               _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_stiffness": (_int, [_vp, _vp, _vp]),
+    "cm_qs_adjoint_rhs": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp,
+                                 _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_ls_start": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
                               _vp]),
     "cm_qs_ls_accept": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp,
                                ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
-                               _vp]),
+                               _vp, _vp, _vp]),
     "cm_qs_noise": (_int, [_vp, _vp, _vp, _vp]),
     "cm_qs_floor": (_int, [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp,
                            _vp]),

@@ -105,6 +105,30 @@ class CellBatch:
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
+    def tuned(cls, node_off, tet_off, x, tets, tile_candidates=None,
+              cache_path=None, order=None, degenerate_tol=None, stream=None):
+        """cm_batch_create_tuned: the tile size (and launch) chosen by timing
+        every candidate; ``self.candidate_ms`` holds each candidate's time."""
+        node_off, tet_off, x, tets = _host_inputs(node_off, tet_off, x, tets)
+        opt = _options(order, None, degenerate_tol)
+        cand = (None if tile_candidates is None else
+                np.ascontiguousarray(tile_candidates, dtype=np.int32))
+        n_cand = 5 if cand is None else len(cand)
+        ms = np.full(n_cand, np.inf)
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().cm_batch_create_tuned(
+            len(node_off) - 1, _ptr(node_off), _ptr(tet_off), _ptr(x),
+            _ptr(tets), ctypes.byref(opt), _ptr(cand), n_cand,
+            cache_path.encode() if cache_path else None, _ptr(ms),
+            _stream(stream), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.n_cells = len(node_off) - 1
+        self._finish(h, node_off, tet_off)
+        self.is_template = False
+        self.candidate_ms = ms
+        return self
+
+    @classmethod
     def from_cells(cls, cells, **kw):
         node_off = np.concatenate([[0], np.cumsum([len(c.x) for c in cells])])
         tet_off = np.concatenate([[0], np.cumsum([len(c.tets) for c in cells])])
@@ -218,6 +242,23 @@ class CellBatch:
         nat.check(fn(self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(n_inverted),
                      _stream(stream)))
         return f, energy
+
+    def forces_checked(self, y, f=None, energy=None, n_inverted=None,
+                       stream=None):
+        """cm_forces_checked: (f, energy, n_nonfinite) with n_nonfinite an
+        int32 device tensor (n_cells,) counting each cell's tetrahedra with
+        a non-finite energy or force."""
+        import torch
+        if f is None:
+            f = self.empty_nodes()
+        if energy is None:
+            energy = torch.empty(self.n_cells, dtype=torch.float64,
+                                 device=self.device)
+        nonfin = torch.empty(self.n_cells, dtype=torch.int32, device=self.device)
+        nat.check(nat.lib().cm_forces_checked(
+            self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(n_inverted),
+            _ptr(nonfin), _stream(stream)))
+        return f, energy, nonfin
 
     def backward(self, y, fbar=None, ebar=None, ybar=None, thetabar=None,
                  stream=None, percell=False, cells=None):

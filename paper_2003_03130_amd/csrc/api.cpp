@@ -191,8 +191,9 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     double* params;
     float *part, *part_b;
     double *tile_acc, *tile_acc_b, *tile_plate;
-    int32_t* tile_ninv;
+    int32_t *tile_ninv, *tile_nonfin;
     if ((rc = h->alloc(&params, 3 * (size_t)h->n_mat)) ||
+        (rc = h->alloc(&tile_nonfin, (size_t)h->n_tiles)) ||
         (rc = h->alloc(&part, 3 * (size_t)h->n_slots)) ||
         (rc = h->alloc(&part_b, 3 * (size_t)h->n_slots)) ||
         (rc = h->alloc(&tile_acc, (size_t)h->n_tiles)) ||
@@ -247,10 +248,12 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     T.tile_acc = tile_acc;
     T.tile_plate = tile_plate;
     T.tile_ninv = tile_ninv;
+    T.tile_nonfin = tile_nonfin;
     h->Tb = T;
     h->Tb.part = part_b;
     h->Tb.tile_acc = tile_acc_b;
     h->Tb.tile_ninv = nullptr;
+    h->Tb.tile_nonfin = nullptr;
   }
   for (cm::DeviceTables* t : {&h->T, &h->Tb}) {
     t->n_nodes = h->n_nodes;
@@ -420,7 +423,8 @@ int cm_set_params(cm_batch h, const double* mu, const double* kappa,
 }
 
 static int forces_impl(cm_batch h, const float* y, float* f, double* energy,
-                       int32_t* ninv, hipStream_t st, bool percell) {
+                       int32_t* ninv, hipStream_t st, bool percell,
+                       int32_t* nonfin = nullptr) {
   if (int rc = check_handle(h)) return rc;
   if (!y || !f) return fail(CM_EINVAL, "y and f must be device pointers");
   if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
@@ -430,11 +434,13 @@ static int forces_impl(cm_batch h, const float* y, float* f, double* energy,
   if (percell && h->is_template)
     return fail(CM_EINVAL, "per-cell launches need contiguous tiles (not a template batch)");
   if (!percell) {
-    CM_HIP(cm::launch_forward(h->T, full_range(h), h->cfg, y, f, energy, ninv, st));
+    CM_HIP(cm::launch_forward(h->T, full_range(h), h->cfg, y, f, energy, ninv, st,
+                              cm::PlateFwd{}, nonfin));
   } else {
     cm::LaunchCfg one{h->cfg.waves, 0};
     for (int32_t c = 0; c < (int32_t)h->n_cells; ++c)
-      CM_HIP(cm::launch_forward(h->T, cell_range(h, c), one, y, f, energy, ninv, st));
+      CM_HIP(cm::launch_forward(h->T, cell_range(h, c), one, y, f, energy, ninv, st,
+                                cm::PlateFwd{}, nonfin));
   }
   return CM_OK;
 }
@@ -466,6 +472,12 @@ static int backward_impl(cm_batch h, const float* y, const float* fbar,
 int cm_forces(cm_batch h, const float* y, float* f, double* energy,
               int32_t* n_inverted, hipStream_t stream) {
   return forces_impl(h, y, f, energy, n_inverted, stream, false);
+}
+
+int cm_forces_checked(cm_batch h, const float* y, float* f, double* energy,
+                      int32_t* n_inverted, int32_t* n_nonfinite, hipStream_t stream) {
+  if (!n_nonfinite) return fail(CM_EINVAL, "n_nonfinite must be a device pointer");
+  return forces_impl(h, y, f, energy, n_inverted, stream, false, n_nonfinite);
 }
 
 int cm_forces_percell(cm_batch h, const float* y, float* f, double* energy,
@@ -538,8 +550,8 @@ static void cache_store(const char* path, const std::string& key, int w, int b,
     std::ifstream in(path);
     std::string line;
     while (std::getline(in, line)) {
-      size_t p = line.find("\": {\"waves\"");
-      if (p == std::string::npos) continue;
+      // every entry line (launch entries and tuned-creation entries)
+      if (line.find("\": {\"") == std::string::npos) continue;
       if (line.find("\"" + key + "\":") != std::string::npos) continue;
       while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
       entries.push_back(line);
@@ -557,25 +569,54 @@ static void cache_store(const char* path, const std::string& key, int w, int b,
   out << "}\n";
 }
 
-int cm_autotune(cm_batch h, const float* y, const char* cache_path,
-                hipStream_t stream) {
-  if (int rc = check_handle(h)) return rc;
-  if (!y) return fail(CM_EINVAL, "y must be a device pointer");
-  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
-  if (int rc = select_device(h)) return rc;
-  hipDeviceProp_t prop;
-  CM_HIP(hipGetDeviceProperties(&prop, h->device));
-  std::string key = std::string(prop.gcnArchName) + "|cu" + std::to_string(h->n_cu) +
-                    "|tets" + std::to_string(h->n_tets) + "|tiles" +
-                    std::to_string(h->n_tiles) + "|tile" + std::to_string(h->tile_tets) +
-                    "|nloc" + std::to_string(h->T.nloc) +
-                    (h->is_template ? "|template" : "");
-  for (char& ch : key)
-    if (ch == '"' || ch == '\\') ch = '_';
-  int w = 0, b = 0;
-  if (cache_path && cache_lookup(cache_path, key, &w, &b))
-    return cm_set_launch(h, w, b);
+// Entries of the tuned creation: "<key>": {"tile": T, "waves": W,
+// "blocks_per_cu": B, "ms": M}, in the same file format.
+static bool cache_lookup_tile(const char* path, const std::string& key, int* w, int* b,
+                              int* t) {
+  std::ifstream in(path);
+  if (!in) return false;
+  std::string line, pre = "\"" + key + "\":";
+  while (std::getline(in, line)) {
+    size_t p = line.find(pre);
+    if (p == std::string::npos) continue;
+    return std::sscanf(line.c_str() + p + pre.size(),
+                       " {\"tile\": %d, \"waves\": %d, \"blocks_per_cu\": %d", t, w,
+                       b) == 3;
+  }
+  return false;
+}
 
+static void cache_store_tile(const char* path, const std::string& key, int w, int b,
+                             int t, double ms) {
+  std::vector<std::string> entries;
+  {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.find("\": {\"") == std::string::npos) continue;
+      if (line.find("\"" + key + "\":") != std::string::npos) continue;
+      while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+      entries.push_back(line);
+    }
+  }
+  char buf[768];
+  std::snprintf(buf, sizeof buf,
+                "  \"%s\": {\"tile\": %d, \"waves\": %d, \"blocks_per_cu\": %d, "
+                "\"ms\": %.6f}",
+                key.c_str(), t, w, b, ms);
+  entries.push_back(buf);
+  std::ofstream out(path, std::ios::trunc);
+  out << "{\n";
+  for (size_t i = 0; i < entries.size(); ++i)
+    out << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+  out << "}\n";
+}
+
+// Times forward + backward for every launch configuration that fits in LDS
+// (waves per block x persistent blocks per CU, two rounds, the better round
+// of each), leaves h->cfg at the fastest and returns its time in *best_ms.
+static int tune_launch(cm_batch h, const float* y, hipStream_t stream,
+                       double* best_ms_out) {
   const size_t n3 = 3 * (size_t)h->n_nodes;
   float *f = nullptr, *ybar = nullptr;
   double *energy = nullptr, *tb = nullptr;
@@ -609,6 +650,8 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   };
   // bring the clocks to their loaded state before measuring
   h->cfg = saved;
+  if (!lds_fits(h, h->cfg.waves, true) || !lds_fits(h, h->cfg.waves, false))
+    h->cfg.waves = 1;
   for (int k = 0; k < 20 && rc == CM_OK; ++k) rc = run();
   double ms_of[4][6];
   for (int wi = 0; wi < 4; ++wi)
@@ -646,8 +689,166 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   cleanup();
   h->cfg = saved;
   if (rc != CM_OK) return rc;
-  if (cache_path) cache_store(cache_path, key, best_w, best_b, best_ms);
+  if (best_ms_out) *best_ms_out = best_ms;
   return cm_set_launch(h, best_w, best_b);
+}
+
+static std::string device_key(cm_batch h) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName) + "|cu" + std::to_string(h->n_cu);
+}
+
+static std::string sanitize_key(std::string key) {
+  for (char& ch : key)
+    if (ch == '"' || ch == '\\') ch = '_';
+  return key;
+}
+
+int cm_autotune(cm_batch h, const float* y, const char* cache_path,
+                hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y) return fail(CM_EINVAL, "y must be a device pointer");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (int rc = select_device(h)) return rc;
+  const std::string key = sanitize_key(
+      device_key(h) + "|tets" + std::to_string(h->n_tets) + "|tiles" +
+      std::to_string(h->n_tiles) + "|tile" + std::to_string(h->tile_tets) + "|nloc" +
+      std::to_string(h->T.nloc) + (h->is_template ? "|template" : ""));
+  int w = 0, b = 0;
+  if (cache_path && cache_lookup(cache_path, key, &w, &b))
+    return cm_set_launch(h, w, b);
+  double best_ms = INFINITY;
+  if (int rc = tune_launch(h, y, stream, &best_ms)) return rc;
+  if (cache_path) {
+    cm_get_launch(h, &w, &b);
+    cache_store(cache_path, key, w, b, best_ms);
+  }
+  return CM_OK;
+}
+
+int cm_batch_create_tuned(int32_t n_cells, const int64_t* node_off,
+                          const int64_t* tet_off, const double* ref_xyz,
+                          const int32_t* tets, const cm_options* opt,
+                          const int32_t* tile_candidates, int32_t n_candidates,
+                          const char* cache_path, double* candidate_ms,
+                          hipStream_t stream, cm_batch* out) {
+  g_err.clear();
+  if (!out) return fail(CM_EINVAL, "out is null");
+  *out = nullptr;
+  static const int32_t kDefault[5] = {512, 640, 768, 896, 1024};
+  if (!tile_candidates) {
+    tile_candidates = kDefault;
+    n_candidates = 5;
+  }
+  if (n_candidates < 1 || n_candidates > 64)
+    return fail(CM_EINVAL, "n_candidates must lie in [1, 64]");
+  for (int32_t k = 0; k < n_candidates; ++k) {
+    const int32_t t = tile_candidates[k];
+    if (t < 64 || t > cm::kMaxTileTets || t % 64 != 0)
+      return fail(CM_EINVAL, "tile candidates must be multiples of 64 in [64, 4096]");
+  }
+  if (candidate_ms)
+    for (int32_t k = 0; k < n_candidates; ++k) candidate_ms[k] = INFINITY;
+  if (n_cells < 1 || !node_off || !tet_off)
+    return fail(CM_EINVAL, "null offsets or no cell");
+  const cm::PrepOptions base = prep_options(opt);
+  // cache key: device, mesh sizes, ordering and the candidate list
+  int dev = 0;
+  CM_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  CM_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string key = std::string(prop.gcnArchName) + "|cu" +
+                    std::to_string(prop.multiProcessorCount) + "|cells" +
+                    std::to_string(n_cells) + "|nodes" + std::to_string(node_off[n_cells]) +
+                    "|tets" + std::to_string(tet_off[n_cells]) + "|order" +
+                    std::to_string(base.order) + "|cand";
+  for (int32_t k = 0; k < n_candidates; ++k) key += "," + std::to_string(tile_candidates[k]);
+  key = sanitize_key(key);
+  int cw = 0, cb = 0, ct = 0;
+  if (cache_path && cache_lookup_tile(cache_path, key, &cw, &cb, &ct)) {
+    cm::PrepOptions po = base;
+    po.tile_tets = ct;
+    cm::Prepared P;
+    std::string err;
+    int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, nullptr, 1, po,
+                               &P, &err);
+    if (rc != CM_OK) return fail(rc, err);
+    cm_batch h = nullptr;
+    if ((rc = create_from(P, po, stream, &h)) != CM_OK) return rc;
+    if ((rc = cm_set_launch(h, cw, cb)) != CM_OK) {
+      cm_destroy(h);
+      return rc;
+    }
+    *out = h;
+    return CM_OK;
+  }
+  cm_batch best = nullptr;
+  double best_ms = INFINITY;
+  float* y = nullptr;
+  for (int32_t k = 0; k < n_candidates; ++k) {
+    cm::PrepOptions po = base;
+    po.tile_tets = tile_candidates[k];
+    cm::Prepared P;
+    std::string err;
+    int rc = cm::prepare_batch(n_cells, node_off, tet_off, ref_xyz, tets, nullptr, 1, po,
+                               &P, &err);
+    if (rc != CM_OK) {
+      if (best) cm_destroy(best);
+      return fail(rc, err);
+    }
+    cm_batch h = nullptr;
+    if ((rc = create_from(P, po, stream, &h)) != CM_OK) {
+      if (best) cm_destroy(best);
+      return rc;
+    }
+    // timing input: the reference positions (float32, internal order) and
+    // unit parameters; neither changes the work done per tetrahedron
+    const size_t N = (size_t)h->n_nodes;
+    std::vector<float> ys(3 * N);
+    for (size_t g = 0; g < N; ++g)
+      for (int c = 0; c < 3; ++c) ys[c * N + g] = (float)ref_xyz[3 * h->new_to_old[g] + c];
+    std::vector<double> mu(h->n_mat, 1.0), ka(h->n_mat, 10.0), w(h->n_mat, 0.5);
+    double ms = INFINITY;
+    if (hipMalloc((void**)&y, 3 * N * sizeof(float)) != hipSuccess) {
+      y = nullptr;
+      rc = fail(CM_ENOMEM, "autotune input allocation failed");
+    } else if (hipMemcpy(y, ys.data(), 3 * N * sizeof(float), hipMemcpyHostToDevice) !=
+               hipSuccess) {
+      rc = fail(CM_EHIP, "autotune input copy failed");
+    } else if ((rc = cm_set_params(h, mu.data(), ka.data(), w.data(), 0, stream)) == CM_OK) {
+      rc = tune_launch(h, y, stream, &ms);
+    }
+    if (y) (void)hipFree(y);
+    y = nullptr;
+    h->params_set = false;  // the caller sets the real parameters
+    if (rc == CM_EINVAL && k + 1 < n_candidates) {
+      // a candidate whose tiles exceed the LDS for every launch is skipped
+      cm_destroy(h);
+      continue;
+    }
+    if (rc != CM_OK) {
+      cm_destroy(h);
+      if (best) cm_destroy(best);
+      return rc;
+    }
+    if (candidate_ms) candidate_ms[k] = ms;
+    if (ms < best_ms) {
+      if (best) cm_destroy(best);
+      best = h;
+      best_ms = ms;
+    } else {
+      cm_destroy(h);
+    }
+  }
+  if (!best) return fail(CM_EINVAL, "no tile candidate fits in LDS");
+  if (cache_path) {
+    int bw = 0, bb = 0;
+    cm_get_launch(best, &bw, &bb);
+    cache_store_tile(cache_path, key, bw, bb, best->tile_tets, best_ms);
+  }
+  *out = best;
+  return CM_OK;
 }
 
 int cm_plate_step(cm_batch h, const float* y, const float* f,
@@ -706,18 +907,23 @@ int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap
 
 int cm_qs_ls_accept(cm_batch h, const float* x, const double* plate, double k_plate,
                     const double* energy_trial, double armijo, double min_move,
-                    float* y, float* y_trial, double* state, hipStream_t stream) {
+                    float* y, float* y_trial, double* state,
+                    const int32_t* n_inverted_trial, int32_t* n_inverted,
+                    hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
   if (!x || !plate || !energy_trial || !y || !y_trial || !state || y_trial == y)
     return fail(CM_EINVAL, "x, plate, energy_trial, y, y_trial (distinct from y) "
                            "and state must be device pointers");
+  if ((n_inverted_trial == nullptr) != (n_inverted == nullptr))
+    return fail(CM_EINVAL, "n_inverted_trial and n_inverted must both be given or "
+                           "both be null");
   if (!std::isfinite(k_plate) || k_plate < 0 || !(armijo >= 0) || !(armijo < 1) ||
       !(min_move >= 0))
     return fail(CM_EINVAL, "k_plate >= 0, 0 <= armijo < 1 and min_move >= 0 required");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_ls_accept(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, x,
                                  plate, k_plate, energy_trial, armijo, min_move, y,
-                                 y_trial, state, stream));
+                                 y_trial, state, n_inverted_trial, n_inverted, stream));
   return CM_OK;
 }
 
@@ -739,6 +945,20 @@ int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_floor(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
                              k_plate, e, ybar, state, stream));
+  return CM_OK;
+}
+
+int cm_qs_adjoint_rhs(cm_batch h, const float* y, const double* plate, double k_plate,
+                      const double* weight, float* r, float* p, float* x, double* state,
+                      const float* minv, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !plate || !r || !p || !x || !state)
+    return fail(CM_EINVAL, "y, plate, r, p, x and state must be device pointers");
+  if (!std::isfinite(k_plate) || k_plate < 0)
+    return fail(CM_EINVAL, "k_plate must be finite and >= 0");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_qs_adjoint_rhs(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y,
+                                   plate, k_plate, weight, r, p, x, state, minv, stream));
   return CM_OK;
 }
 

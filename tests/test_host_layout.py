@@ -414,3 +414,25 @@ def test_preparation_errors(case):
     assert ei.value.status == status
     if case == "degenerate":
         assert "tetrahedron" in str(ei.value)
+
+
+def test_tuned_creation_rejects_bad_candidates():
+    """Candidate tile sizes are validated before any device work."""
+    from paper_2003_03130_amd.cells import _host_inputs, _options, _ptr
+    nat = _lib_or_skip()
+    b = uneven_batch(n_cells=2, seed=79, tet_lo=300, tet_hi=800, ladder=2)
+    node_off, tet_off, x, tets = _host_inputs(b.node_off, b.tet_off, b.x, b.tets)
+    opt = _options(None, None, None)
+    for cand in ([100], [64, 8192], [0]):
+        c = np.array(cand, dtype=np.int32)
+        h = ctypes.c_void_p()
+        rc = nat.lib().cm_batch_create_tuned(
+            2, _ptr(node_off), _ptr(tet_off), _ptr(x), _ptr(tets),
+            ctypes.byref(opt), _ptr(c), len(c), None, None, None,
+            ctypes.byref(h))
+        assert rc == nat.CM_EINVAL and "multiples of 64" in nat.lib().cm_last_error().decode()
+    h = ctypes.c_void_p()
+    rc = nat.lib().cm_batch_create_tuned(
+        2, _ptr(node_off), _ptr(tet_off), _ptr(x), _ptr(tets), ctypes.byref(opt),
+        _ptr(np.array([256], dtype=np.int32)), 0, None, None, None, ctypes.byref(h))
+    assert rc == nat.CM_EINVAL
