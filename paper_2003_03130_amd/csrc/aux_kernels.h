@@ -53,13 +53,18 @@ hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cel
                                const float* x, const double* plate, double k,
                                const double* energy_t, double armijo,
                                double min_move, float* y, float* yt, double* st,
-                               hipStream_t s);
+                               const int32_t* ninv_t, int32_t* ninv, hipStream_t s);
 hipError_t launch_qs_noise(const int64_t* node_off, int64_t N, int32_t n_cells,
                            const float* y, float* e, hipStream_t s);
 hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
                            const float* y, const double* plate, double k,
                            const float* e, const float* ybar, double* st,
                            hipStream_t s);
+// Start of the adjoint CG solve Hess(Pi) lam = weight_c dF_top/dy.
+hipError_t launch_qs_adjoint_rhs(const int64_t* node_off, int64_t N, int32_t n_cells,
+                                 const float* y, const double* plate, double k,
+                                 const double* weight, float* r, float* p, float* x,
+                                 double* st, const float* minv, hipStream_t s);
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,

@@ -40,6 +40,8 @@ struct DeviceTables {
   double* tile_acc = nullptr;      // per tile: energy (fwd) or 3 sums (bwd)
   double* tile_plate = nullptr;    // per tile: top-plate force (fwd)
   int32_t* tile_ninv = nullptr;    // per tile
+  int32_t* tile_nonfin = nullptr;  // per tile: tets with a non-finite energy
+                                   // or force (written by checked passes)
   int64_t n_nodes = 0, n_slots = 0, n_tiles = 0;
   int32_t n_cells = 0;
   int32_t nloc = 0;                // LDS node capacity per wave (multiple of 4)
@@ -95,13 +97,18 @@ size_t backward_lds_per_wave(int nloc);
 // With pl.plate set, the forward pass applies one plate-compression step
 // (see plate.h): it writes pl.y_next (and pl.force) instead of f, and the
 // finalize kernel needs y.
+// With check set, the tile pass counts per tile the tetrahedra whose energy
+// or force contribution is not finite (T.tile_nonfin) and the finalize sums
+// them per cell into nonfin.
 hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
                                const LaunchCfg& cfg, const float* y, float* f,
-                               hipStream_t st, const PlateFwd& pl = PlateFwd{});
+                               hipStream_t st, const PlateFwd& pl = PlateFwd{},
+                               bool check = false);
 hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
                                    float* f, double* energy, int32_t* ninv,
                                    hipStream_t st, const float* y = nullptr,
-                                   const PlateFwd& pl = PlateFwd{});
+                                   const PlateFwd& pl = PlateFwd{},
+                                   int32_t* nonfin = nullptr);
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
@@ -122,7 +129,8 @@ hipError_t launch_backward_finalize(const DeviceTables& T, const Range& r,
 hipError_t launch_forward(const DeviceTables& T, const Range& r,
                           const LaunchCfg& cfg, const float* y, float* f,
                           double* energy, int32_t* ninv, hipStream_t st,
-                          const PlateFwd& pl = PlateFwd{});
+                          const PlateFwd& pl = PlateFwd{},
+                          int32_t* nonfin = nullptr);
 
 hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const LaunchCfg& cfg, const float* y,

@@ -26,6 +26,7 @@ struct FwdArgs {
   const float* y;
   float* f;
   PlateFwd pl;  // used when PL
+  int check;    // count tets with a non-finite energy or force
 };
 
 template <int W, bool PL>
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     wave_sync();
 
     double eacc = 0.0;
-    int ninv = 0;
+    int ninv = 0, nonfin = 0;
     for_each_chunk(a.T.chunks + d.chunk_begin, d.n_chunks, lane,
                    [&](const TetRegs& cur) {
       const uint2 q = cur.q;
@@ -93,6 +94,13 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
         lds_accumulate([&](int i) { return &fs[i].x; }, i0, i1, i2, i3, h);
         eacc += vU;
         ninv += inv ? 1 : 0;
+        if (a.check) {
+          // a NaN or infinity in any component makes the sum non-finite
+          float hs = 0.f;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) hs += h[k][0] + h[k][1] + h[k][2];
+          nonfin += (isfinite(vU) && isfinite(hs)) ? 0 : 1;
+        }
       }
     });
     wave_sync();
@@ -128,9 +136,11 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     }
     eacc = wave_sum(eacc);
     ninv = wave_sum(ninv);
+    if (a.check) nonfin = wave_sum(nonfin);
     if (lane == 0) {
       a.T.tile_acc[t] = eacc;
       a.T.tile_ninv[t] = ninv;
+      if (a.check) a.T.tile_nonfin[t] = nonfin;
     }
     wave_sync();
   }
@@ -144,6 +154,7 @@ struct FinArgs {
   int32_t* ninv;
   const float* y;  // with a plate step
   PlateFwd pl;
+  int32_t* nonfin;  // per cell, nullable (needs a checked tile pass)
 };
 
 // The first cell_blocks workgroups sum the tile energies / inverted counts
@@ -160,18 +171,21 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
     if (wv >= a.r.cell_end - a.r.cell_begin) return;  // uniform per wave
     const int c = a.r.cell_begin + wv;
     double e = 0.0;
-    int ni = 0;
+    int ni = 0, nf = 0;
     const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
     for (int k = lane; k < nt; k += 64) {
       const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
       e += a.T.tile_acc[t];
       ni += a.T.tile_ninv[t];
+      if (a.nonfin) nf += a.T.tile_nonfin[t];
     }
     e = wave_sum(e);
     ni = wave_sum(ni);
+    if (a.nonfin) nf = wave_sum(nf);
     if (lane == 0) {
       if (a.energy) a.energy[c] = e;
       if (a.ninv) a.ninv[c] = ni;
+      if (a.nonfin) a.nonfin[c] = nf;
     }
     if (a.pl.force) {
       // top-plate force: the tile shares, then the nodes of no tetrahedron
@@ -234,9 +248,10 @@ size_t forward_lds_per_wave(int nloc) { return (size_t)32 * nloc; }
 
 hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
                                const LaunchCfg& cfg, const float* y, float* f,
-                               hipStream_t st, const PlateFwd& pl) {
+                               hipStream_t st, const PlateFwd& pl, bool check) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
-  FwdArgs a{T, r, y, f, pl};
+  if (check && !T.tile_nonfin) return hipErrorInvalidValue;
+  FwdArgs a{T, r, y, f, pl, check ? 1 : 0};
   const int grid = grid_for(r, cfg);
   const size_t lds = forward_lds_per_wave(T.nloc) * cfg.waves;
   switch (cfg.waves) {
@@ -251,13 +266,13 @@ hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
 hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
                                    float* f, double* energy, int32_t* ninv,
                                    hipStream_t st, const float* y,
-                                   const PlateFwd& pl) {
+                                   const PlateFwd& pl, int32_t* nonfin) {
   const int64_t n_shr = r.shared_end - r.shared_begin;
   const int64_t n_cells = r.cell_end - r.cell_begin;
   if (n_shr <= 0 && n_cells <= 0) return hipSuccess;
   const int cell_blocks = (int)((n_cells + 3) / 4);  // four waves per block
   const int64_t blocks = cell_blocks + (n_shr + 255) / 256;
-  FinArgs b{T, r, f, energy, ninv, y, pl};
+  FinArgs b{T, r, f, energy, ninv, y, pl, nonfin};
   hipLaunchKernelGGL(forward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      st, b, cell_blocks);
   return hipGetLastError();
@@ -266,10 +281,10 @@ hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
 hipError_t launch_forward(const DeviceTables& T, const Range& r,
                           const LaunchCfg& cfg, const float* y, float* f,
                           double* energy, int32_t* ninv, hipStream_t st,
-                          const PlateFwd& pl) {
-  hipError_t e = launch_forward_main(T, r, cfg, y, f, st, pl);
+                          const PlateFwd& pl, int32_t* nonfin) {
+  hipError_t e = launch_forward_main(T, r, cfg, y, f, st, pl, nonfin != nullptr);
   if (e != hipSuccess) return e;
-  return launch_forward_finalize(T, r, f, energy, ninv, st, y, pl);
+  return launch_forward_finalize(T, r, f, energy, ninv, st, y, pl, nonfin);
 }
 
 }  // namespace cm

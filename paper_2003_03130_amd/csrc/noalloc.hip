@@ -80,6 +80,7 @@ extern "C" int cm_forces_noalloc(cm_batch h, const float* y, float* f,
   T.tile_acc = reinterpret_cast<double*>(b + off_acc);
   T.tile_ninv = reinterpret_cast<int32_t*>(b + off_ninv);
   T.tile_plate = nullptr;  // written only by the plate-step pass
+  T.tile_nonfin = nullptr;  // written only by the checked pass
   const cm::Range r{0, (int32_t)h->n_tiles, 0, (int32_t)h->n_shared, 0,
                     (int32_t)h->n_cells};
   CM_HIP(cm::launch_forward(T, r, h->cfg, y, f, energy, n_inverted, stream));
