@@ -11,7 +11,11 @@ state at plate position `top` minimises Pi(y) = E(y) + sum_nodes phi(y_z),
 i.e. f(y) + p(y) = 0.  Here Pi is minimised by a library trust-region Newton
 method (scipy, Krylov subproblem) on the oracle's energy, forces and
 Hessian-vector products; the top-plate force is F = k sum max(0, y_z - top)^2
-and the bottom-plate force k sum max(0, bottom - y_z)^2.
+and the bottom-plate force k sum max(0, bottom - y_z)^2.  The energy density
+grows without bound as J -> 0 from above, but with the real cube root it is
+finite again for J < 0, so a finite step could jump over that barrier:
+states that invert more tetrahedra than the start has are taken as
+inadmissible (Pi = +inf there, which makes the trust region shrink).
 """
 from __future__ import annotations
 
@@ -37,11 +41,14 @@ def equilibrium(mesh, y0, theta, top, bottom, k, gtol=1e-10, maxiter=500):
     F_bottom, |grad Pi|_inf)."""
     y0 = np.asarray(y0, np.float64)
     shape = y0.shape
+    ninv0 = mesh.forces(y0, theta)[2]
 
     def fun(v):
         y = v.reshape(shape)
-        f, E, _ = mesh.forces(y, theta)
+        f, E, ninv = mesh.forces(y, theta)
         phi, p, _, _, _ = plate_terms(y, top, bottom, k)
+        if ninv > ninv0:
+            return np.inf, -(f + p).ravel()
         return E + phi, -(f + p).ravel()
 
     def hessp(v, d):

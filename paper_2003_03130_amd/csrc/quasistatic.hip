@@ -471,6 +471,57 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   cg_finish(a, s, rn, rzn);
 }
 
+// Adjoint of the equilibrium for the top-plate force.  At an equilibrium
+// f(y; theta) + p(y) = 0 the derivative of F_top = k sum max(0, z - top)^2
+// along the parameters is dF_top/dtheta = lam^T df/dtheta with
+// Hess(Pi) lam = g, g = dF_top/dy (2 k max(0, z - top) on the z entries, 0
+// elsewhere): one more CG solve on the same Hessian-vector products.  This
+// kernel starts that solve: r = w_c g (w_c = weight[c], 1 when null), p =
+// M^-1 r, x = 0, CG state r . z, |r|^2, active iff |r| > 0, forcing term 0
+// (the CG runs to its own tolerance).  g is orthogonal to the symmetry modes
+// of the plates (it has z entries only), so the singular system is
+// consistent.
+struct AdjArgs {
+  const int64_t* node_off;
+  int64_t N;
+  const float* y;
+  const double* plate;
+  double k;
+  const double* weight;
+  float *r, *p, *x;
+  double* st;
+  const float* minv;
+};
+
+__global__ __launch_bounds__(kThreads) void qs_adjoint_rhs_kernel(AdjArgs a) {
+  __shared__ double red[kThreads];
+  const int c = blockIdx.x;
+  const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
+  const double top = a.plate[2 * c];
+  const double w = a.weight ? a.weight[c] : 1.0;
+  double rr = 0.0, rz = 0.0;
+  for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    const double z = a.y[2 * N + i];
+    const float g = (float)(w * 2.0 * a.k * fmax(z - top, 0.0));
+    float zx = 0.f, zy = 0.f, zz = g;
+    if (a.minv) apply_minv(a.minv, N, i, 0.f, 0.f, g, zx, zy, zz);
+    a.r[i] = 0.f; a.r[N + i] = 0.f; a.r[2 * N + i] = g;
+    a.p[i] = zx; a.p[N + i] = zy; a.p[2 * N + i] = zz;
+    a.x[i] = 0.f; a.x[N + i] = 0.f; a.x[2 * N + i] = 0.f;
+    rr += (double)g * g;
+    rz += (double)g * zz;
+  }
+  rr = block_sum(rr, red);
+  rz = block_sum(rz, red);
+  if (threadIdx.x == 0) {
+    double* s = a.st + kQsState * c;
+    s[0] = rz;
+    s[1] = rr;
+    s[2] = rr > 0.0 ? 1.0 : 0.0;
+    s[14] = 0.0;
+  }
+}
+
 // Float32 floor of the residual.  Positions held in float32 carry rounding
 // errors of up to half a unit in the last place, so the residual of a
 // float32 state cannot be resolved below |Hess(Pi) e| for such an error e.
@@ -565,6 +616,8 @@ struct LsArgs {
   float* y;
   float* yt;               // trial positions
   double* st;
+  const int32_t* ninv_t;   // inverted tetrahedra at y_t (nullable)
+  int32_t* ninv;           // inverted tetrahedra at y (nullable)
 };
 
 // Start of the line search on Pi along the Newton step x: s = min(1, cap /
@@ -607,7 +660,10 @@ __global__ __launch_bounds__(kThreads) void qs_ls_start_kernel(LsArgs a) {
 
 // Armijo test per pending cell: accept y_t if Pi(y_t) <= Pi(y) - armijo s
 // (r_N . x), copying y_t into y; else halve s and form the next trial, giving
-// up (no move) once s max|x| < min_move.
+// up (no move) once s max|x| < min_move.  With inverted counts, a trial that
+// inverts more tetrahedra than y has is rejected as well: the energy density
+// grows without bound as J -> 0, but a finite step can jump over that
+// barrier to an inverted state of finite energy.
 __global__ __launch_bounds__(kThreads) void qs_ls_accept_kernel(LsArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -624,7 +680,8 @@ __global__ __launch_bounds__(kThreads) void qs_ls_accept_kernel(LsArgs a) {
   phi = block_sum(phi, red) * (a.k / 3.0);
   const double pit = a.energy_t[c] + phi;
   const double sc = s[9];
-  const bool ok = pit <= s[8] - a.armijo * sc * s[10];
+  const bool feasible = !(a.ninv_t && a.ninv) || a.ninv_t[c] <= a.ninv[c];
+  const bool ok = feasible && pit <= s[8] - a.armijo * sc * s[10];
   const bool give_up = !ok && 0.5 * sc * s[13] < a.min_move;
   if (ok) {
     for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
@@ -641,6 +698,7 @@ __global__ __launch_bounds__(kThreads) void qs_ls_accept_kernel(LsArgs a) {
   }
   if (threadIdx.x == 0) {
     if (ok) {
+      if (a.ninv_t && a.ninv) a.ninv[c] = a.ninv_t[c];
       s[8] = pit;
       s[4] = sc;
       s[6] = sc * s[13];  // largest node move of this step
@@ -703,6 +761,15 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
   return hipGetLastError();
 }
 
+hipError_t launch_qs_adjoint_rhs(const int64_t* node_off, int64_t N, int32_t n_cells,
+                                 const float* y, const double* plate, double k,
+                                 const double* weight, float* r, float* p, float* x,
+                                 double* st, const float* minv, hipStream_t s) {
+  AdjArgs a{node_off, N, y, plate, k, weight, r, p, x, st, minv};
+  hipLaunchKernelGGL(qs_adjoint_rhs_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
@@ -757,7 +824,7 @@ hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cell
                               const float* x, const float* rn, double cap,
                               const float* y, float* yt, double* st, hipStream_t s) {
   LsArgs a{node_off, N, x, rn, nullptr, nullptr, 0.0, cap, 0.0, 0.0,
-           const_cast<float*>(y), yt, st};
+           const_cast<float*>(y), yt, st, nullptr, nullptr};
   hipLaunchKernelGGL(qs_ls_start_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -766,9 +833,9 @@ hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cel
                                const float* x, const double* plate, double k,
                                const double* energy_t, double armijo,
                                double min_move, float* y, float* yt, double* st,
-                               hipStream_t s) {
+                               const int32_t* ninv_t, int32_t* ninv, hipStream_t s) {
   LsArgs a{node_off, N, x, nullptr, plate, energy_t, k, 0.0, armijo, min_move, y, yt,
-           st};
+           st, ninv_t, ninv};
   hipLaunchKernelGGL(qs_ls_accept_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

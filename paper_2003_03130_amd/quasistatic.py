@@ -60,6 +60,10 @@ class QuasiStaticCompression:
         self._yt = batch.empty_nodes()
         self._ft = batch.empty_nodes()
         self._Et = torch.empty(batch.n_cells, dtype=torch.float64, device=dev)
+        # inverted tetrahedra at y and at the line-search trial: a trial may
+        # not invert more than y has (the barrier at J = 0)
+        self._ninv = torch.zeros(batch.n_cells, dtype=torch.int32, device=dev)
+        self._ninv_t = torch.zeros(batch.n_cells, dtype=torch.int32, device=dev)
         self._E = torch.empty(batch.n_cells, dtype=torch.float64, device=dev)
         self._tb = torch.empty(3 * batch.n_mat, dtype=torch.float64,
                                device=dev)
@@ -71,7 +75,7 @@ class QuasiStaticCompression:
 
     def _residual(self, y, plate, restart=False):
         cb = self.cb
-        cb.forces(y, self._f, self._E)
+        cb.forces(y, self._f, self._E, self._ninv)
         nat.check(nat.lib().cm_qs_residual(
             cb._h, _ptr(y), _ptr(self._f), _ptr(self._E), _ptr(plate), self.k,
             self.abs_tol, self.rel_tol, self.step_tol, self.floor_factor,
@@ -131,20 +135,55 @@ class QuasiStaticCompression:
         for _ in range(self.max_backtrack):
             if not self._active(12):
                 return
-            cb.forces(self._yt, self._ft, self._Et)
+            cb.forces(self._yt, self._ft, self._Et, self._ninv_t)
             nat.check(nat.lib().cm_qs_ls_accept(
                 cb._h, _ptr(self._x), _ptr(plate), self.k, _ptr(self._Et),
                 self.armijo, self.min_move, _ptr(y), _ptr(self._yt),
-                _ptr(self.state), _stream(None)))
+                _ptr(self.state), _ptr(self._ninv_t), _ptr(self._ninv),
+                _stream(None)))
             self.stats["trials"] += 1
 
-    def curve(self, y0, tops, bottom):
+    def plate_force_gradient(self, y, plate, weight=None, tol=1e-5):
+        """dF_top/d(mu, kappa, w) per material slot at the equilibrium y of
+        the plate position `plate` (implicit differentiation: one CG solve
+        Hess(Pi) lam = weight dF_top/dy on the device, then thetabar =
+        lam^T df/dtheta from cm_forces_backward).  Call it right after
+        equilibrate() at that position (the preconditioner blocks of its
+        last residual are used).  weight: float64 device tensor (n_cells,)
+        or None (1).  Returns a float64 device tensor (n_mat, 3)."""
+        import torch
+        cb = self.cb
+        lib, st = nat.lib(), _stream(None)
+        nat.check(lib.cm_qs_adjoint_rhs(
+            cb._h, _ptr(y), _ptr(plate), self.k, _ptr(weight), _ptr(self._r),
+            _ptr(self._p), _ptr(self._x), _ptr(self.state), _ptr(self._minv),
+            st))
+        flags = self.state[:, 2]
+        hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
+                    flags.stride(0), _ptr(self._ybar), None, st)
+        cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, float(tol),
+                   _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
+                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
+                   _ptr(self._minv), st)
+        for j in range(4 * self.max_cg):
+            nat.check(lib.cm_forces_backward_cells(*hvp_args))
+            nat.check(lib.cm_qs_cg_step(*cg_args))
+            self.stats["adjoint_cg"] = self.stats.get("adjoint_cg", 0) + 1
+            if j % 8 == 7 and not self._active(2):
+                break
+        tb = torch.empty(3 * cb.n_mat, dtype=torch.float64, device=cb.device)
+        cb.backward(y, self._x, None, self._ybar, tb)
+        return tb.view(-1, 3)
+
+    def curve(self, y0, tops, bottom, jacobian=False, adjoint_tol=1e-5):
         """Top-plate force of every cell at each plate height (tops: (S,) or
         (S, n_cells); bottom: scalar or (n_cells,)), starting from y0 and
         each position from the previous equilibrium (affine predictor).
         Returns (forces (S, n_cells) top, (S, n_cells) bottom, converged (S,),
         final positions); self.residuals (S, n_cells) holds the final
-        projected Newton residual norms |f + p|_2."""
+        projected Newton residual norms |f + p|_2.  With jacobian=True,
+        self.jacobian (S, n_mat, 3) holds dF_top/d(mu, kappa, w) at every
+        plate position (plate_force_gradient after each equilibrium)."""
         import torch
         cb = self.cb
         tops = np.asarray(tops, dtype=np.float64)
@@ -154,15 +193,19 @@ class QuasiStaticCompression:
         y = y0.clone()
         plates = torch.from_numpy(np.stack([tops, np.broadcast_to(
             bot, tops.shape)], axis=2).copy()).to(cb.device)
-        Ft, Fb, ok, res = [], [], [], []
+        Ft, Fb, ok, res, jac = [], [], [], [], []
         for s in range(len(tops)):
             if s > 0:
                 nat.check(nat.lib().cm_qs_predict(
                     cb._h, _ptr(plates[s - 1]), _ptr(plates[s]), _ptr(y),
                     _stream(None)))
             ok.append(self.equilibrate(y, plates[s]))
+            if jacobian:
+                jac.append(self.plate_force_gradient(
+                    y, plates[s], tol=adjoint_tol).cpu().numpy())
             Ft.append(self.force[:, 0].cpu().numpy().copy())
             Fb.append(self.force[:, 1].cpu().numpy().copy())
             res.append(self.state[:, 3].sqrt().cpu().numpy())
         self.residuals = np.array(res)
+        self.jacobian = np.array(jac) if jacobian else None
         return np.array(Ft), np.array(Fb), np.array(ok), y
