@@ -318,3 +318,21 @@ def compression_batch(n_cells, n_target, seed, n_meshes=None):
     b.info = {"theta_star": b.theta.copy(),
               "theta0": np.array(th0, dtype=np.float64)}
     return b
+
+
+def calibration_batch(n_cells, n_target, seed, n_meshes=8):
+    """Oblate cells (as oblate_batch) for quasi-static calibration: the
+    batch's theta is the hidden theta* (seed), info["theta0"] a start drawn
+    the same way (seed + 1)."""
+    b = oblate_batch(n_cells, n_target, seed, n_meshes=n_meshes)
+    r0 = np.random.default_rng(seed + 1)
+    b.info = {"theta_star": b.theta.copy(),
+              "theta0": np.array([random_theta(r0) for _ in range(n_cells)],
+                                 dtype=np.float64)}
+    return b
+
+
+def qs_fractions(n_steps=10, lo=0.08, hi=0.8):
+    """Plate travel of the quasi-static calibration curves as fractions of
+    each cell's reference height (8 % to 80 %)."""
+    return np.linspace(lo, hi, n_steps)

@@ -1,18 +1,22 @@
 """Quasi-static plate compression on the GPU (cm_qs_* with Newton-CG on the
 backward kernels' Hessian-vector products) against the FP64 oracle's
-minimiser of the same potential, along the same loading path.
+minimiser of the same potential, along the same loading path, from first
+contact to 80 % plate travel (the paper's compressions go past the force
+upturn at about 40 % deformation, Sec. "Results" of the FluidFM comparison).
 
 Tolerance: the device stops at |f + p|_2 <= 1e-3 |p|_2 (projected residual,
 float32 positions: the floor is about 5e-6 absolute, 3e-4 |p| at the
 smallest compression), the oracle at a float64 gradient norm of 1e-10; the
-plate force moves by well under the relative residual (measured 1e-5 to
-2e-4), so the bar on the top-plate force is 2e-3 relative.  The plates
-balance up to what the equilibrium test allows: Ft - Fb is the sum of the z
-residuals (the elastic forces of a cell sum to zero), so |Ft - Fb| <=
-sqrt(n) |r|_2 for n nodes.  At the first contact (2 % compression) the plate force of
-a float32 state is resolved only to about 1 %: the residual floor of float32
-positions leaves the state free to wander along the softest modes, which
-change which nodes touch the plates; there the bar is 1e-2."""
+plate force moves by well under the relative residual (measured 3e-5 to
+8e-4 from 5 % on), so the bar on the top-plate force is 2e-3 relative.  At
+the first contact (2 %) the plate force of a float32 state is resolved only
+to about 1 % (the residual floor of float32 positions leaves the state free
+to wander along the softest modes, which changes the nodes that touch the
+plates): there the bar is 1e-2.  The plates balance: at equilibrium the
+elastic forces of a cell sum to zero, so the top and bottom plate forces
+are equal; the bar on |Ft - Fb| / Ft is 5e-3 at first contact and 2e-3 from
+5 % on (measured 3.5e-3 and 1.5e-3).  No tetrahedron may be inverted at any
+equilibrium (the line search keeps the states on the side J > 0)."""
 import warnings
 
 import numpy as np
@@ -48,41 +52,189 @@ def _cells():
     return batch_from_cells(cells)
 
 
+FRACTIONS = np.array([0.02, 0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8])
+
+
+def _plates(b, fractions):
+    top0 = np.array([b.cell(c).x[:, 2].max() for c in range(b.n_cells)])
+    bot = np.array([b.cell(c).x[:, 2].min() for c in range(b.n_cells)])
+    tops = top0[None, :] - np.asarray(fractions)[:, None] * (top0 - bot)[None, :]
+    return tops, bot, top0 - bot
+
+
 def test_force_curve_against_oracle():
+    """Plate travel from 2 % to 80 % of each cell's height: the top-plate
+    force against the oracle at every position, the plate balance, no
+    inverted tetrahedron, the cells' own height compressed by at least 60 %,
+    and the upturn (log-log slope between 40 % and 80 % well above the 3/2 of
+    Hertz contact)."""
     import torch
     from paper_2003_03130_amd import CellBatch
     from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
     b = _cells()
     cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
     cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
-    top0 = np.array([b.cell(c).x[:, 2].max() for c in range(b.n_cells)])
-    bot = np.array([b.cell(c).x[:, 2].min() for c in range(b.n_cells)])
-    delta = np.array([0.02, 0.05, 0.1, 0.2])
-    tops = top0[None, :] - 2.0 * delta[:, None]
+    tops, bot, H = _plates(b, FRACTIONS)
     qs = QuasiStaticCompression(cb, K)
-    Ft, Fb, ok, y = qs.curve(cb.to_device(b.y), tops, bot)
-    assert ok.all(), qs.stats
+    y = cb.to_device(b.y)
+    ninv = torch.zeros(b.n_cells, dtype=torch.int32, device=cb.device)
+    Ft, Fb, ok, heights = [], [], [], []
+    plates = torch.tensor(np.stack([tops, np.broadcast_to(bot, tops.shape)], axis=2),
+                          device=cb.device)
+    for s in range(len(FRACTIONS)):
+        if s > 0:
+            from paper_2003_03130_amd import _native as nat
+            from paper_2003_03130_amd.cells import _ptr, _stream
+            nat.check(nat.lib().cm_qs_predict(cb._h, _ptr(plates[s - 1]),
+                                              _ptr(plates[s]), _ptr(y), _stream(None)))
+        ok.append(qs.equilibrate(y, plates[s]))
+        Ft.append(qs.force[:, 0].cpu().numpy().copy())
+        Fb.append(qs.force[:, 1].cpu().numpy().copy())
+        cb.forces(y, n_inverted=ninv)
+        assert int(ninv.sum().item()) == 0, (s, ninv)
+        yh = cb.to_host(y)
+        heights.append([np.ptp(yh[b.node_off[c]:b.node_off[c + 1], 2])
+                        for c in range(b.n_cells)])
+    Ft, Fb, heights = np.array(Ft), np.array(Fb), np.array(heights)
+    assert all(ok), qs.stats
     print("newton / cg iterations:", qs.stats)
     worst = 0.0
     for c in range(b.n_cells):
         cell = b.cell(c)
         m = oracle.OracleMesh(cell.x, cell.tets)
-        yo = cell.x.copy()
-        for s in range(len(delta)):
+        yo = cell.y.astype(np.float64)
+        for s in range(len(FRACTIONS)):
             with warnings.catch_warnings():
                 warnings.simplefilter("ignore", RuntimeWarning)
                 yo, Fo, Fbo, g = oqs.equilibrium(m, yo, cell.theta, tops[s, c],
                                                  bot[c], K)
+            first = FRACTIONS[s] < 0.03
             err = abs(Ft[s, c] - Fo) / Fo
             worst = max(worst, err)
-            assert err <= (1e-2 if delta[s] < 0.03 else 2e-3), (c, s, Ft[s, c], Fo)
-            # plate balance: Ft - Fb = sum of the z residuals (the elastic
-            # forces sum to zero), at most sqrt(n) |r|_2 by Cauchy-Schwarz
-            n = b.node_off[c + 1] - b.node_off[c]
-            assert abs(Ft[s, c] - Fb[s, c]) <= (np.sqrt(n) * qs.residuals[s, c]
-                                                + 1e-6 * Ft[s, c])
+            assert err <= (1e-2 if first else 2e-3), (c, s, Ft[s, c], Fo)
+            bal = abs(Ft[s, c] - Fb[s, c]) / Ft[s, c]
+            assert bal <= (5e-3 if first else 2e-3), (c, s, bal)
     print("worst relative top-plate force difference:", worst)
     assert np.all(np.diff(Ft, axis=0) > 0)
+    compression = 1.0 - heights[-1] / H
+    print("height compression at 80 % plate travel:", compression)
+    assert np.all(compression >= 0.6)
+    slope = np.log(Ft[-1] / Ft[5]) / np.log(FRACTIONS[-1] / FRACTIONS[5])
+    print("log-log slope of F between 40 % and 80 %:", slope)
+    assert np.all(slope > 2.5)
+
+
+def test_w_sets_the_upturn():
+    """One cell with mu = 1, kappa = 20 and w = 0.25, 0.5, 1 (the paper's
+    fitted values): the forces agree at small compression (the small-strain
+    limit depends on mu = mu1 + mu2 only, eq. elastic-moduli:mr) and spread
+    past the upturn, the smaller w (more of the K invariant) the stiffer;
+    every curve against the oracle."""
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    x, tets = sphere_mesh(300, 5)
+    x = ellipsoid(x, np.array((1.2, 1.05, 0.8)))
+    ws = (0.25, 0.5, 1.0)
+    b = batch_from_cells([Cell(x, tets, x.astype(np.float32), (1.0, 20.0, w))
+                          for w in ws])
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    fr = np.array([0.05, 0.2, 0.4, 0.6, 0.8])
+    tops, bot, _ = _plates(b, fr)
+    qs = QuasiStaticCompression(cb, K)
+    Ft, _, ok, _ = qs.curve(cb.to_device(b.y), tops, bot)
+    assert ok.all()
+    m = oracle.OracleMesh(x, tets)
+    for c, w in enumerate(ws):
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            Fo, _ = oqs.force_curve(m, b.cell(c).y.astype(np.float64), (1.0, 20.0, w),
+                                    tops[:, c], bot[c], K)
+        err = np.abs(Ft[:, c] - Fo) / Fo
+        print(f"w {w}: {Ft[:, c]} (oracle {Fo}), rel. difference {err.max():.2e}")
+        assert err.max() <= 2e-3
+    assert np.ptp(Ft[0]) <= 0.01 * Ft[0].mean()
+    assert Ft[-1, 0] > Ft[-1, 1] > Ft[-1, 2]
+    assert (Ft[-1, 0] - Ft[-1, 2]) > 0.3 * Ft[-1, 2]
+
+
+def test_plate_force_gradient_against_oracle_differences():
+    """dF_top/d(mu, kappa, w) from the adjoint of the equilibrium (one CG
+    solve per plate position, then one backward pass) against central
+    differences of the oracle's equilibrium force (h = 1e-4 relative);
+    bar 2e-3 of the largest component (measured up to 5e-4 at 10 %)."""
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b = _cells()
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    fr = np.array([0.1, 0.4, 0.7])
+    tops, bot, _ = _plates(b, fr)
+    qs = QuasiStaticCompression(cb, K)
+    _, _, ok, _ = qs.curve(cb.to_device(b.y), tops, bot, jacobian=True)
+    assert ok.all()
+    Jg = qs.jacobian
+    print("adjoint CG iterations:", qs.stats.get("adjoint_cg"))
+    for c in range(b.n_cells):
+        cell = b.cell(c)
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        th = np.array(cell.theta)
+        steps = np.array([1e-4 * th[0], 1e-4 * th[1], 1e-4])
+        fd = np.zeros((len(fr), 3))
+        for k in range(3):
+            Fs = []
+            for sgn in (1, -1):
+                tt = th.copy()
+                tt[k] += sgn * steps[k]
+                with warnings.catch_warnings():
+                    warnings.simplefilter("ignore", RuntimeWarning)
+                    F, _ = oqs.force_curve(m, cell.y.astype(np.float64), tuple(tt),
+                                           tops[:, c], bot[c], K)
+                Fs.append(F)
+            fd[:, k] = (Fs[0] - Fs[1]) / (2 * steps[k])
+        for s in range(len(fr)):
+            err = np.abs(Jg[s, c] - fd[s]).max() / np.abs(fd[s]).max()
+            print(f"cell {c} at {fr[s]:.0%}: adjoint {Jg[s, c]}, differences "
+                  f"{fd[s]}, {err:.1e}", flush=True)
+            assert err <= 2e-3, (c, s)
+
+
+def test_calibration_recovers_hidden_parameters():
+    """Force-indentation curves of hidden (mu, kappa, w) to 80 % plate travel
+    from the oracle; Levenberg-Marquardt from another start with the
+    adjoint's derivatives lowers every cell's loss by orders of magnitude
+    and brings (mu, w) to within 1 % and kappa to within 10 % of the hidden
+    values."""
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.calibrate import fit_curves
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b = _cells()
+    theta_star = b.theta.copy()
+    theta0 = theta_star * np.array([1.4, 0.6, 1.0])
+    theta0[:, 2] = np.clip(1.0 - theta_star[:, 2] * 0.7, 0.05, 0.95)
+    fr = np.array([0.05, 0.2, 0.4, 0.6, 0.8])
+    tops, bot, _ = _plates(b, fr)
+    target = np.zeros((len(fr), b.n_cells))
+    for c in range(b.n_cells):
+        cell = b.cell(c)
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            target[:, c], _ = oqs.force_curve(m, cell.y.astype(np.float64),
+                                              cell.theta, tops[:, c], bot[c], K)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(theta0[:, 0], theta0[:, 1], theta0[:, 2])
+    qs = QuasiStaticCompression(cb, K)
+    res = fit_curves(qs, cb.to_device(b.y), tops, bot, target, theta0, iters=8,
+                     log=print)
+    losses = np.array([h["loss"] for h in res["history"]])
+    print("loss per iteration:", losses.sum(axis=1))
+    assert np.all(np.diff(losses, axis=0) <= 0)
+    assert np.all(losses[-1] <= 1e-3 * losses[0])
+    rel = np.abs(res["theta"] - theta_star) / np.abs(theta_star)
+    print("fitted:", res["theta"], "hidden:", theta_star, "rel. error:", rel)
+    assert np.all(rel[:, 0] <= 1e-2) and np.all(np.abs(res["theta"][:, 2] - theta_star[:, 2]) <= 1e-2)
+    assert np.all(rel[:, 1] <= 1e-1)
 
 
 def test_restart_from_equilibrium():
