@@ -242,19 +242,6 @@ def cpu_baseline(b, vbar, ebar, seconds, threads=None, reps=5):
                       f"({int(b.tet_off[n1])} tets, {t1:.2f} s)"}
 
 
-def hertz_targets(theta, top, radius=1.0):
-    """Synthetic force-indentation curves of the hidden parameters (Hertz
-    contact of a sphere between two plates, the paper's small-deformation
-    comparison): F = (4/3) E/(1 - nu^2) sqrt(R/2) (d/2)^(3/2), d = R - top,
-    with E and nu from the small-strain relations of Sec. "Theory"."""
-    mu, kappa = theta[:, 0], theta[:, 1]
-    E = 9 * kappa * mu / (3 * kappa + mu)
-    nu = (3 * kappa - 2 * mu) / (2 * (3 * kappa + mu))
-    d = np.clip(radius - np.asarray(top), 0, None)[:, None]
-    return 4.0 / 3.0 * (E / (1 - nu ** 2))[None, :] * np.sqrt(radius / 2) \
-        * (d / 2) ** 1.5
-
-
 def run_relax(args):
     """Plate compression of 256 cells x ~51k tets over 200 steps: forward
     sweep and checkpointed reverse-mode gradient (dL/d(mu, kappa, w))."""
@@ -273,7 +260,16 @@ def run_relax(args):
     pc = PlateCompression(cb, top, bot, K_PLATE, STOKES_DT / DRAG,
                           checkpoint=20)
     pc.set_theta(b.info["theta0"])
-    Ft = torch.from_numpy(hertz_targets(b.info["theta_star"], top)).to(cb.device)
+    # calibration targets: the oracle's FP64 replay of the same scheme at the
+    # hidden theta* (written by tests/golden/make_relax_targets.py for the
+    # 256-cell, 200-step workload; cells are generated in the same order for
+    # any prefix of that batch)
+    tgt = np.load(os.path.join(ROOT, "tests", "golden", "relax_targets.npy"))
+    if args.relax_steps != tgt.shape[0] or b.n_cells > tgt.shape[1]:
+        raise SystemExit(f"relax targets cover {tgt.shape[1]} cells x "
+                         f"{tgt.shape[0]} steps; run with --relax-steps "
+                         f"{tgt.shape[0]} and at most {tgt.shape[1]} cells")
+    Ft = torch.from_numpy(np.ascontiguousarray(tgt[:, :b.n_cells])).to(cb.device)
     y0 = cb.to_device(b.y)
     scale = 1.0 / (args.relax_steps * b.n_cells)
     pc.forward(y0)  # warm-up
@@ -312,6 +308,12 @@ def run_relax(args):
     _, g_two, _ = pc_two.gradient(y0, Ft, scale)
     torch.cuda.synchronize()
     t_bptt_two = time.perf_counter() - t
+    # the loss at the hidden parameters (targets reproduced by the device)
+    pc.set_theta(b.info["theta_star"])
+    F_star, _, _ = pc.forward(y0)
+    loss_star = float(scale * ((F_star - Ft) ** 2).sum())
+    target_err = float((F_star - Ft).abs().max() / Ft.abs().max())
+    pc.set_theta(b.info["theta0"])
     M, N, S = b.n_tets, b.n_nodes, args.relax_steps
     # a fused step moves the tet stream, reads y and writes y_next
     step_bytes = FWD_BYTES[0] * M + FWD_BYTES[1] * N
@@ -329,9 +331,15 @@ def run_relax(args):
             "plate_force": float(((F_two - F).abs().max() / F.abs().max())),
             "gradient": float(((g_two - g).abs().max() / g.abs().max()))},
         "fwd_step_hbm_frac": step_bytes * S / t_fwd / (HBM_PEAK_GBS * 1e9),
-        "loss": loss, "grad_finite": bool(torch.isfinite(g).all()),
+        "loss": loss, "loss_at_theta_star": loss_star,
+        "targets_vs_device_at_theta_star": target_err,
+        "grad_finite": bool(torch.isfinite(g).all()),
         "max_plate_force": float(F.max()),
-        "targets": "Hertz curves of hidden (mu, kappa, w)",
+        "targets": "oracle FP64 replay of the same 200 steps at the hidden "
+                   "(mu, kappa, w) of every cell (tests/golden/relax_targets.npy)",
+        "compression": "20 % (explicit steps invert tetrahedra at 40-80 % "
+                       "within 200 steps; 80 % is served by the quasi-static "
+                       "and calibration legs)",
     }
     log(f"relax: {out}")
     return out
@@ -447,10 +455,14 @@ def run_shape(args, cb, b, y):
 
 def run_quasistatic(args):
     """Quasi-static force-indentation curves: oblate cells (~2k nodes,
-    ~11k tets each) between plates closing in steps of 0.02 R up to 20 %
-    of the height, every step brought to equilibrium by Newton-CG on the
-    device (inexact Newton, Hessian-vector products only for the cells still
-    in CG); reports wall time, Newton/CG counts and time per CG iteration."""
+    ~11k tets each) between plates closing from first contact to 80 % of
+    each cell's height in args.qs_steps positions, every position brought to
+    equilibrium by Newton-CG on the device (inexact Newton, Hessian-vector
+    products only for the cells still in CG, line search that never inverts
+    a tetrahedron); reports wall time, Newton/CG counts, time per CG
+    iteration, the mean curve, the deepest compression of the cells' own
+    height, the plate balance, and the mean curves of the same cells with w
+    set to 0.25, 0.5 and 1 (the paper's fitted values)."""
     import torch
     from paper_2003_03130_amd import CellBatch
     from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
@@ -463,31 +475,179 @@ def run_quasistatic(args):
                      for c in range(b.n_cells)])
     bot = np.array([b.x[b.node_off[c]:b.node_off[c + 1], 2].min()
                     for c in range(b.n_cells)])
-    delta = np.linspace(0.02, 0.2, 10)
-    tops = top0[None, :] - 2.0 * delta[:, None] * 0.8
+    H = top0 - bot
+    frac = np.linspace(0.04, 0.8, args.qs_steps)
+    tops = top0[None, :] - frac[:, None] * H[None, :]
     log(f"quasi-static workload: {b.n_cells} cells, {b.n_tets} tets "
         f"({time.time() - t:.1f} s)")
     qs = QuasiStaticCompression(cb, K_PLATE)
     y0 = cb.to_device(b.y)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    Ft, Fb, ok, _ = qs.curve(y0, tops, bot)
+    Ft, Fb, ok, y = qs.curve(y0, tops, bot)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     hvp = qs.stats["cg"]
+    ninv = torch.zeros(b.n_cells, dtype=torch.int32, device=cb.device)
+    cb.forces(y, n_inverted=ninv)
+    yh = cb.to_host(y)
+    comp = np.array([1.0 - np.ptp(yh[b.node_off[c]:b.node_off[c + 1], 2]) / H[c]
+                     for c in range(b.n_cells)])
+    # the same cells with w = 0.25, 0.5, 1 (mu, kappa kept)
+    w_curves = {}
+    for w in (0.25, 0.5, 1.0):
+        cb.set_params(b.theta[:, 0], b.theta[:, 1], np.full(b.n_cells, w))
+        qw = QuasiStaticCompression(cb, K_PLATE)
+        Fw, _, okw, _ = qw.curve(y0, tops, bot)
+        w_curves[str(w)] = {"mean_force": [round(float(v), 6) for v in Fw.mean(axis=1)],
+                            "converged": bool(okw.all())}
     out = {
         "workload": f"{b.n_cells} oblate cells, {b.n_tets} tets, plates "
-                    f"closing to 20 % of the height in 10 steps, "
-                    f"{args.qs_tile_tets}-tet tiles",
+                    f"closing from first contact to 80 % of each cell's height "
+                    f"in {args.qs_steps} positions, {args.qs_tile_tets}-tet tiles",
         "wall_s": wall, "newton": qs.stats["newton"], "cg": hvp,
         "converged_steps": int(ok.sum()), "steps": len(ok),
-        "unconverged_cells_last": int((qs.state[:, 2] > 0).sum().item()),
+        "unconverged_cells_last": int((qs.state[:, 11] > 0).sum().item()),
         "ms_per_cg_iteration": 1e3 * wall / max(hvp, 1),
         "eta_max": qs.eta_max,
-        "max_force_mean": float(Ft[-1].mean()),
-        "plate_balance": float(np.max(np.abs(Ft - Fb) / np.maximum(Ft, 1e-30))),
+        "plate_travel": [round(float(v), 4) for v in frac],
+        "mean_force": [round(float(v), 6) for v in Ft.mean(axis=1)],
+        "deepest_plate_travel": float(frac[-1]),
+        "height_compression_mean": float(comp.mean()),
+        "height_compression_min": float(comp.min()),
+        "inverted_tets_final": int(ninv.sum().item()),
+        "plate_balance_max_by_step": [float(v) for v in
+                                      (np.abs(Ft - Fb) / np.maximum(Ft, 1e-30)).max(axis=1)],
+        "upturn_loglog_slope_40_80": float(np.median(
+            np.log(Ft[-1] / Ft[np.argmin(np.abs(frac - 0.4))]) / np.log(0.8 / 0.4))),
+        "w_curves": w_curves,
     }
     log(f"quasi-static: {out}")
+    cb.close()
+    return out
+
+
+def run_latency(args):
+    """Single-cell latency: the 1k-node sphere (~5.3k tets) and the
+    paper-size 20k-node sphere (~115k tets) of the parity configurations, one
+    cell per handle, tile size and launch tuned for the cell.  Per call
+    (HIP events on the launch stream around each call, mean of the calls):
+    forward and forward + backward, warm (back-to-back) and, for the 20k
+    sphere, cold (a 1 GiB buffer written between calls, so that neither L2
+    nor the MALL holds the cell's data)."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import cotangent, paper_sphere_case, small_sphere_case
+    dev = torch.device("cuda", torch.cuda.current_device())
+    flush = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    out = {}
+    for name, case in (("sphere_1k", small_sphere_case(1000)),
+                       ("sphere_20k", paper_sphere_case(2000))):
+        cb = CellBatch.tuned([0, len(case.x)], [0, len(case.tets)], case.x, case.tets,
+                             tile_candidates=[128, 256, 384, 512, 768])
+        cb.set_params(*case.theta)
+        y = cb.to_device(case.y)
+        fbar = cb.to_device(cotangent(case.n_nodes, 7))
+        ebar = torch.full((1,), 0.5, dtype=torch.float64, device=dev)
+        f, ybar = cb.empty_nodes(), cb.empty_nodes()
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+        tb = torch.empty(3, dtype=torch.float64, device=dev)
+
+        def fwd():
+            cb.forces(y, f, E, stream=s)
+
+        def fwd_bwd():
+            cb.forces(y, f, E, stream=s)
+            cb.backward(y, fbar, ebar, ybar, tb, stream=s)
+
+        def per_call(fn, reps, cold):
+            ev = [(torch.cuda.Event(enable_timing=True),
+                   torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            with torch.cuda.stream(s):
+                for _ in range(20):
+                    fn()
+                for e0, e1 in ev:
+                    if cold:
+                        flush.fill_(0.0)
+                    e0.record(s)
+                    fn()
+                    e1.record(s)
+            torch.cuda.synchronize()
+            return 1e3 * float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+        rec = {"tets": cb.n_tets, "nodes": cb.n_nodes,
+               "tile_tets": int(cb.info["tile_tets"]), "launch": list(cb.get_launch()),
+               "fwd_us_warm": per_call(fwd, 200, False),
+               "fwd_bwd_us_warm": per_call(fwd_bwd, 200, False)}
+        if name == "sphere_20k":
+            rec["fwd_us_cold"] = per_call(fwd, 20, True)
+            rec["fwd_bwd_us_cold"] = per_call(fwd_bwd, 20, True)
+        out[name] = rec
+        cb.close()
+    del flush
+    log(f"latency: {out}")
+    return out
+
+
+def run_calibration(args):
+    """Calibration at 80 % compression by the quasi-static route: oblate
+    cells (~2k nodes) with hidden (mu, kappa, w); their force-indentation
+    curves (10 plate positions, 8 % to 80 % of the height) come from the FP64
+    oracle (tests/golden/qs_targets.npy, written by make_qs_targets.py).  From
+    a start drawn like the hidden values, Levenberg-Marquardt per cell with
+    dF/d(mu, kappa, w) from the adjoint of every equilibrium (one more CG
+    solve on the device per position).  Reports the loss and the parameter
+    errors per iteration and the time per iteration."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.calibrate import fit_curves
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    from synth.configs import K_PLATE, calibration_batch, qs_fractions
+    tgt = np.load(os.path.join(ROOT, "tests", "golden", "qs_targets.npy"))
+    n = tgt.shape[1]
+    t = time.time()
+    b = calibration_batch(n, 2000, 7100)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets, tile_tets=args.qs_tile_tets)
+    theta0, theta_star = b.info["theta0"], b.info["theta_star"]
+    cb.set_params(theta0[:, 0], theta0[:, 1], theta0[:, 2])
+    top0 = np.array([b.x[b.node_off[c]:b.node_off[c + 1], 2].max() for c in range(n)])
+    bot = np.array([b.x[b.node_off[c]:b.node_off[c + 1], 2].min() for c in range(n)])
+    tops = top0[None, :] - qs_fractions()[:, None] * (top0 - bot)[None, :]
+    log(f"calibration workload: {n} cells, {b.n_tets} tets ({time.time() - t:.1f} s)")
+    qs = QuasiStaticCompression(cb, K_PLATE)
+    y0 = cb.to_device(b.y)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = fit_curves(qs, y0, tops, bot, tgt, theta0, iters=args.calib_iters,
+                     log=log)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    hist = res["history"]
+
+    def errs(th):
+        rel = np.abs(th - theta_star)
+        rel[:, :2] /= theta_star[:, :2]
+        return {"mu_rel_max": float(rel[:, 0].max()), "kappa_rel_max": float(rel[:, 1].max()),
+                "w_abs_max": float(rel[:, 2].max()),
+                "mu_rel_median": float(np.median(rel[:, 0])),
+                "kappa_rel_median": float(np.median(rel[:, 1])),
+                "w_abs_median": float(np.median(rel[:, 2]))}
+
+    out = {
+        "workload": f"{n} oblate cells, {b.n_tets} tets, 10 plate positions to 80 % of "
+                    f"the height, hidden (mu, kappa, w) per cell",
+        "targets": "FP64 oracle equilibria at the hidden parameters "
+                   "(tests/golden/qs_targets.npy)",
+        "iterations": args.calib_iters, "wall_s": wall,
+        "s_per_iteration": wall / max(args.calib_iters, 1),
+        "loss_by_iteration": [float(h["loss"].sum()) for h in hist],
+        "errors_start": errs(hist[0]["theta"]), "errors_end": errs(res["theta"]),
+        "newton": qs.stats["newton"], "cg": qs.stats["cg"],
+        "adjoint_cg": qs.stats.get("adjoint_cg", 0),
+        "all_converged": all(h["converged"] for h in hist),
+    }
+    log(f"calibration: {out}")
     cb.close()
     return out
 
@@ -601,11 +761,16 @@ def main():
                          "Hessian-vector products are bound by the latency "
                          "of single tiles once few cells are left in CG)")
     ap.add_argument("--no-qs", action="store_true")
+    ap.add_argument("--qs-steps", type=int, default=20)
+    ap.add_argument("--calib-iters", type=int, default=6)
+    ap.add_argument("--no-calibration", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB "
                          "(reference kernel for the HBM byte counters)")
     ap.add_argument("--only", choices=["relax", "qs", "template", "shape",
-                                       "regions"], default=None,
+                                       "regions", "calibration", "latency"],
+                    default=None,
                     help="run one leg alone (for profiling it) and print its "
                          "JSON line; shape and regions build the main "
                          "workload first")
@@ -626,9 +791,10 @@ def main():
     from paper_2003_03130_amd import CellBatch
     from synth.configs import cotangent, uneven_batch
 
-    if args.only in ("relax", "qs", "template"):
+    if args.only in ("relax", "qs", "template", "calibration", "latency"):
         leg = {"relax": run_relax, "qs": run_quasistatic,
-               "template": run_template}[args.only](args)
+               "template": run_template, "calibration": run_calibration,
+               "latency": run_latency}[args.only](args)
         print(json.dumps({"leg": args.only, **leg}), flush=True)
         return
 
@@ -783,6 +949,12 @@ def main():
     quasistatic = None
     if not args.no_qs:
         quasistatic = run_quasistatic(args)
+    calibration = None
+    if not args.no_calibration:
+        calibration = run_calibration(args)
+    latency = None
+    if not args.no_latency:
+        latency = run_latency(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -836,6 +1008,8 @@ def main():
         "regions": regions,
         "shape": shape,
         "quasistatic": quasistatic,
+        "calibration": calibration,
+        "latency": latency,
     }
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)

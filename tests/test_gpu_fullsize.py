@@ -6,6 +6,8 @@ by one), plus properties that hold at any size: every replay is bitwise the
 eager pass, every cell's forces balance (zero net force), no tetrahedron is
 inverted.  Tolerances as everywhere: forces, ybar, thetabar max-normalised
 1e-5, energy 1e-6 relative."""
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +17,7 @@ from synth.configs import cotangent, uneven_batch
 
 pytestmark = pytest.mark.gpu
 TOL, E_TOL = 1e-5, 1e-6
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -87,18 +90,6 @@ def test_full_workload_graph_replay_against_oracle():
     print("worst force, energy, ybar, thetabar:", worst.tolist(), flush=True)
 
 
-def _hertz(theta, top, radius=1.0):
-    """Hertz force of a sphere between two plates for parameters theta
-    (n, 3), d = R - top: F = (4/3) E / (1 - nu^2) sqrt(R/2) (d/2)^(3/2), with
-    E, nu from mu, kappa by the small-strain relations."""
-    mu, kappa = theta[:, 0], theta[:, 1]
-    E = 9 * kappa * mu / (3 * kappa + mu)
-    nu = (3 * kappa - 2 * mu) / (2 * (3 * kappa + mu))
-    d = np.clip(radius - np.asarray(top), 0, None)[:, None]
-    return (4.0 / 3.0 * (E / (1 - nu ** 2))[None, :] * np.sqrt(radius / 2)
-            * (d / 2) ** 1.5)
-
-
 @pytest.mark.timeout(900)
 def test_plate_compression_full_workload_against_oracle():
     """256 spheres of ~51k tetrahedra, 200 plate steps to 20 % compression,
@@ -132,7 +123,28 @@ def test_plate_compression_full_workload_against_oracle():
         print(f"cell {c}: plate force {ferr:.2e}, final positions {yerr:.2e}",
               flush=True)
         assert ferr <= TOL and yerr <= TOL, c
-    Ft = _hertz(b.info["theta_star"], top)
+    # calibration targets: the oracle's FP64 replay at the hidden theta*
+    # (tests/golden/make_relax_targets.py)
+    Ft = np.load(os.path.join(GOLDEN, "relax_targets.npy"))
+    assert Ft.shape == (200, 256)
+    # at theta* the device replay reproduces the targets (same scheme): a
+    # float32 state integrated over 200 steps carries the rounding of every
+    # step, so the bar on these trajectories is 1e-4 of each cell's largest
+    # force (measured up to 1.6e-5); a cell whose final state has inverted
+    # tetrahedra (the explicit scheme at low kappa / mu, reading R14) leaves
+    # the regime where the two trajectories stay close and is reported only
+    pc.set_theta(b.info["theta_star"])
+    Fs, ys, _ = pc.forward(y0)
+    ninv = torch.zeros(b.n_cells, dtype=torch.int32, device=cb.device)
+    cb.forces(ys, n_inverted=ninv)
+    inv = ninv.cpu().numpy() > 0
+    terr = np.abs(Fs.cpu().numpy() - Ft).max(axis=0) / np.abs(Ft).max(axis=0)
+    print(f"targets vs device replay at theta*: {terr[~inv].max():.2e} over "
+          f"{(~inv).sum()} cells; cells with inverted tetrahedra "
+          f"{np.flatnonzero(inv).tolist()}: {terr[inv]}", flush=True)
+    assert terr[~inv].max() <= 1e-4
+    assert inv.sum() <= b.n_cells // 64
+    pc.set_theta(theta0)
     scale = 1.0 / (200 * b.n_cells)
     loss, g, _ = pc.gradient(y0, torch.from_numpy(Ft).to(cb.device), scale)
     g = g.cpu().numpy()
