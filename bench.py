@@ -645,7 +645,8 @@ def run_calibration(args):
         "errors_start": errs(hist[0]["theta"]), "errors_end": errs(res["theta"]),
         "newton": qs.stats["newton"], "cg": qs.stats["cg"],
         "adjoint_cg": qs.stats.get("adjoint_cg", 0),
-        "all_converged": all(h["converged"] for h in hist),
+        "accepted_by_iteration": [int(h["accepted"].sum()) for h in hist[1:]],
+        "unconverged_trials": int(sum((~h["converged"]).sum() for h in hist)),
     }
     log(f"calibration: {out}")
     cb.close()
@@ -762,7 +763,7 @@ def main():
                          "of single tiles once few cells are left in CG)")
     ap.add_argument("--no-qs", action="store_true")
     ap.add_argument("--qs-steps", type=int, default=20)
-    ap.add_argument("--calib-iters", type=int, default=6)
+    ap.add_argument("--calib-iters", type=int, default=8)
     ap.add_argument("--no-calibration", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

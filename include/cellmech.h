@@ -533,6 +533,21 @@ int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
 int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plate,
                   double rel_tol, const float* ybar, float* x, float* r, float* p,
                   float* Ap, double* state, const float* minv, hipStream_t stream);
+/*
+ * cm_qs_cg_iteration: one CG iteration with its Hessian-vector product in a
+ * single call, the same as cm_forces_backward_cells(y, fbar = p, cells =
+ * state column 2) followed by cm_qs_cg_step, with bitwise the same x, r, p
+ * and state: the backward tile pass stores the owned nodes' (df/dy)^T p in
+ * ybar (device float32[3 n_nodes], caller-owned scratch) and leaves the
+ * shared nodes' partials in the handle's backward scratch, whose sums the CG
+ * kernel forms itself in the finalize's order (one launch and one pass over
+ * the shared nodes fewer per iteration).  Uses the backward scratch (do not
+ * overlap with cm_forces_backward*).  Errors: as cm_qs_cg_step, CM_ESTATE
+ * before cm_set_params, CM_EINVAL for a launch beyond the LDS.
+ */
+int cm_qs_cg_iteration(cm_batch h, const float* y, const double* plate, double k_plate,
+                       double rel_tol, float* ybar, float* x, float* r, float* p,
+                       float* Ap, double* state, const float* minv, hipStream_t stream);
 int cm_qs_update(cm_batch h, const float* x, double cap, float* y, double* state,
                  hipStream_t stream);
 int cm_qs_predict(cm_batch h, const double* plate_old, const double* plate_new,

@@ -131,6 +131,9 @@ SIGNATURES = {
     "cm_qs_cg_step": (_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_qs_update": (_int, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp]),
+    "cm_qs_cg_iteration": (_int, [_vp, _vp, _vp, ctypes.c_double,
+                                  ctypes.c_double, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp]),
     "cm_qs_predict": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "cm_layout_sizes": (_int, [_vp, _p64]),
     "cm_layout_export": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

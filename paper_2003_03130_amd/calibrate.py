@@ -9,8 +9,10 @@ parameters comes from the adjoint of the equilibrium at each position (one
 extra CG solve on the device, QuasiStaticCompression.plate_force_gradient).
 The fit is a Levenberg-Marquardt iteration per cell on relative residuals
 r_s = (F_s - F*_s) / max(|F*_s|, floor), in the coordinates (log mu,
-log kappa, w) with w kept in [0, 1]; all cells of the batch are evaluated
-together and accept or reject their own steps.  Every force and derivative
+log kappa, w) with w kept in [0, 1] and every step limited to max_step in
+each coordinate; all cells of the batch are evaluated together and accept
+or reject their own steps (a cell whose equilibria did not all converge
+rejects its step).  Every force and derivative
 comes from the device library; this module only forms the 3 x 3 normal
 equations of each cell.
 """
@@ -29,7 +31,7 @@ def _to_coords(theta):
 
 
 def fit_curves(qs, y0, tops, bottom, F_target, theta0, iters=6, lam=1e-3,
-               floor=None, log=None):
+               floor=None, max_step=0.5, log=None):
     """Levenberg-Marquardt fit of every cell's (mu, kappa, w) to its target
     curve.  qs: QuasiStaticCompression on the batch; y0: start positions
     (device SoA); tops: (S,) or (S, n_cells) plate heights; bottom: scalar or
@@ -48,7 +50,8 @@ def fit_curves(qs, y0, tops, bottom, F_target, theta0, iters=6, lam=1e-3,
 
     def evaluate(theta, jac):
         cb.set_params(theta[:, 0], theta[:, 1], theta[:, 2])
-        Ft, _, ok, _ = qs.curve(y0, tops, bottom, jacobian=jac)
+        Ft, _, _, _ = qs.curve(y0, tops, bottom, jacobian=jac)
+        ok = qs.cell_converged.all(axis=0)
         r = (Ft - F_target) / scale
         J = None
         if jac:
@@ -62,7 +65,7 @@ def fit_curves(qs, y0, tops, bottom, F_target, theta0, iters=6, lam=1e-3,
     r, J, ok = evaluate(theta, True)
     loss = (r ** 2).sum(axis=0)
     hist = [{"loss": loss.copy(), "theta": theta.copy(), "accepted": None,
-             "converged": bool(ok.all())}]
+             "converged": ok.copy()}]
     for it in range(iters):
         # per cell: (J^T J + lam diag(J^T J)) dz = -J^T r
         JtJ = np.einsum("sci,scj->cij", J, J)
@@ -70,12 +73,13 @@ def fit_curves(qs, y0, tops, bottom, F_target, theta0, iters=6, lam=1e-3,
         D = np.einsum("cii->ci", JtJ)
         A = JtJ + lam[:, None, None] * np.einsum("ci,ij->cij", D, np.eye(3))
         dz = -np.linalg.solve(A, g[:, :, None])[:, :, 0]
+        dz = np.clip(dz, -max_step, max_step)
         z_try = z + dz
         z_try[:, 2] = np.clip(z_try[:, 2], 0.0, 1.0)
         theta_try = _to_params(z_try)
         r_t, J_t, ok_t = evaluate(theta_try, True)
         loss_t = (r_t ** 2).sum(axis=0)
-        acc = (loss_t < loss) & ok_t.all()
+        acc = (loss_t < loss) & ok_t
         z = np.where(acc[:, None], z_try, z)
         r = np.where(acc[None, :], r_t, r)
         J = np.where(acc[None, :, None], J_t, J)
@@ -83,7 +87,7 @@ def fit_curves(qs, y0, tops, bottom, F_target, theta0, iters=6, lam=1e-3,
         lam = np.where(acc, lam / 10.0, lam * 10.0)
         theta = _to_params(z)
         hist.append({"loss": loss.copy(), "theta": theta.copy(),
-                     "accepted": acc.copy(), "converged": bool(ok_t.all())})
+                     "accepted": acc.copy(), "converged": ok_t.copy()})
         if log:
             log(f"iteration {it + 1}: loss {loss.sum():.3e}, accepted "
                 f"{int(acc.sum())}/{len(acc)}")

@@ -128,7 +128,7 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
     cm::TileDesc* tiles;
     cm::TetChunk* chunks;
     int32_t *slot_node, *shared_node, *ssp, *ss, *ctf, *ctc, *tmat, *mtf, *mtc, *scell;
-    int32_t *orph_off, *orph, *sfirst;
+    int32_t *orph_off, *orph, *sfirst, *cso;
     int64_t* noff;
     // cell of every shared node; slot_node with bit 31 on the first slot of
     // every shared node; shared nodes in no slot (nodes of no tetrahedron),
@@ -169,8 +169,10 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
         (rc = h->upload(&tmat, P.tile_mat, stream)) ||
         (rc = h->upload(&mtf, P.mat_tile_first, stream)) ||
         (rc = h->upload(&mtc, P.mat_tile_count, stream)) ||
-        (rc = h->upload(&noff, P.node_off, stream)))
+        (rc = h->upload(&noff, P.node_off, stream)) ||
+        (rc = h->upload(&cso, P.cell_shared_off, stream)))
       return bail(rc);
+    T.cell_shared_off = cso;
     h->d_node_off = noff;
     T.tiles = tiles;
     T.chunks = chunks;
@@ -984,6 +986,29 @@ int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plat
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_cg(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
                           k_plate, rel_tol, ybar, x, r, p, Ap, state, minv, stream));
+  return CM_OK;
+}
+
+int cm_qs_cg_iteration(cm_batch h, const float* y, const double* plate, double k_plate,
+                       double rel_tol, float* ybar, float* x, float* r, float* p,
+                       float* Ap, double* state, const float* minv, hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !plate || !ybar || !x || !r || !p || !Ap || !state)
+    return fail(CM_EINVAL, "y, plate, ybar, x, r, p, Ap and state must be device pointers");
+  if (!std::isfinite(k_plate) || k_plate < 0 || !(rel_tol >= 0))
+    return fail(CM_EINVAL, "k_plate and rel_tol must be finite and >= 0");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  if (!lds_fits(h, h->cfg.waves, true))
+    return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  // the Hessian-vector product of the cells still in CG (state column 2),
+  // tile pass only: owned nodes into ybar, shared nodes as slot partials
+  const cm::CellMask mask{state + 2, cm::kQsState};
+  CM_HIP(cm::launch_backward_main(h->Tb, full_range(h), h->cfg, y, p, nullptr, ybar,
+                                  stream, mask, cm::PlateBwd{}, false));
+  CM_HIP(cm::launch_qs_cg(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
+                          k_plate, rel_tol, ybar, x, r, p, Ap, state, minv, stream,
+                          &h->Tb));
   return CM_OK;
 }
 

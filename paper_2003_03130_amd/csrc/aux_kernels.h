@@ -65,11 +65,14 @@ hipError_t launch_qs_adjoint_rhs(const int64_t* node_off, int64_t N, int32_t n_c
                                  const float* y, const double* plate, double k,
                                  const double* weight, float* r, float* p, float* x,
                                  double* st, const float* minv, hipStream_t s);
+// With slots set, ybar holds the owned nodes only (a backward tile pass
+// without its finalize) and the shared nodes' values are summed from the
+// slot partials of those tables (bitwise the finalize's sums).
 hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
                         float* p, float* Ap, double* st, const float* minv,
-                        hipStream_t s);
+                        hipStream_t s, const DeviceTables* slots = nullptr);
 // Small-strain stiffness blocks (the Newton preconditioner), 6 n_nodes
 // floats SoA: xx yy zz xy xz yz; uses the forward scratch.
 hipError_t launch_qs_stiffness(const DeviceTables& T, const Range& r, float* kel,

@@ -30,7 +30,9 @@ struct BwdArgs {
   PlateBwd pl;  // used when PL
 };
 
-template <int W, bool PL>
+// GRAD = false: the Hessian-vector product alone (no energy cotangent, no
+// parameter gradient; tile_acc is not written).
+template <int W, bool PL, bool GRAD>
 __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
   extern __shared__ float4 lds[];
   const int lane = threadIdx.x & 63;
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     const double kappa = a.T.params[nm + mt];
     const double w = a.T.params[2 * nm + mt];
     const Material mat{w * mu, (1.0 - w) * mu, kappa};
-    const double eb = a.ebar ? a.ebar[d.cell] : 0.0;
+    const double eb = (GRAD && a.ebar) ? a.ebar[d.cell] : 0.0;
     // plate step: per-cell values read here, long before the epilogue
     float top = 0.f, bot = 0.f, gw = 0.f;
     if constexpr (PL) {
@@ -94,14 +96,16 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
         const float4 v3 = make_float4(p3.w, w3.x, w3.y, 0.f);
         float h[3][3];
         double gp[3], ge[3];
-        tet_backward(p0, p1, p2, p3, v0, v1, v2, v3, cur.B, cur.V0, mat, eb, h,
-                     gp, ge);
+        tet_backward<GRAD>(p0, p1, p2, p3, v0, v1, v2, v3, cur.B, cur.V0, mat, eb,
+                           h, gp, ge);
         lds_accumulate([&](int i) { return &gs[i].x; }, i0, i1, i2, i3, h);
-        const double vol = (double)cur.V0;
+        if constexpr (GRAD) {
+          const double vol = (double)cur.V0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc[c] = fma(vol, gp[c], acc[c]);
-          acce[c] = fma(vol, ge[c], acce[c]);
+          for (int c = 0; c < 3; ++c) {
+            acc[c] = fma(vol, gp[c], acc[c]);
+            acce[c] = fma(vol, ge[c], acce[c]);
+          }
         }
       }
     });
@@ -127,12 +131,14 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
       float* pp = a.T.part + 3 * s;
       pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
     }
+    if constexpr (GRAD) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = wave_sum(fma(0.5 * eb, acce[c], -acc[c]));
-    if (lane == 0) {
-      a.T.tile_acc[3 * (int64_t)t] = acc[0];
-      a.T.tile_acc[3 * (int64_t)t + 1] = acc[1];
-      a.T.tile_acc[3 * (int64_t)t + 2] = acc[2];
+      for (int c = 0; c < 3; ++c) acc[c] = wave_sum(fma(0.5 * eb, acce[c], -acc[c]));
+      if (lane == 0) {
+        a.T.tile_acc[3 * (int64_t)t] = acc[0];
+        a.T.tile_acc[3 * (int64_t)t + 1] = acc[1];
+        a.T.tile_acc[3 * (int64_t)t + 2] = acc[2];
+      }
     }
     wave_sync();
   }
@@ -229,13 +235,20 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
   }
 }
 
-template <int W>
-hipError_t bwd_w(const BwdArgs& a, int grid, size_t lds, hipStream_t st) {
+template <int W, bool GRAD>
+hipError_t bwd_wg(const BwdArgs& a, int grid, size_t lds, hipStream_t st) {
   if (a.pl.plate)
-    hipLaunchKernelGGL((backward_kernel<W, true>), dim3(grid), dim3(64 * W), lds, st, a);
+    hipLaunchKernelGGL((backward_kernel<W, true, GRAD>), dim3(grid), dim3(64 * W), lds, st,
+                       a);
   else
-    hipLaunchKernelGGL((backward_kernel<W, false>), dim3(grid), dim3(64 * W), lds, st, a);
+    hipLaunchKernelGGL((backward_kernel<W, false, GRAD>), dim3(grid), dim3(64 * W), lds,
+                       st, a);
   return hipGetLastError();
+}
+
+template <int W>
+hipError_t bwd_w(const BwdArgs& a, int grid, size_t lds, hipStream_t st, bool grad) {
+  return grad ? bwd_wg<W, true>(a, grid, lds, st) : bwd_wg<W, false>(a, grid, lds, st);
 }
 
 }  // namespace
@@ -246,7 +259,7 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
                                 float* ybar, hipStream_t st, const CellMask& mask,
-                                const PlateBwd& pl) {
+                                const PlateBwd& pl, bool grad) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
   // the per-wave LDS stride (10 nloc / 4 float4) needs nloc % 4 == 0, else
   // a wave's last float2 would overlap the next wave's records
@@ -255,10 +268,10 @@ hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
   const int grid = grid_for(r, cfg);
   const size_t lds = backward_lds_per_wave(T.nloc) * cfg.waves;
   switch (cfg.waves) {
-    case 1: return bwd_w<1>(a, grid, lds, st);
-    case 2: return bwd_w<2>(a, grid, lds, st);
-    case 4: return bwd_w<4>(a, grid, lds, st);
-    case 8: return bwd_w<8>(a, grid, lds, st);
+    case 1: return bwd_w<1>(a, grid, lds, st, grad);
+    case 2: return bwd_w<2>(a, grid, lds, st, grad);
+    case 4: return bwd_w<4>(a, grid, lds, st, grad);
+    case 8: return bwd_w<8>(a, grid, lds, st, grad);
     default: return hipErrorInvalidValue;
   }
 }
@@ -285,7 +298,11 @@ hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            const float* fbar, const double* ebar, float* ybar,
                            double* thetabar, hipStream_t st, const CellMask& mask,
                            const PlateBwd& pl) {
-  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st, mask, pl);
+  // the parameter gradient and the energy cotangent need the full adjoint;
+  // without them the pass is the Hessian-vector product alone
+  const bool grad = ebar != nullptr || (pl.plate ? pl.thetabar_acc != nullptr
+                                                 : thetabar != nullptr);
+  hipError_t e = launch_backward_main(T, r, cfg, y, fbar, ebar, ybar, st, mask, pl, grad);
   if (e != hipSuccess) return e;
   return launch_backward_finalize(T, r, ybar, thetabar, st, mask, y, fbar, pl);
 }

@@ -17,6 +17,7 @@ struct DeviceTables {
   const int32_t* shared_slot_ptr = nullptr;
   const int32_t* shared_slots = nullptr;
   const int32_t* shared_cell = nullptr;  // cell of every shared node
+  const int32_t* cell_shared_off = nullptr;  // shared nodes of cell c: [off[c], off[c + 1])
   // slot_node with bit 31 set on the first slot of every shared node (the
   // one slot whose tile adds the node's top-plate force to its sum)
   const int32_t* slot_node_first = nullptr;
@@ -109,12 +110,14 @@ hipError_t launch_forward_finalize(const DeviceTables& T, const Range& r,
                                    hipStream_t st, const float* y = nullptr,
                                    const PlateFwd& pl = PlateFwd{},
                                    int32_t* nonfin = nullptr);
+// grad = false: the Hessian-vector product alone (ebar ignored, the per-tile
+// parameter-gradient sums not written; the finalize must not form thetabar).
 hipError_t launch_backward_main(const DeviceTables& T, const Range& r,
                                 const LaunchCfg& cfg, const float* y,
                                 const float* fbar, const double* ebar,
                                 float* ybar, hipStream_t st,
                                 const CellMask& mask = CellMask{},
-                                const PlateBwd& pl = PlateBwd{});
+                                const PlateBwd& pl = PlateBwd{}, bool grad = true);
 // With pl.plate set, the backward pass (fbar = lam_next, no ebar) applies
 // the reverse plate step: it writes pl.lam instead of ybar and adds m
 // thetabar to pl.thetabar_acc; the finalize kernel needs y and lam_next.

@@ -19,8 +19,9 @@
 // exact product of the float32 inputs up to one float64 rounding; a float32
 // edge or product would amplify rounding by the condition number of the
 // reference tetrahedron).  The invariants, the powers of J, the energy
-// density and the coefficients c1..c3 are float64; the remaining 3x3 tensor
-// algebra (F C, cof F, P B^T) is float32.  J^-1/3 is the reciprocal of the
+// density and, in the forward pass, the coefficients c1..c3 are float64; the
+// remaining 3x3 tensor algebra (F C, cof F, P B^T) is float32 (the backward
+// pass forms its coefficient chain in float32 too, see tet_backward).  J^-1/3 is the reciprocal of the
 // real (sign-preserving) cube root: a float32 hardware log2/exp2 seed
 // refined by one Newton step in float64.
 #pragma once
@@ -197,6 +198,14 @@ __device__ __forceinline__ void cofactor_dir(const float F[3][3],
 //   P is linear in (mu1, mu2, kappa), P = mu1 P_I + mu2 P_K + kappa P_J, so
 //   gp = (<P_I, dF>, <P_K, dF>, (J - 1) <cof F, dF>) and
 //   ge = (I - 3, K - 3, (J - 1)^2) (twice the energy parts).
+// F and the invariants are float64 as in the forward pass; the stress
+// coefficients, their derivatives along dF and gp are float32, formed from
+// float32 copies of the float64 invariants (J - 1 included): that chain has
+// no cancellation beyond the one P itself carries, and float32 there keeps
+// float64 off most of the pass.  ge stays float64 (I - 3 and K - 3 cancel).
+// GRAD = false: the Hessian-vector product alone (no energy cotangent, no
+// parameter gradient): ebar is taken as 0 and gp, ge are not formed.
+template <bool GRAD>
 __device__ __forceinline__ void tet_backward(
     const float4& p0, const float4& p1, const float4& p2, const float4& p3,
     const float4& v0, const float4& v1, const float4& v2, const float4& v3,
@@ -231,27 +240,30 @@ __device__ __forceinline__ void tet_backward(
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) fK = fmaf(K[i][j], dF[i][j], fK);
+  // float32 copies of the float64 scalars
+  const double Jm1d = s.J - 1.0;
+  const float TC = (float)s.TC, I2 = (float)s.I2, r2 = (float)s.r2, r4 = (float)s.r4;
+  const float r3 = (float)(s.r2 * s.r);  // 1/J
+  const float Jm1 = (float)Jm1d;
   // directional derivatives of tr C, tr C^2, J and I2 = (trC^2 - trC2)/2;
   // with t = dJ / J: d J^-2/3 = -(2/3) J^-2/3 t, d J^-4/3 = -(4/3) J^-4/3 t
-  const double fFd = (double)fF, fFCd = (double)fFC;
-  const double dTC = 2.0 * fFd;
-  const double dJ = (double)fK;
-  const double dI2 = 2.0 * (s.TC * fFd - fFCd);
-  const double r3 = s.r2 * s.r;          // 1/J
-  const double tq = r3 * dJ;
-  const double a = m.mu1 * s.r2, b = m.mu2 * s.r4;
-  const double da = (-2.0 / 3.0) * a * tq, db = (-4.0 / 3.0) * b * tq;
-  const double c1 = a + b * s.TC, dc1 = da + db * s.TC + b * dTC;
-  const double c2 = -b, dc2 = -db;
-  const double q = -(a * s.TC + 2.0 * b * s.I2) * (1.0 / 3.0);
-  const double dq = -(da * s.TC + a * dTC + 2.0 * (db * s.I2 + b * dI2)) * (1.0 / 3.0);
-  const double Jm1 = s.J - 1.0;
-  const double c3 = q * r3 + m.kappa * Jm1;
-  const double dc3 = r3 * (dq - q * tq) + m.kappa * dJ;
-  const double nv = -(double)V0;
-  const float s1 = (float)(nv * (dc1 - ebar * c1)), t1 = (float)(nv * c1);
-  const float s2 = (float)(nv * (dc2 - ebar * c2)), t2 = (float)(nv * c2);
-  const float s3 = (float)(nv * (dc3 - ebar * c3)), t3 = (float)(nv * c3);
+  const float dTC = 2.f * fF;
+  const float dJ = fK;
+  const float dI2 = 2.f * (TC * fF - fFC);
+  const float tq = r3 * dJ;
+  const float a = (float)m.mu1 * r2, b = (float)m.mu2 * r4, ka = (float)m.kappa;
+  const float da = (-2.f / 3.f) * a * tq, db = (-4.f / 3.f) * b * tq;
+  const float c1 = a + b * TC, dc1 = da + db * TC + b * dTC;
+  const float c2 = -b, dc2 = -db;
+  const float q = -(a * TC + 2.f * b * I2) * (1.f / 3.f);
+  const float dq = -(da * TC + a * dTC + 2.f * (db * I2 + b * dI2)) * (1.f / 3.f);
+  const float c3 = q * r3 + ka * Jm1;
+  const float dc3 = r3 * (dq - q * tq) + ka * dJ;
+  const float nv = -V0;
+  const float eb = GRAD ? (float)ebar : 0.f;
+  const float s1 = nv * (dc1 - eb * c1), t1 = nv * c1;
+  const float s2 = nv * (dc2 - eb * c2), t2 = nv * c2;
+  const float s3 = nv * (dc3 - eb * c3), t3 = nv * c3;
 
   // -V0 (dP - ebar P) with P = c1 F + c2 F C + c3 cof F:
   //   s1 F + t1 dF + s2 F C + t2 (dF C + F dC) + s3 cof F + t3 d(cof F)
@@ -284,12 +296,14 @@ __device__ __forceinline__ void tet_backward(
   // parameter gradient: per unit V0, the directional derivatives p of the
   // energy parts along dF and the energy parts e themselves, so that
   // g = V0 (-p + ebar e / 2) is formed once per tile
-  gp[0] = s.r2 * (fFd - s.TC * tq * (1.0 / 3.0));
-  gp[1] = s.r4 * (s.TC * fFd - fFCd - (2.0 / 3.0) * s.I2 * tq);
-  gp[2] = Jm1 * dJ;
-  ge[0] = s.TC * s.r2 - 3.0;
-  ge[1] = s.I2 * s.r4 - 3.0;
-  ge[2] = Jm1 * Jm1;
+  if constexpr (GRAD) {
+    gp[0] = r2 * (fF - TC * tq * (1.f / 3.f));
+    gp[1] = r4 * (TC * fF - fFC - (2.f / 3.f) * I2 * tq);
+    gp[2] = Jm1 * dJ;
+    ge[0] = s.TC * s.r2 - 3.0;
+    ge[1] = s.I2 * s.r4 - 3.0;
+    ge[2] = Jm1d * Jm1d;
+  }
 }
 
 }  // namespace cm

@@ -313,7 +313,54 @@ struct CgArgs {
   float *x, *r, *p, *Ap;
   double* st;
   const float* minv;  // preconditioner blocks (6 n_nodes), nullable
+  // With part set, ybar holds the owned nodes only (a backward tile pass
+  // without its finalize) and the shared nodes' values are the sums of
+  // their slot partials, formed here in the finalize's order.
+  const float* part;
+  const int32_t* shared_slot_ptr;
+  const int32_t* shared_slots;
+  const int32_t* shared_node;
+  const int32_t* cell_shared_off;
 };
+
+// The shared nodes of a cell are the contiguous ids [sh0, sh0 + ns) (owned
+// nodes first, see layout.h); s0 is the cell's first shared-node entry.
+struct ShrRange {
+  int64_t sh0, sh1;
+  int s0;
+};
+
+__device__ __forceinline__ ShrRange shared_range(const CgArgs& a, int c, int64_t n1) {
+  ShrRange r{n1, n1, 0};
+  if (a.part) {
+    r.s0 = a.cell_shared_off[c];
+    const int ns = a.cell_shared_off[c + 1] - r.s0;
+    if (ns > 0) {
+      r.sh0 = a.shared_node[r.s0];
+      r.sh1 = r.sh0 + ns;
+    }
+  }
+  return r;
+}
+
+// ybar of node i: stored, or for a shared node the sum of its slot partials
+// in slot order (the order of backward_finalize_kernel: bitwise its result).
+__device__ __forceinline__ void ybar_of(const CgArgs& a, const ShrRange& sr, int64_t i,
+                                        float& bx, float& by, float& bz) {
+  if (i >= sr.sh0 && i < sr.sh1) {
+    const int s = sr.s0 + (int)(i - sr.sh0);
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int q = a.shared_slot_ptr[s]; q < a.shared_slot_ptr[s + 1]; ++q) {
+      const float* pp = a.part + 3 * (int64_t)a.shared_slots[q];
+      sx += pp[0];
+      sy += pp[1];
+      sz += pp[2];
+    }
+    bx = sx; by = sy; bz = sz;
+  } else {
+    bx = a.ybar[i]; by = a.ybar[a.N + i]; bz = a.ybar[2 * a.N + i];
+  }
+}
 
 // Nodes per thread up to which a cell's CG iteration keeps every operand in
 // registers (cells of at most kRegNodes * kThreads nodes).
@@ -335,7 +382,7 @@ __device__ __forceinline__ void cg_finish(const CgArgs& a, double* s, double rn,
 // streaming version (which fused multiply-adds the compiler forms may
 // differ between the two, a last-bit difference).
 __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
-                             double top, double bot, double* red) {
+                             double top, double bot, double* red, const ShrRange& sr) {
   const int64_t N = a.N;
   float p[kRegNodes][3], r[kRegNodes][3], ap[kRegNodes][3], x[kRegNodes][3];
   float m[kRegNodes][6];
@@ -356,9 +403,11 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
       }
       const double z = a.y[2 * N + i];
       const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
-      ap[u][0] = -a.ybar[i];
-      ap[u][1] = -a.ybar[N + i];
-      ap[u][2] = (float)(-(double)a.ybar[2 * N + i] + h * (double)p[u][2]);
+      float bx, by, bz;
+      ybar_of(a, sr, i, bx, by, bz);
+      ap[u][0] = -bx;
+      ap[u][1] = -by;
+      ap[u][2] = (float)(-(double)bz + h * (double)p[u][2]);
       pap += (double)p[u][0] * ap[u][0] + (double)p[u][1] * ap[u][1] +
              (double)p[u][2] * ap[u][2];
     }
@@ -420,8 +469,9 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   if (s[2] == 0.0) return;  // uniform over the workgroup
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
+  const ShrRange sr = shared_range(a, c, n1);
   if (n1 - n0 <= (int64_t)kRegNodes * kThreads) {
-    cg_step_regs(a, s, n0, n1, top, bot, red);
+    cg_step_regs(a, s, n0, n1, top, bot, red, sr);
     return;
   }
   double pap = 0.0;
@@ -429,8 +479,10 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     const double z = a.y[2 * N + i];
     const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
-    const float ax = -a.ybar[i], ay = -a.ybar[N + i];
-    const float az = (float)(-(double)a.ybar[2 * N + i] + h * (double)a.p[2 * N + i]);
+    float bx, by, bz;
+    ybar_of(a, sr, i, bx, by, bz);
+    const float ax = -bx, ay = -by;
+    const float az = (float)(-(double)bz + h * (double)a.p[2 * N + i]);
     a.Ap[i] = ax; a.Ap[N + i] = ay; a.Ap[2 * N + i] = az;
     pap += (double)a.p[i] * ax + (double)a.p[N + i] * ay + (double)a.p[2 * N + i] * az;
   }
@@ -774,8 +826,13 @@ hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
                         float* p, float* Ap, double* st, const float* minv,
-                        hipStream_t s) {
-  CgArgs a{node_off, N, y, plate, k, rel_tol, ybar, x, r, p, Ap, st, minv};
+                        hipStream_t s, const DeviceTables* slots) {
+  CgArgs a{node_off, N, y, plate, k, rel_tol, ybar, x, r, p, Ap, st, minv,
+           slots ? slots->part : nullptr,
+           slots ? slots->shared_slot_ptr : nullptr,
+           slots ? slots->shared_slots : nullptr,
+           slots ? slots->shared_node : nullptr,
+           slots ? slots->cell_shared_off : nullptr};
   hipLaunchKernelGGL(qs_cg_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

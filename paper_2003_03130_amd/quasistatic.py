@@ -24,13 +24,16 @@ class QuasiStaticCompression:
     when a Newton step moves no node by more than step_tol; cg_tol: smallest
     relative CG residual; eta_max: largest forcing term of the inexact Newton
     steps (0: every CG solve to cg_tol); precondition: block-Jacobi CG;
+    fused_cg: each CG iteration as one library call with its Hessian-vector
+    product (cm_qs_cg_iteration) instead of two;
     cap: largest node move per Newton step; armijo: sufficient decrease of
     the line search, which gives up below min_move."""
 
     def __init__(self, batch, k_plate, rel_tol=1e-3, abs_tol=1e-9,
                  step_tol=1e-6, floor_factor=2.0, cg_tol=1e-3, max_newton=40,
                  max_cg=400, cap=0.05, armijo=1e-4, min_move=1e-7,
-                 max_backtrack=12, eta_max=0.5, precondition=True):
+                 max_backtrack=12, eta_max=0.5, precondition=True,
+                 fused_cg=True):
         import torch
         self.cb = batch
         self.k = float(k_plate)
@@ -42,6 +45,9 @@ class QuasiStaticCompression:
         self.cg_tol, self.cap = float(cg_tol), float(cap)
         self.eta_max = float(eta_max)
         self.precondition = bool(precondition)
+        # one call per CG iteration (cm_qs_cg_iteration) or the two-call
+        # route (cm_forces_backward_cells + cm_qs_cg_step); bitwise equal
+        self.fused_cg = bool(fused_cg)
         if self.precondition:
             self._kel = torch.empty(6 * batch.n_nodes, dtype=torch.float32,
                                     device=batch.device)
@@ -86,6 +92,40 @@ class QuasiStaticCompression:
     def _active(self, col):
         return bool((self.state[:, col] > 0).any())
 
+    def _cg_loop(self, y, plate, tol, max_iter, counter):
+        """CG iterations for every cell still active (state column 2) until
+        none is (checked every 8 iterations) or max_iter."""
+        cb = self.cb
+        lib, st = nat.lib(), _stream(None)
+        if self.fused_cg:
+            args = (cb._h, _ptr(y), _ptr(plate), self.k, float(tol),
+                    _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
+                    _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
+                    _ptr(self._minv), st)
+            step = lib.cm_qs_cg_iteration
+            for j in range(max_iter):
+                nat.check(step(*args))
+                self.stats[counter] = self.stats.get(counter, 0) + 1
+                if j % 8 == 7 and not self._active(2):
+                    break
+            return
+        # the CG loop's two calls with their arguments fixed once: Hessian-
+        # vector products only for the cells still in CG (state column 2 as
+        # the cell flags; no parameter gradient), then one CG iteration
+        flags = self.state[:, 2]
+        hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
+                    flags.stride(0), _ptr(self._ybar), None, st)
+        cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, float(tol),
+                   _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
+                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
+                   _ptr(self._minv), st)
+        for j in range(max_iter):
+            nat.check(lib.cm_forces_backward_cells(*hvp_args))
+            nat.check(lib.cm_qs_cg_step(*cg_args))
+            self.stats[counter] = self.stats.get(counter, 0) + 1
+            if j % 8 == 7 and not self._active(2):
+                break
+
     def equilibrate(self, y, plate):
         """Newton iterations at one plate position (plate: float64 device
         tensor (n_cells, 2) = top, bottom); y (device SoA) is updated in
@@ -101,28 +141,12 @@ class QuasiStaticCompression:
         nat.check(nat.lib().cm_qs_floor(
             cb._h, _ptr(y), _ptr(plate), self.k, _ptr(self._Ap),
             _ptr(self._ybar), _ptr(self.state), _stream(None)))
-        # the CG loop's two calls with their arguments fixed once: Hessian-
-        # vector products only for the cells still in CG (state column 2 as
-        # the cell flags; no parameter gradient), then one CG iteration
-        lib, st = nat.lib(), _stream(None)
-        flags = self.state[:, 2]
-        hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
-                    flags.stride(0), _ptr(self._ybar), None, st)
-        cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, self.cg_tol,
-                   _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
-                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
-                   _ptr(self._minv), st)
         for it in range(self.max_newton):
             self._residual(y, plate, restart=(it == 0))
             if not self._active(11):
                 return True
             self.stats["newton"] += 1
-            for j in range(self.max_cg):
-                nat.check(lib.cm_forces_backward_cells(*hvp_args))
-                nat.check(lib.cm_qs_cg_step(*cg_args))
-                self.stats["cg"] += 1
-                if j % 8 == 7 and not self._active(2):
-                    break
+            self._cg_loop(y, plate, self.cg_tol, self.max_cg, "cg")
             self._line_search(y, plate)
         self._residual(y, plate)
         return not self._active(11)
@@ -158,19 +182,7 @@ class QuasiStaticCompression:
             cb._h, _ptr(y), _ptr(plate), self.k, _ptr(weight), _ptr(self._r),
             _ptr(self._p), _ptr(self._x), _ptr(self.state), _ptr(self._minv),
             st))
-        flags = self.state[:, 2]
-        hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
-                    flags.stride(0), _ptr(self._ybar), None, st)
-        cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, float(tol),
-                   _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
-                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
-                   _ptr(self._minv), st)
-        for j in range(4 * self.max_cg):
-            nat.check(lib.cm_forces_backward_cells(*hvp_args))
-            nat.check(lib.cm_qs_cg_step(*cg_args))
-            self.stats["adjoint_cg"] = self.stats.get("adjoint_cg", 0) + 1
-            if j % 8 == 7 and not self._active(2):
-                break
+        self._cg_loop(y, plate, tol, 4 * self.max_cg, "adjoint_cg")
         tb = torch.empty(3 * cb.n_mat, dtype=torch.float64, device=cb.device)
         cb.backward(y, self._x, None, self._ybar, tb)
         return tb.view(-1, 3)
@@ -181,7 +193,8 @@ class QuasiStaticCompression:
         each position from the previous equilibrium (affine predictor).
         Returns (forces (S, n_cells) top, (S, n_cells) bottom, converged (S,),
         final positions); self.residuals (S, n_cells) holds the final
-        projected Newton residual norms |f + p|_2.  With jacobian=True,
+        projected Newton residual norms |f + p|_2 and self.cell_converged
+        (S, n_cells) which cells met the tolerance.  With jacobian=True,
         self.jacobian (S, n_mat, 3) holds dF_top/d(mu, kappa, w) at every
         plate position (plate_force_gradient after each equilibrium)."""
         import torch
@@ -193,13 +206,14 @@ class QuasiStaticCompression:
         y = y0.clone()
         plates = torch.from_numpy(np.stack([tops, np.broadcast_to(
             bot, tops.shape)], axis=2).copy()).to(cb.device)
-        Ft, Fb, ok, res, jac = [], [], [], [], []
+        Ft, Fb, ok, res, jac, cok = [], [], [], [], [], []
         for s in range(len(tops)):
             if s > 0:
                 nat.check(nat.lib().cm_qs_predict(
                     cb._h, _ptr(plates[s - 1]), _ptr(plates[s]), _ptr(y),
                     _stream(None)))
             ok.append(self.equilibrate(y, plates[s]))
+            cok.append((self.state[:, 11] == 0).cpu().numpy())
             if jacobian:
                 jac.append(self.plate_force_gradient(
                     y, plates[s], tol=adjoint_tol).cpu().numpy())
@@ -207,5 +221,6 @@ class QuasiStaticCompression:
             Fb.append(self.force[:, 1].cpu().numpy().copy())
             res.append(self.state[:, 3].sqrt().cpu().numpy())
         self.residuals = np.array(res)
+        self.cell_converged = np.array(cok)
         self.jacobian = np.array(jac) if jacobian else None
         return np.array(Ft), np.array(Fb), np.array(ok), y

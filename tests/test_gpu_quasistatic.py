@@ -453,3 +453,36 @@ def test_cg_step_against_its_formula(precondition):
         assert abs(sg[c, 0] - rzn) <= 1e-5 * abs(rzn), c
         stop = (rn ** 2).sum() <= max(rel_tol, 0.1) ** 2 * state[c, 1]
         assert sg[c, 2] == (0.0 if stop else 1.0), c
+
+
+def test_cg_iteration_in_one_call_equals_two_calls():
+    """cm_qs_cg_iteration (the tile pass without its finalize, the shared
+    nodes summed inside the CG kernel) gives bitwise the iterates of
+    cm_forces_backward_cells + cm_qs_cg_step: same plate forces, same
+    Newton and CG counts, same final positions; on cells held in registers
+    and on one of more than 4,096 nodes (streamed)."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b0 = _cells()
+    x, tets = sphere_mesh(6000, 77)
+    x = ellipsoid(x, np.array((1.15, 1.1, 0.8)))
+    cells = [b0.cell(c) for c in range(b0.n_cells)]
+    cells.append(Cell(x, tets, x.astype(np.float32), (1.2, 15.0, 0.4)))
+    b = batch_from_cells(cells)
+    assert b.node_off[-1] - b.node_off[-2] > 4096
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    tops, bot, _ = _plates(b, [0.05, 0.3])
+    out = {}
+    for fused in (False, True):
+        qs = QuasiStaticCompression(cb, K, fused_cg=fused)
+        Ft, Fb, ok, y = qs.curve(cb.to_device(b.y), tops, bot, jacobian=True)
+        torch.cuda.synchronize()
+        assert ok.all()
+        out[fused] = (Ft, Fb, y.cpu().numpy(), qs.jacobian, dict(qs.stats))
+        print(f"fused {fused}: {qs.stats}")
+    a, c = out[False], out[True]
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    assert np.array_equal(a[2], c[2]) and np.array_equal(a[3], c[3])
+    assert a[4] == c[4]
