@@ -146,14 +146,21 @@ def test_plate_compression_full_workload_against_oracle():
     assert inv.sum() <= b.n_cells // 64
     pc.set_theta(theta0)
     scale = 1.0 / (200 * b.n_cells)
-    loss, g, _ = pc.gradient(y0, torch.from_numpy(Ft).to(cb.device), scale)
-    g = g.cpu().numpy()
-    assert np.isfinite(g).all() and np.isfinite(loss)
     c = 128
     cell = b.cell(c)
     m = oracle.OracleMesh(cell.x, cell.tets)
-    _, gc, _ = m.relax_grad(cell.y.astype(np.float64), tuple(theta0[c]), top,
-                            bot, K_PLATE, mob, Ft[:, c], scale)
-    err = np.abs(g[c] - gc).max() / np.abs(gc).max()
-    print(f"cell {c}: gradient {g[c]} oracle {gc} err {err:.2e}", flush=True)
-    assert err <= TOL
+    # the BPTT gradient against the oracle's forward-mode duals: with zero
+    # targets (L = scale sum F^2, every term of one sign) at the per-evaluation
+    # bar, and with the oracle targets, where the residual F - F* changes sign
+    # along the curve and the sum cancels, at the 200-step trajectory bar
+    for name, tgt, bar in (("zero targets", np.zeros_like(Ft), TOL),
+                           ("oracle targets", Ft, 1e-4)):
+        loss, g, _ = pc.gradient(y0, torch.from_numpy(tgt).to(cb.device), scale)
+        g = g.cpu().numpy()
+        assert np.isfinite(g).all() and np.isfinite(loss)
+        _, gc, _ = m.relax_grad(cell.y.astype(np.float64), tuple(theta0[c]), top,
+                                bot, K_PLATE, mob, tgt[:, c], scale)
+        err = np.abs(g[c] - gc).max() / np.abs(gc).max()
+        print(f"cell {c}, {name}: gradient {g[c]} oracle {gc} err {err:.2e}",
+              flush=True)
+        assert err <= bar, name
