@@ -554,6 +554,15 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
       }
     }
     d.n_shr = nsh;
+    // The tile's shared nodes in the order of their internal ids (first
+    // appearance over the tiles), local indices following: the slots of
+    // consecutive shared nodes then form runs inside every tile, so the
+    // finalize reads the partials of neighbouring nodes from the same cache
+    // lines.  The chunk assignment below only compares node identities, so
+    // it and every sum stay the same.
+    std::sort(out.slot_node.begin() + d.shr_begin, out.slot_node.end());
+    for (int32_t j = 0; j < nsh; ++j)
+      loc[out.new_to_old[out.slot_node[d.shr_begin + j]]] = n_own[k] + j;
     const int32_t nloc = d.n_own + d.n_shr;
     out.max_tile_nodes = std::max(out.max_tile_nodes, nloc);
 
