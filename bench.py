@@ -49,14 +49,16 @@ BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
 STORED_TET_BYTES = 48
 F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
 TILE_KERNEL_SOURCES = ("kernels.hip", "backward.hip", "device_util.h",
-                       "kernels.h", "layout.h", "mr_tet.h")
+                       "kernels.h", "layout.h", "mr_tet.h", "prep.cpp")
 
 
 def kernel_source_hash():
     """sha256 of the sources of the forward and backward kernels (their .hip
-    files and the headers they include); a stored counter record applies
-    only to the kernels it was measured on.  Host code and the auxiliary
-    kernels (plates, quasi-static, shape) are not part of it."""
+    files and the headers they include) and of the host code that lays out
+    their data (prep.cpp: tiles, slots, chunks); a stored counter record
+    applies only to the kernels and layout it was measured on.  The other
+    host code and the auxiliary kernels (plates, quasi-static, shape) are
+    not part of it."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2003_03130_amd", "csrc")

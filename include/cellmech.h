@@ -451,8 +451,13 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
  *     eta_prev^2 when that exceeds 0.1, at least half of tolerance / |r_N|,
  *     at most eta_max (eta_max at a new plate position); eta_max = 0 sets
  *     eta = 0.
- *   cm_qs_ls_start: s = min(1, cap / max_i |x_i|), slope r_N . x; y_trial =
- *     y + s x for cells not in equilibrium whose step descends, y otherwise.
+ *   cm_qs_ls_start: for cells not in equilibrium, x is first projected in
+ *     place onto the complement of the symmetry modes (its mean x and y
+ *     components and its rotation about z through the centroid of y are
+ *     removed: Hess(Pi) annihilates them, so the CG leaves whatever its
+ *     preconditioned directions put there); then s = min(1, cap /
+ *     max_i |x_i|), slope r_N . x; y_trial = y + s x for cells not in
+ *     equilibrium whose step descends, y otherwise.
  *   cm_qs_ls_accept (energy_trial = E(y_trial) from cm_forces): a pending
  *     cell accepts y_trial (copied into y) if Pi(y_trial) <= Pi(y) - armijo
  *     s (r_N . x), else halves s and forms the next trial; it gives up (no
@@ -519,7 +524,7 @@ int cm_qs_stiffness(cm_batch h, float* k_el, hipStream_t stream);
 int cm_qs_adjoint_rhs(cm_batch h, const float* y, const double* plate, double k_plate,
                       const double* weight, float* r, float* p, float* x, double* state,
                       const float* minv, hipStream_t stream);
-int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
+int cm_qs_ls_start(cm_batch h, float* x, const float* r_newton, double cap,
                    const float* y, float* y_trial, double* state,
                    hipStream_t stream);
 int cm_qs_ls_accept(cm_batch h, const float* x, const double* plate, double k_plate,

@@ -121,7 +121,7 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
   cm::DeviceTables& T = h->T;
   // host tables built here are copied asynchronously: they live until the
   // stream synchronisation below
-  std::vector<int32_t> shared_cell, orphan_off, orphan, slot_first;
+  std::vector<int32_t> shared_cell, orphan_off, orphan, slot_first, shared_first;
   std::vector<int4> pc;
   std::vector<int2> nbk;
   {
@@ -173,6 +173,15 @@ static int create_from(cm::Prepared& P, const cm::PrepOptions& po,
         (rc = h->upload(&cso, P.cell_shared_off, stream)))
       return bail(rc);
     T.cell_shared_off = cso;
+    // first shared node of every cell (its shared nodes are contiguous)
+    shared_first.resize(h->n_cells);
+    for (int32_t c = 0; c < h->n_cells; ++c)
+      shared_first[c] = P.cell_shared_off[c + 1] > P.cell_shared_off[c]
+                            ? P.shared_node[P.cell_shared_off[c]]
+                            : (int32_t)P.node_off[c + 1];
+    int32_t* csf;
+    if ((rc = h->upload(&csf, shared_first, stream))) return bail(rc);
+    T.cell_shared_first = csf;
     h->d_node_off = noff;
     T.tiles = tiles;
     T.chunks = chunks;
@@ -893,7 +902,7 @@ int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* ene
   return CM_OK;
 }
 
-int cm_qs_ls_start(cm_batch h, const float* x, const float* r_newton, double cap,
+int cm_qs_ls_start(cm_batch h, float* x, const float* r_newton, double cap,
                    const float* y, float* y_trial, double* state,
                    hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;

@@ -47,7 +47,7 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               float* x, float* rn, double* st, double* force,
                               const float* kel, float* minv, hipStream_t s);
 hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
-                              const float* x, const float* rn, double cap,
+                              float* x, const float* rn, double cap,
                               const float* y, float* yt, double* st, hipStream_t s);
 hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cells,
                                const float* x, const double* plate, double k,

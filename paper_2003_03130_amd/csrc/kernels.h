@@ -18,6 +18,7 @@ struct DeviceTables {
   const int32_t* shared_slots = nullptr;
   const int32_t* shared_cell = nullptr;  // cell of every shared node
   const int32_t* cell_shared_off = nullptr;  // shared nodes of cell c: [off[c], off[c + 1])
+  const int32_t* cell_shared_first = nullptr;  // node id of shared_node[off[c]]
   // slot_node with bit 31 set on the first slot of every shared node (the
   // one slot whose tile adds the node's top-plate force to its sum)
   const int32_t* slot_node_first = nullptr;

@@ -42,6 +42,35 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
+// K workgroup sums at once, each in the order of block_sum (bitwise its
+// result): the wavefront totals of sum k are added up by thread k alone, so
+// no thread holds all K NT / 64 totals at once.  red: at least K (NT / 64 +
+// 1) doubles.
+template <int K, int NT = kThreads>
+__device__ void block_sums(double (&v)[K], double* red) {
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * NW + (threadIdx.x >> 6)] = v[k];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    const int k = threadIdx.x;
+    double r = red[k * NW];
+    for (int w = 1; w < NW; ++w) r += red[k * NW + w];
+    red[K * NW + k] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = red[K * NW + k];
+  __syncthreads();  // red is reused by the next reduction
+}
+
 __device__ double block_max(double v, double* red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
@@ -319,8 +348,8 @@ struct CgArgs {
   const float* part;
   const int32_t* shared_slot_ptr;
   const int32_t* shared_slots;
-  const int32_t* shared_node;
   const int32_t* cell_shared_off;
+  const int32_t* cell_shared_first;  // first shared node of every cell
 };
 
 // The shared nodes of a cell are the contiguous ids [sh0, sh0 + ns) (owned
@@ -336,7 +365,7 @@ __device__ __forceinline__ ShrRange shared_range(const CgArgs& a, int c, int64_t
     r.s0 = a.cell_shared_off[c];
     const int ns = a.cell_shared_off[c + 1] - r.s0;
     if (ns > 0) {
-      r.sh0 = a.shared_node[r.s0];
+      r.sh0 = a.cell_shared_first[c];
       r.sh1 = r.sh0 + ns;
     }
   }
@@ -363,7 +392,8 @@ __device__ __forceinline__ void ybar_of(const CgArgs& a, const ShrRange& sr, int
 }
 
 // Nodes per thread up to which a cell's CG iteration keeps every operand in
-// registers (cells of at most kRegNodes * kThreads nodes).
+// registers (cells of at most kRegNodes * kThreads nodes; cells of at most
+// kThreads * 2 nodes take a 2-node variant that needs fewer registers).
 constexpr int kRegNodes = 4;
 
 __device__ __forceinline__ void cg_finish(const CgArgs& a, double* s, double rn,
@@ -375,21 +405,32 @@ __device__ __forceinline__ void cg_finish(const CgArgs& a, double* s, double rn,
   }
 }
 
-// The iteration of qs_cg_kernel for a cell of at most kRegNodes * kThreads
-// nodes: p, r, x, Hess(Pi) p and the preconditioner block of every node are
-// loaded once, in one wave of loads, and kept in registers through the
-// three phases (Ap is not stored).  Same operations in the same order as the
-// streaming version (which fused multiply-adds the compiler forms may
+
+// The iteration of qs_cg_kernel for a cell of at most R * kThreads nodes: p,
+// r, x, Hess(Pi) p and the preconditioner block of every node are loaded
+// once and kept in registers through the three phases (Ap is not stored).
+// The loads come in three waves, each issued whole before any of its
+// results is used: the node values with the slot ranges of the shared
+// nodes, then the ids of their first FS slots (most shared nodes have 2 or
+// 3; the others finish in a loop), then those slots' partials, summed in
+// slot order as the finalize does.  Same operations in the same order as
+// the streaming version (which fused multiply-adds the compiler forms may
 // differ between the two, a last-bit difference).
+template <int R>
 __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
                              double top, double bot, double* red, const ShrRange& sr) {
+  constexpr int kRegNodes = R;
+  constexpr int kFastSlots = R <= 2 ? 4 : 2;
   const int64_t N = a.N;
   float p[kRegNodes][3], r[kRegNodes][3], ap[kRegNodes][3], x[kRegNodes][3];
-  float m[kRegNodes][6];
-  double pap = 0.0;
+  float m[kRegNodes][6], b[kRegNodes][3];
+  double h[kRegNodes];
+  int q0[kRegNodes], nq[kRegNodes];
 #pragma unroll
   for (int u = 0; u < kRegNodes; ++u) {
     const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
+    nq[u] = 0;
+    q0[u] = 0;
     if (i < n1) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -402,12 +443,51 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
         for (int q = 0; q < 6; ++q) m[u][q] = a.minv[q * N + i];
       }
       const double z = a.y[2 * N + i];
-      const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
-      float bx, by, bz;
-      ybar_of(a, sr, i, bx, by, bz);
-      ap[u][0] = -bx;
-      ap[u][1] = -by;
-      ap[u][2] = (float)(-(double)bz + h * (double)p[u][2]);
+      h[u] = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+      if (i >= sr.sh0 && i < sr.sh1) {
+        const int sn = sr.s0 + (int)(i - sr.sh0);
+        q0[u] = a.shared_slot_ptr[sn];
+        nq[u] = a.shared_slot_ptr[sn + 1] - q0[u];
+        b[u][0] = b[u][1] = b[u][2] = 0.f;
+      } else {
+        b[u][0] = a.ybar[i];
+        b[u][1] = a.ybar[N + i];
+        b[u][2] = a.ybar[2 * N + i];
+      }
+    }
+  }
+  int sl[kRegNodes][kFastSlots];
+#pragma unroll
+  for (int u = 0; u < kRegNodes; ++u)
+#pragma unroll
+    for (int j = 0; j < kFastSlots; ++j)
+      sl[u][j] = j < nq[u] ? a.shared_slots[q0[u] + j] : 0;
+#pragma unroll
+  for (int u = 0; u < kRegNodes; ++u) {
+#pragma unroll
+    for (int j = 0; j < kFastSlots; ++j) {
+      if (j < nq[u]) {
+        const float* pp = a.part + 3 * (int64_t)sl[u][j];
+        b[u][0] += pp[0];
+        b[u][1] += pp[1];
+        b[u][2] += pp[2];
+      }
+    }
+    for (int j = kFastSlots; j < nq[u]; ++j) {
+      const float* pp = a.part + 3 * (int64_t)a.shared_slots[q0[u] + j];
+      b[u][0] += pp[0];
+      b[u][1] += pp[1];
+      b[u][2] += pp[2];
+    }
+  }
+  double pap = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRegNodes; ++u) {
+    const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < n1) {
+      ap[u][0] = -b[u][0];
+      ap[u][1] = -b[u][1];
+      ap[u][2] = (float)(-(double)b[u][2] + h[u] * (double)p[u][2]);
       pap += (double)p[u][0] * ap[u][0] + (double)p[u][1] * ap[u][1] +
              (double)p[u][2] * ap[u][2];
     }
@@ -441,8 +521,10 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
              (double)r[u][2] * zv[u][2];
     }
   }
-  rn = block_sum(rn, red);
-  rzn = block_sum(rzn, red);
+  double sums[2] = {rn, rzn};
+  block_sums(sums, red);
+  rn = sums[0];
+  rzn = sums[1];
   const float beta = (float)(rzn / rs);
 #pragma unroll
   for (int u = 0; u < kRegNodes; ++u) {
@@ -470,8 +552,12 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
   const ShrRange sr = shared_range(a, c, n1);
+  if (n1 - n0 <= (int64_t)2 * kThreads) {
+    cg_step_regs<2>(a, s, n0, n1, top, bot, red, sr);
+    return;
+  }
   if (n1 - n0 <= (int64_t)kRegNodes * kThreads) {
-    cg_step_regs(a, s, n0, n1, top, bot, red, sr);
+    cg_step_regs<kRegNodes>(a, s, n0, n1, top, bot, red, sr);
     return;
   }
   double pap = 0.0;
@@ -508,8 +594,10 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
     if (a.minv) apply_minv(a.minv, N, i, rq[0], rq[1], rq[2], z[0], z[1], z[2]);
     rzn += (double)rq[0] * z[0] + (double)rq[1] * z[1] + (double)rq[2] * z[2];
   }
-  rn = block_sum(rn, red);
-  rzn = block_sum(rzn, red);
+  double sums[2] = {rn, rzn};
+  block_sums(sums, red);
+  rn = sums[0];
+  rzn = sums[1];
   const float beta = (float)(rzn / rs);
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     float z[3] = {a.r[i], a.r[N + i], a.r[2 * N + i]};
@@ -660,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void qs_update_kernel(UpdArgs a) {
 struct LsArgs {
   const int64_t* node_off;
   int64_t N;
-  const float* x;
+  float* x;  // projected in place by the start kernel
   const float* rn;         // Newton residual (-grad Pi, projected)
   const double* plate;
   const double* energy_t;  // E at the trial positions (accept)
@@ -672,7 +760,12 @@ struct LsArgs {
   int32_t* ninv;           // inverted tetrahedra at y (nullable)
 };
 
-// Start of the line search on Pi along the Newton step x: s = min(1, cap /
+// Start of the line search on Pi along the Newton step x: x loses its
+// components along the symmetries of the plates (translations in x and y,
+// rotation about z through the centroid of y), which Hess(Pi) annihilates
+// and the preconditioned CG therefore never corrects: they change neither
+// Pi nor the slope, but they inflate max |x| (a shorter capped step) and a
+// finite rotation stretches the cell radially.  Then s = min(1, cap /
 // max |x_i|), slope r_N . x (> 0 for a descent direction), y_t = y + s x for
 // the cells in equilibrium-search, y_t = y for the others.
 __global__ __launch_bounds__(kThreads) void qs_ls_start_kernel(LsArgs a) {
@@ -682,14 +775,46 @@ __global__ __launch_bounds__(kThreads) void qs_ls_start_kernel(LsArgs a) {
   double* s = a.st + kQsState * c;
   const bool act = s[11] != 0.0;
   double mx = 0.0, rx = 0.0;
-  if (act)
-    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int64_t q = d * N + i;
-        mx = fmax(mx, fabs((double)a.x[q]));
-        rx += (double)a.rn[q] * a.x[q];
-      }
+  if (act) {  // uniform over the workgroup
+    const double inv_n = 1.0 / (double)(n1 - n0);
+    double sx = 0.0, sy = 0.0, tx = 0.0, ty = 0.0;
+#pragma unroll 1
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+      sx += a.y[i];
+      sy += a.y[N + i];
+      tx += a.x[i];
+      ty += a.x[N + i];
+    }
+    double c4[4] = {sx, sy, tx, ty};
+    block_sums(c4, red);
+    const double cx = c4[0] * inv_n, cy = c4[1] * inv_n;
+    tx = c4[2] * inv_n;
+    ty = c4[3] * inv_n;
+    // x . w / |w|^2 for w = e_z x (y - c)
+    double tq = 0.0, ww = 0.0;
+#pragma unroll 1
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+      const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
+      tq += dx * a.x[N + i] - dy * a.x[i];
+      ww += dx * dx + dy * dy;
+    }
+    double t2[2] = {tq, ww};
+    block_sums(t2, red);
+    tq = t2[0];
+    ww = t2[1];
+    const double om = ww > 0.0 ? tq / ww : 0.0;
+#pragma unroll 1
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+      const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
+      const float px = (float)((double)a.x[i] - tx + om * dy);
+      const float py = (float)((double)a.x[N + i] - ty - om * dx);
+      const float pz = a.x[2 * N + i];
+      a.x[i] = px;
+      a.x[N + i] = py;
+      mx = fmax(fmax(mx, fabs((double)px)), fmax(fabs((double)py), fabs((double)pz)));
+      rx += (double)a.rn[i] * px + (double)a.rn[N + i] * py + (double)a.rn[2 * N + i] * pz;
+    }
+  }
   mx = block_max(mx, red);
   rx = block_sum(rx, red);
   const bool go = act && mx > 0.0 && rx > 0.0;
@@ -831,8 +956,8 @@ hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
            slots ? slots->part : nullptr,
            slots ? slots->shared_slot_ptr : nullptr,
            slots ? slots->shared_slots : nullptr,
-           slots ? slots->shared_node : nullptr,
-           slots ? slots->cell_shared_off : nullptr};
+           slots ? slots->cell_shared_off : nullptr,
+           slots ? slots->cell_shared_first : nullptr};
   hipLaunchKernelGGL(qs_cg_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -878,7 +1003,7 @@ hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
 }
 
 hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
-                              const float* x, const float* rn, double cap,
+                              float* x, const float* rn, double cap,
                               const float* y, float* yt, double* st, hipStream_t s) {
   LsArgs a{node_off, N, x, rn, nullptr, nullptr, 0.0, cap, 0.0, 0.0,
            const_cast<float*>(y), yt, st, nullptr, nullptr};
@@ -891,8 +1016,9 @@ hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cel
                                const double* energy_t, double armijo,
                                double min_move, float* y, float* yt, double* st,
                                const int32_t* ninv_t, int32_t* ninv, hipStream_t s) {
-  LsArgs a{node_off, N, x, nullptr, plate, energy_t, k, 0.0, armijo, min_move, y, yt,
-           st, ninv_t, ninv};
+  // the accept kernel only reads x
+  LsArgs a{node_off, N, const_cast<float*>(x), nullptr, plate, energy_t, k, 0.0, armijo,
+           min_move, y, yt, st, ninv_t, ninv};
   hipLaunchKernelGGL(qs_ls_accept_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

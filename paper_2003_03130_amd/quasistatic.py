@@ -25,7 +25,9 @@ class QuasiStaticCompression:
     relative CG residual; eta_max: largest forcing term of the inexact Newton
     steps (0: every CG solve to cg_tol); precondition: block-Jacobi CG;
     fused_cg: each CG iteration as one library call with its Hessian-vector
-    product (cm_qs_cg_iteration) instead of two;
+    product (cm_qs_cg_iteration) instead of two; pipelined_checks: the host
+    reads the CG convergence check of a block of iterations only after the
+    next block is queued (same iterates; False: it waits after every block);
     cap: largest node move per Newton step; armijo: sufficient decrease of
     the line search, which gives up below min_move."""
 
@@ -33,7 +35,7 @@ class QuasiStaticCompression:
                  step_tol=1e-6, floor_factor=2.0, cg_tol=1e-3, max_newton=40,
                  max_cg=400, cap=0.05, armijo=1e-4, min_move=1e-7,
                  max_backtrack=12, eta_max=0.5, precondition=True,
-                 fused_cg=True):
+                 fused_cg=True, pipelined_checks=True):
         import torch
         self.cb = batch
         self.k = float(k_plate)
@@ -48,6 +50,7 @@ class QuasiStaticCompression:
         # one call per CG iteration (cm_qs_cg_iteration) or the two-call
         # route (cm_forces_backward_cells + cm_qs_cg_step); bitwise equal
         self.fused_cg = bool(fused_cg)
+        self.pipelined_checks = bool(pipelined_checks)
         if self.precondition:
             self._kel = torch.empty(6 * batch.n_nodes, dtype=torch.float32,
                                     device=batch.device)
@@ -78,6 +81,7 @@ class QuasiStaticCompression:
         self.force = torch.zeros(batch.n_cells, 2, dtype=torch.float64,
                                  device=dev)
         self.stats = {"newton": 0, "cg": 0, "trials": 0}
+        self._flags, self._flag_i = None, 0  # pinned flags of _active_async
 
     def _residual(self, y, plate, restart=False):
         cb = self.cb
@@ -92,9 +96,34 @@ class QuasiStaticCompression:
     def _active(self, col):
         return bool((self.state[:, col] > 0).any())
 
+    def _active_async(self, col):
+        """Queues on the current stream a check whether any cell has state
+        column col set, copied into pinned host memory; returns a function
+        that waits for that copy alone and returns the answer."""
+        import torch
+        if self._flags is None:
+            self._flags = [torch.zeros(1, dtype=torch.bool, pin_memory=True)
+                           for _ in range(2)]
+        buf = self._flags[self._flag_i]
+        self._flag_i ^= 1
+        buf.copy_((self.state[:, col] > 0).any().reshape(1), non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+
+        def wait():
+            ev.synchronize()
+            return bool(buf[0])
+        return wait
+
     def _cg_loop(self, y, plate, tol, max_iter, counter):
-        """CG iterations for every cell still active (state column 2) until
-        none is (checked every 8 iterations) or max_iter."""
+        """CG iterations for every cell still active (state column 2), in
+        blocks of 8, until a block ends with no cell active, or max_iter.
+        The check after a block runs on the device, and the host reads it
+        only once the next block is queued, so the device does not wait for
+        the host between blocks; the block queued behind the last one that
+        mattered runs as no-ops (every kernel skips finished cells), so the
+        iterates are those of a loop that stops right after that block, and
+        the count leaves that block out."""
         cb = self.cb
         lib, st = nat.lib(), _stream(None)
         if self.fused_cg:
@@ -103,28 +132,40 @@ class QuasiStaticCompression:
                     _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
                     _ptr(self._minv), st)
             step = lib.cm_qs_cg_iteration
-            for j in range(max_iter):
+
+            def iteration():
                 nat.check(step(*args))
-                self.stats[counter] = self.stats.get(counter, 0) + 1
-                if j % 8 == 7 and not self._active(2):
+        else:
+            # Hessian-vector products only for the cells still in CG (state
+            # column 2 as the cell flags; no parameter gradient), then one
+            # CG iteration
+            flags = self.state[:, 2]
+            hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
+                        flags.stride(0), _ptr(self._ybar), None, st)
+            cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, float(tol),
+                       _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
+                       _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
+                       _ptr(self._minv), st)
+
+            def iteration():
+                nat.check(lib.cm_forces_backward_cells(*hvp_args))
+                nat.check(lib.cm_qs_cg_step(*cg_args))
+        pending, j = None, 0
+        while j < max_iter:
+            n = min(8, max_iter - j)
+            for _ in range(n):
+                iteration()
+            j += n
+            self.stats[counter] = self.stats.get(counter, 0) + n
+            check = self._active_async(2)
+            if not self.pipelined_checks:
+                if not check():
                     break
-            return
-        # the CG loop's two calls with their arguments fixed once: Hessian-
-        # vector products only for the cells still in CG (state column 2 as
-        # the cell flags; no parameter gradient), then one CG iteration
-        flags = self.state[:, 2]
-        hvp_args = (cb._h, _ptr(y), _ptr(self._p), None, _ptr(flags),
-                    flags.stride(0), _ptr(self._ybar), None, st)
-        cg_args = (cb._h, _ptr(y), _ptr(plate), self.k, float(tol),
-                   _ptr(self._ybar), _ptr(self._x), _ptr(self._r),
-                   _ptr(self._p), _ptr(self._Ap), _ptr(self.state),
-                   _ptr(self._minv), st)
-        for j in range(max_iter):
-            nat.check(lib.cm_forces_backward_cells(*hvp_args))
-            nat.check(lib.cm_qs_cg_step(*cg_args))
-            self.stats[counter] = self.stats.get(counter, 0) + 1
-            if j % 8 == 7 and not self._active(2):
+                continue
+            if pending is not None and not pending():
+                self.stats[counter] -= n  # queued after the solve ended
                 break
+            pending = check
 
     def equilibrate(self, y, plate):
         """Newton iterations at one plate position (plate: float64 device

@@ -486,3 +486,40 @@ def test_cg_iteration_in_one_call_equals_two_calls():
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     assert np.array_equal(a[2], c[2]) and np.array_equal(a[3], c[3])
     assert a[4] == c[4]
+
+
+def test_pipelined_checks_keep_the_iterates():
+    """Convergence checks read a block of 8 CG iterations late give bitwise
+    the iterates of the loop that waits after every block (the block queued
+    behind the last one that mattered runs as no-ops): same plate forces,
+    Newton and CG counts, parameter derivatives and final positions; on
+    cells of the 2-node and 4-node register paths of the CG kernel and one
+    streamed."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b0 = _cells()
+    cells = [b0.cell(c) for c in range(b0.n_cells)]
+    for n, seed, ax in ((3000, 78, (1.1, 1.2, 0.8)), (6000, 77, (1.15, 1.1, 0.8))):
+        x, tets = sphere_mesh(n, seed)
+        x = ellipsoid(x, np.array(ax))
+        cells.append(Cell(x, tets, x.astype(np.float32), (1.2, 15.0, 0.4)))
+    b = batch_from_cells(cells)
+    sizes = np.diff(b.node_off)
+    assert sizes.min() <= 2048 and ((sizes > 2048) & (sizes <= 4096)).any()
+    assert sizes.max() > 4096
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    tops, bot, _ = _plates(b, [0.05, 0.3, 0.5])
+    out = {}
+    for pipe in (False, True):
+        qs = QuasiStaticCompression(cb, K, pipelined_checks=pipe)
+        Ft, Fb, ok, y = qs.curve(cb.to_device(b.y), tops, bot, jacobian=True)
+        torch.cuda.synchronize()
+        assert ok.all()
+        out[pipe] = (Ft, Fb, y.cpu().numpy(), qs.jacobian, dict(qs.stats))
+        print(f"pipelined {pipe}: {qs.stats}", flush=True)
+    a, c = out[False], out[True]
+    for k in range(4):
+        assert np.array_equal(a[k], c[k]), k
+    assert a[4] == c[4]
