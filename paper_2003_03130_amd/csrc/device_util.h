@@ -23,12 +23,15 @@ struct TetRegs {
   float V0;
 };
 
+// Chunks are read once per pass: non-temporal loads keep them from
+// displacing the node data that neighbouring tiles reuse from the caches.
 __device__ __forceinline__ void load_tet(const TetChunk* ch, int lane,
                                          TetRegs& r) {
-  r.q = *reinterpret_cast<const uint2*>(ch->idx[lane]);
+  r.q.x = __builtin_nontemporal_load(&ch->idx[lane][0]);
+  r.q.y = __builtin_nontemporal_load(&ch->idx[lane][1]);
 #pragma unroll
-  for (int m = 0; m < 9; ++m) r.B[m] = ch->B[m][lane];
-  r.V0 = ch->V0[lane];
+  for (int m = 0; m < 9; ++m) r.B[m] = __builtin_nontemporal_load(&ch->B[m][lane]);
+  r.V0 = __builtin_nontemporal_load(&ch->V0[lane]);
 }
 
 // Adds the contributions h[0..2] of vertex slots 0..2 and -(h0 + h1 + h2) of

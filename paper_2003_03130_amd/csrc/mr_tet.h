@@ -21,8 +21,9 @@
 // reference tetrahedron).  The invariants, the powers of J, the energy
 // density and, in the forward pass, the coefficients c1..c3 are float64; the
 // remaining 3x3 tensor algebra (F C, cof F, P B^T) is float32 (the backward
-// pass forms its coefficient chain in float32 too, see tet_backward).  J^-1/3 is the reciprocal of the
-// real (sign-preserving) cube root: a float32 hardware log2/exp2 seed
+// pass forms its coefficient chain in float32 too, see tet_backward).
+// J^-1/3 is the reciprocal of the real (sign-preserving) cube root: a
+// float32 hardware log2/exp2 seed
 // refined by one Newton step in float64.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -199,10 +200,11 @@ __device__ __forceinline__ void cofactor_dir(const float F[3][3],
 //   gp = (<P_I, dF>, <P_K, dF>, (J - 1) <cof F, dF>) and
 //   ge = (I - 3, K - 3, (J - 1)^2) (twice the energy parts).
 // F and the invariants are float64 as in the forward pass; the stress
-// coefficients, their derivatives along dF and gp are float32, formed from
+// coefficients and their derivatives along dF are float32, formed from
 // float32 copies of the float64 invariants (J - 1 included): that chain has
 // no cancellation beyond the one P itself carries, and float32 there keeps
-// float64 off most of the pass.  ge stays float64 (I - 3 and K - 3 cancel).
+// float64 off most of the pass.  gp and ge stay float64 (the deviatoric
+// parts of gp, I - 3 and K - 3 cancel down to the order of the strain).
 // GRAD = false: the Hessian-vector product alone (no energy cotangent, no
 // parameter gradient): ebar is taken as 0 and gp, ge are not formed.
 template <bool GRAD>
@@ -297,9 +299,15 @@ __device__ __forceinline__ void tet_backward(
   // energy parts along dF and the energy parts e themselves, so that
   // g = V0 (-p + ebar e / 2) is formed once per tile
   if constexpr (GRAD) {
-    gp[0] = r2 * (fF - TC * tq * (1.f / 3.f));
-    gp[1] = r4 * (TC * fF - fFC - (2.f / 3.f) * I2 * tq);
-    gp[2] = Jm1 * dJ;
+    // gp[0] and gp[1] are deviatoric projections: <F, dF> and the TC dJ / 3J
+    // term cancel down to the order of the strain, so they are formed in
+    // float64 from the float64 invariants (a float32 copy of TC or 1/J would
+    // enter amplified by 1/strain)
+    const double fFd = (double)fF, dJd = (double)dJ;
+    const double tqd = (s.r2 * s.r) * dJd;
+    gp[0] = s.r2 * (fFd - s.TC * tqd * (1.0 / 3.0));
+    gp[1] = s.r4 * (s.TC * fFd - (double)fFC - (2.0 / 3.0) * s.I2 * tqd);
+    gp[2] = Jm1d * dJd;
     ge[0] = s.TC * s.r2 - 3.0;
     ge[1] = s.I2 * s.r4 - 3.0;
     ge[2] = Jm1d * Jm1d;
