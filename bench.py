@@ -49,13 +49,15 @@ BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
 STORED_TET_BYTES = 48
 F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
 TILE_KERNEL_SOURCES = ("kernels.hip", "backward.hip", "device_util.h",
-                       "kernels.h", "layout.h", "mr_tet.h", "prep.cpp")
+                       "kernels.h", "layout.h", "mr_tet.h", "prep.cpp",
+                       "util.hip")
 
 
 def kernel_source_hash():
     """sha256 of the sources of the forward and backward kernels (their .hip
     files and the headers they include) and of the host code that lays out
-    their data (prep.cpp: tiles, slots, chunks); a stored counter record
+    their data (prep.cpp: tiles, slots, chunks), and of the reference copy
+    kernel the counters are scaled by (util.hip); a stored counter record
     applies only to the kernels and layout it was measured on.  The other
     host code and the auxiliary kernels (plates, quasi-static, shape) are
     not part of it."""
@@ -71,9 +73,10 @@ def kernel_source_hash():
 
 def measured_traffic(kernel, info):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    record (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration),
-    or None if absent, taken on other kernel sources or on another layout of
-    the workload (tiles, slots, chunks)."""
+    records (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration;
+    one record per layout of the workload that was profiled: tiles, slots,
+    chunks), or None if absent, taken on other kernel sources or on no
+    record of this layout."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -81,11 +84,12 @@ def measured_traffic(kernel, info):
         return None
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    lay = rec.get("layout", {})
-    if not lay or any(info.get(k) != v for k, v in lay.items()):
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes")
+    for r in rec.get("records", []):
+        lay = r.get("layout", {})
+        if lay and all(info.get(k) == v for k, v in lay.items()):
+            k = r.get("kernels", {}).get(kernel)
+            return None if k is None else k.get("bytes")
+    return None
 
 
 def log(msg):
@@ -856,10 +860,15 @@ def main():
     log(f"device copy: {copy_gbps:.0f} GB/s")
 
     if args.calibrate_copy:
+        # the library's plain copy kernel (stream_copy_kernel): the reference
+        # of known traffic for the byte counters
         nf = args.calibrate_copy * 2 ** 20 // 4
         src = torch.ones(nf, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        from paper_2003_03130_amd import _native as nat
+        from paper_2003_03130_amd.cells import _ptr, _stream
+        nat.check(nat.lib().cm_stream_copy(_ptr(src), _ptr(dst), nf, _stream(None)))
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy} MiB read + written")
         del src, dst

@@ -596,6 +596,15 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
                        hipStream_t stream);
 
 /*
+ * cm_stream_copy: dst[i] = src[i] for i < n (device float arrays, n >= 0; no
+ * overlap), one dword per lane per load instruction like the tile kernels'
+ * chunk stream, asynchronous on `stream`.  A kernel of known traffic (4 n
+ * bytes read, 4 n written) against which hardware byte counters are scaled.
+ * Errors: CM_EINVAL for n < 0 or null pointers with n > 0.
+ */
+int cm_stream_copy(const float* src, float* dst, int64_t n, hipStream_t stream);
+
+/*
  * Host-only view of the prepared layout (no device work), for validation and
  * debugging of the preparation step.  cm_layout_create runs exactly the
  * preparation of cm_batch_create (same arguments, same errors).

@@ -1,7 +1,8 @@
 """Entry points no driver in the package calls: cm_mesh_create (the
-single-cell form of cm_batch_create) and cm_qs_update (the bounded Newton
+single-cell form of cm_batch_create), cm_qs_update (the bounded Newton
 update, y += s x, s = min(1, cap / m), m the largest |component| of x over a
-cell's nodes)."""
+cell's nodes) and cm_stream_copy (the reference copy of the byte-counter
+calibration)."""
 import ctypes
 
 import numpy as np
@@ -81,3 +82,26 @@ def test_qs_update_formula():
             assert st[c, 4] == float(s) and abs(st[c, 6] - m * float(s)) <= 1e-12 * m
         else:
             assert st[c, 4] == -7.0 and st[c, 6] == -7.0  # untouched
+
+
+def test_stream_copy():
+    """cm_stream_copy copies n floats exactly (sizes below, at and above one
+    workgroup's 256 and past the 65,536-workgroup grid cap, so the grid
+    stride loop runs), leaves the rest of dst alone, accepts n = 0 and
+    rejects n < 0 and null pointers."""
+    import torch
+    from paper_2003_03130_amd import _native as nat
+    from paper_2003_03130_amd.cells import _ptr, _stream
+    lib = nat.lib()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for n in (1, 255, 256, 1000, 65536 * 256 + 77):
+        src = torch.randn(n + 8, device="cuda", generator=g)
+        dst = torch.full((n + 8,), -7.0, device="cuda")
+        nat.check(lib.cm_stream_copy(_ptr(src), _ptr(dst), n, _stream(None)))
+        torch.cuda.synchronize()
+        assert torch.equal(dst[:n], src[:n]), n
+        assert bool((dst[n:] == -7.0).all()), n
+    dst = torch.zeros(4, device="cuda")
+    nat.check(lib.cm_stream_copy(None, _ptr(dst), 0, _stream(None)))
+    assert lib.cm_stream_copy(_ptr(dst), _ptr(dst), -1, _stream(None)) == nat.CM_EINVAL
+    assert lib.cm_stream_copy(None, _ptr(dst), 4, _stream(None)) == nat.CM_EINVAL

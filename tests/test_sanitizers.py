@@ -64,9 +64,8 @@ def test_host_library_under_asan_ubsan(tmp_path):
     if not rt:
         pytest.skip("clang AddressSanitizer runtime not found")
     csrc = os.path.join(ROOT, "paper_2003_03130_amd", "csrc")
-    srcs = [os.path.join(csrc, s) for s in
-            ("api.cpp", "prep.cpp", "kernels.hip", "backward.hip", "relax.hip",
-             "shape.hip", "quasistatic.hip", "noalloc.hip")]
+    from paper_2003_03130_amd.build import SOURCES
+    srcs = [os.path.join(csrc, s) for s in SOURCES]
     lib = str(tmp_path / "libcellmech_san.so")
     cmd = [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
            "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
