@@ -468,7 +468,9 @@ def run_quasistatic(args):
     a tetrahedron); reports wall time, Newton/CG counts, time per CG
     iteration, the mean curve, the deepest compression of the cells' own
     height, the plate balance, and the mean curves of the same cells with w
-    set to 0.25, 0.5 and 1 (the paper's fitted values)."""
+    set to 0.25, 0.5 and 1 (the paper's fitted values); then the same cells
+    indented by a sphere (the colloidal-probe setup) to 40 % of their height,
+    with its curve, balance, held centroids and small-depth exponent."""
     import torch
     from paper_2003_03130_amd import CellBatch
     from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
@@ -507,6 +509,38 @@ def run_quasistatic(args):
         Fw, _, okw, _ = qw.curve(y0, tops, bot)
         w_curves[str(w)] = {"mean_force": [round(float(v), 6) for v in Fw.mean(axis=1)],
                             "converged": bool(okw.all())}
+    # the colloidal-probe setup: a sphere of 0.66 times the cell radius (the
+    # paper's probe-to-particle ratio) on each cell's axis, the cell on the
+    # bottom plate with its centroid held laterally; Poisson ratio 0.48 (kappa
+    # = 24.7 mu) and w = 1, the paper's choices for that comparison
+    sphere_fr = np.linspace(0.02, 0.4, 10)
+    kappa_s = b.theta[:, 0] * 2.0 * 1.48 / (3.0 * (1.0 - 2.0 * 0.48))
+    cb.set_params(b.theta[:, 0], kappa_s, np.ones(b.n_cells))
+    tops_s = top0[None, :] - sphere_fr[:, None] * H[None, :]
+    qsph = QuasiStaticCompression(cb, K_PLATE, sphere_radius=0.66)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Fs, Fsb, oks, ys = qsph.curve(y0, tops_s, bot)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t
+    cb.forces(ys, n_inverted=ninv)
+    start_c = qsph.cell_centroids(y0).cpu().numpy()
+    sphere = {
+        "setup": "sphere radius 0.66 on each cell's axis (centroid held laterally), "
+                 "nu = 0.48 (kappa = 24.7 mu), w = 1",
+        "indentation_fraction_of_height": [round(float(v), 4) for v in sphere_fr],
+        "wall_s": wall_s, "newton": qsph.stats["newton"], "cg": qsph.stats["cg"],
+        "ms_per_cg_iteration": 1e3 * wall_s / max(qsph.stats["cg"], 1),
+        "converged_steps": int(oks.sum()), "steps": len(oks),
+        "mean_force": [round(float(v), 6) for v in Fs.mean(axis=1)],
+        "balance_max_by_step": [float(v) for v in
+                                (np.abs(Fs - Fsb) / np.maximum(Fs, 1e-30)).max(axis=1)],
+        "centroid_drift_max": float(np.abs(qsph.cell_centroids(ys).cpu().numpy()
+                                           - start_c).max()),
+        "inverted_tets_final": int(ninv.sum().item()),
+        "loglog_slope_first_half": float(np.median(
+            np.log(Fs[4] / Fs[1]) / np.log(sphere_fr[4] / sphere_fr[1]))),
+    }
     out = {
         "workload": f"{b.n_cells} oblate cells, {b.n_tets} tets, plates "
                     f"closing from first contact to 80 % of each cell's height "
@@ -527,6 +561,7 @@ def run_quasistatic(args):
         "upturn_loglog_slope_40_80": float(np.median(
             np.log(Ft[-1] / Ft[np.argmin(np.abs(frac - 0.4))]) / np.log(0.8 / 0.4))),
         "w_curves": w_curves,
+        "sphere_indenter": sphere,
     }
     log(f"quasi-static: {out}")
     cb.close()

@@ -497,6 +497,29 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
  * Errors: CM_EINVAL for null pointers, negative or non-finite k_plate or
  * tolerances, cap <= 0, eta_max outside [0, 1).
  */
+/*
+ * cm_qs_set_indenter: the top contact of the quasi-static entry points of
+ * this handle (Sec. "Simulation setup": two plates, or a sphere indenting
+ * the cell as in the colloidal-probe comparison of Sec. "Validation with
+ * AFM experiments").  radius = 0 (the default): the flat top plate at
+ * plate[2c].  radius > 0: a sphere of that radius whose lowest point is at
+ * plate[2c] and whose vertical axis passes through (axis_xy[2c],
+ * axis_xy[2c + 1]) (device float64[2 n_cells], copied on `stream`).  The
+ * sphere repels nodes with the plates' penalty law in the penetration depth
+ * g = max(0, radius - |y - c|): potential (k/3) g^3, force k g^2 n along the
+ * unit vector n from the centre, the force on the sphere k sum g^2 (c_z -
+ * y_z) / |y - c| upward (reported as the top force).  Frictionless contacts
+ * leave sliding off the sphere's axis unstable, so under the sphere each
+ * cell's centroid is held laterally: the residual, the CG iterates (the
+ * Hessian-vector products and preconditioned directions), the adjoint's
+ * right-hand side and the Newton step lose their lateral translation and
+ * their rotation about the vertical axis through the centroid.  cm_qs_update
+ * and cm_qs_predict are the same for both contacts.  Errors: CM_EINVAL for a
+ * negative or non-finite radius, or a sphere without axis_xy.
+ */
+int cm_qs_set_indenter(cm_batch h, double radius, const double* axis_xy,
+                       hipStream_t stream);
+
 int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* energy,
                    const double* plate, double k_plate, double abs_tol,
                    double rel_tol, double step_tol, double floor_factor,

@@ -89,6 +89,7 @@ SIGNATURES = {
                                 _vp, _vp]),
     "cm_graph_launch": (_int, [_vp, _vp]),
     "cm_stream_copy": (_int, [_vp, _vp, ctypes.c_int64, _vp]),
+    "cm_qs_set_indenter": (_int, [_vp, ctypes.c_double, _vp, _vp]),
     "cm_profile_kernels": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _vp, _vp]),
     "cm_plate_step": (_int, [_vp, _vp, _vp, _vp, ctypes.c_double,

@@ -878,6 +878,33 @@ int cm_plate_step(cm_batch h, const float* y, const float* f,
   return CM_OK;
 }
 
+int cm_qs_set_indenter(cm_batch h, double radius, const double* axis_xy,
+                       hipStream_t stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!(radius >= 0.0) || !std::isfinite(radius))
+    return fail(CM_EINVAL, "radius must be finite and >= 0");
+  if (radius > 0.0 && !axis_xy)
+    return fail(CM_EINVAL, "a sphere needs axis_xy (device float64[2 n_cells])");
+  if (int rc = select_device(h)) return rc;
+  if (radius > 0.0) {
+    if (!h->qs_ind.axis) {
+      double *ax, *geo;
+      int rc;
+      if ((rc = h->alloc(&ax, 2 * (size_t)h->n_cells)) ||
+          (rc = h->alloc(&geo, 3 * (size_t)h->n_cells)))
+        return rc;
+      CM_HIP(hipMemsetAsync(geo, 0, 3 * (size_t)h->n_cells * sizeof(double), stream));
+      h->qs_ind.axis = ax;
+      h->qs_ind.geo = geo;
+    }
+    CM_HIP(hipMemcpyAsync(const_cast<double*>(h->qs_ind.axis), axis_xy,
+                          2 * (size_t)h->n_cells * sizeof(double), hipMemcpyDeviceToDevice,
+                          stream));
+  }
+  h->qs_ind.R = radius;
+  return CM_OK;
+}
+
 int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* energy,
                    const double* plate, double k_plate, double abs_tol,
                    double rel_tol, double step_tol, double floor_factor,
@@ -898,7 +925,7 @@ int cm_qs_residual(cm_batch h, const float* y, const float* f, const double* ene
   CM_HIP(cm::launch_qs_residual(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, f,
                                 energy, plate, k_plate, abs_tol, rel_tol, step_tol,
                                 floor_factor, eta_max, restart ? 1 : 0, r, p, x,
-                                r_newton, state, force, k_el, minv, stream));
+                                r_newton, state, force, k_el, minv, stream, h->qs_ind));
   return CM_OK;
 }
 
@@ -934,7 +961,8 @@ int cm_qs_ls_accept(cm_batch h, const float* x, const double* plate, double k_pl
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_ls_accept(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, x,
                                  plate, k_plate, energy_trial, armijo, min_move, y,
-                                 y_trial, state, n_inverted_trial, n_inverted, stream));
+                                 y_trial, state, n_inverted_trial, n_inverted, stream,
+                                 h->qs_ind));
   return CM_OK;
 }
 
@@ -955,7 +983,7 @@ int cm_qs_floor(cm_batch h, const float* y, const double* plate, double k_plate,
     return fail(CM_EINVAL, "k_plate must be finite and >= 0");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_floor(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
-                             k_plate, e, ybar, state, stream));
+                             k_plate, e, ybar, state, stream, h->qs_ind));
   return CM_OK;
 }
 
@@ -969,7 +997,8 @@ int cm_qs_adjoint_rhs(cm_batch h, const float* y, const double* plate, double k_
     return fail(CM_EINVAL, "k_plate must be finite and >= 0");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_adjoint_rhs(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y,
-                                   plate, k_plate, weight, r, p, x, state, minv, stream));
+                                   plate, k_plate, weight, r, p, x, state, minv, stream,
+                                   h->qs_ind));
   return CM_OK;
 }
 
@@ -994,7 +1023,8 @@ int cm_qs_cg_step(cm_batch h, const float* y, const double* plate, double k_plat
     return fail(CM_EINVAL, "k_plate and rel_tol must be finite and >= 0");
   if (int rc = select_device(h)) return rc;
   CM_HIP(cm::launch_qs_cg(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
-                          k_plate, rel_tol, ybar, x, r, p, Ap, state, minv, stream));
+                          k_plate, rel_tol, ybar, x, r, p, Ap, state, minv, stream,
+                          nullptr, h->qs_ind));
   return CM_OK;
 }
 
@@ -1017,7 +1047,7 @@ int cm_qs_cg_iteration(cm_batch h, const float* y, const double* plate, double k
                                   stream, mask, cm::PlateBwd{}, false));
   CM_HIP(cm::launch_qs_cg(h->d_node_off, h->n_nodes, (int32_t)h->n_cells, y, plate,
                           k_plate, rel_tol, ybar, x, r, p, Ap, state, minv, stream,
-                          &h->Tb));
+                          &h->Tb, h->qs_ind));
   return CM_OK;
 }
 

@@ -45,7 +45,8 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               double rel_tol, double step_tol, double floor_factor,
                               double eta_max, int restart, float* r, float* p,
                               float* x, float* rn, double* st, double* force,
-                              const float* kel, float* minv, hipStream_t s);
+                              const float* kel, float* minv, hipStream_t s,
+                              const Indenter& ind = Indenter{});
 hipError_t launch_qs_ls_start(const int64_t* node_off, int64_t N, int32_t n_cells,
                               float* x, const float* rn, double cap,
                               const float* y, float* yt, double* st, hipStream_t s);
@@ -53,18 +54,21 @@ hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cel
                                const float* x, const double* plate, double k,
                                const double* energy_t, double armijo,
                                double min_move, float* y, float* yt, double* st,
-                               const int32_t* ninv_t, int32_t* ninv, hipStream_t s);
+                               const int32_t* ninv_t, int32_t* ninv, hipStream_t s,
+                               const Indenter& ind = Indenter{});
 hipError_t launch_qs_noise(const int64_t* node_off, int64_t N, int32_t n_cells,
                            const float* y, float* e, hipStream_t s);
 hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
                            const float* y, const double* plate, double k,
                            const float* e, const float* ybar, double* st,
-                           hipStream_t s);
-// Start of the adjoint CG solve Hess(Pi) lam = weight_c dF_top/dy.
+                           hipStream_t s, const Indenter& ind = Indenter{});
+// Start of the adjoint CG solve Hess(Pi) lam = weight_c dF_top/dy (under the
+// sphere, of the projected system).
 hipError_t launch_qs_adjoint_rhs(const int64_t* node_off, int64_t N, int32_t n_cells,
                                  const float* y, const double* plate, double k,
                                  const double* weight, float* r, float* p, float* x,
-                                 double* st, const float* minv, hipStream_t s);
+                                 double* st, const float* minv, hipStream_t s,
+                                 const Indenter& ind = Indenter{});
 // With slots set, ybar holds the owned nodes only (a backward tile pass
 // without its finalize) and the shared nodes' values are summed from the
 // slot partials of those tables (bitwise the finalize's sums).
@@ -72,7 +76,8 @@ hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
                         float* p, float* Ap, double* st, const float* minv,
-                        hipStream_t s, const DeviceTables* slots = nullptr);
+                        hipStream_t s, const DeviceTables* slots = nullptr,
+                        const Indenter& ind = Indenter{});
 // Small-strain stiffness blocks (the Newton preconditioner), 6 n_nodes
 // floats SoA: xx yy zz xy xz yz; uses the forward scratch.
 hipError_t launch_qs_stiffness(const DeviceTables& T, const Range& r, float* kel,

@@ -58,6 +58,7 @@ struct cm_batch_s {
   cm::LaunchCfg cfg;
   bool params_set = false;
   bool is_template = false;  // cells share one chunk array (tiles interleaved)
+  cm::Indenter qs_ind;       // top contact of the quasi-static entry points
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   // fork/join of the forward and backward branches of a captured graph

@@ -86,6 +86,18 @@ struct PlateBwd {
   float* lam = nullptr;
 };
 
+// Top contact of the quasi-static solver: R = 0 the flat top plate at the
+// plate height; R > 0 a sphere of radius R with its lowest point at the plate
+// height and its axis at (axis[2c], axis[2c + 1]) for cell c (the colloidal
+// probe).  Under the sphere the cells' centroids are held laterally; geo
+// receives per cell the centroid x, y and sum (dx^2 + dy^2) about it of the
+// positions at the last Newton residual, for the CG's projections.
+struct Indenter {
+  double R = 0.0;
+  const double* axis = nullptr;
+  double* geo = nullptr;
+};
+
 struct LaunchCfg {
   int waves = 1;   // tiles (wavefronts) per workgroup: 1, 2, 4 or 8
   int blocks = 0;  // persistent workgroups; 0 = one workgroup per W tiles

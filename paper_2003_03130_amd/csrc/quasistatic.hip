@@ -83,6 +83,58 @@ __device__ double block_max(double v, double* red) {
   return r;
 }
 
+// Sphere indenter (Indenter with R > 0): node (x, y, z) against the sphere
+// of cell c whose lowest point is at height top.  g = max(0, R - d) is the
+// penetration, d the distance to the centre, n the unit vector from the
+// centre to the node (zero without contact).  The penalty potential is
+// (k/3) g^3 as for the plates: force k g^2 n on the node, k g^2 (c_z - z) / d
+// upward on the sphere, Hessian 2 k g n n^T - k (g^2 / d) (I - n n^T).
+struct SphereHit {
+  double g, d, n[3];
+};
+
+__device__ __forceinline__ SphereHit sphere_hit(const Indenter& ind, int c, double top,
+                                                double x, double y, double z) {
+  SphereHit h;
+  const double rx = x - ind.axis[2 * c], ry = y - ind.axis[2 * c + 1];
+  const double rz = z - (top + ind.R);
+  h.d = sqrt(rx * rx + ry * ry + rz * rz);
+  h.g = h.d > 0.0 ? fmax(ind.R - h.d, 0.0) : 0.0;
+  const double inv = h.g > 0.0 ? 1.0 / h.d : 0.0;
+  h.n[0] = rx * inv;
+  h.n[1] = ry * inv;
+  h.n[2] = rz * inv;
+  return h;
+}
+
+// Hessian of the sphere's penalty potential times v.
+__device__ __forceinline__ void sphere_hess(const SphereHit& h, double k, double vx,
+                                            double vy, double vz, double out[3]) {
+  if (!(h.g > 0.0)) {
+    out[0] = out[1] = out[2] = 0.0;
+    return;
+  }
+  const double nv = h.n[0] * vx + h.n[1] * vy + h.n[2] * vz;
+  const double a = 2.0 * k * h.g * nv, b = k * h.g * h.g / h.d;
+  out[0] = a * h.n[0] - b * (vx - nv * h.n[0]);
+  out[1] = a * h.n[1] - b * (vy - nv * h.n[1]);
+  out[2] = a * h.n[2] - b * (vz - nv * h.n[2]);
+}
+
+// Projection onto the complement of the modes the sphere setup removes
+// (translations in x and y, which the held centroid takes, and the rotation
+// about the vertical axis through the centroid (cx, cy), a symmetry): from
+// the cell sums sx = sum v_x, sy = sum v_y, sr = sum (dx v_y - dy v_x), with
+// inv_n = 1 / nodes and ww = sum (dx^2 + dy^2).
+struct ModeFit {
+  double tx, ty, om;
+};
+
+__device__ __forceinline__ ModeFit mode_fit(double sx, double sy, double sr,
+                                           double inv_n, double ww) {
+  return ModeFit{sx * inv_n, sy * inv_n, ww > 0.0 ? sr / ww : 0.0};
+}
+
 // Inverse of the symmetric 3x3 block (xx yy zz xy xz yz) in float64; the
 // identity where the block is not positive definite (unused nodes).
 __device__ void sym3_inverse(const double m[6], float o[6]) {
@@ -135,6 +187,7 @@ struct ResArgs {
   double* force;  // per cell: top, bottom plate force (nullable)
   const float* kel;  // small-strain stiffness blocks (6 n_nodes), nullable
   float* minv;       // out with kel: inverse preconditioner blocks (6 n_nodes)
+  Indenter ind;
 };
 
 // r = f + p (the negative gradient of Pi) with its components along the
@@ -154,11 +207,12 @@ struct ResArgs {
 // new plate position), and at least half the ratio of the equilibrium
 // tolerance to |r_N| (no more accuracy than the test needs).
 __global__ __launch_bounds__(kResThreads) void qs_residual_kernel(ResArgs a) {
-  __shared__ double red[kResThreads / 64];
+  __shared__ double red[64];
   const int c = blockIdx.x;
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
   const double inv_n = 1.0 / (double)(n1 - n0);
+  const bool sph = a.ind.R > 0.0;  // uniform over the workgroup
   auto rz_of = [&](int64_t i, double& dt, double& db, double& pz) {
     const double z = a.y[2 * N + i];
     dt = fmax(z - top, 0.0);
@@ -166,13 +220,29 @@ __global__ __launch_bounds__(kResThreads) void qs_residual_kernel(ResArgs a) {
     pz = a.k * (db * db - dt * dt);
     return (double)a.f[2 * N + i] + pz;
   };
+  // lateral force of the sphere on node i (zero for the plates)
+  auto lat = [&](int64_t i, double& px, double& py) {
+    px = py = 0.0;
+    if (sph) {
+      const SphereHit h = sphere_hit(a.ind, c, top, a.y[i], a.y[N + i], a.y[2 * N + i]);
+      px = a.k * h.g * h.g * h.n[0];
+      py = a.k * h.g * h.g * h.n[1];
+    }
+  };
   // centroid (x, y) and mean residual (x, y)
   double sx = 0.0, sy = 0.0, mx = 0.0, my = 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
     sx += a.y[i];
     sy += a.y[N + i];
-    mx += a.f[i];
-    my += a.f[N + i];
+    if (sph) {
+      double px, py;
+      lat(i, px, py);
+      mx += (double)a.f[i] + px;
+      my += (double)a.f[N + i] + py;
+    } else {
+      mx += a.f[i];
+      my += a.f[N + i];
+    }
   }
   const double cx = block_sum<kResThreads>(sx, red) * inv_n;
   const double cy = block_sum<kResThreads>(sy, red) * inv_n;
@@ -182,29 +252,64 @@ __global__ __launch_bounds__(kResThreads) void qs_residual_kernel(ResArgs a) {
   double tq = 0.0, ww = 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
     const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
-    tq += dx * a.f[N + i] - dy * a.f[i];
+    if (sph) {
+      double px, py;
+      lat(i, px, py);
+      tq += dx * ((double)a.f[N + i] + py) - dy * ((double)a.f[i] + px);
+    } else {
+      tq += dx * a.f[N + i] - dy * a.f[i];
+    }
     ww += dx * dx + dy * dy;
   }
   tq = block_sum<kResThreads>(tq, red);
   ww = block_sum<kResThreads>(ww, red);
   const double om = ww > 0.0 ? tq / ww : 0.0;
   double rr = 0.0, rzs = 0.0, ft = 0.0, fb = 0.0, pp = 0.0, phi = 0.0;
+  double zs[3] = {0.0, 0.0, 0.0};  // sphere: mode sums of z = M^-1 r
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
     double dt, db, pz;
-    const double rzd = rz_of(i, dt, db, pz);
+    double rzd = rz_of(i, dt, db, pz);
+    double fx = a.f[i], fy = a.f[N + i];
+    double blk_c[6] = {0.0, 0.0, 2.0 * a.k * (dt + db), 0.0, 0.0, 0.0};
+    if (sph) {
+      // the sphere in place of the top plate: dt = 0, its force on all axes
+      const SphereHit h = sphere_hit(a.ind, c, top, a.y[i], a.y[N + i], a.y[2 * N + i]);
+      const double kg2 = a.k * h.g * h.g, kg = 2.0 * a.k * h.g;
+      dt = 0.0;
+      pz = a.k * db * db + kg2 * h.n[2];
+      rzd = (double)a.f[2 * N + i] + pz;
+      fx += kg2 * h.n[0];
+      fy += kg2 * h.n[1];
+      phi += h.g * h.g * h.g;
+      ft += kg2 * -h.n[2];
+      pp += kg2 * h.n[0] * kg2 * h.n[0] + kg2 * h.n[1] * kg2 * h.n[1];
+      // the preconditioner takes the positive part 2 k g n n^T of its Hessian
+      blk_c[0] = kg * h.n[0] * h.n[0];
+      blk_c[1] = kg * h.n[1] * h.n[1];
+      blk_c[2] = 2.0 * a.k * db + kg * h.n[2] * h.n[2];
+      blk_c[3] = kg * h.n[0] * h.n[1];
+      blk_c[4] = kg * h.n[0] * h.n[2];
+      blk_c[5] = kg * h.n[1] * h.n[2];
+    }
     phi += dt * dt * dt + db * db * db;
     const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
-    const float rx = (float)((double)a.f[i] - mx + om * dy);
-    const float ry = (float)((double)a.f[N + i] - my - om * dx);
+    const float rx = (float)(fx - mx + om * dy);
+    const float ry = (float)(fy - my - om * dx);
     const float rz = (float)rzd;
     pp += pz * pz;
     // preconditioned start direction p = z = M^-1 r, M = stiffness block +
     // penalty Hessian (2 k (max(0, z - top) + max(0, bottom - z)) on zz)
     float zx = rx, zy = ry, zz = rz;
     if (a.kel) {
-      const double blk[6] = {a.kel[i], a.kel[N + i],
-                             a.kel[2 * N + i] + 2.0 * a.k * (dt + db),
-                             a.kel[3 * N + i], a.kel[4 * N + i], a.kel[5 * N + i]};
+      double blk[6] = {a.kel[i], a.kel[N + i], a.kel[2 * N + i] + blk_c[2],
+                       a.kel[3 * N + i], a.kel[4 * N + i], a.kel[5 * N + i]};
+      if (sph) {
+        blk[0] += blk_c[0];
+        blk[1] += blk_c[1];
+        blk[3] += blk_c[3];
+        blk[4] += blk_c[4];
+        blk[5] += blk_c[5];
+      }
       float o[6];
       sym3_inverse(blk, o);
 #pragma unroll
@@ -214,11 +319,32 @@ __global__ __launch_bounds__(kResThreads) void qs_residual_kernel(ResArgs a) {
     a.r[i] = rx; a.r[N + i] = ry; a.r[2 * N + i] = rz;
     a.p[i] = zx; a.p[N + i] = zy; a.p[2 * N + i] = zz;
     rzs += (double)rx * zx + (double)ry * zy + (double)rz * zz;
+    if (sph) {
+      zs[0] += zx;
+      zs[1] += zy;
+      zs[2] += dx * zy - dy * zx;
+    }
     a.x[i] = 0.f; a.x[N + i] = 0.f; a.x[2 * N + i] = 0.f;
     if (a.rn) { a.rn[i] = rx; a.rn[N + i] = ry; a.rn[2 * N + i] = rz; }
     rr += (double)rx * rx + (double)ry * ry + (double)rz * rz;
     ft += a.k * dt * dt;
     fb += a.k * db * db;
+  }
+  if (sph) {
+    // p = z projected like r (the CG then stays in the complement of the
+    // modes); r . z is unchanged by it since r lies in that complement
+    block_sums<3, kResThreads>(zs, red);
+    const ModeFit m = mode_fit(zs[0], zs[1], zs[2], inv_n, ww);
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kResThreads) {
+      const double dx = a.y[i] - cx, dy = a.y[N + i] - cy;
+      a.p[i] = (float)((double)a.p[i] - m.tx + m.om * dy);
+      a.p[N + i] = (float)((double)a.p[N + i] - m.ty - m.om * dx);
+    }
+    if (threadIdx.x == 0) {
+      a.ind.geo[3 * c] = cx;
+      a.ind.geo[3 * c + 1] = cy;
+      a.ind.geo[3 * c + 2] = ww;
+    }
   }
   rr = block_sum<kResThreads>(rr, red);
   rzs = block_sum<kResThreads>(rzs, red);
@@ -350,6 +476,7 @@ struct CgArgs {
   const int32_t* shared_slots;
   const int32_t* cell_shared_off;
   const int32_t* cell_shared_first;  // first shared node of every cell
+  Indenter ind;
 };
 
 // The shared nodes of a cell are the contiguous ids [sh0, sh0 + ns) (owned
@@ -416,15 +543,16 @@ __device__ __forceinline__ void cg_finish(const CgArgs& a, double* s, double rn,
 // slot order as the finalize does.  Same operations in the same order as
 // the streaming version (which fused multiply-adds the compiler forms may
 // differ between the two, a last-bit difference).
-template <int R>
-__device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
+template <int R, bool SPH>
+__device__ void cg_step_regs(const CgArgs& a, double* s, int c, int64_t n0, int64_t n1,
                              double top, double bot, double* red, const ShrRange& sr) {
   constexpr int kRegNodes = R;
   constexpr int kFastSlots = R <= 2 ? 4 : 2;
   const int64_t N = a.N;
   float p[kRegNodes][3], r[kRegNodes][3], ap[kRegNodes][3], x[kRegNodes][3];
   float m[kRegNodes][6], b[kRegNodes][3];
-  double h[kRegNodes];
+  double h[kRegNodes];        // plates: penalty Hessian on zz
+  float yv[kRegNodes][3];     // sphere: positions
   int q0[kRegNodes], nq[kRegNodes];
 #pragma unroll
   for (int u = 0; u < kRegNodes; ++u) {
@@ -442,8 +570,13 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
 #pragma unroll
         for (int q = 0; q < 6; ++q) m[u][q] = a.minv[q * N + i];
       }
-      const double z = a.y[2 * N + i];
-      h[u] = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+      if constexpr (SPH) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) yv[u][d] = a.y[d * N + i];
+      } else {
+        const double z = a.y[2 * N + i];
+        h[u] = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+      }
       if (i >= sr.sh0 && i < sr.sh1) {
         const int sn = sr.s0 + (int)(i - sr.sh0);
         q0[u] = a.shared_slot_ptr[sn];
@@ -480,31 +613,66 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
       b[u][2] += pp[2];
     }
   }
-  double pap = 0.0;
+  // sphere: centroid and sum (dx^2 + dy^2) of the Newton step's positions
+  double gcx = 0.0, gcy = 0.0, gww = 0.0;
+  if constexpr (SPH) {
+    gcx = a.ind.geo[3 * c];
+    gcy = a.ind.geo[3 * c + 1];
+    gww = a.ind.geo[3 * c + 2];
+  }
+  const double inv_n = 1.0 / (double)(n1 - n0);
+  double pap = 0.0, sa[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int u = 0; u < kRegNodes; ++u) {
     const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
     if (i < n1) {
-      ap[u][0] = -b[u][0];
-      ap[u][1] = -b[u][1];
-      ap[u][2] = (float)(-(double)b[u][2] + h[u] * (double)p[u][2]);
+      if constexpr (SPH) {
+        const SphereHit hh = sphere_hit(a.ind, c, top, yv[u][0], yv[u][1], yv[u][2]);
+        double hp[3];
+        sphere_hess(hh, a.k, p[u][0], p[u][1], p[u][2], hp);
+        hp[2] += 2.0 * a.k * fmax(bot - (double)yv[u][2], 0.0) * (double)p[u][2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ap[u][d] = (float)(-(double)b[u][d] + hp[d]);
+        const double dx = yv[u][0] - gcx, dy = yv[u][1] - gcy;
+        sa[0] += ap[u][0];
+        sa[1] += ap[u][1];
+        sa[2] += dx * ap[u][1] - dy * ap[u][0];
+      } else {
+        ap[u][0] = -b[u][0];
+        ap[u][1] = -b[u][1];
+        ap[u][2] = (float)(-(double)b[u][2] + h[u] * (double)p[u][2]);
+      }
       pap += (double)p[u][0] * ap[u][0] + (double)p[u][1] * ap[u][1] +
              (double)p[u][2] * ap[u][2];
     }
   }
-  pap = block_sum(pap, red);
+  ModeFit ma{0.0, 0.0, 0.0};
+  if constexpr (SPH) {
+    double v[4] = {pap, sa[0], sa[1], sa[2]};
+    block_sums(v, red);
+    pap = v[0];
+    ma = mode_fit(v[1], v[2], v[3], inv_n, gww);
+  } else {
+    pap = block_sum(pap, red);
+  }
   const double rs = s[0];
   if (!(pap > 0.0)) {
     if (threadIdx.x == 0) s[2] = 0.0;
     return;
   }
   const float alpha = (float)(rs / pap);
-  double rn = 0.0, rzn = 0.0;
+  double rn = 0.0, rzn = 0.0, sz[3] = {0.0, 0.0, 0.0};
   float zv[kRegNodes][3];
 #pragma unroll
   for (int u = 0; u < kRegNodes; ++u) {
     const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
     if (i < n1) {
+      if constexpr (SPH) {
+        // Ap projected: the held centroid and the symmetry take its mode part
+        const double dx = yv[u][0] - gcx, dy = yv[u][1] - gcy;
+        ap[u][0] = (float)((double)ap[u][0] - ma.tx + ma.om * dy);
+        ap[u][1] = (float)((double)ap[u][1] - ma.ty - ma.om * dx);
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int64_t q = d * N + i;
@@ -519,17 +687,37 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
       if (a.minv) sym3_mul(m[u], r[u][0], r[u][1], r[u][2], zv[u][0], zv[u][1], zv[u][2]);
       rzn += (double)r[u][0] * zv[u][0] + (double)r[u][1] * zv[u][1] +
              (double)r[u][2] * zv[u][2];
+      if constexpr (SPH) {
+        const double dx = yv[u][0] - gcx, dy = yv[u][1] - gcy;
+        sz[0] += zv[u][0];
+        sz[1] += zv[u][1];
+        sz[2] += dx * zv[u][1] - dy * zv[u][0];
+      }
     }
   }
-  double sums[2] = {rn, rzn};
-  block_sums(sums, red);
-  rn = sums[0];
-  rzn = sums[1];
+  ModeFit mz{0.0, 0.0, 0.0};
+  if constexpr (SPH) {
+    double v[5] = {rn, rzn, sz[0], sz[1], sz[2]};
+    block_sums(v, red);
+    rn = v[0];
+    rzn = v[1];
+    mz = mode_fit(v[2], v[3], v[4], inv_n, gww);
+  } else {
+    double sums[2] = {rn, rzn};
+    block_sums(sums, red);
+    rn = sums[0];
+    rzn = sums[1];
+  }
   const float beta = (float)(rzn / rs);
 #pragma unroll
   for (int u = 0; u < kRegNodes; ++u) {
     const int64_t i = n0 + threadIdx.x + (int64_t)u * kThreads;
     if (i < n1) {
+      if constexpr (SPH) {
+        const double dx = yv[u][0] - gcx, dy = yv[u][1] - gcy;
+        zv[u][0] = (float)((double)zv[u][0] - mz.tx + mz.om * dy);
+        zv[u][1] = (float)((double)zv[u][1] - mz.ty - mz.om * dx);
+      }
 #pragma unroll
       for (int d = 0; d < 3; ++d) a.p[d * N + i] = zv[u][d] + beta * p[u][d];
     }
@@ -543,7 +731,13 @@ __device__ void cg_step_regs(const CgArgs& a, double* s, int64_t n0, int64_t n1,
 // at |r| <= max(rel_tol, eta) |r_0| (eta the forcing term of the Newton
 // step, 0 without forcing) or on non-positive curvature.  Cells of up to
 // kRegNodes * kThreads nodes keep their operands in registers; larger ones
-// stream them three times (Ap through memory).
+// stream them three times (Ap through memory).  SPH (the sphere indenter):
+// the contact Hessian is a 3x3 block per node, and Ap and z are projected
+// onto the complement of the lateral translations and the rotation about
+// the vertical axis (the residual and the first direction are projected by
+// the residual kernel), so the iterates stay there: the CG of the system
+// with the centroid held.
+template <bool SPH>
 __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   __shared__ double red[kThreads];
   const int c = blockIdx.x;
@@ -553,55 +747,118 @@ __global__ __launch_bounds__(kThreads) void qs_cg_kernel(CgArgs a) {
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
   const ShrRange sr = shared_range(a, c, n1);
   if (n1 - n0 <= (int64_t)2 * kThreads) {
-    cg_step_regs<2>(a, s, n0, n1, top, bot, red, sr);
+    cg_step_regs<2, SPH>(a, s, c, n0, n1, top, bot, red, sr);
     return;
   }
-  if (n1 - n0 <= (int64_t)kRegNodes * kThreads) {
-    cg_step_regs<kRegNodes>(a, s, n0, n1, top, bot, red, sr);
-    return;
+  if constexpr (!SPH) {
+    // (the sphere's 4-node variant would exceed 128 VGPRs: its cells of more
+    // than 2,048 nodes stream)
+    if (n1 - n0 <= (int64_t)kRegNodes * kThreads) {
+      cg_step_regs<kRegNodes, SPH>(a, s, c, n0, n1, top, bot, red, sr);
+      return;
+    }
   }
-  double pap = 0.0;
+  double gcx = 0.0, gcy = 0.0, gww = 0.0;
+  if constexpr (SPH) {
+    gcx = a.ind.geo[3 * c];
+    gcy = a.ind.geo[3 * c + 1];
+    gww = a.ind.geo[3 * c + 2];
+  }
+  const double inv_n = 1.0 / (double)(n1 - n0);
+  double pap = 0.0, sa[3] = {0.0, 0.0, 0.0};
 
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
-    const double z = a.y[2 * N + i];
-    const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
     float bx, by, bz;
     ybar_of(a, sr, i, bx, by, bz);
-    const float ax = -bx, ay = -by;
-    const float az = (float)(-(double)bz + h * (double)a.p[2 * N + i]);
+    float ax, ay, az;
+    if constexpr (SPH) {
+      const double yx = a.y[i], yy = a.y[N + i], yz = a.y[2 * N + i];
+      const SphereHit hh = sphere_hit(a.ind, c, top, yx, yy, yz);
+      double hp[3];
+      sphere_hess(hh, a.k, a.p[i], a.p[N + i], a.p[2 * N + i], hp);
+      hp[2] += 2.0 * a.k * fmax(bot - yz, 0.0) * (double)a.p[2 * N + i];
+      ax = (float)(-(double)bx + hp[0]);
+      ay = (float)(-(double)by + hp[1]);
+      az = (float)(-(double)bz + hp[2]);
+      const double dx = yx - gcx, dy = yy - gcy;
+      sa[0] += ax;
+      sa[1] += ay;
+      sa[2] += dx * ay - dy * ax;
+    } else {
+      const double z = a.y[2 * N + i];
+      const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+      ax = -bx;
+      ay = -by;
+      az = (float)(-(double)bz + h * (double)a.p[2 * N + i]);
+    }
     a.Ap[i] = ax; a.Ap[N + i] = ay; a.Ap[2 * N + i] = az;
     pap += (double)a.p[i] * ax + (double)a.p[N + i] * ay + (double)a.p[2 * N + i] * az;
   }
-  pap = block_sum(pap, red);
+  ModeFit ma{0.0, 0.0, 0.0};
+  if constexpr (SPH) {
+    double v[4] = {pap, sa[0], sa[1], sa[2]};
+    block_sums(v, red);
+    pap = v[0];
+    ma = mode_fit(v[1], v[2], v[3], inv_n, gww);
+  } else {
+    pap = block_sum(pap, red);
+  }
   const double rs = s[0];
   if (!(pap > 0.0)) {
     if (threadIdx.x == 0) s[2] = 0.0;
     return;
   }
   const float alpha = (float)(rs / pap);
-  double rn = 0.0, rzn = 0.0;
+  double rn = 0.0, rzn = 0.0, sz[3] = {0.0, 0.0, 0.0};
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+    float apv[3] = {a.Ap[i], a.Ap[N + i], a.Ap[2 * N + i]};
+    double dx = 0.0, dy = 0.0;
+    if constexpr (SPH) {
+      dx = a.y[i] - gcx;
+      dy = a.y[N + i] - gcy;
+      apv[0] = (float)((double)apv[0] - ma.tx + ma.om * dy);
+      apv[1] = (float)((double)apv[1] - ma.ty - ma.om * dx);
+    }
     float rq[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int64_t q = d * N + i;
       a.x[q] += alpha * a.p[q];
-      rq[d] = a.r[q] - alpha * a.Ap[q];
+      rq[d] = a.r[q] - alpha * apv[d];
       a.r[q] = rq[d];
       rn += (double)rq[d] * rq[d];
     }
     float z[3] = {rq[0], rq[1], rq[2]};
     if (a.minv) apply_minv(a.minv, N, i, rq[0], rq[1], rq[2], z[0], z[1], z[2]);
     rzn += (double)rq[0] * z[0] + (double)rq[1] * z[1] + (double)rq[2] * z[2];
+    if constexpr (SPH) {
+      sz[0] += z[0];
+      sz[1] += z[1];
+      sz[2] += dx * z[1] - dy * z[0];
+    }
   }
-  double sums[2] = {rn, rzn};
-  block_sums(sums, red);
-  rn = sums[0];
-  rzn = sums[1];
+  ModeFit mz{0.0, 0.0, 0.0};
+  if constexpr (SPH) {
+    double v[5] = {rn, rzn, sz[0], sz[1], sz[2]};
+    block_sums(v, red);
+    rn = v[0];
+    rzn = v[1];
+    mz = mode_fit(v[2], v[3], v[4], inv_n, gww);
+  } else {
+    double sums[2] = {rn, rzn};
+    block_sums(sums, red);
+    rn = sums[0];
+    rzn = sums[1];
+  }
   const float beta = (float)(rzn / rs);
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     float z[3] = {a.r[i], a.r[N + i], a.r[2 * N + i]};
     if (a.minv) apply_minv(a.minv, N, i, z[0], z[1], z[2], z[0], z[1], z[2]);
+    if constexpr (SPH) {
+      const double dx = a.y[i] - gcx, dy = a.y[N + i] - gcy;
+      z[0] = (float)((double)z[0] - mz.tx + mz.om * dy);
+      z[1] = (float)((double)z[1] - mz.ty - mz.om * dx);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int64_t q = d * N + i;
@@ -631,6 +888,7 @@ struct AdjArgs {
   float *r, *p, *x;
   double* st;
   const float* minv;
+  Indenter ind;
 };
 
 __global__ __launch_bounds__(kThreads) void qs_adjoint_rhs_kernel(AdjArgs a) {
@@ -640,6 +898,67 @@ __global__ __launch_bounds__(kThreads) void qs_adjoint_rhs_kernel(AdjArgs a) {
   const double top = a.plate[2 * c];
   const double w = a.weight ? a.weight[c] : 1.0;
   double rr = 0.0, rz = 0.0;
+  if (a.ind.R > 0.0) {  // uniform over the workgroup
+    // sphere: F = k sum g^2 m with m = (c_z - z) / d = -n_z, so
+    // dF/dy = -k (2 g m n + (g^2 / d)(e_z + m n)); r = w P dF/dy and p = P M^-1 r
+    // with P the projection of the held centroid and the rotation symmetry
+    // (centroid and sum (dx^2 + dy^2) of the last residual's positions)
+    const double gcx = a.ind.geo[3 * c], gcy = a.ind.geo[3 * c + 1];
+    const double gww = a.ind.geo[3 * c + 2];
+    const double inv_n = 1.0 / (double)(n1 - n0);
+    double sg[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+      const double yx = a.y[i], yy = a.y[N + i], yz = a.y[2 * N + i];
+      const SphereHit h = sphere_hit(a.ind, c, top, yx, yy, yz);
+      double g[3] = {0.0, 0.0, 0.0};
+      if (h.g > 0.0) {
+        const double m = -h.n[2], q = h.g * h.g / h.d;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] = -w * a.k * (2.0 * h.g * m * h.n[d] + q * m * h.n[d]);
+        g[2] -= w * a.k * q;
+      }
+      const float gx = (float)g[0], gy = (float)g[1];
+      a.r[i] = gx; a.r[N + i] = gy; a.r[2 * N + i] = (float)g[2];
+      const double dx = yx - gcx, dy = yy - gcy;
+      sg[0] += gx;
+      sg[1] += gy;
+      sg[2] += dx * gy - dy * gx;
+    }
+    block_sums(sg, red);
+    const ModeFit mg = mode_fit(sg[0], sg[1], sg[2], inv_n, gww);
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // |r|^2, r . z, mode sums of z
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+      const double dx = a.y[i] - gcx, dy = a.y[N + i] - gcy;
+      const float rx = (float)((double)a.r[i] - mg.tx + mg.om * dy);
+      const float ry = (float)((double)a.r[N + i] - mg.ty - mg.om * dx);
+      const float rzv = a.r[2 * N + i];
+      float zx = rx, zy = ry, zz = rzv;
+      if (a.minv) apply_minv(a.minv, N, i, rx, ry, rzv, zx, zy, zz);
+      a.r[i] = rx; a.r[N + i] = ry;
+      a.p[i] = zx; a.p[N + i] = zy; a.p[2 * N + i] = zz;
+      a.x[i] = 0.f; a.x[N + i] = 0.f; a.x[2 * N + i] = 0.f;
+      v[0] += (double)rx * rx + (double)ry * ry + (double)rzv * rzv;
+      v[1] += (double)rx * zx + (double)ry * zy + (double)rzv * zz;
+      v[2] += zx;
+      v[3] += zy;
+      v[4] += dx * zy - dy * zx;
+    }
+    block_sums(v, red);
+    const ModeFit mz = mode_fit(v[2], v[3], v[4], inv_n, gww);
+    for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
+      const double dx = a.y[i] - gcx, dy = a.y[N + i] - gcy;
+      a.p[i] = (float)((double)a.p[i] - mz.tx + mz.om * dy);
+      a.p[N + i] = (float)((double)a.p[N + i] - mz.ty - mz.om * dx);
+    }
+    if (threadIdx.x == 0) {
+      double* s = a.st + kQsState * c;
+      s[0] = v[1];
+      s[1] = v[0];
+      s[2] = v[0] > 0.0 ? 1.0 : 0.0;
+      s[14] = 0.0;
+    }
+    return;
+  }
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     const double z = a.y[2 * N + i];
     const float g = (float)(w * 2.0 * a.k * fmax(z - top, 0.0));
@@ -692,6 +1011,7 @@ struct FloorArgs {
   const float* e;
   const float* ybar;
   double* st;
+  Indenter ind;
 };
 
 __global__ __launch_bounds__(kThreads) void qs_floor_kernel(FloorArgs a) {
@@ -700,11 +1020,22 @@ __global__ __launch_bounds__(kThreads) void qs_floor_kernel(FloorArgs a) {
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
   double acc = 0.0;
+  const bool sph = a.ind.R > 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     const double z = a.y[2 * N + i];
-    const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
-    const double hx = -(double)a.ybar[i], hy = -(double)a.ybar[N + i];
-    const double hz = -(double)a.ybar[2 * N + i] + h * (double)a.e[2 * N + i];
+    double hx = -(double)a.ybar[i], hy = -(double)a.ybar[N + i], hz;
+    if (sph) {
+      const SphereHit hh = sphere_hit(a.ind, c, top, a.y[i], a.y[N + i], z);
+      double he[3];
+      sphere_hess(hh, a.k, a.e[i], a.e[N + i], a.e[2 * N + i], he);
+      hx += he[0];
+      hy += he[1];
+      hz = -(double)a.ybar[2 * N + i] + he[2] +
+           2.0 * a.k * fmax(bot - z, 0.0) * (double)a.e[2 * N + i];
+    } else {
+      const double h = 2.0 * a.k * (fmax(z - top, 0.0) + fmax(bot - z, 0.0));
+      hz = -(double)a.ybar[2 * N + i] + h * (double)a.e[2 * N + i];
+    }
     acc += hx * hx + hy * hy + hz * hz;
   }
   acc = block_sum(acc, red);
@@ -758,6 +1089,7 @@ struct LsArgs {
   double* st;
   const int32_t* ninv_t;   // inverted tetrahedra at y_t (nullable)
   int32_t* ninv;           // inverted tetrahedra at y (nullable)
+  Indenter ind;
 };
 
 // Start of the line search on Pi along the Newton step x: x loses its
@@ -849,9 +1181,12 @@ __global__ __launch_bounds__(kThreads) void qs_ls_accept_kernel(LsArgs a) {
   const int64_t n0 = a.node_off[c], n1 = a.node_off[c + 1], N = a.N;
   const double top = a.plate[2 * c], bot = a.plate[2 * c + 1];
   double phi = 0.0;
+  const bool sph = a.ind.R > 0.0;
   for (int64_t i = n0 + threadIdx.x; i < n1; i += kThreads) {
     const double z = a.yt[2 * N + i];
-    const double dt = fmax(z - top, 0.0), db = fmax(bot - z, 0.0);
+    double dt = fmax(z - top, 0.0);
+    const double db = fmax(bot - z, 0.0);
+    if (sph) dt = sphere_hit(a.ind, c, top, a.yt[i], a.yt[N + i], z).g;
     phi += dt * dt * dt + db * db * db;
   }
   phi = block_sum(phi, red) * (a.k / 3.0);
@@ -931,9 +1266,10 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
                               double rel_tol, double step_tol, double floor_factor,
                               double eta_max, int restart, float* r, float* p,
                               float* x, float* rn, double* st, double* force,
-                              const float* kel, float* minv, hipStream_t s) {
+                              const float* kel, float* minv, hipStream_t s,
+                              const Indenter& ind) {
   ResArgs a{node_off, N, y, f, energy, plate, k, abs_tol, rel_tol, step_tol,
-            floor_factor, eta_max, restart, r, p, x, rn, st, force, kel, minv};
+            floor_factor, eta_max, restart, r, p, x, rn, st, force, kel, minv, ind};
   hipLaunchKernelGGL(qs_residual_kernel, dim3(n_cells), dim3(kResThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -941,8 +1277,9 @@ hipError_t launch_qs_residual(const int64_t* node_off, int64_t N, int32_t n_cell
 hipError_t launch_qs_adjoint_rhs(const int64_t* node_off, int64_t N, int32_t n_cells,
                                  const float* y, const double* plate, double k,
                                  const double* weight, float* r, float* p, float* x,
-                                 double* st, const float* minv, hipStream_t s) {
-  AdjArgs a{node_off, N, y, plate, k, weight, r, p, x, st, minv};
+                                 double* st, const float* minv, hipStream_t s,
+                                 const Indenter& ind) {
+  AdjArgs a{node_off, N, y, plate, k, weight, r, p, x, st, minv, ind};
   hipLaunchKernelGGL(qs_adjoint_rhs_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -951,14 +1288,17 @@ hipError_t launch_qs_cg(const int64_t* node_off, int64_t N, int32_t n_cells,
                         const float* y, const double* plate, double k,
                         double rel_tol, const float* ybar, float* x, float* r,
                         float* p, float* Ap, double* st, const float* minv,
-                        hipStream_t s, const DeviceTables* slots) {
+                        hipStream_t s, const DeviceTables* slots, const Indenter& ind) {
   CgArgs a{node_off, N, y, plate, k, rel_tol, ybar, x, r, p, Ap, st, minv,
            slots ? slots->part : nullptr,
            slots ? slots->shared_slot_ptr : nullptr,
            slots ? slots->shared_slots : nullptr,
            slots ? slots->cell_shared_off : nullptr,
-           slots ? slots->cell_shared_first : nullptr};
-  hipLaunchKernelGGL(qs_cg_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
+           slots ? slots->cell_shared_first : nullptr, ind};
+  if (ind.R > 0.0)
+    hipLaunchKernelGGL(qs_cg_kernel<true>, dim3(n_cells), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(qs_cg_kernel<false>, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -996,8 +1336,8 @@ hipError_t launch_qs_noise(const int64_t* node_off, int64_t N, int32_t n_cells,
 hipError_t launch_qs_floor(const int64_t* node_off, int64_t N, int32_t n_cells,
                            const float* y, const double* plate, double k,
                            const float* e, const float* ybar, double* st,
-                           hipStream_t s) {
-  FloorArgs a{node_off, N, y, plate, k, e, ybar, st};
+                           hipStream_t s, const Indenter& ind) {
+  FloorArgs a{node_off, N, y, plate, k, e, ybar, st, ind};
   hipLaunchKernelGGL(qs_floor_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -1015,10 +1355,11 @@ hipError_t launch_qs_ls_accept(const int64_t* node_off, int64_t N, int32_t n_cel
                                const float* x, const double* plate, double k,
                                const double* energy_t, double armijo,
                                double min_move, float* y, float* yt, double* st,
-                               const int32_t* ninv_t, int32_t* ninv, hipStream_t s) {
+                               const int32_t* ninv_t, int32_t* ninv, hipStream_t s,
+                               const Indenter& ind) {
   // the accept kernel only reads x
   LsArgs a{node_off, N, const_cast<float*>(x), nullptr, plate, energy_t, k, 0.0, armijo,
-           min_move, y, yt, st, ninv_t, ninv};
+           min_move, y, yt, st, ninv_t, ninv, ind};
   hipLaunchKernelGGL(qs_ls_accept_kernel, dim3(n_cells), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -1,5 +1,6 @@
-"""Quasi-static plate compression of a batch of cells (force-indentation
-curves): each plate position is brought to equilibrium by Newton steps whose
+"""Quasi-static plate compression or sphere indentation of a batch of cells
+(force-indentation curves): each plate or indenter position is brought to
+equilibrium by Newton steps whose
 systems are solved per cell by conjugate gradients on the device (cm_qs_*;
 Hessian-vector products from cm_forces_backward), each step globalised by a
 backtracking (Armijo) line search on the total potential and solved only as
@@ -29,13 +30,18 @@ class QuasiStaticCompression:
     reads the CG convergence check of a block of iterations only after the
     next block is queued (same iterates; False: it waits after every block);
     cap: largest node move per Newton step; armijo: sufficient decrease of
-    the line search, which gives up below min_move."""
+    the line search, which gives up below min_move; sphere_radius > 0: a
+    sphere of that radius indents the cells instead of the top plate (its
+    lowest point at the "top" height, its axis at sphere_axis (n_cells, 2),
+    by default each cell's centroid at the first equilibrium; the centroids
+    are held laterally, see cm_qs_set_indenter)."""
 
     def __init__(self, batch, k_plate, rel_tol=1e-3, abs_tol=1e-9,
                  step_tol=1e-6, floor_factor=2.0, cg_tol=1e-3, max_newton=40,
                  max_cg=400, cap=0.05, armijo=1e-4, min_move=1e-7,
                  max_backtrack=12, eta_max=0.5, precondition=True,
-                 fused_cg=True, pipelined_checks=True):
+                 fused_cg=True, pipelined_checks=True, sphere_radius=0.0,
+                 sphere_axis=None):
         import torch
         self.cb = batch
         self.k = float(k_plate)
@@ -51,6 +57,9 @@ class QuasiStaticCompression:
         # route (cm_forces_backward_cells + cm_qs_cg_step); bitwise equal
         self.fused_cg = bool(fused_cg)
         self.pipelined_checks = bool(pipelined_checks)
+        self.sphere_radius = float(sphere_radius)
+        self._sphere_axis = None if sphere_axis is None else torch.as_tensor(
+            np.asarray(sphere_axis, dtype=np.float64).reshape(batch.n_cells, 2)).to(batch.device)
         if self.precondition:
             self._kel = torch.empty(6 * batch.n_nodes, dtype=torch.float32,
                                     device=batch.device)
@@ -82,6 +91,30 @@ class QuasiStaticCompression:
                                  device=dev)
         self.stats = {"newton": 0, "cg": 0, "trials": 0}
         self._flags, self._flag_i = None, 0  # pinned flags of _active_async
+
+    def cell_centroids(self, y):
+        """(n_cells, 2) float64 device tensor: every cell's mean x and y."""
+        import torch
+        cb = self.cb
+        N = cb.n_nodes
+        counts = torch.from_numpy(np.diff(cb.node_off)).to(cb.device)
+        cell = torch.repeat_interleave(torch.arange(cb.n_cells, device=cb.device), counts)
+        out = torch.zeros(cb.n_cells, 2, dtype=torch.float64, device=cb.device)
+        out[:, 0].index_add_(0, cell, y[:N].double())
+        out[:, 1].index_add_(0, cell, y[N:2 * N].double())
+        return out / counts[:, None].double()
+
+    def _set_contact(self, y):
+        """Puts this solver's top contact on the handle, which holds one
+        (plates, or the sphere with its axes)."""
+        cb = self.cb
+        if self.sphere_radius > 0.0:
+            if self._sphere_axis is None:
+                self._sphere_axis = self.cell_centroids(y).contiguous()
+            nat.check(nat.lib().cm_qs_set_indenter(
+                cb._h, self.sphere_radius, _ptr(self._sphere_axis), _stream(None)))
+        else:
+            nat.check(nat.lib().cm_qs_set_indenter(cb._h, 0.0, None, _stream(None)))
 
     def _residual(self, y, plate, restart=False):
         cb = self.cb
@@ -171,6 +204,7 @@ class QuasiStaticCompression:
         """Newton iterations at one plate position (plate: float64 device
         tensor (n_cells, 2) = top, bottom); y (device SoA) is updated in
         place.  Returns True when every cell met the tolerance."""
+        self._set_contact(y)
         cb = self.cb
         if self.precondition:  # for the current parameters
             nat.check(nat.lib().cm_qs_stiffness(cb._h, _ptr(self._kel),
@@ -216,6 +250,7 @@ class QuasiStaticCompression:
         equilibrate() at that position (the preconditioner blocks of its
         last residual are used).  weight: float64 device tensor (n_cells,)
         or None (1).  Returns a float64 device tensor (n_mat, 3)."""
+        self._set_contact(y)
         import torch
         cb = self.cb
         lib, st = nat.lib(), _stream(None)
