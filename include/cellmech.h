@@ -443,7 +443,9 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
  *     x and y, rotation about z through the centroid); active iff |r_N|_2 >
  *     max(abs_tol, rel_tol |penalty|_2, floor_factor rho) and the last step
  *     moved some node by more than step_tol (restart != 0: no last step, at
- *     a new plate position); force (nullable) float64[2 n_cells] = top and
+ *     a new plate position; under the sphere the residual also loses its
+ *     lateral mean, the held centroid's force); force (nullable)
+ *     float64[2 n_cells] = top (the sphere's, under the sphere) and
  *     bottom plate forces k sum max(0, .)^2; energy (nullable) E(y) per cell
  *     from cm_forces, giving Pi(y) in the state.  eta_max in [0, 1): with
  *     eta_max > 0 the Newton step is inexact (Eisenstat and Walker's second
@@ -487,7 +489,9 @@ int cm_plate_backward_step(cm_batch h, const float* y, const float* lam_next,
  *   cm_qs_cg_step: one CG iteration for every active cell, preconditioned
  *     by minv (nullable: plain CG; pass the array cm_qs_residual filled); a
  *     cell stops at |r| <= max(rel_tol, eta) |r_0| or at non-positive
- *     curvature.
+ *     curvature.  Under the sphere the contact Hessian is a 3x3 block per
+ *     node and Hess(Pi) p and the preconditioned direction are projected
+ *     like the residual (see cm_qs_set_indenter).
  *   cm_qs_update: y += s x per cell, s = min(1, cap / m) with m the
  *     largest |component| of x over the cell's nodes; for a cell with m > 0,
  *     state[4] = s and state[6] = m s (its largest coordinate move).
@@ -538,11 +542,16 @@ int cm_qs_stiffness(cm_batch h, float* k_el, hipStream_t stream);
  * |r|^2, active iff |r| > 0, forcing term 0).  The caller then runs the CG
  * loop of a Newton step (cm_forces_backward_cells + cm_qs_cg_step, which
  * stop at cg_tol) and gets lam in x; cm_forces_backward(y, fbar = lam) then
- * gives thetabar = weight dF_top/d(mu, kappa, w) per material slot.  g has
- * z entries only, so it is orthogonal to the symmetry modes of the plates
+ * gives thetabar = weight dF_top/d(mu, kappa, w) per material slot.  Under
+ * the plates g has z entries only, so it is orthogonal to the symmetry modes
  * (translations in x and y, rotation about z) and the singular system is
- * consistent.  Errors: CM_EINVAL for null pointers or a negative or
- * non-finite k_plate.
+ * consistent.  Under the sphere (cm_qs_set_indenter) F_top = k sum g_s^2 m
+ * with g_s the penetration and m = (c_z - y_z) / |y - c|, so g = -k (2 g_s m n
+ * + (g_s^2 / |y - c|)(e_z + m n)) per node; r and p are projected onto the
+ * complement of the lateral translations and the vertical rotation (the
+ * held centroid), as the CG keeps its iterates there; pass the blocks and
+ * positions of the last cm_qs_residual (its centroids are used).  Errors:
+ * CM_EINVAL for null pointers or a negative or non-finite k_plate.
  */
 int cm_qs_adjoint_rhs(cm_batch h, const float* y, const double* plate, double k_plate,
                       const double* weight, float* r, float* p, float* x, double* state,
