@@ -622,3 +622,35 @@ def test_sphere_force_gradient_against_oracle_differences():
             print(f"sphere, cell {c} at {fr[s]:.0%}: adjoint {Jg[s, c]}, differences "
                   f"{fd[s]}, {err:.1e}", flush=True)
             assert err <= 2e-3, (c, s)
+
+
+def test_sphere_indentation_of_a_streamed_cell_against_oracle():
+    """Under the sphere, cells of more than 2,048 nodes take the CG kernel's
+    streaming path (its 2-node register variant covers the smaller ones): a
+    2,409-node cell indented by 10 % and 25 % of its height against the
+    oracle (bar 2e-3), its centroid held and the sphere and plate forces in
+    balance."""
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    x, tets = sphere_mesh(2300, 41)
+    x = ellipsoid(x, np.array((1.1, 1.2, 0.8)))
+    theta = (1.2, 15.0, 0.4)
+    b = batch_from_cells([Cell(x, tets, x.astype(np.float32), theta)])
+    assert b.node_off[1] > 2048
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    tops, bot, _ = _plates(b, [0.1, 0.25])
+    axes = _sphere_axes(b)
+    qs = QuasiStaticCompression(cb, K, sphere_radius=SPHERE_R, sphere_axis=axes)
+    Ft, Fb, ok, y = qs.curve(cb.to_device(b.y), tops, bot)
+    assert ok.all(), qs.stats
+    assert np.abs(qs.cell_centroids(y).cpu().numpy() - axes).max() <= 1e-5
+    m = oracle.OracleMesh(x, tets)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", RuntimeWarning)
+        Fo, _ = oqs.force_curve(m, b.y.astype(np.float64), theta, tops[:, 0], bot[0], K,
+                                sphere=(SPHERE_R, axes[0, 0], axes[0, 1]))
+    err = np.abs(Ft[:, 0] - Fo) / Fo
+    print("streamed sphere cell: device", Ft[:, 0], "oracle", Fo, "err", err, qs.stats, flush=True)
+    assert err.max() <= 2e-3
+    assert (np.abs(Ft[:, 0] - Fb[:, 0]) / Ft[:, 0]).max() <= 2e-3
