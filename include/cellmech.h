@@ -645,11 +645,14 @@ int cm_stream_copy(const float* src, float* dst, int64_t n, hipStream_t stream);
  * tables into caller-owned host arrays (each nullable):
  *   tiles        int32[n_tiles * 8]   (chunk_begin, n_tets, own_begin, n_own,
  *                                      shr_begin, n_shr, cell, n_chunks)
- *   chunks       uint8[n_chunks * 3072] (64 tetrahedra each: uint32 idx[64][2]
- *                                      holding 4 x uint16 local indices in
- *                                      vertex-slot order, 0xffffffff in
- *                                      idx[lane][0] for an empty lane,
- *                                      float B[9][64], float V0[64])
+ *   chunks       uint8[n_chunks * 3072] (64 tetrahedra each, three rows of
+ *                                      64 16-byte records: uint32 a[64][4] =
+ *                                      (v0 | v1 << 16, v2 | v3 << 16 local
+ *                                      indices in vertex-slot order, bits of
+ *                                      float V0, bits of float B[0]), float
+ *                                      b[64][4] = B[1..4], float c[64][4] =
+ *                                      B[5..8] (B row-major); 0xffffffff in
+ *                                      a[lane][0] for an empty lane)
  *   slot_node    int32[n_slots]       shared_node   int32[n_shared]
  *   shared_slot_ptr int32[n_shared+1] shared_slots  int32[n_slots]
  *   cell_tile_off   int32[n_cells+1]  cell_shared_off int32[n_cells+1]

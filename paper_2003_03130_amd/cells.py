@@ -449,13 +449,17 @@ class HostLayout:
                 _ptr(self.mat_tile_count)))
         finally:
             nat.lib().cm_layout_destroy(h)
+        # three rows of 64 16-byte records per chunk: (idx01, idx23, V0, B0),
+        # (B1..B4), (B5..B8)
         ch = raw.reshape(self.n_chunks, 3072)
-        idx = ch[:, :512].view(np.uint32).reshape(self.n_chunks, 64, 2)
+        a = ch[:, :1024].view(np.uint32).reshape(self.n_chunks, 64, 4)
+        idx = a[..., :2]
         self.local_idx = np.stack([idx[..., 0] & 0xFFFF, idx[..., 0] >> 16,
                                    idx[..., 1] & 0xFFFF, idx[..., 1] >> 16],
                                   axis=-1).astype(np.int64)
         self.empty = idx[..., 0] == 0xFFFFFFFF
-        self.B = ch[:, 512:512 + 2304].view(np.float32).reshape(
-            self.n_chunks, 9, 64).transpose(0, 2, 1).reshape(
+        af = a.view(np.float32)
+        rest = ch[:, 1024:].view(np.float32).reshape(self.n_chunks, 2, 64, 4)
+        self.B = np.concatenate([af[..., 3:4], rest[:, 0], rest[:, 1]], axis=-1).reshape(
             self.n_chunks, 64, 3, 3)
-        self.V0 = ch[:, 2816:].view(np.float32).reshape(self.n_chunks, 64)
+        self.V0 = np.ascontiguousarray(af[..., 2])

@@ -35,17 +35,24 @@ struct TileDesc {
 // Marks a chunk lane that holds no tetrahedron.
 constexpr uint32_t kEmptyLane = 0xffffffffu;
 
-// 64 tetrahedra, structure of arrays inside the chunk (3072 bytes): every
-// lane of a wave reads its tetrahedron with fully coalesced loads.
-// Within a chunk the tetrahedra and the order of their vertices are chosen
+// 64 tetrahedra per chunk (3072 bytes).  Within a chunk the tetrahedra and
+// the order of their vertices are chosen
 // so that, for each vertex slot 0..3, the 64 lanes name 64 different tile
 // nodes: the lanes of one wave can then add their contributions to the
 // tile's LDS accumulators slot by slot with plain read-modify-writes and no
 // two lanes of an instruction touch the same node.
+// The 64 tetrahedra of a chunk are stored as three rows of 64 16-byte
+// records, so that each row is one 16-byte load per lane over 1,024
+// contiguous bytes:
+//   a[l] = (v0 | v1 << 16, v2 | v3 << 16, bits of V0, bits of B[0])
+//   b[l] = (B[1], B[2], B[3], B[4]),   c[l] = (B[5], B[6], B[7], B[8])
+// with the 4 x uint16 local vertex indices, the reference volume
+// V0 = |det J| / 6 and B = J^-1 row-major (B[3k + j], k = edge, j = axis).
+// An empty lane has a[l][0] = a[l][1] = kEmptyLane and zeros elsewhere.
 struct TetChunk {
-  uint32_t idx[kChunk][2];  // 4 x uint16 local vertex indices (v0|v1<<16, v2|v3<<16)
-  float B[9][kChunk];       // B = J^-1, row-major B[k][j], k = edge, j = axis
-  float V0[kChunk];         // reference volume |det J| / 6
+  uint32_t a[kChunk][4];
+  float b[kChunk][4];
+  float c[kChunk][4];
 };
 static_assert(sizeof(TetChunk) == 3072, "chunk layout");
 static_assert(sizeof(TileDesc) == 32, "tile layout");

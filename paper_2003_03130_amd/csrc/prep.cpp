@@ -620,16 +620,19 @@ void prepare_cell(int32_t c, int64_t n, int64_t m, const double* X,
     for (size_t q = base; q < out.chunks.size(); ++q) {
       TetChunk& ch = out.chunks[q];
       std::memset(&ch, 0, sizeof(TetChunk));
-      for (int l = 0; l < kChunk; ++l) ch.idx[l][0] = ch.idx[l][1] = kEmptyLane;
+      for (int l = 0; l < kChunk; ++l) ch.a[l][0] = ch.a[l][1] = kEmptyLane;
     }
     for (const Placed& pl : placed) {
       TetChunk& ch = out.chunks[base + pl.chunk];
-      ch.idx[pl.lane][0] = (uint32_t)loc[pl.v[0]] | ((uint32_t)loc[pl.v[1]] << 16);
-      ch.idx[pl.lane][1] = (uint32_t)loc[pl.v[2]] | ((uint32_t)loc[pl.v[3]] << 16);
+      ch.a[pl.lane][0] = (uint32_t)loc[pl.v[0]] | ((uint32_t)loc[pl.v[1]] << 16);
+      ch.a[pl.lane][1] = (uint32_t)loc[pl.v[2]] | ((uint32_t)loc[pl.v[3]] << 16);
       double Bt[9];
       const double det = reference_inverse(X, pl.v, Bt, nullptr);
-      for (int q = 0; q < 9; ++q) ch.B[q][pl.lane] = (float)Bt[q];
-      ch.V0[pl.lane] = (float)(std::fabs(det) / 6.0);
+      const float v0f = (float)(std::fabs(det) / 6.0), b0f = (float)Bt[0];
+      std::memcpy(&ch.a[pl.lane][2], &v0f, sizeof(float));
+      std::memcpy(&ch.a[pl.lane][3], &b0f, sizeof(float));
+      for (int q = 1; q < 5; ++q) ch.b[pl.lane][q - 1] = (float)Bt[q];
+      for (int q = 5; q < 9; ++q) ch.c[pl.lane][q - 5] = (float)Bt[q];
       if (det < 0) out.chunk_neg[base + pl.chunk] |= 1ull << pl.lane;
     }
   }

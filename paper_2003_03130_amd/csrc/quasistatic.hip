@@ -412,7 +412,9 @@ __global__ __launch_bounds__(64) void qs_stiffness_kernel(StiffArgs a) {
   wave_sync();
   const TetChunk* ch = a.T.chunks + d.chunk_begin;
   for (int k = 0; k < d.n_chunks; ++k) {
-    const uint2 q = *reinterpret_cast<const uint2*>(ch[k].idx[lane]);
+    TetRegs tr;
+    load_tet(ch + k, lane, tr);
+    const uint2 q = tr.q;
     if (q.x != kEmptyLane) {
       const int idx[4] = {(int)(q.x & 0xffff), (int)(q.x >> 16), (int)(q.y & 0xffff),
                           (int)(q.y >> 16)};
@@ -420,10 +422,10 @@ __global__ __launch_bounds__(64) void qs_stiffness_kernel(StiffArgs a) {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) b[r][j] = ch[k].B[3 * r + j][lane];
+        for (int j = 0; j < 3; ++j) b[r][j] = tr.B[3 * r + j];
 #pragma unroll
       for (int j = 0; j < 3; ++j) b[3][j] = -(b[0][j] + b[1][j] + b[2][j]);
-      const float v0 = ch[k].V0[lane];
+      const float v0 = tr.V0;
       // vertex slots in order: the lanes of one slot name distinct nodes
 #pragma unroll
       for (int s = 0; s < 4; ++s) {

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64) void shape_moments_kernel(MomArgs a) {
   int ninv = 0;
   const TetChunk* ch = a.T.chunks + d.chunk_begin;
   for (int k = 0; k < d.n_chunks; ++k) {
-    const uint2 q = *reinterpret_cast<const uint2*>(ch[k].idx[lane]);
+    const uint2 q = make_uint2(ch[k].a[lane][0], ch[k].a[lane][1]);
     const uint64_t neg = a.chunk_neg[d.chunk_begin + k];  // wave-uniform
     if (q.x == kEmptyLane) continue;
     const float4 p[4] = {ys[q.x & 0xffff], ys[q.x >> 16], ys[q.y & 0xffff],
