@@ -68,6 +68,9 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
       gw = plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, d.cell);
     }
 
+    // the first chunk's loads go out before the node gather
+    TetRegs first{};
+    if (d.n_chunks > 0) load_tet(a.T.chunks + d.chunk_begin, lane, first);
     for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
       const int64_t g = l < d.n_own ? (int64_t)d.own_begin + l
                                     : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(64 * W) void backward_kernel(BwdArgs a) {
     // per lane: sum V0 gp and sum V0 ge (the tile's parameter gradient is
     // -sum V0 gp + ebar/2 sum V0 ge)
     double acc[3] = {0.0, 0.0, 0.0}, acce[3] = {0.0, 0.0, 0.0};
-    for_each_chunk(a.T.chunks + d.chunk_begin, d.n_chunks, lane,
+    for_each_chunk_from(a.T.chunks + d.chunk_begin, d.n_chunks, lane, first,
                    [&](const TetRegs& cur) {
       const uint2 q = cur.q;
       if (q.x != kEmptyLane) {

@@ -70,12 +70,14 @@ __device__ __forceinline__ void lds_accumulate(Acc acc, int i0, int i1, int i2,
 // reached with one fixed set of outstanding loads (one chunk in flight, or
 // none at the last chunk), so the compiler waits only for the chunk that
 // body reads.
+// As for_each_chunk, with the first chunk's registers ra loaded by the
+// caller (before the tile's nodes are staged, so that its loads are in
+// flight meanwhile).
 template <class Body>
-__device__ __forceinline__ void for_each_chunk(const TetChunk* ch, int n,
-                                               int lane, Body body) {
+__device__ __forceinline__ void for_each_chunk_from(const TetChunk* ch, int n,
+                                                    int lane, TetRegs ra, Body body) {
   if (n <= 0) return;
-  TetRegs ra, rb;
-  load_tet(ch, lane, ra);
+  TetRegs rb;
   for (int k = 0;; k += 2) {
     if (k + 1 >= n) {
       body(ra);
@@ -90,6 +92,15 @@ __device__ __forceinline__ void for_each_chunk(const TetChunk* ch, int n,
     load_tet(ch + k + 2, lane, ra);
     body(rb);
   }
+}
+
+template <class Body>
+__device__ __forceinline__ void for_each_chunk(const TetChunk* ch, int n,
+                                               int lane, Body body) {
+  if (n <= 0) return;
+  TetRegs ra;
+  load_tet(ch, lane, ra);
+  for_each_chunk_from(ch, n, lane, ra, body);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -59,6 +59,9 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
       bot = (float)a.pl.plate[2 * d.cell + 1];
     }
 
+    // the first chunk's loads go out before the node gather
+    TetRegs first{};
+    if (d.n_chunks > 0) load_tet(a.T.chunks + d.chunk_begin, lane, first);
     for (int l = lane; l < d.n_own + d.n_shr; l += 64) {
       int64_t g;
       float flag = 0.f;
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
 
     double eacc = 0.0;
     int ninv = 0, nonfin = 0;
-    for_each_chunk(a.T.chunks + d.chunk_begin, d.n_chunks, lane,
+    for_each_chunk_from(a.T.chunks + d.chunk_begin, d.n_chunks, lane, first,
                    [&](const TetRegs& cur) {
       const uint2 q = cur.q;
       if (q.x != kEmptyLane) {
