@@ -654,3 +654,46 @@ def test_sphere_indentation_of_a_streamed_cell_against_oracle():
     print("streamed sphere cell: device", Ft[:, 0], "oracle", Fo, "err", err, qs.stats, flush=True)
     assert err.max() <= 2e-3
     assert (np.abs(Ft[:, 0] - Fb[:, 0]) / Ft[:, 0]).max() <= 2e-3
+
+
+def test_calibration_by_sphere_indentation():
+    """The paper's AFM comparison fits the model to colloidal-probe curves:
+    force curves of hidden (mu, kappa, w) under the sphere to 40 % of the
+    height from the oracle, then Levenberg-Marquardt from another start with
+    the sphere's adjoint derivatives (equilibria to 1e-5 of the penalty
+    force, which the adjoint needs under the sphere).  The loss falls by
+    orders of magnitude and mu is recovered to 1 %; kappa and w, which
+    shallow sphere indentation constrains less than deep plate compression,
+    to within 10 % and 0.05."""
+    from paper_2003_03130_amd import CellBatch
+    from paper_2003_03130_amd.calibrate import fit_curves
+    from paper_2003_03130_amd.quasistatic import QuasiStaticCompression
+    b = _cells()
+    theta_star = b.theta.copy()
+    theta0 = theta_star * np.array([1.4, 0.6, 1.0])
+    theta0[:, 2] = np.clip(1.0 - theta_star[:, 2] * 0.7, 0.05, 0.95)
+    fr = np.array([0.05, 0.1, 0.2, 0.3, 0.4])
+    tops, bot, _ = _plates(b, fr)
+    axes = _sphere_axes(b)
+    target = np.zeros((len(fr), b.n_cells))
+    for c in range(b.n_cells):
+        cell = b.cell(c)
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            target[:, c], _ = oqs.force_curve(m, cell.y.astype(np.float64), cell.theta,
+                                              tops[:, c], bot[c], K,
+                                              sphere=(SPHERE_R, axes[c, 0], axes[c, 1]))
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(theta0[:, 0], theta0[:, 1], theta0[:, 2])
+    qs = QuasiStaticCompression(cb, K, sphere_radius=SPHERE_R, sphere_axis=axes, rel_tol=1e-5)
+    res = fit_curves(qs, cb.to_device(b.y), tops, bot, target, theta0, iters=8, log=print)
+    losses = np.array([h["loss"] for h in res["history"]])
+    print("sphere calibration, loss per iteration:", losses.sum(axis=1), flush=True)
+    assert np.all(np.diff(losses, axis=0) <= 0)
+    assert np.all(losses[-1] <= 1e-3 * losses[0])
+    rel = np.abs(res["theta"] - theta_star) / np.abs(theta_star)
+    print("fitted:", res["theta"], "hidden:", theta_star, "rel. error:", rel, flush=True)
+    assert np.all(rel[:, 0] <= 1e-2)
+    assert np.all(rel[:, 1] <= 1e-1)
+    assert np.all(np.abs(res["theta"][:, 2] - theta_star[:, 2]) <= 5e-2)
