@@ -853,7 +853,8 @@ def main():
         tuning = {"tile_candidates": cand,
                   "candidate_ms_fwd_bwd": [round(float(v), 5) for v in cb.candidate_ms],
                   "tile_tets": int(cb.info["tile_tets"]),
-                  "launch": list(cb.get_launch()), "s": round(time.time() - t, 1)}
+                  "launch": list(cb.get_launch()),
+                  "persistent": bool(cb.get_launch()[1] > 0), "s": round(time.time() - t, 1)}
         log(f"tuned creation (tile size and launch) in {time.time() - t:.1f} s: "
             f"{tuning}")
     else:
@@ -1027,6 +1028,9 @@ def main():
                         f"{N} nodes; one step = batched forward + backward",
             "n_cells": b.n_cells, "n_tets": M, "n_nodes": N,
             "tile_tets": cb.info["tile_tets"], "launch": list(launch),
+            # launch = (tiles per workgroup, workgroups per CU); 0 workgroups
+            # per CU is one workgroup per group of tiles (not persistent)
+            "persistent": bool(launch[1] > 0),
             "tile_order": {0: "input", 1: "rcm", 2: "morton", 3: "bisection",
                            None: "bisection"}[args.order],
             "parallelism": "single GPU",
