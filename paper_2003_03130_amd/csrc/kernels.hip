@@ -35,10 +35,12 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nloc = a.T.nloc;
-  // positions and force accumulators as two float4 arrays: 16-byte records
-  // spread random-index LDS accesses over all banks
-  float4* ys = lds + (size_t)wave * 2 * nloc;
-  float4* fs = ys + nloc;
+  // positions as a float4 array (16-byte records spread random-index reads
+  // over all banks), force accumulators as packed float3 (12 bytes): 28
+  // bytes per tile node; the wave's stride of 7 nloc / 4 float4 is exact
+  // because nloc is a multiple of 4
+  float4* ys = lds + (size_t)wave * (7 * nloc / 4);
+  float* fs = reinterpret_cast<float*>(ys + nloc);
   const int64_t N = a.T.n_nodes;
 
   int t0, t1;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
                         : (int64_t)a.T.slot_node[d.shr_begin + l - d.n_own];
       }
       ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], flag);
-      fs[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+      fs[3 * l] = 0.f; fs[3 * l + 1] = 0.f; fs[3 * l + 2] = 0.f;
     }
     wave_sync();
 
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
         double vU;
         bool inv;
         tet_forward(p0, p1, p2, p3, cur.B, cur.V0, mat, h, vU, inv);
-        lds_accumulate([&](int i) { return &fs[i].x; }, i0, i1, i2, i3, h);
+        lds_accumulate([&](int i) { return &fs[3 * i]; }, i0, i1, i2, i3, h);
         eacc += vU;
         ninv += inv ? 1 : 0;
         if (a.check) {
@@ -113,7 +115,8 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
       // force (the flagged nodes)
       double fp = 0.0;
       for (int i = lane; i < d.n_own; i += 64) {
-        const float4 p = ys[i], v = fs[i];
+        const float4 p = ys[i];
+        const float3 v = make_float3(fs[3 * i], fs[3 * i + 1], fs[3 * i + 2]);
         plate_node_step(p.x, p.y, p.z, v.x, v.y, v.z, top, bot, a.pl.k, a.pl.m,
                         a.pl.y_next, N, (int64_t)d.own_begin + i);
         fp += plate_top_term(p.z, top, a.pl.k);
@@ -127,13 +130,14 @@ __global__ __launch_bounds__(64 * W) void forward_kernel(FwdArgs a) {
     } else {
       for (int i = lane; i < d.n_own; i += 64) {
         const int64_t g = d.own_begin + i;
-        const float4 v = fs[i];
+        const float3 v = make_float3(fs[3 * i], fs[3 * i + 1], fs[3 * i + 2]);
         a.f[g] = v.x; a.f[N + g] = v.y; a.f[2 * N + g] = v.z;
       }
     }
     for (int j = lane; j < d.n_shr; j += 64) {
       const int64_t s = d.shr_begin + j;
-      const float4 v = fs[d.n_own + j];
+      const int l3 = 3 * (d.n_own + j);
+      const float3 v = make_float3(fs[l3], fs[l3 + 1], fs[l3 + 2]);
       float* pp = a.T.part + 3 * s;
       pp[0] = v.x; pp[1] = v.y; pp[2] = v.z;
     }
@@ -247,13 +251,15 @@ hipError_t fwd_w(const FwdArgs& a, int grid, size_t lds, hipStream_t st) {
 
 }  // namespace
 
-size_t forward_lds_per_wave(int nloc) { return (size_t)32 * nloc; }
+size_t forward_lds_per_wave(int nloc) { return (size_t)28 * nloc; }
 
 hipError_t launch_forward_main(const DeviceTables& T, const Range& r,
                                const LaunchCfg& cfg, const float* y, float* f,
                                hipStream_t st, const PlateFwd& pl, bool check) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
   if (check && !T.tile_nonfin) return hipErrorInvalidValue;
+  // the per-wave LDS stride (7 nloc / 4 float4) needs nloc % 4 == 0
+  if (T.nloc <= 0 || T.nloc % 4 != 0) return hipErrorInvalidValue;
   FwdArgs a{T, r, y, f, pl, check ? 1 : 0};
   const int grid = grid_for(r, cfg);
   const size_t lds = forward_lds_per_wave(T.nloc) * cfg.waves;
