@@ -260,6 +260,28 @@ int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
                        hipStream_t stream);
 
 /*
+ * cm_forces_and_backward: cm_forces and cm_forces_backward in one pass over
+ * the tetrahedra, for a loss L(f, E) whose cotangents fbar and ebar are
+ * known before the forces (a loss linear in f and E, such as
+ * L = sum_i v_i . f_i with fixed v).  Forces by eq. elastic-force-vertex-1
+ * as for cm_forces; ybar and thetabar as for cm_forces_backward.
+ *   y, f, energy, n_inverted : as cm_forces;
+ *   fbar, ebar, ybar, thetabar : as cm_forces_backward.
+ * Every tetrahedron's deformation gradient, invariants and cofactor matrix
+ * are formed once for both results, and each chunk of the mesh is read
+ * once; the per-tetrahedron arithmetic and every summation order are those
+ * of the two separate calls, so all outputs equal theirs bit for bit.
+ * Launch shape: the handle's (cm_set_launch), with waves per workgroup
+ * halved until the pass's LDS (52 B per tile node and wave) fits in 64 KiB.
+ * Nothing is allocated.  Errors: as cm_forces and cm_forces_backward, and
+ * CM_EINVAL if f or ybar alias each other, y or fbar (outputs are written
+ * while other tiles still read the inputs).
+ */
+int cm_forces_and_backward(cm_batch h, const float* y, float* f, double* energy,
+                           int32_t* n_inverted, const float* fbar, const double* ebar,
+                           float* ybar, double* thetabar, hipStream_t stream);
+
+/*
  * cm_forces_backward_cells: cm_forces_backward restricted to the cells c
  * with cell_flags[c * flag_stride] != 0 (for iterative solvers in which
  * cells finish at different times, e.g. the conjugate gradients of
@@ -336,7 +358,8 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
  *   mode 3: the per-cell launches of mode 1;
  *   mode 4, 5: as 1, 3 but with the backward pass as a parallel branch of
  *   the graph (it reads y, fbar and ebar only and has its own scratch), so
- *   the two passes may overlap on the device.
+ *   the two passes may overlap on the device;
+ *   mode 6: forward and backward in one pass (cm_forces_and_backward).
  * Pointers are captured as given and must stay valid while the graph is
  * used.  Re-capturing replaces the previous graph.  cm_graph_launch replays
  * it on `stream` (CM_ESTATE if nothing was captured).
@@ -618,8 +641,11 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
  * forward + backward evaluation, measured with HIP events recorded on
  * `stream` around `reps` back-to-back launches of each kernel:
  *   ms[0] forward tile kernel,  ms[1] forward finalize kernel,
- *   ms[2] backward tile kernel, ms[3] backward finalize kernel.
- * Buffers as in cm_forces / cm_forces_backward (fbar, ebar nullable).
+ *   ms[2] backward tile kernel, ms[3] backward finalize kernel,
+ *   ms[4] tile kernel of cm_forces_and_backward (NaN where that pass does
+ *         not apply: aliased buffers or too little LDS).
+ * Buffers as in cm_forces / cm_forces_backward (fbar, ebar nullable);
+ * ms holds 5 entries.
  * Synchronises the stream; not graph-safe.
  */
 int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,

@@ -76,6 +76,8 @@ SIGNATURES = {
     "cm_forces_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_checked": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cm_forces_and_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp]),
     "cm_forces_percell": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_forces_backward_percell": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cm_batch_create_tuned": (_int, [_i32, _vp, _vp, _vp, _vp,

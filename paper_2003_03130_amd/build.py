@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcellmech.so")
 SOURCES = ["api.cpp", "prep.cpp", "kernels.hip", "backward.hip", "relax.hip",
-           "shape.hip", "quasistatic.hip", "noalloc.hip", "util.hip"]
+           "shape.hip", "quasistatic.hip", "noalloc.hip", "util.hip", "fused.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -289,6 +289,28 @@ class CellBatch:
                      _ptr(thetabar), _stream(stream)))
         return ybar, thetabar
 
+    def forces_and_backward(self, y, fbar=None, ebar=None, f=None, energy=None,
+                            n_inverted=None, ybar=None, thetabar=None,
+                            stream=None):
+        """cm_forces_and_backward: forward and backward in one pass, for
+        cotangents (fbar, ebar) given up front; returns (f, energy, ybar,
+        thetabar), bitwise those of forces() followed by backward()."""
+        import torch
+        if f is None:
+            f = self.empty_nodes()
+        if energy is None:
+            energy = torch.empty(self.n_cells, dtype=torch.float64,
+                                 device=self.device)
+        if ybar is None:
+            ybar = self.empty_nodes()
+        if thetabar is None:
+            thetabar = torch.empty(3 * self.n_mat, dtype=torch.float64,
+                                   device=self.device)
+        nat.check(nat.lib().cm_forces_and_backward(
+            self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(n_inverted),
+            _ptr(fbar), _ptr(ebar), _ptr(ybar), _ptr(thetabar), _stream(stream)))
+        return f, energy, ybar, thetabar
+
     # ------------------------------------------------------------ launch
     def set_launch(self, waves_per_block, blocks_per_cu):
         nat.check(nat.lib().cm_set_launch(self._h, waves_per_block,
@@ -366,8 +388,9 @@ class CellBatch:
     def profile_kernels(self, y, f, energy, fbar, ebar, ybar, thetabar,
                         reps=10, stream=None):
         """Average ms per launch of the forward tile, forward finalize,
-        backward tile and backward finalize kernels (HIP events)."""
-        ms = np.zeros(4, dtype=np.float64)
+        backward tile, backward finalize and fused forward + backward tile
+        kernels (HIP events)."""
+        ms = np.zeros(5, dtype=np.float64)
         nat.check(nat.lib().cm_profile_kernels(
             self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(fbar), _ptr(ebar),
             _ptr(ybar), _ptr(thetabar), int(reps), _ptr(ms), _stream(stream)))

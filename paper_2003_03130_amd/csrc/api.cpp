@@ -60,6 +60,17 @@ bool lds_fits(const cm_batch_s* h, int waves, bool backward) {
   return per * (size_t)waves <= 65536;
 }
 
+// The fused forward + backward pass needs more LDS per wave than either
+// pass: it runs with the handle's launch shape, its waves per workgroup
+// halved until its LDS fits (results do not depend on the launch shape).
+bool fused_cfg(const cm_batch_s* h, cm::LaunchCfg* cfg) {
+  *cfg = h->cfg;
+  while (cfg->waves > 1 &&
+         cm::forward_backward_lds_per_wave(h->T.nloc) * (size_t)cfg->waves > 65536)
+    cfg->waves /= 2;
+  return cm::forward_backward_lds_per_wave(h->T.nloc) * (size_t)cfg->waves <= 65536;
+}
+
 }  // namespace
 
 extern "C" {
@@ -478,6 +489,32 @@ static int backward_impl(cm_batch h, const float* y, const float* fbar,
                                  ybar, thetabar, st));
   }
   return CM_OK;
+}
+
+static int forward_backward_impl(cm_batch h, const float* y, float* f,
+                                 double* energy, int32_t* ninv, const float* fbar,
+                                 const double* ebar, float* ybar, double* thetabar,
+                                 hipStream_t st) {
+  if (int rc = check_handle(h)) return rc;
+  if (!y || !f || !ybar) return fail(CM_EINVAL, "y, f and ybar must be device pointers");
+  // the outputs are written while other tiles still read the inputs
+  if (f == ybar || f == y || ybar == y || (fbar && (f == fbar || ybar == fbar)))
+    return fail(CM_EINVAL, "f and ybar must not alias each other, y or fbar");
+  if (!h->params_set) return fail(CM_ESTATE, "cm_set_params was not called");
+  cm::LaunchCfg cfg;
+  if (!fused_cfg(h, &cfg))
+    return fail(CM_EINVAL, "fused pass: one tile's nodes exceed 64 KiB of LDS");
+  if (int rc = select_device(h)) return rc;
+  CM_HIP(cm::launch_forward_backward(h->T, h->Tb, full_range(h), cfg, y, f, energy, ninv,
+                                     fbar, ebar, ybar, thetabar, st));
+  return CM_OK;
+}
+
+int cm_forces_and_backward(cm_batch h, const float* y, float* f, double* energy,
+                           int32_t* n_inverted, const float* fbar, const double* ebar,
+                           float* ybar, double* thetabar, hipStream_t stream) {
+  return forward_backward_impl(h, y, f, energy, n_inverted, fbar, ebar, ybar, thetabar,
+                               stream);
 }
 
 int cm_forces(cm_batch h, const float* y, float* f, double* energy,
@@ -1181,16 +1218,26 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
     return fail(CM_EINVAL, "launch configuration exceeds 64 KiB of LDS");
   if (int rc = select_device(h)) return rc;
   const cm::Range r = full_range(h);
-  hipEvent_t ev[5];
-  for (int i = 0; i < 5; ++i) CM_HIP(hipEventCreate(&ev[i]));
+  cm::LaunchCfg fcfg;
+  const bool fused = fused_cfg(h, &fcfg) && f != ybar && f != y && ybar != y &&
+                     (!fbar || (f != fbar && ybar != fbar));
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) CM_HIP(hipEventCreate(&ev[i]));
   int rc = CM_OK;
-  for (int k = 0; k < 4 && rc == CM_OK; ++k) {
+  for (int k = 0; k < 5 && rc == CM_OK; ++k) {
+    if (k == 4 && !fused) {
+      ms[k] = NAN;
+      break;
+    }
     auto once = [&]() -> hipError_t {
       switch (k) {
         case 0: return cm::launch_forward_main(h->T, r, h->cfg, y, f, st);
         case 1: return cm::launch_forward_finalize(h->T, r, f, energy, nullptr, st);
         case 2: return cm::launch_backward_main(h->Tb, r, h->cfg, y, fbar, ebar, ybar, st);
-        default: return cm::launch_backward_finalize(h->Tb, r, ybar, thetabar, st);
+        case 3: return cm::launch_backward_finalize(h->Tb, r, ybar, thetabar, st);
+        default:
+          return cm::launch_forward_backward_main(h->T, h->Tb, r, fcfg, y, f, fbar, ebar,
+                                                  ybar, st);
       }
     };
     hipError_t e = once();  // warm-up
@@ -1203,7 +1250,7 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
     if (e != hipSuccess) rc = fail(CM_EHIP, std::string("profile: ") + hipGetErrorString(e));
     ms[k] = (double)t / reps;
   }
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   return rc;
 }
 
@@ -1212,18 +1259,22 @@ int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
                      const double* ebar, float* ybar, double* thetabar,
                      hipStream_t stream) {
   if (int rc = check_handle(h)) return rc;
-  if (mode < 0 || mode > 5) return fail(CM_EINVAL, "mode must be 0..5");
+  if (mode < 0 || mode > 6) return fail(CM_EINVAL, "mode must be 0..6");
   if (!stream) return fail(CM_EINVAL, "capture needs a non-null stream");
   if (int rc = select_device(h)) return rc;
   if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
   if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
   CM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
   const bool percell = mode == 2 || mode == 3 || mode == 5;
-  const bool bwd = mode == 1 || mode == 3 || mode >= 4;
-  const bool fork = mode >= 4;
+  const bool bwd = mode == 1 || mode == 3 || mode == 4 || mode == 5;
+  const bool fork = mode == 4 || mode == 5;
+  const bool fused = mode == 6;
   int rc = CM_OK;
   hipError_t e = hipSuccess;
-  if (fork) {
+  if (fused) {
+    rc = forward_backward_impl(h, y, f, energy, n_inverted, fbar, ebar, ybar, thetabar,
+                               stream);
+  } else if (fork) {
     // The backward pass reads y, fbar, ebar only (never the forward's
     // outputs) and uses its own scratch, so it can be a parallel branch.
     e = hipEventRecord(h->ev_fork, stream);
@@ -1231,7 +1282,7 @@ int cm_graph_capture(cm_batch h, int mode, const float* y, float* f,
     if (e == hipSuccess)
       rc = backward_impl(h, y, fbar, ebar, ybar, thetabar, h->side, percell);
   }
-  if (e == hipSuccess && rc == CM_OK)
+  if (!fused && e == hipSuccess && rc == CM_OK)
     rc = forces_impl(h, y, f, energy, n_inverted, stream, percell);
   if (bwd && !fork && rc == CM_OK)
     rc = backward_impl(h, y, fbar, ebar, ybar, thetabar, stream, percell);

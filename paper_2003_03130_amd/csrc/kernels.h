@@ -106,6 +106,7 @@ struct LaunchCfg {
 // LDS bytes per wave of the forward / backward kernel for nloc tile nodes.
 size_t forward_lds_per_wave(int nloc);
 size_t backward_lds_per_wave(int nloc);
+size_t forward_backward_lds_per_wave(int nloc);
 
 // The two kernels of each pass, separately (for per-kernel timing).
 // With pl.plate set, the forward pass applies one plate-compression step
@@ -154,5 +155,21 @@ hipError_t launch_backward(const DeviceTables& T, const Range& r,
                            double* thetabar, hipStream_t st,
                            const CellMask& mask = CellMask{},
                            const PlateBwd& pl = PlateBwd{});
+
+// Forward and backward in one tile pass (fused.hip): the outputs of
+// launch_forward (f, energy, ninv) and of launch_backward (ybar, thetabar)
+// for cotangents fbar, ebar given up front, bitwise equal to the two
+// separate passes.  T holds the forward's scratch, Tb the backward's (both
+// with the same tiling).  The main kernel alone, for per-kernel timing:
+hipError_t launch_forward_backward_main(const DeviceTables& T, const DeviceTables& Tb,
+                                        const Range& r, const LaunchCfg& cfg,
+                                        const float* y, float* f, const float* fbar,
+                                        const double* ebar, float* ybar, hipStream_t st,
+                                        bool grad = true);
+hipError_t launch_forward_backward(const DeviceTables& T, const DeviceTables& Tb,
+                                   const Range& r, const LaunchCfg& cfg, const float* y,
+                                   float* f, double* energy, int32_t* ninv,
+                                   const float* fbar, const double* ebar, float* ybar,
+                                   double* thetabar, hipStream_t st);
 
 }  // namespace cm

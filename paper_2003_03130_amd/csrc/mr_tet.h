@@ -25,6 +25,11 @@
 // J^-1/3 is the reciprocal of the real (sign-preserving) cube root: a
 // float32 hardware log2/exp2 seed
 // refined by one Newton step in float64.
+// Every helper contracts a * b + c into a fused multiply-add only within
+// one expression, as written (fp contract on): the rounding of each result
+// is then fixed by the source alone, whatever code the helper is inlined
+// into, so the separate passes and the fused forward + backward pass round
+// identically.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -36,6 +41,7 @@ struct Material {
 
 // Real J^-1/3 (negative for J < 0, infinite/NaN for J = 0).
 __device__ __forceinline__ double inv_cbrt(double J) {
+#pragma clang fp contract(on)
   const float jf = (float)J;
   float s = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(fabsf(jf)) * (1.0f / 3.0f));
   s = copysignf(s, jf);
@@ -53,6 +59,7 @@ struct Scalars {
 // C = F^T F rounded to float32 (C00 C11 C22 C01 C02 C12).
 __device__ __forceinline__ void invariants(const double f[3][3], float Cf[6],
                                            Scalars& s) {
+#pragma clang fp contract(on)
   const double C00 = f[0][0] * f[0][0] + f[1][0] * f[1][0] + f[2][0] * f[2][0];
   const double C11 = f[0][1] * f[0][1] + f[1][1] * f[1][1] + f[2][1] * f[2][1];
   const double C22 = f[0][2] * f[0][2] + f[1][2] * f[1][2] + f[2][2] * f[2][2];
@@ -75,6 +82,7 @@ __device__ __forceinline__ void invariants(const double f[3][3], float Cf[6],
 // Cofactor matrix cof F = det(F) F^-T (columns are cross products of the
 // other two columns of F).
 __device__ __forceinline__ void cofactor(const float F[3][3], float K[3][3]) {
+#pragma clang fp contract(on)
   K[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
   K[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
   K[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
@@ -89,6 +97,7 @@ __device__ __forceinline__ void cofactor(const float F[3][3], float K[3][3]) {
 // F C with C symmetric stored as C00 C11 C22 C01 C02 C12.
 __device__ __forceinline__ void times_sym(const float F[3][3], const float C[6],
                                           float R[3][3]) {
+#pragma clang fp contract(on)
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     R[i][0] = F[i][0] * C[0] + F[i][1] * C[3] + F[i][2] * C[4];
@@ -102,6 +111,7 @@ __device__ __forceinline__ void times_sym(const float F[3][3], const float C[6],
 __device__ __forceinline__ void deformation_gradient(
     const float4& p0, const float4& p1, const float4& p2, const float4& p3,
     const float B[9], double F[3][3], float f32[3][3]) {
+#pragma clang fp contract(on)
   const double e[3][3] = {
       {(double)p0.x - (double)p3.x, (double)p0.y - (double)p3.y, (double)p0.z - (double)p3.z},
       {(double)p1.x - (double)p3.x, (double)p1.y - (double)p3.y, (double)p1.z - (double)p3.z},
@@ -122,6 +132,7 @@ __device__ __forceinline__ void deformation_gradient(
 __device__ __forceinline__ void direction_gradient(
     const float4& v0, const float4& v1, const float4& v2, const float4& v3,
     const float B[9], float D[3][3]) {
+#pragma clang fp contract(on)
   const float e[3][3] = {{v0.x - v3.x, v0.y - v3.y, v0.z - v3.z},
                          {v1.x - v3.x, v1.y - v3.y, v1.z - v3.z},
                          {v2.x - v3.x, v2.y - v3.y, v2.z - v3.z}};
@@ -132,19 +143,14 @@ __device__ __forceinline__ void direction_gradient(
       D[i][j] = e[0][i] * B[j] + e[1][i] * B[3 + j] + e[2][i] * B[6 + j];
 }
 
-// Forward: forces h[k][i] on vertices k = 0..2 (vertex 3 takes the negative
-// sum) and the tetrahedron's energy V0 U (float64).
-__device__ __forceinline__ void tet_forward(const float4& p0, const float4& p1,
-                                            const float4& p2, const float4& p3,
-                                            const float B[9], float V0,
-                                            const Material& m, float h[3][3],
-                                            double& vU, bool& inverted) {
-  double Fd[3][3];
-  float F[3][3], Cf[6];
-  deformation_gradient(p0, p1, p2, p3, B, Fd, F);
-  Scalars s;
-  invariants(Fd, Cf, s);
-  inverted = !(s.J > 0.0);
+// Stress and forces from F (float32 copy), C and the float64 scalars: h[k][i]
+// on vertices k = 0..2 (vertex 3 takes the negative sum) and the
+// tetrahedron's energy V0 U (float64).
+__device__ __forceinline__ void stress_forces(const float F[3][3], const float Cf[6],
+                                              const Scalars& s, const float B[9],
+                                              float V0, const Material& m,
+                                              float h[3][3], double& vU) {
+#pragma clang fp contract(on)
   const double Jm1 = s.J - 1.0;
   const double U = 0.5 * m.mu1 * (s.TC * s.r2 - 3.0) +
                    0.5 * m.mu2 * (s.I2 * s.r4 - 3.0) + 0.5 * m.kappa * Jm1 * Jm1;
@@ -174,12 +180,30 @@ __device__ __forceinline__ void tet_forward(const float4& p0, const float4& p1,
       h[k][i] = P[i][0] * B[3 * k] + P[i][1] * B[3 * k + 1] + P[i][2] * B[3 * k + 2];
 }
 
+// Forward: forces h[k][i] on vertices k = 0..2 (vertex 3 takes the negative
+// sum) and the tetrahedron's energy V0 U (float64).
+__device__ __forceinline__ void tet_forward(const float4& p0, const float4& p1,
+                                            const float4& p2, const float4& p3,
+                                            const float B[9], float V0,
+                                            const Material& m, float h[3][3],
+                                            double& vU, bool& inverted) {
+#pragma clang fp contract(on)
+  double Fd[3][3];
+  float F[3][3], Cf[6];
+  deformation_gradient(p0, p1, p2, p3, B, Fd, F);
+  Scalars s;
+  invariants(Fd, Cf, s);
+  inverted = !(s.J > 0.0);
+  stress_forces(F, Cf, s, B, V0, m, h, vU);
+}
+
 // d(cof F) along dF: the columns of cof F are cross products of the other
 // two columns of F (cyclic), so each derivative column is a sum of two
 // cross products.
 __device__ __forceinline__ void cofactor_dir(const float F[3][3],
                                              const float D[3][3],
                                              float R[3][3]) {
+#pragma clang fp contract(on)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int a = (c + 1) % 3, b = (c + 2) % 3;
@@ -190,7 +214,8 @@ __device__ __forceinline__ void cofactor_dir(const float F[3][3],
   }
 }
 
-// Backward of one tetrahedron for a loss L(f, E):
+// Backward of one tetrahedron for a loss L(f, E) (adjoint_terms takes F, dF,
+// C, cof F and the float64 scalars; tet_backward forms them first):
 //   dF = D_fbar B is the direction of the Hessian-vector product (the forces
 //   are -grad E, so (df/dy)^T fbar = d/de f(y + e fbar));
 //   h[k][i] = (-V0 (dP[dF] - ebar P) B^T)_ik, the contribution to ybar of
@@ -208,19 +233,12 @@ __device__ __forceinline__ void cofactor_dir(const float F[3][3],
 // GRAD = false: the Hessian-vector product alone (no energy cotangent, no
 // parameter gradient): ebar is taken as 0 and gp, ge are not formed.
 template <bool GRAD>
-__device__ __forceinline__ void tet_backward(
-    const float4& p0, const float4& p1, const float4& p2, const float4& p3,
-    const float4& v0, const float4& v1, const float4& v2, const float4& v3,
-    const float B[9], float V0, const Material& m, double ebar, float h[3][3],
-    double gp[3], double ge[3]) {
-  double Fd[3][3];
-  float F[3][3], dF[3][3], Cf[6];
-  deformation_gradient(p0, p1, p2, p3, B, Fd, F);
-  direction_gradient(v0, v1, v2, v3, B, dF);
-  Scalars s;
-  invariants(Fd, Cf, s);
-  float K[3][3];
-  cofactor(F, K);
+__device__ __forceinline__ void adjoint_terms(const float F[3][3], const float dF[3][3],
+                                              const float Cf[6], const float K[3][3],
+                                              const Scalars& s, const float B[9],
+                                              float V0, const Material& m, double ebar,
+                                              float h[3][3], double gp[3], double ge[3]) {
+#pragma clang fp contract(on)
   // dC = dF^T F + F^T dF (symmetric): diagonal dC_jj = 2 u_j with
   // u_j = <F e_j, dF e_j>; off-diagonal 01 02 12
   float u[3];
@@ -312,6 +330,23 @@ __device__ __forceinline__ void tet_backward(
     ge[1] = s.I2 * s.r4 - 3.0;
     ge[2] = Jm1d * Jm1d;
   }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void tet_backward(
+    const float4& p0, const float4& p1, const float4& p2, const float4& p3,
+    const float4& v0, const float4& v1, const float4& v2, const float4& v3,
+    const float B[9], float V0, const Material& m, double ebar, float h[3][3],
+    double gp[3], double ge[3]) {
+#pragma clang fp contract(on)
+  double Fd[3][3];
+  float F[3][3], dF[3][3], Cf[6], K[3][3];
+  deformation_gradient(p0, p1, p2, p3, B, Fd, F);
+  direction_gradient(v0, v1, v2, v3, B, dF);
+  Scalars s;
+  invariants(Fd, Cf, s);
+  cofactor(F, K);
+  adjoint_terms<GRAD>(F, dF, Cf, K, s, B, V0, m, ebar, h, gp, ge);
 }
 
 }  // namespace cm

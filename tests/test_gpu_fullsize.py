@@ -2,7 +2,8 @@
 seed 3000) in the configuration the benchmark times — autotuned launch,
 forward + backward captured as one graph and replayed — checked against the
 FP64 oracle on 64 cells spread over the batch (the oracle evaluates them one
-by one), plus properties that hold at any size: every replay is bitwise the
+by one), plus properties that hold at any size: every replay, of the
+separate passes and of the fused forward + backward pass, is bitwise the
 eager pass, every cell's forces balance (zero net force), no tetrahedron is
 inverted.  Tolerances as everywhere: forces, ybar, thetabar max-normalised
 1e-5, energy 1e-6 relative."""
@@ -63,6 +64,18 @@ def test_full_workload_graph_replay_against_oracle():
         torch.cuda.synchronize()
         for got, want in zip((f, E, ninv, ybar, tb), eager):
             assert torch.equal(got, want), rep
+    # the benchmark's fused step (forward and backward in one pass, graph
+    # mode 6): bitwise the separate passes on every replay
+    with torch.cuda.stream(s):
+        cb.graph_capture(6, y, f, E, ninv, fbar, ebar, ybar, tb, stream=s)
+    for rep in range(3):
+        for t in (f, ybar):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        cb.graph_launch(stream=s)
+        torch.cuda.synchronize()
+        for got, want in zip((f, E, ninv, ybar, tb), eager):
+            assert torch.equal(got, want), ("fused", rep)
     fh, yh = cb.to_host(f), cb.to_host(ybar)
     Eh, nh = E.cpu().numpy(), ninv.cpu().numpy()
     th = tb.cpu().numpy().reshape(-1, 3)
