@@ -6,14 +6,18 @@ U[0.7, 1.3] R, 500-20,000 tetrahedra each, ~42 M tetrahedra in total), each
 with its own compression + shear, node noise and (mu, kappa, w); synthetic,
 seeded (synth.configs.uneven_batch).
 
-One step = one hot-path pass over the whole batch: the forward kernels
-(forces + energies) followed by the backward kernels (Hessian-vector product
-and parameter gradient), replayed as one captured HIP graph.  The reported
-value is tetrahedra per second of that step.  Also reported: forward-only
-throughput, the same passes as one launch per cell (single-cell baseline),
-per-kernel device times from HIP events, a roofline entry for the dominant
-kernel, sampled parity against the FP64 oracle, and the oracle timed on the
-host (CPU baseline).
+One step = one hot-path pass over the whole batch for the loss
+L = sum_i v_i . f_i + sum_c ebar_c E_c (seeded v, ebar): forces and energies,
+the Hessian-vector product ybar and the parameter gradient, computed by the
+fused forward + backward tile pass (cm_forces_and_backward, whose outputs are
+bitwise those of the separate passes; the step checks that) and replayed as
+one captured HIP graph.  The reported value is tetrahedra per second of that
+step.  Also reported: the same step as separate forward and backward passes
+(the route of a loss whose cotangents depend on the forces, e.g. through
+autograd), forward-only throughput, the passes as one launch per cell
+(single-cell baseline), per-kernel device times from HIP events, a roofline
+entry for the dominant kernel, sampled parity against the FP64 oracle, and
+the oracle timed on the host (CPU baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -39,18 +43,23 @@ ALU_PEAK_TFLOPS = 78.6
 # backward ~900 (the same plus the stress derivative along the direction and
 # the parameter terms, ~2.5x the forward).
 FWD_FLOPS, BWD_FLOPS = 350, 900
+# The fused pass shares the deformation gradient, invariants and cofactor
+# matrix: the backward's operations plus the forward-only ones (stress
+# assembly ~78, P B^T 54, energy and float64 coefficients ~28).
+FUSED_FLOPS = BWD_FLOPS + 160
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # Algorithmic bytes per tetrahedron and per node (int32 indices, float32
 # inverse edge matrix and volume, float32 SoA node arrays), per pass.
 FWD_BYTES = (56, 24)    # 16 idx + 36 B + 4 V0 per tet; y in + f out per node
 BWD_BYTES = (56, 36)    # same tet stream; y, fbar in + ybar out per node
+FUSED_BYTES = (56, 48)  # one tet stream; y, fbar in + f, ybar out per node
 # Bytes per tetrahedron of the stored chunk format (uint16 tile-local
 # indices: 8 + 36 + 4), the other denominator reported beside the canonical.
 STORED_TET_BYTES = 48
 F_TOL, E_TOL, G_TOL = 1e-5, 1e-6, 1e-5
-TILE_KERNEL_SOURCES = ("kernels.hip", "backward.hip", "device_util.h",
-                       "kernels.h", "layout.h", "mr_tet.h", "prep.cpp",
-                       "util.hip")
+TILE_KERNEL_SOURCES = ("kernels.hip", "backward.hip", "fused.hip",
+                       "device_util.h", "finalize.h", "kernels.h", "layout.h",
+                       "mr_tet.h", "prep.cpp", "util.hip")
 
 
 def kernel_source_hash():
@@ -387,7 +396,7 @@ def run_template(args):
     par = parity(cb, b, f, E, ybar, tb, vbar, ebar_h, sample)
     s = torch.cuda.Stream()
     res = {}
-    for name, mode in (("fwd", 0), ("fwd_bwd", 1)):
+    for name, mode in (("fwd", 0), ("fwd_bwd", 1), ("fwd_bwd_fused", 6)):
         with torch.cuda.stream(s):
             cb.graph_capture(mode, y, f, E, None, fbar, ebar, ybar, tb,
                              stream=s)
@@ -402,6 +411,7 @@ def run_template(args):
                     f"and parameters",
         "launch": list(cb.get_launch()),
         "fwd_bwd_tets_per_s": M / (res["fwd_bwd"] * 1e-3),
+        "fwd_bwd_fused_tets_per_s": M / (res["fwd_bwd_fused"] * 1e-3),
         "fwd_tets_per_s": M / (res["fwd"] * 1e-3),
         "ms": {k: round(v, 5) for k, v in res.items()},
         "kernel_ms": [round(v, 5) for v in ms],
@@ -755,12 +765,17 @@ def run_regions(args, b):
     with torch.cuda.stream(s):
         cb.graph_capture(1, y, f, E, None, fbar, ebar, ybar, tb, stream=s)
     step = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
+    with torch.cuda.stream(s):
+        cb.graph_capture(6, y, f, E, None, fbar, ebar, ybar, tb, stream=s)
+    step_fused = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
     out = {
         "workload": f"main workload, {R} material regions per cell "
                     f"(nucleus, cytoplasm, cortex by reference radius), "
                     f"{cb.n_mat} parameter sets",
         "n_tiles": cb.info["n_tiles"], "launch": list(cb.get_launch()),
         "ms_per_step": step, "fwd_bwd_tets_per_s": b.n_tets / (step * 1e-3),
+        "ms_per_step_fused": step_fused,
+        "fwd_bwd_fused_tets_per_s": b.n_tets / (step_fused * 1e-3),
         "parity": worst,
     }
     log(f"regions: {out}")
@@ -930,20 +945,35 @@ def main():
     log(f"parity on {len(sample)} cells ({time.time() - t:.1f} s): {par}")
     n_inverted = int(ninv.sum().item())
 
+    # the fused pass must reproduce the separate passes bit for bit (the
+    # oracle parity above then holds for it too)
+    eager = [t.clone() for t in (f, E, ninv, ybar, tb)]
+    for t in (f, ybar):
+        t.fill_(float("nan"))
+    cb.forces_and_backward(y, fbar, ebar, f=f, energy=E, n_inverted=ninv,
+                           ybar=ybar, thetabar=tb)
+    torch.cuda.synchronize()
+    fused_bitwise = all(torch.equal(a, c) for a, c in
+                        zip((f, E, ninv, ybar, tb), eager))
+    log(f"fused pass bitwise equal to the separate passes: {fused_bitwise}")
+    if not fused_bitwise:
+        raise SystemExit("fused forward + backward differs from the separate "
+                         "passes")
+
     s = torch.cuda.Stream()
     M, N = b.n_tets, b.n_nodes
     res = {}
-    for name, mode in (("fwd", 0), ("fwd_bwd", 1)):
+    for name, mode in (("fwd", 0), ("fwd_bwd", 1), ("fwd_bwd_fused", 6)):
         with torch.cuda.stream(s):
             cb.graph_capture(mode, y, f, E, ninv, fbar, ebar, ybar, tb,
                              stream=s)
         res[name] = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
         log(f"batched {name}: {res[name]:.4f} ms/step")
-    step_ms = res["fwd_bwd"]
+    step_ms = res["fwd_bwd_fused"]
     # per-kernel event times right after the step timing, clocks loaded
     ms = kernel_times(cb, s, y, f, E, fbar, ebar, ybar, tb)
-    log(f"kernel ms (fwd tile, fwd finalize, bwd tile, bwd finalize): "
-        f"{np.round(ms, 4).tolist()}")
+    log(f"kernel ms (fwd tile, fwd finalize, bwd tile, bwd finalize, "
+        f"fused tile, fused finalize): {np.round(ms, 4).tolist()}")
     if not args.no_percell:
         psteps = max(2, args.steps // 4)
         for name, mode in (("percell_fwd_bwd", 3), ("percell_fwd", 2)):
@@ -957,6 +987,7 @@ def main():
 
     fwd_b = FWD_BYTES[0] * M + FWD_BYTES[1] * N
     bwd_b = BWD_BYTES[0] * M + BWD_BYTES[1] * N
+    fused_b = FUSED_BYTES[0] * M + FUSED_BYTES[1] * N
     def views(ms_k, nbytes, flops):
         return {"ms": ms_k, "bytes": nbytes, "GBps": nbytes / ms_k / 1e6,
                 "hbm_frac": nbytes / ms_k / 1e6 / HBM_PEAK_GBS,
@@ -965,9 +996,12 @@ def main():
     kern = {
         "forward_tile": views(ms[0], fwd_b, FWD_FLOPS * M),
         "backward_tile": views(ms[2], bwd_b, BWD_FLOPS * M),
+        "fused_tile": views(ms[4], fused_b, FUSED_FLOPS * M),
         "forward_finalize_ms": ms[1], "backward_finalize_ms": ms[3],
+        "fused_finalize_ms": ms[5],
     }
-    dom = "backward_tile" if ms[2] >= ms[0] else "forward_tile"
+    # the step's dominant kernel: the fused tile kernel
+    dom = "fused_tile"
     kd = kern[dom]
     traffic = measured_traffic(dom, cb.info)
     if kd["alu_frac"] > kd["hbm_frac"]:
@@ -1025,7 +1059,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{b.n_cells} uneven ellipsoid cells, {M} tets, "
-                        f"{N} nodes; one step = batched forward + backward",
+                        f"{N} nodes; one step = batched forward + backward "
+                        f"(fused pass; separate passes in ms.fwd_bwd)",
+            "step": "cm_forces_and_backward: forces, energies, ybar and "
+                    "thetabar of L = sum v.f + sum ebar E in one pass, "
+                    "bitwise the separate passes",
             "n_cells": b.n_cells, "n_tets": M, "n_nodes": N,
             "tile_tets": cb.info["tile_tets"], "launch": list(launch),
             # launch = (tiles per workgroup, workgroups per CU); 0 workgroups
@@ -1037,16 +1075,22 @@ def main():
         },
         "fwd_tets_per_s": M / (res["fwd"] * 1e-3),
         "fwd_bwd_tets_per_s": M / (step_ms * 1e-3),
+        "fwd_bwd_separate_tets_per_s": M / (res["fwd_bwd"] * 1e-3),
+        "fused_bitwise_equal": fused_bitwise,
         "hbm_copy_GBps": copy_gbps,
         "hbm_frac_fwd": fwd_b / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
-        "hbm_frac_fwd_bwd": (fwd_b + bwd_b) / (step_ms * 1e-3)
+        # separate passes: both passes' algorithmic bytes over their step
+        "hbm_frac_fwd_bwd": (fwd_b + bwd_b) / (res["fwd_bwd"] * 1e-3)
+        / (HBM_PEAK_GBS * 1e9),
+        # fused pass: its own algorithmic bytes (one tet stream) over its step
+        "hbm_frac_fwd_bwd_fused": fused_b / (step_ms * 1e-3)
         / (HBM_PEAK_GBS * 1e9),
         # the same fractions with the stored chunk bytes per tetrahedron
         "hbm_frac_fwd_stored": (fwd_b - (FWD_BYTES[0] - STORED_TET_BYTES) * M)
         / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "hbm_frac_fwd_bwd_stored": (fwd_b + bwd_b - (FWD_BYTES[0] + BWD_BYTES[0]
                                                      - 2 * STORED_TET_BYTES) * M)
-        / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        / (res["fwd_bwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "ms": {k: round(v, 5) for k, v in res.items()},
         "autotune": tuning,
         "kernels": kern,
@@ -1065,7 +1109,7 @@ def main():
     if not args.no_percell:
         out["percell_fwd_tets_per_s"] = M / (res["percell_fwd"] * 1e-3)
         out["percell_fwd_bwd_tets_per_s"] = M / (res["percell_fwd_bwd"] * 1e-3)
-        out["batched_speedup_fwd_bwd"] = res["percell_fwd_bwd"] / step_ms
+        out["batched_speedup_fwd_bwd"] = res["percell_fwd_bwd"] / res["fwd_bwd"]
     print(json.dumps(out), flush=True)
 
 

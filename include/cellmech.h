@@ -312,8 +312,10 @@ int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
 /*
  * Launch configuration of the batched kernels: waves (tiles) per workgroup
  * (1, 2, 4, 8) and persistent workgroups per compute unit (0 = one workgroup
- * per group of tiles, not persistent).  cm_autotune times forward + backward
- * for every candidate that fits in LDS on `stream`, with the handle's data,
+ * per group of tiles, not persistent).  cm_autotune times one forward +
+ * backward evaluation -- the fused pass of cm_forces_and_backward where its
+ * LDS fits, else cm_forces then cm_forces_backward -- for every candidate
+ * that fits in LDS on `stream`, with the handle's data,
  * the caller's positions `y` (device, SoA, also used as the cotangent) and
  * the parameters already set, and keeps the fastest.  `cache_path`
  * (nullable) is a JSON file keyed by device name and mesh statistics; a hit
@@ -324,8 +326,9 @@ int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
  * cm_batch_create_tuned: cm_batch_create with the tile size chosen by
  * measurement.  For every candidate tile size (tile_candidates, host
  * int32[n_candidates], multiples of 64 in [64, 4096]; NULL = {512, 640, 768,
- * 896, 1024}) the meshes are prepared and uploaded, and forward + backward
- * are timed as in cm_autotune for every launch configuration, with the
+ * 896, 1024}) the meshes are prepared and uploaded, and one forward +
+ * backward evaluation is timed as in cm_autotune for every launch
+ * configuration, with the
  * reference positions as input and unit parameters (the work per
  * tetrahedron does not depend on them); the fastest tile size and launch
  * are kept, the other handles freed as soon as they lose.  candidate_ms
@@ -642,10 +645,11 @@ int cm_shape(cm_batch h, const float* y, const double* d_ref, double* out,
  * `stream` around `reps` back-to-back launches of each kernel:
  *   ms[0] forward tile kernel,  ms[1] forward finalize kernel,
  *   ms[2] backward tile kernel, ms[3] backward finalize kernel,
- *   ms[4] tile kernel of cm_forces_and_backward (NaN where that pass does
- *         not apply: aliased buffers or too little LDS).
+ *   ms[4] tile kernel and ms[5] finalize kernel of cm_forces_and_backward
+ *         (NaN where that pass does not apply: aliased buffers or too
+ *         little LDS).
  * Buffers as in cm_forces / cm_forces_backward (fbar, ebar nullable);
- * ms holds 5 entries.
+ * ms holds 6 entries.
  * Synchronises the stream; not graph-safe.
  */
 int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,

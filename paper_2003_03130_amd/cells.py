@@ -388,9 +388,9 @@ class CellBatch:
     def profile_kernels(self, y, f, energy, fbar, ebar, ybar, thetabar,
                         reps=10, stream=None):
         """Average ms per launch of the forward tile, forward finalize,
-        backward tile, backward finalize and fused forward + backward tile
-        kernels (HIP events)."""
-        ms = np.zeros(5, dtype=np.float64)
+        backward tile and backward finalize kernels and of the fused forward
+        + backward tile and finalize kernels (HIP events)."""
+        ms = np.zeros(6, dtype=np.float64)
         nat.check(nat.lib().cm_profile_kernels(
             self._h, _ptr(y), _ptr(f), _ptr(energy), _ptr(fbar), _ptr(ebar),
             _ptr(ybar), _ptr(thetabar), int(reps), _ptr(ms), _stream(stream)))

@@ -691,7 +691,12 @@ static int tune_launch(cm_batch h, const float* y, hipStream_t stream,
   }
   const int waves[4] = {1, 2, 4, 8};
   const int bpcu[6] = {0, 1, 2, 4, 8, 16};
+  // the objective is one full forward + backward evaluation: the fused pass
+  // (the fastest route) where its LDS fits, else the two separate passes
   auto run = [&]() {
+    cm::LaunchCfg fc;
+    if (fused_cfg(h, &fc))
+      return forward_backward_impl(h, y, f, energy, nullptr, y, nullptr, ybar, tb, stream);
     int r = forces_impl(h, y, f, energy, nullptr, stream, false);
     if (r == CM_OK) r = backward_impl(h, y, y, energy, ybar, tb, stream, false);
     return r;
@@ -1221,13 +1226,13 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
   cm::LaunchCfg fcfg;
   const bool fused = fused_cfg(h, &fcfg) && f != ybar && f != y && ybar != y &&
                      (!fbar || (f != fbar && ybar != fbar));
-  hipEvent_t ev[6];
-  for (int i = 0; i < 6; ++i) CM_HIP(hipEventCreate(&ev[i]));
+  hipEvent_t ev[7];
+  for (int i = 0; i < 7; ++i) CM_HIP(hipEventCreate(&ev[i]));
   int rc = CM_OK;
-  for (int k = 0; k < 5 && rc == CM_OK; ++k) {
-    if (k == 4 && !fused) {
+  for (int k = 0; k < 6 && rc == CM_OK; ++k) {
+    if (k >= 4 && !fused) {
       ms[k] = NAN;
-      break;
+      continue;
     }
     auto once = [&]() -> hipError_t {
       switch (k) {
@@ -1235,9 +1240,12 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
         case 1: return cm::launch_forward_finalize(h->T, r, f, energy, nullptr, st);
         case 2: return cm::launch_backward_main(h->Tb, r, h->cfg, y, fbar, ebar, ybar, st);
         case 3: return cm::launch_backward_finalize(h->Tb, r, ybar, thetabar, st);
-        default:
+        case 4:
           return cm::launch_forward_backward_main(h->T, h->Tb, r, fcfg, y, f, fbar, ebar,
                                                   ybar, st);
+        default:
+          return cm::launch_forward_backward_finalize(h->T, h->Tb, r, f, energy, nullptr,
+                                                      ybar, thetabar, st);
       }
     };
     hipError_t e = once();  // warm-up
@@ -1250,7 +1258,7 @@ int cm_profile_kernels(cm_batch h, const float* y, float* f, double* energy,
     if (e != hipSuccess) rc = fail(CM_EHIP, std::string("profile: ") + hipGetErrorString(e));
     ms[k] = (double)t / reps;
   }
-  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 7; ++i) (void)hipEventDestroy(ev[i]);
   return rc;
 }
 

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
+#include "finalize.h"
 #include "kernels.h"
 #include "mr_tet.h"
 #include "plate.h"
@@ -176,21 +177,9 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
     if (!tb || wv >= (a.r.cell_end - a.r.cell_begin) * R) return;
     const int mt = a.r.cell_begin * R + wv;  // material slot
     if (m.flags && m.flags[(int64_t)(mt / R) * m.stride] == 0.0) return;
-    double gI = 0.0, gK = 0.0, gJ = 0.0;
-    const int t0 = a.T.mat_tile_first[mt], nt = a.T.mat_tile_count[mt];
-    for (int k = lane; k < nt; k += 64) {
-      const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
-      gI += a.T.tile_acc[3 * t];
-      gK += a.T.tile_acc[3 * t + 1];
-      gJ += a.T.tile_acc[3 * t + 2];
-    }
-    gI = wave_sum(gI);
-    gK = wave_sum(gK);
-    gJ = wave_sum(gJ);
+    double t3[3];
+    slot_theta(a.T, a.T.tile_acc, mt, lane, t3);
     if (lane == 0) {
-      const int nm = a.T.n_mat;
-      const double mu = a.T.params[mt], w = a.T.params[2 * nm + mt];
-      const double t3[3] = {w * gI + (1.0 - w) * gK, gJ, mu * (gI - gK)};
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         if (a.pl.plate)
@@ -220,19 +209,12 @@ __global__ __launch_bounds__(256) void backward_finalize_kernel(BwdFinArgs a,
         bot = (float)a.pl.plate[2 * c + 1];
         gw = plate_loss_weight(a.pl.F_meas, a.pl.F_target, a.pl.scale, c);
       }
-      float sx = 0.f, sy = 0.f, sz = 0.f;
-      for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
-        const int64_t sl = a.T.shared_slots[q];
-        const float* pp = a.T.part + 3 * sl;
-        sx += pp[0];
-        sy += pp[1];
-        sz += pp[2];
-      }
+      const float3 sm = shared_sum(a.T, a.T.part, s);
       if (a.pl.plate) {
-        plate_node_adjoint(pz, lx, ly, lz, sx, sy, sz, top, bot, a.pl.k, a.pl.m, gw,
+        plate_node_adjoint(pz, lx, ly, lz, sm.x, sm.y, sm.z, top, bot, a.pl.k, a.pl.m, gw,
                            a.pl.lam, N, g);
       } else {
-        a.ybar[g] = sx; a.ybar[N + g] = sy; a.ybar[2 * N + g] = sz;
+        a.ybar[g] = sm.x; a.ybar[N + g] = sm.y; a.ybar[2 * N + g] = sm.z;
       }
     }
   }

@@ -9,11 +9,12 @@
 // are those of the forward kernel and of the backward kernel, so f, E,
 // the inverted counts, ybar and thetabar equal those of the two separate
 // passes bit for bit.  Scratch: the forward's slot partials and tile records
-// (T) and the backward's (part_b, tile_acc_b), finalized by the two
-// passes' own finalize kernels.
+// (T) and the backward's (part_b, tile_acc_b), finalized by one kernel that
+// forms both passes' sums.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
+#include "finalize.h"
 #include "kernels.h"
 #include "mr_tet.h"
 
@@ -158,6 +159,75 @@ void forward_backward_kernel(FusedArgs a) {
   }
 }
 
+struct FusedFinArgs {
+  DeviceTables T;             // forward tables: part holds the force partials
+  const float* part_b;        // ybar partials
+  const double* tile_acc_b;   // per-tile parameter-gradient sums
+  Range r;
+  float* f;
+  double* energy;             // nullable
+  int32_t* ninv;              // nullable
+  float* ybar;
+  double* thetabar;           // nullable (then slot_blocks = 0)
+};
+
+// One launch for both passes' finalize work: the first cell_blocks
+// workgroups form each cell's energy and inverted count (one wavefront per
+// cell), the next slot_blocks each material slot's parameter gradient (one
+// wavefront per slot); the others sum the force and the ybar partials of
+// every shared node in tile order from one read of its slot list.  Every
+// sum is the one the forward and the backward finalize kernels form.
+__global__ __launch_bounds__(256) void forward_backward_finalize_kernel(
+    FusedFinArgs a, int cell_blocks, int slot_blocks) {
+  const int b = blockIdx.x;
+  if (b < cell_blocks + slot_blocks) {
+    const int lane = threadIdx.x & 63;
+    if (b < cell_blocks) {
+      const int wv = (b * 256 + (int)threadIdx.x) >> 6;
+      if (wv >= a.r.cell_end - a.r.cell_begin) return;  // uniform per wave
+      const int c = a.r.cell_begin + wv;
+      const CellSums cs = cell_sums(a.T, c, lane, false);
+      if (lane == 0) {
+        if (a.energy) a.energy[c] = cs.e;
+        if (a.ninv) a.ninv[c] = cs.ni;
+      }
+    } else {
+      const int R = a.T.n_regions;
+      const int wv = ((b - cell_blocks) * 256 + (int)threadIdx.x) >> 6;
+      if (wv >= (a.r.cell_end - a.r.cell_begin) * R) return;  // uniform per wave
+      const int mt = a.r.cell_begin * R + wv;  // material slot
+      double t3[3];
+      slot_theta(a.T, a.tile_acc_b, mt, lane, t3);
+      if (lane == 0) {
+        a.thetabar[3 * (int64_t)mt] = t3[0];
+        a.thetabar[3 * (int64_t)mt + 1] = t3[1];
+        a.thetabar[3 * (int64_t)mt + 2] = t3[2];
+      }
+    }
+    return;
+  }
+  const int64_t gid =
+      (int64_t)(b - cell_blocks - slot_blocks) * blockDim.x + threadIdx.x;
+  if (gid >= a.r.shared_end - a.r.shared_begin) return;
+  const int s = a.r.shared_begin + (int)gid;
+  const int64_t g = a.T.shared_node[s];
+  const int64_t N = a.T.n_nodes;
+  float fx = 0.f, fy = 0.f, fz = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+  for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
+    const int64_t sl = a.T.shared_slots[q];
+    const float* pf = a.T.part + 3 * sl;
+    const float* pb = a.part_b + 3 * sl;
+    fx += pf[0];
+    fy += pf[1];
+    fz += pf[2];
+    bx += pb[0];
+    by += pb[1];
+    bz += pb[2];
+  }
+  a.f[g] = fx; a.f[N + g] = fy; a.f[2 * N + g] = fz;
+  a.ybar[g] = bx; a.ybar[N + g] = by; a.ybar[2 * N + g] = bz;
+}
+
 template <int W>
 hipError_t fb_w(const FusedArgs& a, int grid, size_t lds, hipStream_t st, bool grad) {
   if (grad)
@@ -204,9 +274,24 @@ hipError_t launch_forward_backward(const DeviceTables& T, const DeviceTables& Tb
   hipError_t e =
       launch_forward_backward_main(T, Tb, r, cfg, y, f, fbar, ebar, ybar, st, grad);
   if (e != hipSuccess) return e;
-  e = launch_forward_finalize(T, r, f, energy, ninv, st);
-  if (e != hipSuccess) return e;
-  return launch_backward_finalize(Tb, r, ybar, thetabar, st);
+  return launch_forward_backward_finalize(T, Tb, r, f, energy, ninv, ybar, thetabar, st);
+}
+
+hipError_t launch_forward_backward_finalize(const DeviceTables& T, const DeviceTables& Tb,
+                                            const Range& r, float* f, double* energy,
+                                            int32_t* ninv, float* ybar, double* thetabar,
+                                            hipStream_t st) {
+  const int64_t n_shr = r.shared_end - r.shared_begin;
+  const int64_t n_cells = r.cell_end - r.cell_begin;
+  const int64_t n_slots = thetabar ? n_cells * T.n_regions : 0;
+  if (n_shr <= 0 && n_cells <= 0) return hipSuccess;
+  const int cell_blocks = (int)((n_cells + 3) / 4);  // four waves per block
+  const int slot_blocks = (int)((n_slots + 3) / 4);
+  const int64_t blocks = cell_blocks + slot_blocks + (n_shr + 255) / 256;
+  FusedFinArgs b{T, Tb.part, Tb.tile_acc, r, f, energy, ninv, ybar, thetabar};
+  hipLaunchKernelGGL(forward_backward_finalize_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     st, b, cell_blocks, slot_blocks);
+  return hipGetLastError();
 }
 
 }  // namespace cm

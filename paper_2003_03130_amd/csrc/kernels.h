@@ -166,6 +166,10 @@ hipError_t launch_forward_backward_main(const DeviceTables& T, const DeviceTable
                                         const float* y, float* f, const float* fbar,
                                         const double* ebar, float* ybar, hipStream_t st,
                                         bool grad = true);
+hipError_t launch_forward_backward_finalize(const DeviceTables& T, const DeviceTables& Tb,
+                                            const Range& r, float* f, double* energy,
+                                            int32_t* ninv, float* ybar, double* thetabar,
+                                            hipStream_t st);
 hipError_t launch_forward_backward(const DeviceTables& T, const DeviceTables& Tb,
                                    const Range& r, const LaunchCfg& cfg, const float* y,
                                    float* f, double* energy, int32_t* ninv,

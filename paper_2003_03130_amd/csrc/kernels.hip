@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
+#include "finalize.h"
 #include "kernels.h"
 #include "mr_tet.h"
 #include "plate.h"
@@ -177,24 +178,14 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
     const int lane = threadIdx.x & 63;
     if (wv >= a.r.cell_end - a.r.cell_begin) return;  // uniform per wave
     const int c = a.r.cell_begin + wv;
-    double e = 0.0;
-    int ni = 0, nf = 0;
-    const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
-    for (int k = lane; k < nt; k += 64) {
-      const int64_t t = t0 + (int64_t)k * a.T.tile_stride;
-      e += a.T.tile_acc[t];
-      ni += a.T.tile_ninv[t];
-      if (a.nonfin) nf += a.T.tile_nonfin[t];
-    }
-    e = wave_sum(e);
-    ni = wave_sum(ni);
-    if (a.nonfin) nf = wave_sum(nf);
+    const CellSums cs = cell_sums(a.T, c, lane, a.nonfin != nullptr);
     if (lane == 0) {
-      if (a.energy) a.energy[c] = e;
-      if (a.ninv) a.ninv[c] = ni;
-      if (a.nonfin) a.nonfin[c] = nf;
+      if (a.energy) a.energy[c] = cs.e;
+      if (a.ninv) a.ninv[c] = cs.ni;
+      if (a.nonfin) a.nonfin[c] = cs.nf;
     }
     if (a.pl.force) {
+      const int t0 = a.T.cell_tile_first[c], nt = a.T.cell_tile_count[c];
       // top-plate force: the tile shares, then the nodes of no tetrahedron
       double fp = 0.0;
       for (int k = lane; k < nt; k += 64)
@@ -223,19 +214,12 @@ __global__ __launch_bounds__(256) void forward_finalize_kernel(FinArgs a,
       top = (float)a.pl.plate[2 * c];
       bot = (float)a.pl.plate[2 * c + 1];
     }
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int q = a.T.shared_slot_ptr[s]; q < a.T.shared_slot_ptr[s + 1]; ++q) {
-      const int64_t sl = a.T.shared_slots[q];
-      const float* pp = a.T.part + 3 * sl;
-      sx += pp[0];
-      sy += pp[1];
-      sz += pp[2];
-    }
+    const float3 sm = shared_sum(a.T, a.T.part, s);
     if (a.pl.plate) {
-      plate_node_step(px, py, pz, sx, sy, sz, top, bot, a.pl.k, a.pl.m, a.pl.y_next, N,
-                      g);
+      plate_node_step(px, py, pz, sm.x, sm.y, sm.z, top, bot, a.pl.k, a.pl.m, a.pl.y_next,
+                      N, g);
     } else {
-      a.f[g] = sx; a.f[N + g] = sy; a.f[2 * N + g] = sz;
+      a.f[g] = sm.x; a.f[N + g] = sm.y; a.f[2 * N + g] = sm.z;
     }
   }
 }
