@@ -583,7 +583,8 @@ def run_latency(args):
     paper-size 20k-node sphere (~115k tets) of the parity configurations, one
     cell per handle, tile size and launch tuned for the cell.  Per call
     (HIP events on the launch stream around each call, mean of the calls):
-    forward and forward + backward, warm (back-to-back) and, for the 20k
+    forward, forward + backward as two calls, and as one fused call
+    (cm_forces_and_backward), warm (back-to-back) and, for the 20k
     sphere, cold (a 1 GiB buffer written between calls, so that neither L2
     nor the MALL holds the cell's data)."""
     import torch
@@ -612,6 +613,10 @@ def run_latency(args):
             cb.forces(y, f, E, stream=s)
             cb.backward(y, fbar, ebar, ybar, tb, stream=s)
 
+        def fwd_bwd_fused():
+            cb.forces_and_backward(y, fbar, ebar, f=f, energy=E, ybar=ybar,
+                                   thetabar=tb, stream=s)
+
         def per_call(fn, reps, cold):
             ev = [(torch.cuda.Event(enable_timing=True),
                    torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -630,10 +635,12 @@ def run_latency(args):
         rec = {"tets": cb.n_tets, "nodes": cb.n_nodes,
                "tile_tets": int(cb.info["tile_tets"]), "launch": list(cb.get_launch()),
                "fwd_us_warm": per_call(fwd, 200, False),
-               "fwd_bwd_us_warm": per_call(fwd_bwd, 200, False)}
+               "fwd_bwd_us_warm": per_call(fwd_bwd, 200, False),
+               "fwd_bwd_fused_us_warm": per_call(fwd_bwd_fused, 200, False)}
         if name == "sphere_20k":
             rec["fwd_us_cold"] = per_call(fwd, 20, True)
             rec["fwd_bwd_us_cold"] = per_call(fwd_bwd, 20, True)
+            rec["fwd_bwd_fused_us_cold"] = per_call(fwd_bwd_fused, 20, True)
         out[name] = rec
         cb.close()
     del flush
@@ -1066,6 +1073,9 @@ def main():
                     "bitwise the separate passes",
             "n_cells": b.n_cells, "n_tets": M, "n_nodes": N,
             "tile_tets": cb.info["tile_tets"], "launch": list(launch),
+            "layout": {k: int(cb.info[k]) for k in ("n_tiles", "n_chunks",
+                                                    "n_slots", "n_shared",
+                                                    "max_tile_nodes")},
             # launch = (tiles per workgroup, workgroups per CU); 0 workgroups
             # per CU is one workgroup per group of tiles (not persistent)
             "persistent": bool(launch[1] > 0),
