@@ -272,7 +272,7 @@ int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
  * once; the per-tetrahedron arithmetic and every summation order are those
  * of the two separate calls, so all outputs equal theirs bit for bit.
  * Launch shape: the handle's (cm_set_launch), with waves per workgroup
- * halved until the pass's LDS (52 B per tile node and wave) fits in 64 KiB.
+ * halved until the pass's LDS (48 B per tile node and wave) fits in 64 KiB.
  * Nothing is allocated.  Errors: as cm_forces and cm_forces_backward, and
  * CM_EINVAL if f or ybar alias each other, y or fbar (outputs are written
  * while other tiles still read the inputs).

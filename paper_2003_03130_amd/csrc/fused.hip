@@ -40,14 +40,13 @@ void forward_backward_kernel(FusedArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nloc = a.T.nloc;
-  // per wave (52 bytes per tile node): (y.x, y.y, y.z, fbar.x) as float4,
-  // ybar accumulators as float4, (fbar.y, fbar.z) as float2, force
-  // accumulators as packed float3; the wave's stride of 13 nloc / 4 float4
-  // is exact because nloc is a multiple of 4 (checked at launch)
-  float4* ys = lds + (size_t)wave * (13 * nloc / 4);
-  float4* gs = ys + nloc;
-  float2* vs = reinterpret_cast<float2*>(gs + nloc);
+  // per wave (48 bytes per tile node): (y.x, y.y, y.z, fbar.x) as float4,
+  // (fbar.y, fbar.z) as float2, force and ybar accumulators as packed
+  // float3; the wave's stride of 3 nloc float4 is exact
+  float4* ys = lds + (size_t)wave * (3 * nloc);
+  float2* vs = reinterpret_cast<float2*>(ys + nloc);
   float* fs = reinterpret_cast<float*>(vs + nloc);
+  float* gs = fs + 3 * nloc;
   const int64_t N = a.T.n_nodes;
   const bool has_fbar = a.fbar != nullptr;
 
@@ -72,8 +71,8 @@ void forward_backward_kernel(FusedArgs a) {
       ys[l] = make_float4(a.y[g], a.y[N + g], a.y[2 * N + g], vx);
       vs[l] = has_fbar ? make_float2(a.fbar[N + g], a.fbar[2 * N + g])
                        : make_float2(0.f, 0.f);
-      gs[l] = make_float4(0.f, 0.f, 0.f, 0.f);
       fs[3 * l] = 0.f; fs[3 * l + 1] = 0.f; fs[3 * l + 2] = 0.f;
+      gs[3 * l] = 0.f; gs[3 * l + 1] = 0.f; gs[3 * l + 2] = 0.f;
     }
     wave_sync();
 
@@ -112,7 +111,7 @@ void forward_backward_kernel(FusedArgs a) {
         cofactor(F, K);
         direction_gradient(v0, v1, v2, v3, cur.B, dF);
         adjoint_terms<GRAD>(F, dF, Cf, K, sc, cur.B, cur.V0, mat, eb, h, gp, ge);
-        lds_accumulate([&](int i) { return &gs[i].x; }, i0, i1, i2, i3, h);
+        lds_accumulate([&](int i) { return &gs[3 * i]; }, i0, i1, i2, i3, h);
         if constexpr (GRAD) {
           const double vol = (double)cur.V0;
 #pragma unroll
@@ -127,18 +126,16 @@ void forward_backward_kernel(FusedArgs a) {
 
     for (int i = lane; i < d.n_own; i += 64) {
       const int64_t g = d.own_begin + i;
-      const float4 v = gs[i];
       a.f[g] = fs[3 * i]; a.f[N + g] = fs[3 * i + 1]; a.f[2 * N + g] = fs[3 * i + 2];
-      a.ybar[g] = v.x; a.ybar[N + g] = v.y; a.ybar[2 * N + g] = v.z;
+      a.ybar[g] = gs[3 * i]; a.ybar[N + g] = gs[3 * i + 1]; a.ybar[2 * N + g] = gs[3 * i + 2];
     }
     for (int j = lane; j < d.n_shr; j += 64) {
       const int64_t s = d.shr_begin + j;
       const int l = d.n_own + j;
-      const float4 v = gs[l];
       float* pf = a.T.part + 3 * s;
       pf[0] = fs[3 * l]; pf[1] = fs[3 * l + 1]; pf[2] = fs[3 * l + 2];
       float* pb = a.part_b + 3 * s;
-      pb[0] = v.x; pb[1] = v.y; pb[2] = v.z;
+      pb[0] = gs[3 * l]; pb[1] = gs[3 * l + 1]; pb[2] = gs[3 * l + 2];
     }
     eacc = wave_sum(eacc);
     ninv = wave_sum(ninv);
@@ -241,7 +238,7 @@ hipError_t fb_w(const FusedArgs& a, int grid, size_t lds, hipStream_t st, bool g
 
 }  // namespace
 
-size_t forward_backward_lds_per_wave(int nloc) { return (size_t)52 * nloc; }
+size_t forward_backward_lds_per_wave(int nloc) { return (size_t)48 * nloc; }
 
 hipError_t launch_forward_backward_main(const DeviceTables& T, const DeviceTables& Tb,
                                         const Range& r, const LaunchCfg& cfg,
@@ -249,7 +246,8 @@ hipError_t launch_forward_backward_main(const DeviceTables& T, const DeviceTable
                                         const double* ebar, float* ybar, hipStream_t st,
                                         bool grad) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
-  // the per-wave LDS stride (13 nloc / 4 float4) needs nloc % 4 == 0
+  // the per-wave LDS layout keeps its float4 records 16-byte aligned only
+  // for nloc % 4 == 0
   if (T.nloc <= 0 || T.nloc % 4 != 0) return hipErrorInvalidValue;
   FusedArgs a{T, Tb.part, Tb.tile_acc, r, y, fbar, ebar, f, ybar};
   const int grid = grid_for(r, cfg);
