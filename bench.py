@@ -1095,6 +1095,11 @@ def main():
         # fused pass: its own algorithmic bytes (one tet stream) over its step
         "hbm_frac_fwd_bwd_fused": fused_b / (step_ms * 1e-3)
         / (HBM_PEAK_GBS * 1e9),
+        # the separate passes' canonical bytes over the fused step: the
+        # fraction of the HBM roof at which a forward + backward that moves
+        # both passes' bytes would have to run to match the fused throughput
+        "hbm_frac_fwd_bwd_effective": (fwd_b + bwd_b) / (step_ms * 1e-3)
+        / (HBM_PEAK_GBS * 1e9),
         # the same fractions with the stored chunk bytes per tetrahedron
         "hbm_frac_fwd_stored": (fwd_b - (FWD_BYTES[0] - STORED_TET_BYTES) * M)
         / (res["fwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
