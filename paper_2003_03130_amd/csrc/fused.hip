@@ -246,8 +246,9 @@ hipError_t launch_forward_backward_main(const DeviceTables& T, const DeviceTable
                                         const double* ebar, float* ybar, hipStream_t st,
                                         bool grad) {
   if (r.tile_end <= r.tile_begin) return hipSuccess;
-  // the per-wave LDS layout keeps its float4 records 16-byte aligned only
-  // for nloc % 4 == 0
+  // every layout rounds nloc up to a multiple of 4 (the separate passes'
+  // LDS strides need it; this pass's 48-byte stride keeps its float4
+  // records aligned for any nloc)
   if (T.nloc <= 0 || T.nloc % 4 != 0) return hipErrorInvalidValue;
   FusedArgs a{T, Tb.part, Tb.tile_acc, r, y, fbar, ebar, f, ybar};
   const int grid = grid_for(r, cfg);
