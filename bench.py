@@ -129,6 +129,22 @@ def time_graph(cb, stream, steps, warmup, ramp_s=0.0):
     return e0.elapsed_time(e1) / steps
 
 
+def replay_stats(cb, stream, reps):
+    """Median, min and max ms of `reps` replays of the captured graph, each
+    bracketed by its own pair of events (after the timed run, clocks loaded)."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        cb.graph_launch(stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return {"median": float(np.median(t)), "min": float(t.min()),
+            "max": float(t.max()), "replays": reps}
+
+
 def kernel_times(cb, stream, y, f, E, fbar, ebar, ybar, tb, reps=20):
     """Average device time of each kernel (cm_profile_kernels: HIP events on
     the launch stream around `reps` back-to-back launches), taken after
@@ -970,12 +986,15 @@ def main():
     s = torch.cuda.Stream()
     M, N = b.n_tets, b.n_nodes
     res = {}
+    replays = {}
     for name, mode in (("fwd", 0), ("fwd_bwd", 1), ("fwd_bwd_fused", 6)):
         with torch.cuda.stream(s):
             cb.graph_capture(mode, y, f, E, ninv, fbar, ebar, ybar, tb,
                              stream=s)
         res[name] = time_graph(cb, s, args.steps, args.warmup, ramp_s=0.5)
-        log(f"batched {name}: {res[name]:.4f} ms/step")
+        replays[name] = replay_stats(cb, s, args.steps)
+        log(f"batched {name}: {res[name]:.4f} ms/step, replays "
+            f"{replays[name]}")
     step_ms = res["fwd_bwd_fused"]
     # per-kernel event times right after the step timing, clocks loaded
     ms = kernel_times(cb, s, y, f, E, fbar, ebar, ybar, tb)
@@ -1107,6 +1126,8 @@ def main():
                                                      - 2 * STORED_TET_BYTES) * M)
         / (res["fwd_bwd"] * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "ms": {k: round(v, 5) for k, v in res.items()},
+        # each replay timed on its own (after the timed run): median, min, max
+        "replay_ms": replays,
         "autotune": tuning,
         "kernels": kern,
         "roofline": roofline,
