@@ -1,8 +1,9 @@
 """Full-size parity: the 4,096-cell uneven workload (41,987,047 tetrahedra,
 seed 3000) in the configuration the benchmark times — autotuned launch,
 forward + backward captured as one graph and replayed — checked against the
-FP64 oracle on 64 cells spread over the batch (the oracle evaluates them one
-by one), plus properties that hold at any size: every replay, of the
+FP64 oracle on every cell (its OpenMP build over all cells) and, with the
+inverted counts, on 64 cells spread over the batch (the oracle evaluates them
+one by one), plus properties that hold at any size: every replay, of the
 separate passes and of the fused forward + backward pass, is bitwise the
 eager pass, every cell's forces balance (zero net force), no tetrahedron is
 inverted.  Tolerances as everywhere: forces, ybar, thetabar max-normalised
@@ -101,6 +102,28 @@ def test_full_workload_graph_replay_against_oracle():
         assert err[0] <= TOL and err[1] <= E_TOL, (c, err)
         assert err[2] <= TOL and err[3] <= TOL, (c, err)
     print("worst force, energy, ybar, thetabar:", worst.tolist(), flush=True)
+    # every cell against the oracle: its timing-mode build (the same source,
+    # -O3 and OpenMP over cells) evaluates all 41,987,047 tetrahedra on the host
+    import tempfile
+    so = os.path.join(tempfile.gettempdir(), f"cm_oracle_omp_{os.getpid()}.so")
+    oracle.build_timing(so)
+    ob = oracle.OracleBatch(b.node_off, b.tet_off, b.x, b.tets, lib_path=so)
+    ob.threads(min(16, os.cpu_count() or 1))
+    fo, Eo, yo, to = ob.fwd_bwd(b.y.astype(np.float64), b.theta,
+                                v.astype(np.float64), eb_h)
+    start = b.node_off[:-1]
+
+    def per_cell(g, o):
+        num = np.maximum.reduceat(np.abs(g.astype(np.float64) - o).max(axis=1), start)
+        return num / np.maximum.reduceat(np.abs(o).max(axis=1), start)
+
+    ef, ey = per_cell(fh, fo), per_cell(yh, yo)
+    eE = np.abs(Eh - Eo) / np.abs(Eo)
+    et = np.abs(th - to).max(axis=1) / np.abs(to).max(axis=1)
+    print(f"all {b.n_cells} cells: worst force {ef.max():.2e}, energy {eE.max():.2e}, "
+          f"ybar {ey.max():.2e}, thetabar {et.max():.2e}", flush=True)
+    assert ef.max() <= TOL and eE.max() <= E_TOL
+    assert ey.max() <= TOL and et.max() <= TOL
 
 
 @pytest.mark.timeout(900)
