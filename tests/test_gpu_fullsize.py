@@ -7,7 +7,9 @@ one by one), plus properties that hold at any size: every replay, of the
 separate passes and of the fused forward + backward pass, is bitwise the
 eager pass, every cell's forces balance (zero net force), no tetrahedron is
 inverted.  Tolerances as everywhere: forces, ybar, thetabar max-normalised
-1e-5, energy 1e-6 relative."""
+1e-5, energy 1e-6 relative; on the every-cell check a cell's thetabar may
+instead differ by up to twice its own sensitivity to the float32 storage of
+B and V0, measured with the oracle."""
 import os
 
 import numpy as np
@@ -122,8 +124,22 @@ def test_full_workload_graph_replay_against_oracle():
     et = np.abs(th - to).max(axis=1) / np.abs(to).max(axis=1)
     print(f"all {b.n_cells} cells: worst force {ef.max():.2e}, energy {eE.max():.2e}, "
           f"ybar {ey.max():.2e}, thetabar {et.max():.2e}", flush=True)
-    assert ef.max() <= TOL and eE.max() <= E_TOL
-    assert ey.max() <= TOL and et.max() <= TOL
+    assert ef.max() <= TOL and eE.max() <= E_TOL and ey.max() <= TOL
+    # thetabar of a random cotangent sums thousands of per-tet terms of both
+    # signs, and dL/dw is a difference of two such sums: on a few cells it
+    # moves by more than 1e-5 when only B and V0 are rounded to float32 (the
+    # storage the device uses).  Each cell's bar is 1e-5 or twice that
+    # sensitivity, measured by the oracle itself on those rounded inputs.
+    ob.B[:] = ob.B.astype(np.float32).astype(np.float64)
+    ob.V0[:] = ob.V0.astype(np.float32).astype(np.float64)
+    to32 = ob.fwd_bwd(b.y.astype(np.float64), b.theta, v.astype(np.float64), eb_h)[3]
+    sens = np.abs(to32 - to).max(axis=1) / np.abs(to).max(axis=1)
+    bar = np.maximum(TOL, 2.0 * sens)
+    over = np.flatnonzero(et > TOL)
+    print(f"thetabar above 1e-5 on {len(over)} cells: "
+          + ", ".join(f"cell {c} {et[c]:.2e} (float32-input sensitivity {sens[c]:.2e})"
+                      for c in over), flush=True)
+    assert np.all(et <= bar), [(c, et[c], sens[c]) for c in np.flatnonzero(et > bar)]
 
 
 @pytest.mark.timeout(900)
