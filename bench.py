@@ -16,8 +16,9 @@ step.  Also reported: the same step as separate forward and backward passes
 (the route of a loss whose cotangents depend on the forces, e.g. through
 autograd), forward-only throughput, the passes as one launch per cell
 (single-cell baseline), per-kernel device times from HIP events, a roofline
-entry for the dominant kernel, sampled parity against the FP64 oracle, and
-the oracle timed on the host (CPU baseline).
+entry for the dominant kernel, parity against the FP64 oracle (64 sampled
+cells, and every cell through the oracle's OpenMP build), and the oracle
+timed on the host (CPU baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -200,7 +201,62 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(b, vbar, ebar, seconds, threads=None, reps=5):
+def build_oracle_omp():
+    """The oracle's timing-mode build (-O3 -march=native -fopenmp) in a
+    temporary file."""
+    import tempfile
+
+    import oracle
+    so = os.path.join(tempfile.gettempdir(), f"cm_oracle_omp_{os.getpid()}.so")
+    oracle.build_timing(so)
+    return so
+
+
+def parity_all_cells(b, dev, vbar, ebar, so, threads=None):
+    """Every cell of the workload against the FP64 oracle (its OpenMP build):
+    max-normalised force, ybar and thetabar errors and relative energy
+    errors, worst over the cells.  dev = host (f, E, ybar, thetabar (n, 3)) of
+    the benchmarked step.  thetabar's bar per cell is 1e-5 or twice the
+    cell's sensitivity to float32 storage of B and V0 (the oracle run again
+    on rounded B and V0)."""
+    import oracle
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(
+            16, os.cpu_count() or 1)
+    t = time.time()
+    ob = oracle.OracleBatch(b.node_off, b.tet_off, b.x, b.tets, lib_path=so)
+    ob.threads(threads)
+    y64, v64 = b.y.astype(np.float64), vbar.astype(np.float64)
+    fo, Eo, yo, to = ob.fwd_bwd(y64, b.theta, v64, ebar)
+    ob.B[:] = ob.B.astype(np.float32).astype(np.float64)
+    ob.V0[:] = ob.V0.astype(np.float32).astype(np.float64)
+    to32 = ob.fwd_bwd(y64, b.theta, v64, ebar)[3]
+    fh, Eh, yh, th = dev
+    start = b.node_off[:-1]
+
+    def per_cell(g, o):
+        num = np.maximum.reduceat(np.abs(g.astype(np.float64) - o).max(axis=1), start)
+        return num / np.maximum.reduceat(np.abs(o).max(axis=1), start)
+
+    ef, ey = per_cell(fh, fo), per_cell(yh, yo)
+    eE = np.abs(Eh - Eo) / np.abs(Eo)
+    sc = np.abs(to).max(axis=1)
+    et = np.abs(th - to).max(axis=1) / sc
+    sens = np.abs(to32 - to).max(axis=1) / sc
+    over = np.flatnonzero(et > G_TOL)
+    return {"cells": int(b.n_cells), "force": float(ef.max()),
+            "energy": float(eE.max()), "ybar": float(ey.max()),
+            "thetabar": float(et.max()),
+            "thetabar_above_1e-5": [{"cell": int(c), "err": float(et[c]),
+                                     "float32_input_sensitivity": float(sens[c])}
+                                    for c in over],
+            "ok": bool(ef.max() <= F_TOL and eE.max() <= E_TOL
+                       and ey.max() <= G_TOL
+                       and np.all(et <= np.maximum(G_TOL, 2.0 * sens))),
+            "s": round(time.time() - t, 1)}
+
+
+def cpu_baseline(b, vbar, ebar, seconds, so, threads=None, reps=5):
     """The FP64 oracle (forward by the derivative-table path + backward by
     dual-number JVPs, unchanged) in its timing mode: built with -O3
     -march=native -fopenmp for this host, OpenMP over the cells of the
@@ -210,15 +266,11 @@ def cpu_baseline(b, vbar, ebar, seconds, threads=None, reps=5):
     the GPU's host share of 16 cores) over a prefix of the workload's cells
     of about seconds / (reps + 3) each, beside the median of 3 one-thread
     runs on a shorter prefix."""
-    import tempfile
-
     import oracle
     os.environ.setdefault("OMP_PROC_BIND", "close")
     if threads is None:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(
             16, os.cpu_count() or 1)
-    so = os.path.join(tempfile.gettempdir(), f"cm_oracle_omp_{os.getpid()}.so")
-    oracle.build_timing(so)
     tets = np.diff(b.tet_off)
 
     def prefix(n_tets):
@@ -255,10 +307,6 @@ def cpu_baseline(b, vbar, ebar, seconds, threads=None, reps=5):
 
     _, t1, _ = timed(1, n1, 3)
     used, tm, all_t = timed(threads, nm, reps)
-    try:
-        os.remove(so)
-    except OSError:
-        pass
     return {"value": float(b.tet_off[nm] / tm), "unit": "tets/s",
             "cores": int(used), "kind": "oracle",
             "single_thread_value": float(b.tet_off[n1] / t1),
@@ -822,6 +870,8 @@ def main():
     ap.add_argument("--parity-cells", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity-all", action="store_true",
+                    help="skip the every-cell oracle check of the main workload")
     ap.add_argument("--no-percell", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", type=str, default=None,
@@ -967,6 +1017,8 @@ def main():
     par = parity(cb, b, f, E, ybar, tb, vbar, ebar_h, sample)
     log(f"parity on {len(sample)} cells ({time.time() - t:.1f} s): {par}")
     n_inverted = int(ninv.sum().item())
+    dev_out = (cb.to_host(f), E.cpu().numpy(), cb.to_host(ybar),
+               tb.cpu().numpy().reshape(-1, 3))
 
     # the fused pass must reproduce the separate passes bit for bit (the
     # oracle parity above then holds for it too)
@@ -1064,11 +1116,20 @@ def main():
     if not args.no_latency:
         latency = run_latency(args)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        t = time.time()
-        cpu = cpu_baseline(b, vbar, ebar_h, args.cpu_seconds)
-        log(f"cpu baseline: {cpu}")
+    cpu = par_all = None
+    if not args.no_cpu_baseline or not args.no_parity_all:
+        os.environ.setdefault("OMP_PROC_BIND", "close")
+        so = build_oracle_omp()
+        if not args.no_parity_all:
+            par_all = parity_all_cells(b, dev_out, vbar, ebar_h, so)
+            log(f"parity on every cell: {par_all}")
+        if not args.no_cpu_baseline:
+            cpu = cpu_baseline(b, vbar, ebar_h, args.cpu_seconds, so)
+            log(f"cpu baseline: {cpu}")
+        try:
+            os.remove(so)
+        except OSError:
+            pass
 
     out = {
         "metric": METRIC,
@@ -1132,6 +1193,7 @@ def main():
         "kernels": kern,
         "roofline": roofline,
         "parity": par,
+        "parity_all_cells": par_all,
         "n_inverted": n_inverted,
         "cpu_baseline": cpu,
         "relax": relax,
