@@ -5,10 +5,10 @@
 // twice and form F, the invariants and cof F of every tetrahedron twice;
 // here each lane evaluates its tetrahedron once -- the forward half, then the
 // adjoint half from the same F, invariants and cof F -- and adds the forces
-// and the ybar contributions to two LDS accumulators of the same tile nodes.  Per-tet arithmetic, tile order and every summation order
-// are those of the forward kernel and of the backward kernel, so f, E,
-// the inverted counts, ybar and thetabar equal those of the two separate
-// passes bit for bit.  Scratch: the forward's slot partials and tile records
+// and the ybar contributions to two LDS accumulators of the same tile nodes.
+// Per-tet arithmetic, tile order and every summation order are those of the
+// forward kernel and of the backward kernel, so f, E, the inverted counts,
+// ybar and thetabar equal those of the two separate passes bit for bit.  Scratch: the forward's slot partials and tile records
 // (T) and the backward's (part_b, tile_acc_b), finalized by one kernel that
 // forms both passes' sums.
 #include <hip/hip_runtime.h>
@@ -98,7 +98,8 @@ void forward_backward_kernel(FusedArgs a) {
         eacc += vU;
         ninv += sc.J > 0.0 ? 0 : 1;
         // the forward half's temporaries are dead before the adjoint half
-        // is formed (168 VGPRs: three waves per SIMD instead of two)
+        // is formed: the kernel fits the 168 VGPRs of three waves per SIMD
+        // (185 without the barrier: two waves)
         __builtin_amdgcn_sched_barrier(0);
         // adjoint half from the same F, invariants and cof F, as tet_backward
         const float2 w0 = vs[i0], w1 = vs[i1], w2 = vs[i2], w3 = vs[i3];
