@@ -218,3 +218,28 @@ def test_fused_graph_replays_and_aliasing_rejected():
         cb.forces_and_backward(y, fb, eb, f=f, ybar=f)
     with pytest.raises(CellmechError, match="alias"):
         cb.forces_and_backward(y, fb, eb, f=fb)
+
+
+def test_fused_node_of_no_tetrahedron():
+    """A node that no tetrahedron uses is a shared node with no slot: the
+    fused finalize writes zero force and zero ybar for it, as the separate
+    passes do, and every other output is bitwise theirs."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    c0, c1 = small_sphere_case(1021), small_sphere_case(1022)
+    extra = np.array([[0.0, 0.0, 2.0]])
+    x = np.concatenate([c0.x, extra, c1.x])
+    y = np.concatenate([c0.y, extra, c1.y]).astype(np.float32)
+    n0 = len(c0.x) + 1
+    tets = np.concatenate([c0.tets, c1.tets])
+    cb = CellBatch([0, n0, n0 + len(c1.x)], [0, len(c0.tets), len(tets)], x, tets)
+    cb.set_params([c0.theta[0], c1.theta[0]], [c0.theta[1], c1.theta[1]],
+                  [c0.theta[2], c1.theta[2]])
+    yd = cb.to_device(y)
+    fb = cb.to_device(cotangent(cb.n_nodes, 1023))
+    eb = torch.tensor([0.3, 0.6], dtype=torch.float64, device=cb.device)
+    want = _separate(cb, yd, fb, eb, 2)
+    got = _fused(cb, yd, fb, eb, 2)
+    _assert_equal(got, want)
+    assert not cb.to_host(got[0])[len(c0.x)].any()
+    assert not cb.to_host(got[3])[len(c0.x)].any()
