@@ -274,8 +274,9 @@ int cm_forces_backward(cm_batch h, const float* y, const float* fbar,
  * Launch shape: the handle's (cm_set_launch), with waves per workgroup
  * halved until the pass's LDS (48 B per tile node and wave) fits in 64 KiB.
  * Nothing is allocated.  Errors: as cm_forces and cm_forces_backward, and
- * CM_EINVAL if f or ybar alias each other, y or fbar (outputs are written
- * while other tiles still read the inputs).
+ * CM_EINVAL if f or ybar equals another of f, ybar, y, fbar (outputs are
+ * written while other tiles still read the inputs; buffers that overlap
+ * without being equal are not detected and must not be passed).
  */
 int cm_forces_and_backward(cm_batch h, const float* y, float* f, double* energy,
                            int32_t* n_inverted, const float* fbar, const double* ebar,
