@@ -243,3 +243,37 @@ def test_fused_node_of_no_tetrahedron():
     _assert_equal(got, want)
     assert not cb.to_host(got[0])[len(c0.x)].any()
     assert not cb.to_host(got[3])[len(c0.x)].any()
+
+
+def test_fused_tiny_and_ragged_cells():
+    """A 1-tetrahedron cell, two tetrahedra sharing a face, a 5-tetrahedron
+    cube and a sphere in one batch (tiles of one chunk with mostly empty
+    lanes beside full tiles): bitwise the separate passes, and the oracle's
+    forces, energies, ybar and thetabar per cell."""
+    import torch
+    from paper_2003_03130_amd import CellBatch
+    from synth.configs import batch_from_cells
+    from test_gpu_forward import _tiny_cells
+    cells = _tiny_cells()
+    b = batch_from_cells(cells)
+    cb = CellBatch(b.node_off, b.tet_off, b.x, b.tets)
+    cb.set_params(b.theta[:, 0], b.theta[:, 1], b.theta[:, 2])
+    y = cb.to_device(b.y)
+    v = cotangent(b.n_nodes, 79)
+    fb = cb.to_device(v)
+    ebh = np.array([0.4, -0.2, 0.9, 0.1])
+    eb = torch.tensor(ebh, dtype=torch.float64, device=cb.device)
+    got = _fused(cb, y, fb, eb, b.n_cells)
+    _assert_equal(got, _separate(cb, y, fb, eb, b.n_cells))
+    f, E, yb = cb.to_host(got[0]), got[1].cpu().numpy(), cb.to_host(got[3])
+    tb = got[4].cpu().numpy().reshape(-1, 3)
+    for c, cell in enumerate(cells):
+        n0, n1 = b.node_off[c], b.node_off[c + 1]
+        m = oracle.OracleMesh(cell.x, cell.tets)
+        y64 = cell.y.astype(np.float64)
+        fo, Eo, _ = m.forces(y64, cell.theta)
+        yo, to = m.backward(y64, cell.theta, v[n0:n1].astype(np.float64), float(ebh[c]))
+        assert force_rel_err(f[n0:n1], fo) <= TOL, c
+        assert rel_err(E[c], Eo) <= E_TOL, c
+        assert force_rel_err(yb[n0:n1], yo) <= TOL, c
+        assert force_rel_err(tb[c], to) <= TOL, c
