@@ -319,8 +319,9 @@ int cm_forces_backward_percell(cm_batch h, const float* y, const float* fbar,
  * that fits in LDS on `stream`, with the handle's data,
  * the caller's positions `y` (device, SoA, also used as the cotangent) and
  * the parameters already set, and keeps the fastest.  `cache_path`
- * (nullable) is a JSON file keyed by device name and mesh statistics; a hit
- * skips the measurement, a miss appends the result.  Tuning allocates and
+ * (nullable) is a JSON file keyed by device name, mesh statistics and the
+ * timed objective; a hit skips the measurement, a miss appends the result.
+ * Tuning allocates and
  * frees scratch outputs and synchronises the stream: it is not graph-safe.
  */
 /*

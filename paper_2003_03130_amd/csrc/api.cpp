@@ -752,6 +752,10 @@ static std::string device_key(cm_batch h) {
   return std::string(prop.gcnArchName) + "|cu" + std::to_string(h->n_cu);
 }
 
+// Names what a cached timing measured (one fused forward + backward
+// evaluation), so that entries timed with another objective are not reused.
+static const char* const kTuneObjective = "|fused-fwd-bwd";
+
 static std::string sanitize_key(std::string key) {
   for (char& ch : key)
     if (ch == '"' || ch == '\\') ch = '_';
@@ -767,7 +771,7 @@ int cm_autotune(cm_batch h, const float* y, const char* cache_path,
   const std::string key = sanitize_key(
       device_key(h) + "|tets" + std::to_string(h->n_tets) + "|tiles" +
       std::to_string(h->n_tiles) + "|tile" + std::to_string(h->tile_tets) + "|nloc" +
-      std::to_string(h->T.nloc) + (h->is_template ? "|template" : ""));
+      std::to_string(h->T.nloc) + (h->is_template ? "|template" : "") + kTuneObjective);
   int w = 0, b = 0;
   if (cache_path && cache_lookup(cache_path, key, &w, &b))
     return cm_set_launch(h, w, b);
@@ -817,7 +821,7 @@ int cm_batch_create_tuned(int32_t n_cells, const int64_t* node_off,
                     "|tets" + std::to_string(tet_off[n_cells]) + "|order" +
                     std::to_string(base.order) + "|cand";
   for (int32_t k = 0; k < n_candidates; ++k) key += "," + std::to_string(tile_candidates[k]);
-  key = sanitize_key(key);
+  key = sanitize_key(key + kTuneObjective);
   int cw = 0, cb = 0, ct = 0;
   if (cache_path && cache_lookup_tile(cache_path, key, &cw, &cb, &ct)) {
     cm::PrepOptions po = base;
